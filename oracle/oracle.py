@@ -1,0 +1,127 @@
+"""ctypes access to the FP64 oracle library (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "liboracle.so")
+
+
+def load():
+    """Load liboracle.so, building it first if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(lib_path()):
+        from .build import build
+        build()
+    lib = ctypes.CDLL(lib_path())
+    c_u64p = ctypes.POINTER(ctypes.c_uint64)
+    c_dp = ctypes.POINTER(ctypes.c_double)
+    c_i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.or_gate_matrix.argtypes = [ctypes.c_int, c_dp]
+    lib.or_full_state.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, c_dp]
+    lib.or_pext.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.or_pext.restype = ctypes.c_uint64
+    lib.or_cut_gates.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64,
+                                 c_i64p, ctypes.c_int]
+    lib.or_num_cut.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64]
+    lib.or_path_sum.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64,
+                                c_u64p, ctypes.c_int64, c_u64p, ctypes.c_int64, c_dp, c_dp, c_dp]
+    lib.or_num_paths.argtypes = [ctypes.c_int, ctypes.c_double]
+    lib.or_num_paths.restype = ctypes.c_int64
+    lib.or_sample_paths.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, c_u64p,
+                                    ctypes.c_int64, c_i64p]
+    _LIB = lib
+    return lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses (OMP_NUM_THREADS, else all cores)."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    return int(v) if v else (os.cpu_count() or 1)
+
+
+def gate_matrix(kind: int) -> np.ndarray:
+    out = np.zeros(8, dtype=np.float64)
+    if load().or_gate_matrix(kind, _ptr(out, ctypes.c_double)):
+        raise ValueError("not a one-qubit gate kind")
+    return (out[0::2] + 1j * out[1::2]).reshape(2, 2)
+
+
+def full_state(n: int, gates: np.ndarray) -> np.ndarray:
+    """O1: the 2^n complex128 state after all gates (list order)."""
+    g = np.ascontiguousarray(gates)
+    psi = np.empty(2 << n, dtype=np.float64)
+    if load().or_full_state(n, g.ctypes.data, g.size, _ptr(psi, ctypes.c_double)):
+        raise ValueError("invalid circuit")
+    return psi.view(np.complex128)
+
+
+def pext(x: int, mask: int) -> int:
+    return int(load().or_pext(x, mask))
+
+
+def num_cut(n: int, gates: np.ndarray, mask_a: int) -> int:
+    g = np.ascontiguousarray(gates)
+    return int(load().or_num_cut(n, g.ctypes.data, g.size, mask_a))
+
+
+def cut_gates(n: int, gates: np.ndarray, mask_a: int) -> np.ndarray:
+    """Indices (into ``gates``) of the crossing CZs in path-bit order."""
+    g = np.ascontiguousarray(gates)
+    k = num_cut(n, g, mask_a)
+    idx = np.zeros(max(k, 1), dtype=np.int64)
+    load().or_cut_gates(n, g.ctypes.data, g.size, mask_a, _ptr(idx, ctypes.c_int64), k)
+    return idx[:k]
+
+
+def path_sum(n: int, gates: np.ndarray, mask_a: int, paths, bits, norms: bool = False):
+    """O2: sum over ``paths`` of psiA_p(x_A) psiB_p(x_B) for each bitstring.
+
+    Returns complex128 amplitudes, plus (||psiA_p||^2, ||psiB_p||^2) arrays
+    when ``norms`` is true.
+    """
+    g = np.ascontiguousarray(gates)
+    p = np.ascontiguousarray(np.asarray(paths, dtype=np.uint64))
+    b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint64))
+    amps = np.zeros(2 * max(b.size, 1), dtype=np.float64)
+    na = np.zeros(max(p.size, 1)) if norms else None
+    nb = np.zeros(max(p.size, 1)) if norms else None
+    rc = load().or_path_sum(n, g.ctypes.data, g.size, mask_a,
+                            _ptr(p, ctypes.c_uint64), p.size, _ptr(b, ctypes.c_uint64), b.size,
+                            _ptr(amps, ctypes.c_double),
+                            _ptr(na, ctypes.c_double) if norms else None,
+                            _ptr(nb, ctypes.c_double) if norms else None)
+    if rc:
+        raise ValueError("invalid path-sum request")
+    out = amps.view(np.complex128)[: b.size]
+    if norms:
+        return out, na[: p.size], nb[: p.size]
+    return out
+
+
+def num_paths(k: int, f: float) -> int:
+    return int(load().or_num_paths(k, f))
+
+
+def sample_paths(k: int, f: float, seed: int) -> np.ndarray:
+    m = num_paths(k, f)
+    if m < 0:
+        raise ValueError("bad k or f")
+    out = np.zeros(m, dtype=np.uint64)
+    n_out = ctypes.c_int64(0)
+    if load().or_sample_paths(k, f, seed, _ptr(out, ctypes.c_uint64), m, ctypes.byref(n_out)):
+        raise ValueError("sampling failed")
+    return out[: n_out.value]

@@ -1,0 +1,438 @@
+/*
+ * FP64 CPU oracle for the Schroedinger-Feynman path sum.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code, header, table or helper with the GPU library; both only read the
+ * same gate records and input arrays.
+ *
+ * What it computes (arXiv:1807.10749):
+ *   O1  full state vector: |0...0> evolved gate by gate in list order
+ *       (Section 1: the circuits start with H on every qubit and interleave
+ *       CZ layers with one-qubit gates).
+ *   O2  Schroedinger-Feynman path sum (Section 2, Eq. (CZ); Section 3, the
+ *       path expansion |psi> = sum_j |phi_j>): the qubits are split into
+ *       block A (holding qubit 0) and block B; every CZ that crosses the cut
+ *       is written P0 (x) I + P1 (x) Z, each path picks one term per crossing
+ *       CZ, both blocks are evolved separately, and requested amplitudes are
+ *       accumulated as sum_p psiA_p(x_A) * psiB_p(x_B) ("Final-state
+ *       amplitudes", end of Section 2).
+ *   Path selection for fidelity f (Section 3, Eq. (fid)): ceil(f 2^k)
+ *   distinct path ids drawn with Floyd's algorithm over SplitMix64.
+ *
+ * Readings of points the paper leaves open (kept identical in the GPU path
+ * by definition, never by shared code):
+ *   - gate matrices: H = [[1,1],[1,-1]]/sqrt2, X^1/2 = [[1+i,1-i],[1-i,1+i]]/2,
+ *     Y^1/2 = [[1+i,-1-i],[1+i,1+i]]/2, T = diag(1, e^{i pi/4});
+ *   - bitstring bit q is the value of qubit q; local index of a qubit inside
+ *     its block is its rank among the block's qubits;
+ *   - crossing CZs are ordered by (cycle, smaller qubit id); crossing CZ j
+ *     is decided by bit (k-1-j) of the path id; the projector goes on the
+ *     block-A endpoint and Z on the block-B endpoint.
+ *
+ * Everything is plain loops in double precision.  OpenMP is used only to
+ * spread independent loop iterations over host cores.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    uint8_t kind;   /* 0 H, 1 X^1/2, 2 Y^1/2, 3 T, 4 CZ */
+    uint8_t pad;
+    uint16_t cycle;
+    uint16_t q0, q1;
+} or_gate;
+
+enum { OR_H = 0, OR_XH = 1, OR_YH = 2, OR_T = 3, OR_CZ = 4 };
+
+/* ------------------------------------------------------------------ */
+/* Gate matrices, row-major m[0]=u00 m[1]=u01 m[2]=u10 m[3]=u11.        */
+/* ------------------------------------------------------------------ */
+static int gate_matrix(int kind, double complex m[4])
+{
+    const double r = 1.0 / sqrt(2.0);
+    switch (kind) {
+    case OR_H:
+        m[0] = r; m[1] = r; m[2] = r; m[3] = -r;
+        return 0;
+    case OR_XH:
+        m[0] = 0.5 * (1.0 + I); m[1] = 0.5 * (1.0 - I);
+        m[2] = 0.5 * (1.0 - I); m[3] = 0.5 * (1.0 + I);
+        return 0;
+    case OR_YH:
+        m[0] = 0.5 * (1.0 + I); m[1] = 0.5 * (-1.0 - I);
+        m[2] = 0.5 * (1.0 + I); m[3] = 0.5 * (1.0 + I);
+        return 0;
+    case OR_T:
+        m[0] = 1.0; m[1] = 0.0; m[2] = 0.0; m[3] = cexp(I * M_PI / 4.0);
+        return 0;
+    default:
+        return -1;
+    }
+}
+
+/* Exported copy of the matrices for the tests: out = 8 doubles (re, im). */
+int or_gate_matrix(int kind, double *out)
+{
+    double complex m[4];
+    if (gate_matrix(kind, m)) return -1;
+    for (int i = 0; i < 4; ++i) { out[2 * i] = creal(m[i]); out[2 * i + 1] = cimag(m[i]); }
+    return 0;
+}
+
+/* Apply a one-qubit matrix on bit t of a 2^n vector. */
+static void apply_1q(double complex *psi, int n, int t, const double complex m[4])
+{
+    const int64_t half = (int64_t)1 << (n - 1);
+    const uint64_t low = ((uint64_t)1 << t) - 1;
+#pragma omp parallel for schedule(static) if (n > 14)
+    for (int64_t i = 0; i < half; ++i) {
+        uint64_t i0 = (((uint64_t)i & ~low) << 1) | ((uint64_t)i & low);
+        uint64_t i1 = i0 | ((uint64_t)1 << t);
+        double complex a = psi[i0], b = psi[i1];
+        psi[i0] = m[0] * a + m[1] * b;
+        psi[i1] = m[2] * a + m[3] * b;
+    }
+}
+
+/* CZ on bits a, b: negate amplitudes whose bits a and b are both 1. */
+static void apply_cz(double complex *psi, int n, int a, int b)
+{
+    const int64_t size = (int64_t)1 << n;
+#pragma omp parallel for schedule(static) if (n > 14)
+    for (int64_t i = 0; i < size; ++i)
+        if ((((uint64_t)i >> a) & 1) && (((uint64_t)i >> b) & 1)) psi[i] = -psi[i];
+}
+
+/* Projector P_s on bit a: zero amplitudes whose bit a differs from s. */
+static void apply_projector(double complex *psi, int n, int a, int s)
+{
+    const int64_t size = (int64_t)1 << n;
+#pragma omp parallel for schedule(static) if (n > 14)
+    for (int64_t i = 0; i < size; ++i)
+        if ((int)(((uint64_t)i >> a) & 1) != s) psi[i] = 0.0;
+}
+
+/* Pauli Z on bit b: negate amplitudes whose bit b is 1. */
+static void apply_z(double complex *psi, int n, int b)
+{
+    const int64_t size = (int64_t)1 << n;
+#pragma omp parallel for schedule(static) if (n > 14)
+    for (int64_t i = 0; i < size; ++i)
+        if (((uint64_t)i >> b) & 1) psi[i] = -psi[i];
+}
+
+static int check_gates(int n, const or_gate *g, size_t ng)
+{
+    for (size_t i = 0; i < ng; ++i) {
+        if (g[i].kind > OR_CZ || g[i].q0 >= n) return -1;
+        if (g[i].kind == OR_CZ && (g[i].q1 >= n || g[i].q1 == g[i].q0)) return -1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* O1: full state vector.  psi_out holds 2^n complex (re, im) doubles. */
+/* ------------------------------------------------------------------ */
+int or_full_state(int n, const or_gate *gates, size_t ng, double *psi_out)
+{
+    if (n < 1 || n > 34 || check_gates(n, gates, ng)) return -1;
+    double complex *psi = (double complex *)psi_out;
+    const int64_t size = (int64_t)1 << n;
+#pragma omp parallel for schedule(static) if (n > 14)
+    for (int64_t i = 0; i < size; ++i) psi[i] = 0.0;
+    psi[0] = 1.0;
+    for (size_t i = 0; i < ng; ++i) {
+        if (gates[i].kind == OR_CZ) {
+            apply_cz(psi, n, gates[i].q0, gates[i].q1);
+        } else {
+            double complex m[4];
+            gate_matrix(gates[i].kind, m);
+            apply_1q(psi, n, gates[i].q0, m);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Bit helpers                                                         */
+/* ------------------------------------------------------------------ */
+uint64_t or_pext(uint64_t x, uint64_t mask)
+{
+    uint64_t out = 0;
+    int j = 0;
+    for (int q = 0; q < 64; ++q)
+        if ((mask >> q) & 1) { out |= ((x >> q) & 1) << j; ++j; }
+    return out;
+}
+
+static int popcount64(uint64_t x)
+{
+    int c = 0;
+    while (x) { x &= x - 1; ++c; }
+    return c;
+}
+
+/* Local index of qubit q inside the block given by mask = its rank. */
+static int local_index(uint64_t mask, int q)
+{
+    return popcount64(mask & (((uint64_t)1 << q) - 1));
+}
+
+/* Crossing CZs ordered by (cycle, smaller qubit); returns k or -1.
+ * idx_out (capacity cap) receives gate indices in path-bit order. */
+int or_cut_gates(int n, const or_gate *gates, size_t ng, uint64_t mask_a,
+                 int64_t *idx_out, int cap)
+{
+    if (check_gates(n, gates, ng)) return -1;
+    int k = 0;
+    for (size_t i = 0; i < ng; ++i) {
+        if (gates[i].kind != OR_CZ) continue;
+        int ina = (int)((mask_a >> gates[i].q0) & 1), inb = (int)((mask_a >> gates[i].q1) & 1);
+        if (ina == inb) continue;
+        if (k < cap && idx_out) idx_out[k] = (int64_t)i;
+        ++k;
+    }
+    if (k > cap || !idx_out) return k;
+    /* insertion sort on (cycle, min qubit) keeps equal keys in list order */
+    for (int a = 1; a < k; ++a) {
+        int64_t v = idx_out[a];
+        int cv = gates[v].cycle;
+        int mv = gates[v].q0 < gates[v].q1 ? gates[v].q0 : gates[v].q1;
+        int b = a - 1;
+        while (b >= 0) {
+            int64_t w = idx_out[b];
+            int cw = gates[w].cycle;
+            int mw = gates[w].q0 < gates[w].q1 ? gates[w].q0 : gates[w].q1;
+            if (cw < cv || (cw == cv && mw <= mv)) break;
+            idx_out[b + 1] = w;
+            --b;
+        }
+        idx_out[b + 1] = v;
+    }
+    return k;
+}
+
+/* ------------------------------------------------------------------ */
+/* O2: Schroedinger-Feynman path sum.                                  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int n, qa, qb, k;
+    uint64_t mask_a, mask_b;
+    const or_gate *gates;
+    size_t ng;
+    int *bit_of_gate;   /* per gate: path bit position deciding it, or -1 */
+} or_cut_info;
+
+/* Evolve both blocks for one path id.  psiA has 2^qa entries, psiB 2^qb. */
+static void evolve_path(const or_cut_info *c, uint64_t path,
+                        double complex *psiA, double complex *psiB)
+{
+    const int64_t sa = (int64_t)1 << c->qa, sb = (int64_t)1 << c->qb;
+    for (int64_t i = 0; i < sa; ++i) psiA[i] = 0.0;
+    for (int64_t i = 0; i < sb; ++i) psiB[i] = 0.0;
+    psiA[0] = 1.0;
+    psiB[0] = 1.0;
+    for (size_t g = 0; g < c->ng; ++g) {
+        const or_gate *G = &c->gates[g];
+        int q0 = G->q0;
+        int a0 = (int)((c->mask_a >> q0) & 1);
+        if (G->kind != OR_CZ) {
+            double complex m[4];
+            gate_matrix(G->kind, m);
+            if (a0) apply_1q(psiA, c->qa, local_index(c->mask_a, q0), m);
+            else    apply_1q(psiB, c->qb, local_index(c->mask_b, q0), m);
+            continue;
+        }
+        int q1 = G->q1;
+        int a1 = (int)((c->mask_a >> q1) & 1);
+        if (a0 && a1) {
+            apply_cz(psiA, c->qa, local_index(c->mask_a, q0), local_index(c->mask_a, q1));
+        } else if (!a0 && !a1) {
+            apply_cz(psiB, c->qb, local_index(c->mask_b, q0), local_index(c->mask_b, q1));
+        } else {
+            /* crossing CZ = P0 (x) I + P1 (x) Z; this path takes term s */
+            int s = (int)((path >> c->bit_of_gate[g]) & 1);
+            int qa_ = a0 ? q0 : q1, qb_ = a0 ? q1 : q0;
+            apply_projector(psiA, c->qa, local_index(c->mask_a, qa_), s);
+            if (s) apply_z(psiB, c->qb, local_index(c->mask_b, qb_));
+        }
+    }
+}
+
+static int make_cut_info(int n, const or_gate *gates, size_t ng, uint64_t mask_a, or_cut_info *c)
+{
+    if (n < 2 || n > 64 || check_gates(n, gates, ng)) return -1;
+    uint64_t all = n == 64 ? ~(uint64_t)0 : (((uint64_t)1 << n) - 1);
+    if (!(mask_a & 1) || (mask_a & ~all) || (mask_a == all)) return -1;
+    c->n = n;
+    c->mask_a = mask_a;
+    c->mask_b = all & ~mask_a;
+    c->qa = popcount64(c->mask_a);
+    c->qb = popcount64(c->mask_b);
+    c->gates = gates;
+    c->ng = ng;
+    if (c->qa > 30 || c->qb > 30) return -1;
+    int k = or_cut_gates(n, gates, ng, mask_a, NULL, 0);
+    if (k < 0 || k > 63) return -1;
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (k ? k : 1));
+    c->bit_of_gate = (int *)malloc(sizeof(int) * (ng ? ng : 1));
+    for (size_t i = 0; i < ng; ++i) c->bit_of_gate[i] = -1;
+    or_cut_gates(n, gates, ng, mask_a, idx, k);
+    for (int j = 0; j < k; ++j) c->bit_of_gate[idx[j]] = k - 1 - j;
+    free(idx);
+    c->k = k;
+    return 0;
+}
+
+/*
+ * amps_out: 2*nbits doubles (re, im), overwritten with
+ *   sum over the listed paths (in the listed order) of psiA_p(x_A) psiB_p(x_B).
+ * normsA_out / normsB_out (optional, npaths doubles): ||psiA_p||^2, ||psiB_p||^2.
+ */
+int or_path_sum(int n, const or_gate *gates, size_t ng, uint64_t mask_a,
+                const uint64_t *paths, int64_t npaths,
+                const uint64_t *bits, int64_t nbits, double *amps_out,
+                double *normsA_out, double *normsB_out)
+{
+    or_cut_info c;
+    if (make_cut_info(n, gates, ng, mask_a, &c)) return -1;
+    for (int64_t p = 0; p < npaths; ++p)
+        if (c.k < 64 && (paths[p] >> c.k) != 0) { free(c.bit_of_gate); return -1; }
+    uint64_t all = n == 64 ? ~(uint64_t)0 : (((uint64_t)1 << n) - 1);
+    for (int64_t j = 0; j < nbits; ++j)
+        if (bits[j] & ~all) { free(c.bit_of_gate); return -1; }
+
+    const int64_t sa = (int64_t)1 << c.qa, sb = (int64_t)1 << c.qb;
+    uint64_t *xa = (uint64_t *)malloc(sizeof(uint64_t) * (nbits ? nbits : 1));
+    uint64_t *xb = (uint64_t *)malloc(sizeof(uint64_t) * (nbits ? nbits : 1));
+    for (int64_t j = 0; j < nbits; ++j) {
+        xa[j] = or_pext(bits[j], c.mask_a);
+        xb[j] = or_pext(bits[j], c.mask_b);
+    }
+    double complex *amps = (double complex *)amps_out;
+    for (int64_t j = 0; j < nbits; ++j) amps[j] = 0.0;
+
+    /* Large blocks: one path at a time, amplitude loops spread over cores.
+     * Small blocks: paths spread over cores, each core summing its own
+     * contiguous run of paths; the per-core sums are added in core order. */
+    const int per_path_parallel = (c.qa > 16 || c.qb > 16);
+    if (per_path_parallel) {
+        double complex *A = (double complex *)malloc(sizeof(double complex) * sa);
+        double complex *B = (double complex *)malloc(sizeof(double complex) * sb);
+        for (int64_t p = 0; p < npaths; ++p) {
+            evolve_path(&c, paths[p], A, B);
+            for (int64_t j = 0; j < nbits; ++j) amps[j] += A[xa[j]] * B[xb[j]];
+            if (normsA_out) { double s = 0; for (int64_t i = 0; i < sa; ++i) s += creal(A[i] * conj(A[i])); normsA_out[p] = s; }
+            if (normsB_out) { double s = 0; for (int64_t i = 0; i < sb; ++i) s += creal(B[i] * conj(B[i])); normsB_out[p] = s; }
+        }
+        free(A); free(B);
+    } else {
+        int nt = 1;
+#ifdef _OPENMP
+        nt = omp_get_max_threads();
+#endif
+        if (nt > npaths && npaths > 0) nt = (int)npaths;
+        if (nt < 1) nt = 1;
+        double complex *part = (double complex *)calloc((size_t)nt * (nbits ? nbits : 1), sizeof(double complex));
+#pragma omp parallel num_threads(nt)
+        {
+            int t = 0;
+#ifdef _OPENMP
+            t = omp_get_thread_num();
+#endif
+            int64_t lo = npaths * t / nt, hi = npaths * (t + 1) / nt;
+            double complex *A = (double complex *)malloc(sizeof(double complex) * sa);
+            double complex *B = (double complex *)malloc(sizeof(double complex) * sb);
+            double complex *acc = part + (size_t)t * (nbits ? nbits : 1);
+            for (int64_t p = lo; p < hi; ++p) {
+                evolve_path(&c, paths[p], A, B);
+                for (int64_t j = 0; j < nbits; ++j) acc[j] += A[xa[j]] * B[xb[j]];
+                if (normsA_out) { double s = 0; for (int64_t i = 0; i < sa; ++i) s += creal(A[i] * conj(A[i])); normsA_out[p] = s; }
+                if (normsB_out) { double s = 0; for (int64_t i = 0; i < sb; ++i) s += creal(B[i] * conj(B[i])); normsB_out[p] = s; }
+            }
+            free(A); free(B);
+        }
+        for (int t = 0; t < nt; ++t)
+            for (int64_t j = 0; j < nbits; ++j) amps[j] += part[(size_t)t * nbits + j];
+        free(part);
+    }
+    free(xa); free(xb); free(c.bit_of_gate);
+    return 0;
+}
+
+/* Number of crossing CZs for a cut, or -1. */
+int or_num_cut(int n, const or_gate *gates, size_t ng, uint64_t mask_a)
+{
+    return or_cut_gates(n, gates, ng, mask_a, NULL, 0);
+}
+
+/* ------------------------------------------------------------------ */
+/* Path selection: ceil(f 2^k) distinct ids, Floyd's algorithm          */
+/* (Bentley and Floyd, "A sample of brilliance", CACM 1987) driven by   */
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014); a bounded draw in   */
+/* [0, m) is floor(r * m / 2^64) for a 64-bit output r.                */
+/* ------------------------------------------------------------------ */
+static uint64_t splitmix_next(uint64_t *state)
+{
+    *state += 0x9E3779B97F4A7C15ULL;
+    uint64_t z = *state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y);
+}
+
+/* Open-addressing set of uint64 (key + 1 stored, 0 = empty). */
+typedef struct { uint64_t *slot; uint64_t cap; } u64set;
+
+static int set_insert(u64set *s, uint64_t key)   /* 1 if inserted, 0 if present */
+{
+    uint64_t h = key * 0x9E3779B97F4A7C15ULL;
+    uint64_t i = h & (s->cap - 1);
+    for (;;) {
+        if (s->slot[i] == 0) { s->slot[i] = key + 1; return 1; }
+        if (s->slot[i] == key + 1) return 0;
+        i = (i + 1) & (s->cap - 1);
+    }
+}
+
+int64_t or_num_paths(int k, double f)
+{
+    if (k < 0 || k > 62 || !(f > 0.0) || f > 1.0) return -1;
+    return (int64_t)ceil(ldexp(f, k));
+}
+
+int or_sample_paths(int k, double f, uint64_t seed, uint64_t *out, int64_t cap, int64_t *n_out)
+{
+    int64_t m = or_num_paths(k, f);
+    if (m < 0 || m > cap) return -1;
+    const uint64_t N = (uint64_t)1 << k;
+    u64set s;
+    s.cap = 1;
+    while (s.cap < 2 * (uint64_t)m + 2) s.cap <<= 1;
+    s.slot = (uint64_t *)calloc(s.cap, sizeof(uint64_t));
+    uint64_t st = seed;
+    int64_t filled = 0;
+    for (uint64_t j = N - (uint64_t)m; j < N; ++j) {
+        uint64_t r = splitmix_next(&st);
+        uint64_t t = (uint64_t)(((unsigned __int128)r * (unsigned __int128)(j + 1)) >> 64);
+        if (set_insert(&s, t)) out[filled++] = t;
+        else { set_insert(&s, j); out[filled++] = j; }
+    }
+    free(s.slot);
+    qsort(out, (size_t)m, sizeof(uint64_t), cmp_u64);
+    *n_out = m;
+    return 0;
+}
