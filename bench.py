@@ -1,0 +1,175 @@
+"""Benchmark: Schroedinger-Feynman path sum on one MI355X.
+
+Default workload: 5x6 grid (30 qubits), depth 1+24+1, vertical cut 15+15
+(k = 15 crossing CZs), all 2^15 paths (f = 1), 1e5 uniformly random
+bitstrings.  One "step" is one full run_paths call over all paths with
+inputs (bitstrings, workspace, output) already resident in HBM.
+
+Prints one JSON line with paths/s (value), amps/s, the roofline of the
+dominant kernel measured with HIP events on the launch stream, the plain
+one-path-per-launch GPU form on a subset of paths, and the FP64 CPU oracle
+on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="grid5x6_d24")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-paths", type=int, default=64)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path sum would shard "
+              "aligned path blocks across GPUs with one final reduction, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1807_10749_amd import binding as sf
+    from workload import CONFIGS, make_workload, path_block
+
+    cfg = CONFIGS[args.workload]
+    w = make_workload(args.workload)
+    gates, bits = w["gates"], w["bitstrings"]
+    n = cfg.n_qubits
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    c = sf.Circuit(cfg.rows, cfg.cols, gates, cfg.cut_mask())
+    if cfg.paths == "all":
+        ids, begin, npaths = None, 0, 1 << c.k
+    elif cfg.paths == "block":
+        begin, npaths = path_block(c.k, cfg.block_bits, cfg.path_seed)
+        ids = None
+    else:
+        ids = sf.sample_paths(c.k, cfg.f, cfg.path_seed)
+        begin, npaths = 0, ids.size
+    flags_base = sf.SF_FP64_SWEEPS if cfg.fp64_sweeps else 0
+
+    d_bits = torch.from_numpy(bits.view(np.int64)).cuda()
+    d_amps = torch.zeros(2 * bits.size, dtype=torch.float64, device="cuda")
+    ws_bytes = sf.workspace_size(c.handle, npaths, bits.size, flags_base)
+    free_b, _ = torch.cuda.mem_get_info()
+    ws_bytes = min(ws_bytes, int(free_b * 0.85))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    flags = flags_base | sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
+
+    def step(extra=0):
+        sf.run_paths(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags | extra, stream, ws, ws_bytes)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sweep_ms = gather_ms = 0.0
+    sweep_launches = gather_launches = 0
+    sweep_bytes = gather_bytes = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(sf.SF_TIMING)
+        st = c.stats()
+        sweep_ms += st["ms_sweep"]
+        gather_ms += st["ms_gather"]
+        sweep_launches += st["n_sweep_launches"]
+        gather_launches += st["n_gather_launches"]
+        sweep_bytes += st["sweep_bytes"]
+        gather_bytes += st["gather_bytes"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    paths_per_s = npaths * args.steps / elapsed
+    amps_per_s = bits.size * args.steps / elapsed
+
+    # dominant kernel category by measured time
+    if sweep_ms >= gather_ms:
+        dom, dom_ms, dom_n, dom_bytes = "pass_kernel (gate sweep)", sweep_ms, sweep_launches, sweep_bytes
+    else:
+        dom, dom_ms, dom_n, dom_bytes = "gather_kernel (path sum)", gather_ms, gather_launches, gather_bytes
+    avg_launch_ms = dom_ms / max(dom_n, 1)
+    achieved = (dom_bytes / max(dom_n, 1)) / (avg_launch_ms * 1e-3) / 1e9 if dom_n else 0.0
+
+    # plain one-path-per-launch GPU form on a subset of the same paths
+    plain_n = min(args.plain_paths, npaths)
+    plain_ids = ids[:plain_n] if ids is not None else None
+    sf.run_paths(c.handle, plain_ids, begin, plain_n, d_bits, bits.size, d_amps, flags | sf.SF_PLAIN, stream, ws, ws_bytes)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    sf.run_paths(c.handle, plain_ids, begin, plain_n, d_bits, bits.size, d_amps, flags | sf.SF_PLAIN, stream, ws, ws_bytes)
+    torch.cuda.synchronize()
+    plain_paths_per_s = plain_n / (time.perf_counter() - tp)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cfg, gates, bits, c.k, ids, begin, npaths, args.cpu_seconds)
+
+    out = {
+        "metric": "Feynman paths/s at fidelity f (amps/s, HBM GB/s % peak alongside)",
+        "value": paths_per_s,
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if cfg.fp64_sweeps else "c64 sweeps, f64 path sum",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": f"{cfg.rows}x{cfg.cols}", "depth": f"1+{cfg.depth}+1",
+                   "cut": f"{bin(cfg.cut_mask()).count('1')}+{n - bin(cfg.cut_mask()).count('1')}",
+                   "k": c.k, "paths": npaths, "f": cfg.f if cfg.paths == "sample" else npaths / 2.0 ** c.k,
+                   "bitstrings": int(bits.size)},
+        "amps_per_s": amps_per_s,
+        "plain_form": {"paths_per_s": plain_paths_per_s, "paths": plain_n,
+                       "speedup_of_batched": paths_per_s / plain_paths_per_s},
+        "kernel_ms_per_step": {"sweep": sweep_ms / args.steps, "gather": gather_ms / args.steps},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": avg_launch_ms, "launches_per_step": dom_n / args.steps,
+                     "bytes_per_launch": dom_bytes / max(dom_n, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    c.close()
+
+
+def cpu_baseline(cfg, gates, bits, k, ids, begin, npaths, budget_s):
+    """The FP64 oracle's path sum on a bounded, time-boxed sample of the same workload."""
+    import oracle
+    from oracle.build import build
+    if not os.path.exists(oracle.lib_path()):
+        build()
+    all_ids = ids if ids is not None else None
+    chunk = 16
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < npaths:
+        m = min(chunk, npaths - done)
+        sel = all_ids[done:done + m] if all_ids is not None else np.arange(begin + done, begin + done + m, dtype=np.uint64)
+        oracle.path_sum(cfg.n_qubits, gates, cfg.cut_mask(), sel, bits)
+        done += m
+        chunk = min(chunk * 2, 4096)
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "paths/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {done} of {npaths} paths x all {bits.size} bitstrings, {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * sfpath.h -- C ABI of the MI355X Schroedinger-Feynman path-sum library.
+ *
+ * Method (arXiv:1807.10749): the qubit grid is cut into block A (which
+ * holds qubit 0) and block B (Section 2; Section 9, "Performance
+ * estimation": a single straight-line cut).  Every CZ that crosses the cut
+ * is split as P0 (x) I + P1 (x) Z (Section 2, Eq. (CZ)), so k crossing CZs
+ * give 2^k paths and |psi> = sum_j |phi_j> (Section 3).  Each path evolves
+ * the two blocks separately; requested amplitudes are accumulated over paths
+ * as amp(x) = sum_p psiA_p(x_A) psiB_p(x_B) (Section 2, "Final-state
+ * amplitudes").  Summing a fraction f of the paths trades fidelity for time
+ * (Section 3, Eq. (fid)).
+ *
+ * Conventions:
+ *   - qubit id on an R x C grid is r*C + c; bitstring bit q = value of qubit
+ *     q (x is a uint64); x_A / x_B are the bits of x at the block's qubits,
+ *     packed in ascending qubit order;
+ *   - gate kinds 0 H, 1 X^1/2, 2 Y^1/2, 3 T, 4 CZ with
+ *     H = [[1,1],[1,-1]]/sqrt2, X^1/2 = [[1+i,1-i],[1-i,1+i]]/2,
+ *     Y^1/2 = [[1+i,-1-i],[1+i,1+i]]/2, T = diag(1, e^{i pi/4});
+ *   - the crossing CZs are ordered by (cycle, smaller qubit id); crossing CZ
+ *     j is decided by bit (k-1-j) of a path id (the earliest CZ is the most
+ *     significant bit, so an aligned block of 2^b ids shares its prefix);
+ *     path bit 0 takes P0 on the A endpoint, bit 1 takes P1 on the A endpoint
+ *     and Z on the B endpoint.
+ *
+ * Errors: every function returns 0 on success or a negative code below and
+ * never throws; last_error() gives a message for the calling thread.
+ * Device errors of asynchronous work surface at the next synchronising call.
+ */
+#ifndef SFPATH_H
+#define SFPATH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SF_OK              0
+#define SF_ERR_INVALID   (-1)  /* bad argument: qubit outside the grid, non-adjacent CZ, id >= 2^k ... */
+#define SF_ERR_OOM       (-2)  /* host or device memory, or a workspace that is too small */
+#define SF_ERR_UNSUPPORTED (-3) /* n > 64, a block > 30 qubits, k > 62, ... */
+#define SF_ERR_NO_CUT    (-4)  /* run_paths before set_cut */
+#define SF_ERR_DEVICE    (-5)  /* HIP runtime error (no GPU, launch failure, fault) */
+
+/* One gate record, 8 bytes. q1 is ignored for one-qubit gates. */
+typedef struct {
+    uint8_t kind;     /* 0 H, 1 X^1/2, 2 Y^1/2, 3 T, 4 CZ */
+    uint8_t pad;
+    uint16_t cycle;   /* clock cycle; must not decrease along the list */
+    uint16_t q0, q1;
+} sf_gate_t;
+
+typedef struct sf_circuit sf_circuit_t;   /* opaque, library-owned */
+
+/* run_paths flags */
+#define SF_ACCUMULATE     1u   /* add into amps instead of overwriting */
+#define SF_OUT_ON_DEVICE  2u   /* amps is a device pointer */
+#define SF_FP64_SWEEPS    4u   /* evolve the blocks in complex128 instead of complex64 */
+#define SF_PLAIN          8u   /* one path at a time, no batching, no shared prefixes */
+#define SF_BITS_ON_DEVICE 16u  /* bitstrings is a device pointer */
+#define SF_TIMING         32u  /* time every kernel with HIP events (see get_run_stats) */
+
+/*
+ * create_circuit: copy a gate list on an R x C grid (rows*cols <= 64).
+ * Gates must act on grid qubits; a CZ must join grid neighbours; cycles
+ * must not decrease along the list and a qubit may appear at most once per
+ * cycle (Section 1 circuits: one layer of gates per clock cycle).
+ * The library owns *out until destroy_circuit.
+ */
+int create_circuit(int rows, int cols, const sf_gate_t *gates, size_t n_gates,
+                   sf_circuit_t **out);
+
+/* destroy_circuit: free the circuit, its plans and any device memory it holds. */
+int destroy_circuit(sf_circuit_t *c);
+
+/*
+ * set_cut: choose block A as the qubits whose bits are set in block_a_mask
+ * (bit 0 must be set; block B is the rest of the grid and must not be empty;
+ * each block at most 30 qubits).  Writes the number k of crossing CZs
+ * (Section 2: "cross-block" CZ gates, xCZ) to *k_out.  Plans are rebuilt.
+ */
+int set_cut(sf_circuit_t *c, uint64_t block_a_mask, uint32_t *k_out);
+
+/*
+ * choose_cut: the straight-line cut of Section 9 (Performance estimation):
+ * among all vertical and horizontal grid cuts, minimise the larger block,
+ * then the number of crossing CZs; ties prefer vertical cuts, then the cut
+ * nearest to column/row 0.  Writes block A's mask (holding qubit 0).
+ */
+int choose_cut(const sf_circuit_t *c, uint64_t *block_a_mask);
+
+/*
+ * num_paths: ceil(f * 2^k), the number of paths kept at fidelity f
+ * (Section 3, Eq. (fid)); 0 < f <= 1, k <= 62.
+ */
+int num_paths(uint32_t k, double f, uint64_t *n_out);
+
+/*
+ * sample_paths: ceil(f * 2^k) distinct path ids, uniform, sorted ascending
+ * (Section 3: which terms are kept does not matter for these circuits).
+ * Floyd's algorithm (Bentley & Floyd 1987) over SplitMix64 (Steele, Lea &
+ * Flood 2014) seeded with `seed`; a bounded draw in [0, m) is
+ * floor(r * m / 2^64) for a 64-bit output r.  `out` is host memory with
+ * room for `cap` ids.
+ */
+int sample_paths(uint32_t k, double f, uint64_t seed, uint64_t *out, uint64_t cap,
+                 uint64_t *n_out);
+
+/*
+ * run_paths: amps[j] = sum over the given paths p of psiA_p(x_A) psiB_p(x_B)
+ * for x = bitstrings[j] (plus the previous content of amps with
+ * SF_ACCUMULATE).  The raw partial sum is returned: no 1/sqrt(f) rescale.
+ *   path_ids   host array of n_paths distinct ids < 2^k, or NULL for the
+ *              range [path_begin, path_begin + n_paths);
+ *   bitstrings n_bits uint64 values < 2^n (host, or device with
+ *              SF_BITS_ON_DEVICE);
+ *   amps       2*n_bits doubles (re, im), host or device (SF_OUT_ON_DEVICE);
+ *   hip_stream hipStream_t to enqueue on (NULL = default stream);
+ *   workspace  caller-owned device memory of workspace_bytes, or NULL to let
+ *              the library allocate (and keep, until destroy_circuit) what
+ *              it needs.  A non-NULL workspace smaller than 256 MiB or than
+ *              one slot per tree level is rejected with SF_ERR_OOM.
+ * Returns after the work has finished (the stream is synchronised).
+ * Blocks evolve in complex64 (complex128 with SF_FP64_SWEEPS); the
+ * cross-path sum is formed in FP64.
+ */
+int run_paths(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin,
+              uint64_t n_paths, const uint64_t *bitstrings, size_t n_bits,
+              double *amps, uint32_t flags, void *hip_stream,
+              void *workspace, size_t workspace_bytes);
+
+/*
+ * workspace_size: device bytes run_paths would use for a request of
+ * n_paths paths and n_bits bitstrings with the current tuning when it
+ * may keep every tree level of the request resident (the library then
+ * runs the levels breadth-first).  Any workspace of at least 256 MiB
+ * works; smaller ones make run_paths process the tree in more batches.
+ */
+int workspace_size(const sf_circuit_t *c, uint64_t n_paths, size_t n_bits, uint32_t flags,
+                   size_t *bytes);
+
+/* Tuning knobs (see set_tuning / autotune). 0 = library default. */
+typedef struct {
+    uint32_t reg_qubits;     /* qubits held in registers per pass, 1..5 (1..4 with SF_FP64_SWEEPS) */
+    uint32_t leaf_batch;     /* max paths per leaf batch (power of two) */
+    uint32_t max_slots;      /* max slots of any batch (power of two) */
+    uint32_t waves_per_cu;   /* persistent-grid size per compute unit */
+} sf_tuning_t;
+
+int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);
+int get_tuning(const sf_circuit_t *c, sf_tuning_t *t);
+
+/* Statistics of the last run_paths call on this circuit. Times are only
+ * filled when the run used SF_TIMING. */
+typedef struct {
+    double ms_total;         /* host wall time of run_paths */
+    double ms_sweep;         /* summed kernel time of gate-sweep passes */
+    double ms_gather;        /* summed kernel time of gather / path-sum */
+    double ms_other;         /* init, pext, zero fill */
+    uint64_t n_sweep_launches;
+    uint64_t n_gather_launches;
+    uint64_t sweep_bytes;    /* algorithmic bytes: read + written by sweep passes */
+    uint64_t gather_bytes;   /* algorithmic bytes read by gather launches */
+    uint64_t n_batches;      /* leaf batches */
+    uint64_t n_passes_a, n_passes_b;  /* passes per leaf path of block A / B (full plan) */
+} sf_run_stats_t;
+
+int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char *last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFPATH_H */

@@ -1,0 +1,220 @@
+"""ctypes binding of libsfpath.so: the C ABI of include/sfpath.h, same names.
+
+Argument marshalling only: every step of the path sum runs in the library's
+HIP kernels.  Importing this module loads the library and raises if it has
+not been built (``python -m paper_1807_10749_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfpath.so")
+
+SF_OK, SF_ERR_INVALID, SF_ERR_OOM, SF_ERR_UNSUPPORTED, SF_ERR_NO_CUT, SF_ERR_DEVICE = 0, -1, -2, -3, -4, -5
+SF_ACCUMULATE, SF_OUT_ON_DEVICE, SF_FP64_SWEEPS, SF_PLAIN, SF_BITS_ON_DEVICE, SF_TIMING = 1, 2, 4, 8, 16, 32
+
+EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_paths", "sample_paths",
+           "run_paths", "workspace_size", "set_tuning", "get_tuning", "get_run_stats", "last_error"]
+
+
+class SFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sfpath error {code}: {msg}")
+        self.code = code
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("reg_qubits", ctypes.c_uint32), ("leaf_batch", ctypes.c_uint32),
+                ("max_slots", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("ms_sweep", ctypes.c_double),
+                ("ms_gather", ctypes.c_double), ("ms_other", ctypes.c_double),
+                ("n_sweep_launches", ctypes.c_uint64), ("n_gather_launches", ctypes.c_uint64),
+                ("sweep_bytes", ctypes.c_uint64), ("gather_bytes", ctypes.c_uint64),
+                ("n_batches", ctypes.c_uint64), ("n_passes_a", ctypes.c_uint64),
+                ("n_passes_b", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1807_10749_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t
+    pu64 = ctypes.POINTER(ctypes.c_uint64)
+    lib.create_circuit.argtypes = [ctypes.c_int, ctypes.c_int, vp, sz, ctypes.POINTER(vp)]
+    lib.destroy_circuit.argtypes = [vp]
+    lib.set_cut.argtypes = [vp, u64, ctypes.POINTER(u32)]
+    lib.choose_cut.argtypes = [vp, pu64]
+    lib.num_paths.argtypes = [u32, ctypes.c_double, pu64]
+    lib.sample_paths.argtypes = [u32, ctypes.c_double, u64, vp, u64, pu64]
+    lib.run_paths.argtypes = [vp, vp, u64, u64, vp, sz, vp, u32, vp, vp, sz]
+    lib.workspace_size.argtypes = [vp, u64, sz, u32, ctypes.POINTER(sz)]
+    lib.set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.get_run_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
+    lib.last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.last_error().decode()
+
+
+def _check(rc: int):
+    if rc != SF_OK:
+        raise SFError(rc, last_error())
+
+
+def _ptr(x) -> Optional[int]:
+    """Address of a numpy array or torch tensor (None stays None)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return int(x)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+# ---------------------------------------------------------------- C ABI, same names
+
+def create_circuit(rows: int, cols: int, gates: np.ndarray) -> int:
+    g = np.ascontiguousarray(gates)
+    if g.dtype.itemsize != 8:
+        raise ValueError("gate records must be 8 bytes")
+    out = ctypes.c_void_p()
+    _check(lib.create_circuit(rows, cols, g.ctypes.data if g.size else None, g.size, ctypes.byref(out)))
+    return out.value
+
+
+def destroy_circuit(c: int):
+    _check(lib.destroy_circuit(c))
+
+
+def set_cut(c: int, block_a_mask: int) -> int:
+    k = ctypes.c_uint32()
+    _check(lib.set_cut(c, block_a_mask, ctypes.byref(k)))
+    return k.value
+
+
+def choose_cut(c: int) -> int:
+    m = ctypes.c_uint64()
+    _check(lib.choose_cut(c, ctypes.byref(m)))
+    return m.value
+
+
+def num_paths(k: int, f: float) -> int:
+    n = ctypes.c_uint64()
+    _check(lib.num_paths(k, f, ctypes.byref(n)))
+    return n.value
+
+
+def sample_paths(k: int, f: float, seed: int) -> np.ndarray:
+    m = num_paths(k, f)
+    out = np.empty(m, dtype=np.uint64)
+    n = ctypes.c_uint64()
+    _check(lib.sample_paths(k, f, seed, out.ctypes.data, m, ctypes.byref(n)))
+    return out[: n.value]
+
+
+def run_paths(c: int, path_ids, path_begin: int, n_paths: int, bitstrings, n_bits: int, amps,
+              flags: int = 0, stream=None, workspace=None, workspace_bytes: int = 0):
+    """Raw call; bitstrings/amps/workspace are numpy arrays, torch tensors or addresses."""
+    ids = None
+    if path_ids is not None:
+        ids = np.ascontiguousarray(path_ids, dtype=np.uint64)
+        n_paths = ids.size
+    _check(lib.run_paths(c, _ptr(ids), path_begin, n_paths, _ptr(bitstrings), n_bits, _ptr(amps), flags,
+                         _stream_handle(stream), _ptr(workspace), workspace_bytes))
+
+
+def workspace_size(c: int, n_paths: int, n_bits: int, flags: int = 0) -> int:
+    b = ctypes.c_size_t()
+    _check(lib.workspace_size(c, n_paths, n_bits, flags, ctypes.byref(b)))
+    return b.value
+
+
+def set_tuning(c: int, reg_qubits=0, leaf_batch=0, max_slots=0, waves_per_cu=0):
+    t = Tuning(reg_qubits, leaf_batch, max_slots, waves_per_cu)
+    _check(lib.set_tuning(c, ctypes.byref(t)))
+
+
+def get_tuning(c: int) -> dict:
+    t = Tuning()
+    _check(lib.get_tuning(c, ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in Tuning._fields_}
+
+
+def get_run_stats(c: int) -> dict:
+    s = RunStats()
+    _check(lib.get_run_stats(c, ctypes.byref(s)))
+    return s.as_dict()
+
+
+# ---------------------------------------------------------------- convenience wrapper
+
+class Circuit:
+    """Owns one library circuit; marshals numpy inputs to run_paths."""
+
+    def __init__(self, rows: int, cols: int, gates: np.ndarray, block_a_mask: Optional[int] = None):
+        self.rows, self.cols, self.n = rows, cols, rows * cols
+        self.handle = create_circuit(rows, cols, gates)
+        if block_a_mask is None:
+            block_a_mask = choose_cut(self.handle)
+        self.mask_a = block_a_mask
+        self.k = set_cut(self.handle, block_a_mask)
+
+    def close(self):
+        if self.handle:
+            destroy_circuit(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def amplitudes(self, bitstrings: np.ndarray, path_ids=None, path_begin: int = 0,
+                   n_paths: Optional[int] = None, flags: int = 0, stream=None, workspace=None) -> np.ndarray:
+        """complex128 array: sum over the paths of psiA_p(x_A) psiB_p(x_B) per bitstring (host arrays)."""
+        bits = np.ascontiguousarray(bitstrings, dtype=np.uint64)
+        amps = np.zeros(2 * max(bits.size, 1), dtype=np.float64)
+        if path_ids is None and n_paths is None:
+            n_paths = 1 << self.k
+        ws_bytes = 0
+        if workspace is not None:
+            ws_bytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else workspace.nbytes
+        run_paths(self.handle, path_ids, path_begin, n_paths or 0, bits, bits.size, amps, flags, stream,
+                  workspace, ws_bytes)
+        return amps.view(np.complex128)[: bits.size]
+
+    def tune(self, **kw):
+        set_tuning(self.handle, **kw)
+
+    def stats(self) -> dict:
+        return get_run_stats(self.handle)

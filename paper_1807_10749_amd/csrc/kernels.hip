@@ -1,0 +1,415 @@
+// HIP kernels for gfx950 (CDNA4): gate-sweep passes, gather + FP64 path sum.
+//
+// Pass kernel: one wave64 owns a tile of 64 * 2^R amplitudes (lane bits =
+// the 6 lowest extended bits, R register bits = chosen qubits, the rest
+// from the tile index).  It loads the tile once, applies a whole list of
+// gates (register tier, lane-shuffle tier, bitmask diagonal groups) and
+// stores it once, so one HBM round trip covers many gates.  Loads of one
+// register index by the 64 lanes are 64 consecutive complex values (512 B
+// in complex64), i.e. whole cache lines.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace sf {
+
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { using type = float2; };
+template <> struct Cplx<double> { using type = double2; };
+
+template <typename T>
+__device__ __forceinline__ T inv_sqrt2() { return T(0.70710678118654752440084436210485); }
+
+// ---------------------------------------------------------------- register tier
+
+template <int K, int R, typename C>
+__device__ __forceinline__ void reg_gate(int kind, C (&v)[1 << R])
+{
+    constexpr int N = 1 << R;
+    constexpr int B = 1 << K;
+    if (kind == GK_H) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (j & B) continue;
+            C a = v[j], b = v[j | B];
+            v[j].x = a.x + b.x; v[j].y = a.y + b.y;
+            v[j | B].x = a.x - b.x; v[j | B].y = a.y - b.y;
+        }
+    } else if (kind == GK_X) {
+        // [[1,-i],[-i,1]]: a' = a - i b, b' = b - i a
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (j & B) continue;
+            C a = v[j], b = v[j | B];
+            v[j].x = a.x + b.y; v[j].y = a.y - b.x;
+            v[j | B].x = b.x + a.y; v[j | B].y = b.y - a.x;
+        }
+    } else {
+        // [[1,-1],[1,1]]: a' = a - b, b' = a + b
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (j & B) continue;
+            C a = v[j], b = v[j | B];
+            v[j].x = a.x - b.x; v[j].y = a.y - b.y;
+            v[j | B].x = a.x + b.x; v[j | B].y = a.y + b.y;
+        }
+    }
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void reg_dispatch(int k, int kind, C (&v)[1 << R])
+{
+    switch (k) {
+    case 0: if constexpr (R > 0) reg_gate<0, R>(kind, v); break;
+    case 1: if constexpr (R > 1) reg_gate<1, R>(kind, v); break;
+    case 2: if constexpr (R > 2) reg_gate<2, R>(kind, v); break;
+    case 3: if constexpr (R > 3) reg_gate<3, R>(kind, v); break;
+    case 4: if constexpr (R > 4) reg_gate<4, R>(kind, v); break;
+    default: break;
+    }
+}
+
+// ---------------------------------------------------------------- lane tier
+
+template <int R, typename C>
+__device__ __forceinline__ void lane_gate(int b, int kind, int lane, C (&v)[1 << R])
+{
+    constexpr int N = 1 << R;
+    const int m = 1 << b;
+    const bool hi = (lane & m) != 0;
+    if (kind == GK_H) {
+        // lo' = lo + hi, hi' = lo - hi
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            C o = v[j];
+            C t;
+            t.x = __shfl_xor(o.x, m);
+            t.y = __shfl_xor(o.y, m);
+            v[j].x = hi ? t.x - o.x : o.x + t.x;
+            v[j].y = hi ? t.y - o.y : o.y + t.y;
+        }
+    } else if (kind == GK_X) {
+        // both halves: self' = self - i * other
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            C o = v[j];
+            C t;
+            t.x = __shfl_xor(o.x, m);
+            t.y = __shfl_xor(o.y, m);
+            v[j].x = o.x + t.y;
+            v[j].y = o.y - t.x;
+        }
+    } else {
+        // lo' = lo - hi, hi' = lo + hi
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            C o = v[j];
+            C t;
+            t.x = __shfl_xor(o.x, m);
+            t.y = __shfl_xor(o.y, m);
+            v[j].x = hi ? t.x + o.x : o.x - t.x;
+            v[j].y = hi ? t.y + o.y : o.y - t.y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- diagonal groups
+
+__device__ __forceinline__ int tab_entry(const uint64_t (&tab)[4], int j)
+{
+    return (int)((tab[j >> 4] >> ((j & 15) * 4)) & 15u);
+}
+
+template <int R, typename T, typename C>
+__device__ __forceinline__ void apply_diag(const DiagGroup *gp, const uint8_t *terms, uint64_t eB,
+                                           uint64_t sp, C (&v)[1 << R])
+{
+    constexpr int N = 1 << R;
+    const DiagGroup g = *gp;
+    const uint8_t *t = terms + 2 * (size_t)g.term_off;
+    int mB = 0;
+    uint32_t cmask = 0;
+    bool keep = true;
+    uint32_t pset = 0, pval = 0;
+    for (int i = 0; i < g.n_lin_b; ++i, t += 2) mB += t[1] * (int)((eB >> t[0]) & 1u);
+    for (int i = 0; i < g.n_quad_bb; ++i, t += 2) mB += 4 * (int)((eB >> t[0]) & (eB >> t[1]) & 1u);
+    for (int i = 0; i < g.n_quad_br; ++i, t += 2) cmask ^= ((uint32_t)(eB >> t[0]) & 1u) << t[1];
+    for (int i = 0; i < g.n_zs_b; ++i, t += 2) mB += 4 * (int)((eB >> t[0]) & (sp >> t[1]) & 1u);
+    for (int i = 0; i < g.n_zs_r; ++i, t += 2) cmask ^= ((uint32_t)(sp >> t[1]) & 1u) << t[0];
+    for (int i = 0; i < g.n_proj_b; ++i, t += 2) keep = keep && (((eB >> t[0]) & 1u) == ((sp >> t[1]) & 1u));
+    for (int i = 0; i < g.n_proj_r; ++i, t += 2) {
+        const uint32_t bit = 1u << t[0];
+        const uint32_t s = (uint32_t)((sp >> t[1]) & 1u) << t[0];
+        if ((pset & bit) && ((pval & bit) != s)) keep = false;
+        pset |= bit;
+        pval |= s;
+    }
+    const bool has_proj = (g.flags & 2u) != 0;
+    if (!(g.flags & 1u)) {
+        // every weight is a multiple of 4: the phase is a sign
+        const int sB = (mB >> 2) & 1;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int s = sB ^ ((tab_entry(g.tab, j) >> 2) & 1) ^ (__popc((uint32_t)j & cmask) & 1);
+            T x = s ? -v[j].x : v[j].x;
+            T y = s ? -v[j].y : v[j].y;
+            if (has_proj) {
+                const bool k = keep && (((uint32_t)j & pset) == pval);
+                x = k ? x : T(0);
+                y = k ? y : T(0);
+            }
+            v[j].x = x;
+            v[j].y = y;
+        }
+    } else {
+        const T r = inv_sqrt2<T>();
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int m = (mB + tab_entry(g.tab, j) + 4 * __popc((uint32_t)j & cmask)) & 7;
+            T x = v[j].x, y = v[j].y;
+            if (m & 1) {                      // times omega = (1+i)/sqrt2
+                const T nx = (x - y) * r, ny = (x + y) * r;
+                x = nx; y = ny;
+            }
+            if (m & 2) {                      // times i
+                const T nx = -y;
+                y = x; x = nx;
+            }
+            if (m & 4) { x = -x; y = -y; }    // times -1
+            if (has_proj) {
+                const bool k = keep && (((uint32_t)j & pset) == pval);
+                x = k ? x : T(0);
+                y = k ? y : T(0);
+            }
+            v[j].x = x;
+            v[j].y = y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- pass kernel
+
+template <int R>
+__device__ __forceinline__ uint64_t reg_offset(const int32_t (&pos)[6], int j, int shift_down, int shift_up)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        if (j & (1 << k)) o += (uint64_t)1 << (pos[k] - shift_down + shift_up);
+    return o;
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int N = 1 << R;
+    const unsigned lane = threadIdx.x & 63u;
+    const uint64_t nwaves = (uint64_t)gridDim.x * 4u;
+    int32_t pos[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pos[k] = a.reg_pos[k];
+    const uint64_t pmask_dst = ((uint64_t)1 << a.p_dst) - 1u;
+
+    // the wave index is uniform across a wave; say so, so tile arithmetic stays in scalar registers
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint64_t tile = (uint64_t)blockIdx.x * 4u + wid; tile < a.n_tiles; tile += nwaves) {
+        // wave-uniform part of the extended index: tile bits spread around the register positions
+        uint64_t et = tile << 6;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int p = pos[k];
+            et = ((et >> p) << (p + 1)) | (et & (((uint64_t)1 << p) - 1u));
+        }
+        const uint64_t eB = et | (uint64_t)lane;     // this lane's amplitude with register bits 0
+        const uint64_t slot = eB & pmask_dst;
+        const uint64_t sp = a.slot_path ? a.slot_path[slot] : 0u;
+
+        C v[N];
+        if (a.src_mode == SRC_INIT) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const uint64_t ej = eB + reg_offset<R>(pos, j, 0, 0);
+                v[j].x = (ej & a.init_zero_mask) ? T(0) : T(1);
+                v[j].y = T(0);
+            }
+        } else if (a.src_mode == SRC_FANOUT) {
+            // parent slot inside the source batch; clamped so padded slots stay in bounds
+            uint32_t ps = a.slot_parent[slot] - a.slot_parent_base;
+            const uint32_t pmax = (1u << a.p_src) - 1u;
+            ps = ps > pmax ? pmax : ps;
+            // source index = ((et >> p_dst) << p_src) + ((lane >> p_dst) << p_src) + ps: the first
+            // term is wave-uniform (et has zeros in bits 0..5), the rest a small per-lane offset
+            const uint64_t su = (et >> a.p_dst) << a.p_src;
+            const uint32_t sl = ((lane >> a.p_dst) << a.p_src) + ps;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const C *row = (const C *)a.src + (su + reg_offset<R>(pos, j, a.p_dst, a.p_src));   // uniform
+                v[j] = row[sl];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const C *row = (const C *)a.src + (et + reg_offset<R>(pos, j, 0, 0));   // uniform
+                v[j] = row[lane];
+            }
+        }
+
+        for (uint32_t i = 0; i < a.n_ops; ++i) {
+            const PassOp op = a.ops[i];
+            if (op.type == PO_REG) {
+                reg_dispatch<R>(op.target, op.kind, v);
+            } else if (op.type == PO_LANE) {
+                lane_gate<R>(op.target, op.kind, (int)lane, v);
+            } else {
+                apply_diag<R, T>(a.groups + op.group, a.terms, eB, sp, v);
+            }
+        }
+
+        if (a.rescale != 1.0) {
+            const T sc = (T)a.rescale;
+#pragma unroll
+            for (int j = 0; j < N; ++j) { v[j].x *= sc; v[j].y *= sc; }
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            C *row = (C *)a.dst + (et + reg_offset<R>(pos, j, 0, 0));   // uniform
+            row[lane] = v[j];
+        }
+    }
+}
+
+template <typename T>
+static hipError_t launch_pass_t(int R, const PassArgs &a, unsigned grid, hipStream_t s)
+{
+    switch (R) {
+    case 0: pass_kernel<T, 0><<<grid, 256, 0, s>>>(a); break;
+    case 1: pass_kernel<T, 1><<<grid, 256, 0, s>>>(a); break;
+    case 2: pass_kernel<T, 2><<<grid, 256, 0, s>>>(a); break;
+    case 3: pass_kernel<T, 3><<<grid, 256, 0, s>>>(a); break;
+    case 4: pass_kernel<T, 4><<<grid, 256, 0, s>>>(a); break;
+    case 5: if constexpr (sizeof(T) == 4) { pass_kernel<T, 5><<<grid, 256, 0, s>>>(a); break; }
+            return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(bool fp64, int R, const PassArgs &a, unsigned grid, hipStream_t s)
+{
+    return fp64 ? launch_pass_t<double>(R, a, grid, s) : launch_pass_t<float>(R, a, grid, s);
+}
+
+// ---------------------------------------------------------------- gather + FP64 path sum
+
+// amp[j] += scale * sum_{slot < n_slots} A[x_A(j) * P + slot] * B[x_B(j) * P + slot]
+// Lanes of a wave split over slots (L = min(P, 64) lanes per bitstring);
+// products and sums are formed in FP64 (a product of two FP32 values is
+// exact in FP64).  Each bitstring has one owner, so no atomics are needed.
+template <typename T>
+__global__ __launch_bounds__(256) void gather_kernel(GatherArgs g)
+{
+    using C = typename Cplx<T>::type;
+    const int lane = threadIdx.x & 63;
+    const uint32_t P = 1u << g.p;
+    const uint32_t L = P < 64u ? P : 64u;
+    const uint32_t G = 64u / L;
+    const uint64_t wave = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint64_t j = wave * G + (uint32_t)lane / L;
+    const uint32_t sl = (uint32_t)lane % L;
+    double re = 0.0, im = 0.0;
+    if (j < g.n_bits) {
+        const C *ra = (const C *)g.a + ((uint64_t)g.xa[j] << g.p);
+        const C *rb = (const C *)g.b + ((uint64_t)g.xb[j] << g.p);
+        for (uint32_t s = sl; s < g.n_slots; s += L) {
+            const C x = ra[s], y = rb[s];
+            const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+            re += xr * yr - xi * yi;
+            im += xr * yi + xi * yr;
+        }
+    }
+    for (uint32_t m = 1; m < L; m <<= 1) {
+        re += __shfl_xor(re, (int)m);
+        im += __shfl_xor(im, (int)m);
+    }
+    if (j < g.n_bits && sl == 0) {
+        double *o = g.acc + 2 * j;
+        o[0] += g.scale_re * re - g.scale_im * im;
+        o[1] += g.scale_re * im + g.scale_im * re;
+    }
+}
+
+hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s)
+{
+    if (g.n_bits == 0) return hipSuccess;
+    const uint64_t P = (uint64_t)1 << g.p;
+    const uint64_t L = P < 64 ? P : 64;
+    const uint64_t per_wave = 64 / L;
+    const uint64_t waves = (g.n_bits + per_wave - 1) / per_wave;
+    const uint64_t blocks = (waves + 3) / 4;
+    if (fp64) gather_kernel<double><<<(unsigned)blocks, 256, 0, s>>>(g);
+    else gather_kernel<float><<<(unsigned)blocks, 256, 0, s>>>(g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- small helpers
+
+__device__ __forceinline__ uint32_t pext64(uint64_t x, uint64_t m)
+{
+    uint32_t r = 0;
+    int k = 0;
+    while (m) {
+        const int q = __ffsll((long long)m) - 1;
+        r |= (uint32_t)((x >> q) & 1u) << k;
+        ++k;
+        m &= m - 1;
+    }
+    return r;
+}
+
+__global__ void pext_kernel(const uint64_t *bits, uint64_t n, uint64_t ma, uint64_t mb, uint64_t all,
+                            uint32_t *xa, uint32_t *xb, int *bad)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t x = bits[i];
+    if (x & ~all) *bad = 1;
+    xa[i] = pext64(x, ma);
+    xb[i] = pext64(x, mb);
+}
+
+hipError_t launch_pext(const uint64_t *bits, uint64_t n, uint64_t mask_a, uint64_t mask_b,
+                       uint64_t all, uint32_t *xa, uint32_t *xb, int *bad, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    pext_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(bits, n, mask_a, mask_b, all, xa, xb, bad);
+    return hipGetLastError();
+}
+
+__global__ void fill_zero_kernel(double *p, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void fill_zero_i32_kernel(int *p, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    fill_zero_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero_i32(int *p, uint64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    fill_zero_i32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+}  // namespace sf

@@ -1,0 +1,31 @@
+// Host-side launchers of the HIP kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include "sf_device.hpp"
+
+namespace sf {
+
+// Largest number of register qubits a pass kernel is instantiated for.  The
+// op interpreter keeps about two copies of the tile in registers, so 2^5
+// complex64 (2^4 complex128) amplitudes per lane leave room for 3 waves/SIMD.
+constexpr int kMaxRegBits = 5;
+constexpr int kMaxRegBitsF64 = 4;
+
+// Stream one pass over a block state (see PassArgs).  R = register bits
+// (0..kMaxRegBits), fp64 selects complex128 states.
+hipError_t launch_pass(bool fp64, int R, const PassArgs &a, unsigned grid, hipStream_t s);
+
+// Gather + FP64 path sum for one leaf batch.
+hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s);
+
+// x_A = pext(x, mask_a), x_B = pext(x, mask_b) per bitstring; *bad is set to
+// 1 if some bitstring has bits outside `all`.
+hipError_t launch_pext(const uint64_t *bits, uint64_t n, uint64_t mask_a, uint64_t mask_b,
+                       uint64_t all, uint32_t *xa, uint32_t *xb, int *bad, hipStream_t s);
+
+// Fill n doubles with zero (a kernel, so it can also sit inside a captured graph).
+hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t s);
+hipError_t launch_fill_zero_i32(int *p, uint64_t n, hipStream_t s);
+
+}  // namespace sf

@@ -1,0 +1,360 @@
+// Planner: cut -> per-block programs -> tree levels -> fused passes.
+//
+// * Crossing CZs (Section 2, "cross-block" CZ) are ordered by (cycle,
+//   smaller qubit) and crossing CZ j is decided by path bit (k-1-j), so an
+//   aligned block of path ids shares a prefix (Section 2: x = x_p + x_b,
+//   processes spawned per x_p-bit prefix).
+// * Each block's program is cut into segments at the cycles holding
+//   crossing CZs.  Segment l starts with the branch operators of level l
+//   (P_s on the block-A endpoint, Z^s on the block-B endpoint; Section 2,
+//   Eq. (CZ)); everything between two such cycles is shared by all paths
+//   with the same prefix (the checkpoint/branch scheme of Section 2).
+// * A segment is split into passes: each pass may apply non-diagonal gates
+//   only to qubits held in lane bits or in its R register bits; diagonal
+//   gates join any pass once their qubits' earlier gates are scheduled and
+//   are merged into as few bitmask groups as possible (Section 2:
+//   clustering gates of a kind with reordering; bitmask + mod-8 evaluation
+//   of all diagonal gates in one pass).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "sf_host.hpp"
+
+namespace sf {
+
+static int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+int build_programs(Circuit &c, std::string &err)
+{
+    const int n = c.n;
+    int local[64];
+    for (int q = 0; q < n; ++q) {
+        const uint64_t m = ((c.mask_a >> q) & 1) ? c.mask_a : c.mask_b;
+        local[q] = popcount64(m & ((q ? (uint64_t(1) << q) : 0) - 1));
+        if (q == 0) local[q] = 0;
+    }
+    auto in_a = [&](int q) { return ((c.mask_a >> q) & 1) != 0; };
+
+    // crossing CZs in path-bit order
+    c.cut_gate.clear();
+    for (size_t i = 0; i < c.gates.size(); ++i) {
+        const sf_gate_t &g = c.gates[i];
+        if (g.kind == 4 && in_a(g.q0) != in_a(g.q1)) c.cut_gate.push_back((int)i);
+    }
+    std::stable_sort(c.cut_gate.begin(), c.cut_gate.end(), [&](int a, int b) {
+        const sf_gate_t &x = c.gates[a], &y = c.gates[b];
+        const int mx = std::min(x.q0, x.q1), my = std::min(y.q0, y.q1);
+        return x.cycle != y.cycle ? x.cycle < y.cycle : mx < my;
+    });
+    c.k = (int)c.cut_gate.size();
+    if (c.k > 62) {
+        err = "more than 62 crossing CZs";
+        return SF_ERR_UNSUPPORTED;
+    }
+    std::vector<int> bit_of_gate(c.gates.size(), -1);
+    for (int j = 0; j < c.k; ++j) bit_of_gate[c.cut_gate[j]] = c.k - 1 - j;
+
+    // tree levels: one per clock cycle that holds crossing CZs
+    c.levels.clear();
+    c.levels.push_back(Level{-1, 0, 0, 0});
+    for (int j = 0; j < c.k; ++j) {
+        const int cy = c.gates[c.cut_gate[j]].cycle;
+        if (c.levels.size() == 1 || c.levels.back().cycle != cy)
+            c.levels.push_back(Level{cy, j, 0, 0});
+        c.levels.back().n_cut++;
+        c.levels.back().bits_after = j + 1;
+    }
+    const int L = (int)c.levels.size() - 1;
+
+    for (int h = 0; h < 2; ++h) {
+        HalfProgram &hp = c.half[h];
+        hp.q = popcount64(h == 0 ? c.mask_a : c.mask_b);
+        hp.segments.assign(L + 1, {});
+        hp.init_h_mask = 0;
+    }
+    int seg = 0;   // number of levels whose cycle is below the current gate's cycle
+    for (size_t i = 0; i < c.gates.size(); ++i) {
+        const sf_gate_t &g = c.gates[i];
+        while (seg < L && c.levels[seg + 1].cycle < g.cycle) ++seg;
+        if (bit_of_gate[i] >= 0) {
+            int lvl = 1;
+            while (c.levels[lvl].cycle != g.cycle) ++lvl;
+            const int qa = in_a(g.q0) ? g.q0 : g.q1;
+            const int qb = in_a(g.q0) ? g.q1 : g.q0;
+            const uint8_t u = (uint8_t)bit_of_gate[i];
+            c.half[0].segments[lvl].push_back(HalfOp{HK_PROJ, (uint8_t)local[qa], 0, u});
+            c.half[1].segments[lvl].push_back(HalfOp{HK_ZCTL, (uint8_t)local[qb], 0, u});
+            continue;
+        }
+        const int h = in_a(g.q0) ? 0 : 1;
+        HalfOp op{0, (uint8_t)local[g.q0], 0, 0};
+        switch (g.kind) {
+        case 0: op.kind = HK_H; break;
+        case 1: op.kind = HK_X; break;
+        case 2: op.kind = HK_Y; break;
+        case 3: op.kind = HK_T; break;
+        default: op.kind = HK_CZ; op.q1 = (uint8_t)local[g.q1]; break;
+        }
+        c.half[h].segments[seg].push_back(op);
+    }
+
+    // fold each qubit's opening H (if it is the qubit's first operation) into the initial state,
+    // then the scalar of the unnormalised gates and the power-of-two rescaling per segment
+    const std::complex<double> s_h(1.0 / std::sqrt(2.0), 0.0), s_xy(0.5, 0.5);
+    for (int h = 0; h < 2; ++h) {
+        HalfProgram &hp = c.half[h];
+        uint64_t touched = 0;
+        std::vector<HalfOp> kept;
+        int folded = 0;
+        for (const HalfOp &op : hp.segments[0]) {
+            const uint64_t m = (uint64_t(1) << op.q0) | (op.kind == HK_CZ ? uint64_t(1) << op.q1 : 0);
+            if (op.kind == HK_H && !(touched & m)) {
+                hp.init_h_mask |= m;
+                ++folded;
+                touched |= m;
+                continue;
+            }
+            touched |= m;
+            kept.push_back(op);
+        }
+        hp.segments[0] = kept;
+        hp.init_scale = std::pow(s_h, folded);
+        hp.seg_scale.assign(L + 1, 1.0);
+        hp.seg_rescale_exp.assign(L + 1, 0);
+        int carry = 0;
+        for (int l = 0; l <= L; ++l) {
+            int nh = 0, nxy = 0;
+            for (const HalfOp &op : hp.segments[l]) {
+                if (op.kind == HK_H) ++nh;
+                else if (op.kind == HK_X || op.kind == HK_Y) ++nxy;
+            }
+            carry += nh + nxy;              // each unnormalised gate multiplies the norm by sqrt2
+            const int e = carry / 2;
+            carry -= 2 * e;
+            hp.seg_rescale_exp[l] = e;
+            hp.seg_scale[l] = std::pow(s_h, nh) * std::pow(s_xy, nxy) * std::ldexp(1.0, e);
+        }
+    }
+    c.plan_cache.clear();
+    return SF_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Diagonal group construction
+// ----------------------------------------------------------------------------
+
+namespace {
+
+struct PendingDiag {
+    std::map<int, int> lin;                        // ext bit -> weight mod 8
+    std::vector<std::pair<int, int>> quad;         // ext bit pairs (a < b), XOR set
+    std::vector<std::pair<int, int>> zs;           // (ext bit, path bit), XOR set
+    std::vector<std::pair<int, int>> proj;         // (ext bit, path bit), set
+    uint64_t touched = 0;                          // local qubits
+    bool empty() const { return lin.empty() && quad.empty() && zs.empty() && proj.empty(); }
+};
+
+void toggle(std::vector<std::pair<int, int>> &v, std::pair<int, int> x)
+{
+    auto it = std::find(v.begin(), v.end(), x);
+    if (it == v.end()) v.push_back(x);
+    else v.erase(it);
+}
+
+// Emits the group into pp and appends a PO_DIAG op.
+void flush(PendingDiag &pd, PassPlan &pp, const int (&kidx)[64])
+{
+    if (pd.empty()) { pd = PendingDiag(); return; }
+    DiagGroup g;
+    std::memset(&g, 0, sizeof(g));
+    g.term_off = (uint32_t)(pp.terms.size() / 2);
+    std::vector<uint8_t> t;
+    auto reg = [&](int bit) { return kidx[bit]; };   // -1 if not a register bit
+    int tab[64] = {0};
+    const int N = 1 << pp.R;
+    bool odd = false;
+    // lin
+    std::vector<std::pair<int, int>> lin_b;
+    for (auto &kv : pd.lin) {
+        const int w = kv.second & 7;
+        if (!w) continue;
+        if (w & 1) odd = true;
+        const int k = reg(kv.first);
+        if (k >= 0) {
+            for (int j = 0; j < N; ++j) if ((j >> k) & 1) tab[j] += w;
+        } else {
+            lin_b.push_back({kv.first, w});
+        }
+    }
+    std::vector<std::pair<int, int>> qbb, qbr, zsb, zsr, pb, pr;
+    for (auto &e : pd.quad) {
+        const int ka = reg(e.first), kb = reg(e.second);
+        if (ka >= 0 && kb >= 0) {
+            for (int j = 0; j < N; ++j) if (((j >> ka) & 1) && ((j >> kb) & 1)) tab[j] += 4;
+        } else if (ka < 0 && kb < 0) {
+            qbb.push_back(e);
+        } else if (ka < 0) {
+            qbr.push_back({e.first, kb});
+        } else {
+            qbr.push_back({e.second, ka});
+        }
+    }
+    for (auto &e : pd.zs) {
+        const int k = reg(e.first);
+        if (k >= 0) zsr.push_back({k, e.second});
+        else zsb.push_back(e);
+    }
+    for (auto &e : pd.proj) {
+        const int k = reg(e.first);
+        if (k >= 0) pr.push_back({k, e.second});
+        else pb.push_back(e);
+    }
+    auto put = [&](const std::vector<std::pair<int, int>> &v) {
+        for (auto &e : v) { t.push_back((uint8_t)e.first); t.push_back((uint8_t)e.second); }
+    };
+    put(lin_b); put(qbb); put(qbr); put(zsb); put(zsr); put(pb); put(pr);
+    g.n_lin_b = (uint16_t)lin_b.size();
+    g.n_quad_bb = (uint16_t)qbb.size();
+    g.n_quad_br = (uint16_t)qbr.size();
+    g.n_zs_b = (uint16_t)zsb.size();
+    g.n_zs_r = (uint16_t)zsr.size();
+    g.n_proj_b = (uint16_t)pb.size();
+    g.n_proj_r = (uint16_t)pr.size();
+    g.flags = (odd ? 1u : 0u) | ((pb.size() + pr.size()) ? 2u : 0u);
+    for (int j = 0; j < 64; ++j) {
+        const uint64_t v = (uint64_t)(tab[j] & 7);
+        g.tab[j >> 4] |= v << ((j & 15) * 4);
+    }
+    if (!zsb.empty() || !zsr.empty() || !pb.empty() || !pr.empty()) pp.needs_slot_path = true;
+    pp.terms.insert(pp.terms.end(), t.begin(), t.end());
+    PassOp op{PO_DIAG, 0, 0, 0, (uint32_t)pp.groups.size()};
+    pp.groups.push_back(g);
+    pp.ops.push_back(op);
+    pd = PendingDiag();
+}
+
+}  // namespace
+
+const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R)
+{
+    const auto key = std::make_tuple(half, level, p, R);
+    auto it = c.plan_cache.find(key);
+    if (it != c.plan_cache.end()) return it->second;
+
+    const HalfProgram &hp = c.half[half];
+    const int q = hp.q;
+    const int n_ext = p + q;
+    const int n_lane_q = std::max(0, std::min(q, 6 - p));  // qubits 0..n_lane_q-1 sit in lane bits
+    const int n_free = q - n_lane_q;
+    const int R_eff = std::max(0, std::min({R, n_ext - 6, n_free}));
+
+    SegmentPlan sp;
+    std::vector<HalfOp> rem = hp.segments[level];
+    // rescaling inside the segment: keep the running norm gain below 2^16
+    int carry = 0;
+    for (int l = 0; l < level; ++l) {
+        int nn = 0;
+        for (const HalfOp &op : hp.segments[l]) if (!is_diag(op.kind)) ++nn;
+        carry = (carry + nn) % 2;
+    }
+    int taken = 0;
+    const int seg_exp = hp.seg_rescale_exp[level];
+
+    bool first = true;
+    while (first || !rem.empty()) {
+        first = false;
+        PassPlan pp;
+        std::vector<int> regq;
+        std::vector<HalfOp> sched, defer;
+        uint64_t blocked = 0;
+        for (const HalfOp &op : rem) {
+            const uint64_t qm = (uint64_t(1) << op.q0) | (op.kind == HK_CZ ? uint64_t(1) << op.q1 : 0);
+            if (qm & blocked) { defer.push_back(op); blocked |= qm; continue; }
+            if (!is_diag(op.kind)) {
+                const int t = op.q0;
+                const bool lane = t < n_lane_q;
+                const bool have = std::find(regq.begin(), regq.end(), t) != regq.end();
+                if (lane || have) { sched.push_back(op); continue; }
+                if ((int)regq.size() < R_eff) { regq.push_back(t); sched.push_back(op); continue; }
+                defer.push_back(op);
+                blocked |= qm;
+                continue;
+            }
+            sched.push_back(op);
+        }
+        if (sched.empty() && !rem.empty()) {
+            // only possible with no register bits while some qubit is outside the lane bits
+            sp.ok = false;
+            break;
+        }
+        // pad the register bits with untouched qubits so every tile holds 64 * 2^R_eff amplitudes
+        for (int t = q - 1; t >= n_lane_q && (int)regq.size() < R_eff; --t)
+            if (std::find(regq.begin(), regq.end(), t) == regq.end()) regq.push_back(t);
+        std::sort(regq.begin(), regq.end());
+        pp.R = (int)regq.size();
+        int kidx[64];
+        for (int i = 0; i < 64; ++i) kidx[i] = -1;
+        for (int k = 0; k < pp.R; ++k) {
+            pp.reg_pos[k] = p + regq[k];
+            kidx[p + regq[k]] = k;
+        }
+        PendingDiag pd;
+        for (const HalfOp &op : sched) {
+            if (!is_diag(op.kind)) {
+                const uint64_t qm = uint64_t(1) << op.q0;
+                if (pd.touched & qm) flush(pd, pp, kidx);
+                PassOp po;
+                po.kind = op.kind == HK_H ? GK_H : (op.kind == HK_X ? GK_X : GK_Y);
+                po.pad = 0;
+                po.group = 0;
+                if (op.q0 < n_lane_q) { po.type = PO_LANE; po.target = (uint8_t)(p + op.q0); }
+                else { po.type = PO_REG; po.target = (uint8_t)kidx[p + op.q0]; }
+                pp.ops.push_back(po);
+                ++pp.n_nondiag;
+                continue;
+            }
+            switch (op.kind) {
+            case HK_T:
+                pd.lin[p + op.q0] = (pd.lin[p + op.q0] + 1) & 7;
+                pd.touched |= uint64_t(1) << op.q0;
+                break;
+            case HK_CZ: {
+                int a = p + op.q0, b = p + op.q1;
+                if (a > b) std::swap(a, b);
+                toggle(pd.quad, {a, b});
+                pd.touched |= (uint64_t(1) << op.q0) | (uint64_t(1) << op.q1);
+                break;
+            }
+            case HK_PROJ: {
+                std::pair<int, int> e{p + op.q0, op.bit};
+                if (std::find(pd.proj.begin(), pd.proj.end(), e) == pd.proj.end()) pd.proj.push_back(e);
+                pd.touched |= uint64_t(1) << op.q0;
+                break;
+            }
+            case HK_ZCTL:
+                toggle(pd.zs, {p + op.q0, op.bit});
+                pd.touched |= uint64_t(1) << op.q0;
+                break;
+            default:
+                break;
+            }
+        }
+        flush(pd, pp, kidx);
+        // rescale: intermediate passes only when the gain got large, the last pass settles the segment
+        carry += pp.n_nondiag;
+        if (carry >= 32) {
+            const int e = std::min(carry / 2, seg_exp - taken);
+            pp.rescale_exp = e;
+            taken += e;
+            carry -= 2 * e;
+        }
+        sp.passes.push_back(std::move(pp));
+        rem.swap(defer);
+    }
+    sp.passes.back().rescale_exp += seg_exp - taken;
+    auto res = c.plan_cache.emplace(key, std::move(sp));
+    return res.first->second;
+}
+
+}  // namespace sf

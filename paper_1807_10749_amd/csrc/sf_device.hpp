@@ -1,0 +1,90 @@
+// Structures shared by the host planner and the HIP kernels.
+//
+// A block state of q qubits evolved for P = 2^p paths at once is stored as
+// one array of 2^(p+q) complex numbers, "extended index" e = i*P + slot:
+// the slot (path) bits are the p lowest bits and qubit t is bit p+t.  The
+// slot axis behaves like p extra low qubits that no gate touches, so every
+// gate sees contiguous runs of P amplitudes (coalesced HBM access) and the
+// gather reads one contiguous row of P values per requested index.
+//
+// A "pass" streams the whole array once.  A wave owns a tile of 64 * 2^R
+// amplitudes: lane l holds the 2^R amplitudes whose 6 lowest extended bits
+// equal l and whose R "register bits" (chosen qubits) run over all values;
+// the remaining bits come from the tile index.  Gates on register qubits are
+// applied in registers, gates on the (up to 6) qubits that sit in lane bits
+// with cross-lane shuffles, and diagonal gates (CZ, T, and the per-path
+// projector / Z of crossing CZs, Section 2 Eq. (CZ)) as bitmask phase
+// evaluations (the paper's bitmask + mod-8 arithmetic of Section 2).
+#pragma once
+#include <stdint.h>
+
+namespace sf {
+
+// One-qubit gate kinds applied by the kernels (unnormalised forms):
+//   H' = [[1,1],[1,-1]]          H     = H' / sqrt2
+//   X' = [[1,-i],[-i,1]]         X^1/2 = X' (1+i)/2
+//   Y' = [[1,-1],[1,1]]          Y^1/2 = Y' (1+i)/2
+// Each primed form has norm gain sqrt2; the host tracks the scalars and
+// folds exact powers of two back in ("rescaling").
+enum GateKind : uint8_t { GK_H = 0, GK_X = 1, GK_Y = 2 };
+
+enum PassOpType : uint8_t { PO_REG = 0, PO_LANE = 1, PO_DIAG = 2 };
+
+struct PassOp {
+    uint8_t type;    // PassOpType
+    uint8_t kind;    // GateKind for PO_REG / PO_LANE
+    uint8_t target;  // register index k (PO_REG) or lane bit b (PO_LANE)
+    uint8_t pad;
+    uint32_t group;  // diagonal group index (PO_DIAG)
+};
+
+// A merged set of commuting diagonal operators, evaluated per amplitude as
+//   keep(e) * omega^{m(e)},  omega = e^{i pi/4},
+//   m(e) = sum_lin w * e_b + 4 sum_quad e_a e_b + 4 sum_zs e_b s_u   (mod 8)
+//   keep(e) = prod_proj [e_a == s_u]
+// where e_x is bit x of the extended index and s_u bit u of the slot's path
+// id.  Terms are pre-split by whether their bits are register bits ("r",
+// given by register index k) or base bits ("b", extended bit position).
+struct DiagGroup {
+    uint16_t n_lin_b, n_quad_bb, n_quad_br, n_zs_b, n_zs_r, n_proj_b, n_proj_r;
+    uint16_t flags;            // bit 0: some odd phase weight; bit 1: has projectors
+    uint32_t term_off;         // offset (in byte pairs) into the term array
+    uint32_t pad;
+    uint64_t tab[4];           // m contribution of register-only terms, 4 bits per j < 64
+};
+// term layout (pairs of bytes), in this order:
+//   lin_b  (bit, weight)   quad_bb (bit_a, bit_b)   quad_br (bit_a, k)
+//   zs_b   (bit_b, u)      zs_r    (k, u)           proj_b  (bit_a, u)   proj_r (k, u)
+
+enum SrcMode : int32_t { SRC_SAME = 0, SRC_INIT = 1, SRC_FANOUT = 2 };
+
+struct PassArgs {
+    void *dst;
+    const void *src;
+    const uint64_t *slot_path;    // per destination slot: path id of the node (low bits 0 below its level)
+    const uint32_t *slot_parent;  // per destination slot: slot of its parent in src (SRC_FANOUT)
+    const PassOp *ops;
+    const DiagGroup *groups;
+    const uint8_t *terms;
+    uint64_t n_tiles;             // 2^(n_ext - 6 - R)
+    uint64_t init_zero_mask;      // SRC_INIT: extended bits that must be 0 for a non-zero amplitude
+    double rescale;               // multiply every amplitude by this at the end (exact power of 2)
+    uint32_t n_ops;
+    uint32_t slot_parent_base;    // SRC_FANOUT: parent slot = slot_parent[slot] - slot_parent_base
+    int32_t p_dst, p_src;         // slot bits of destination and source
+    int32_t src_mode;
+    int32_t reg_pos[6];           // extended bit positions of register bits, ascending
+};
+
+struct GatherArgs {
+    const void *a;                // block-A leaf states, 2^(p+qA) complex
+    const void *b;                // block-B leaf states, 2^(p+qB) complex
+    const uint32_t *xa, *xb;      // per bitstring: x_A, x_B
+    double *acc;                  // 2 * n_bits doubles (re, im), accumulated
+    uint64_t n_bits;
+    uint32_t n_slots;             // real slots (<= 2^p)
+    int32_t p;
+    double scale_re, scale_im;    // product of both blocks' tracked scalars
+};
+
+}  // namespace sf

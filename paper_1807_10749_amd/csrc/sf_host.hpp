@@ -1,0 +1,97 @@
+// Host-side data structures: circuit, cut, per-block programs and pass plans.
+#pragma once
+#include <complex>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sfpath.h"
+#include "sf_device.hpp"
+
+namespace sf {
+
+// Operations of one block's program, in local qubit indices.
+enum HalfKind : uint8_t {
+    HK_H = 0, HK_X = 1, HK_Y = 2, HK_T = 3, HK_CZ = 4,
+    HK_PROJ = 5,   // keep amplitudes whose bit q0 equals path bit `bit` (crossing CZ, block A side)
+    HK_ZCTL = 6,   // negate amplitudes whose bit q0 is 1 when path bit `bit` is 1 (block B side)
+};
+
+struct HalfOp {
+    uint8_t kind;
+    uint8_t q0, q1;
+    uint8_t bit;   // path bit index u (bit u of the path id), HK_PROJ / HK_ZCTL only
+};
+
+inline bool is_diag(uint8_t k) { return k == HK_T || k == HK_CZ || k == HK_PROJ || k == HK_ZCTL; }
+
+// One pass of a segment: kernel ops plus the register-bit choice.
+struct PassPlan {
+    int R = 0;                      // register bits used
+    int reg_pos[6] = {0, 0, 0, 0, 0, 0};
+    std::vector<PassOp> ops;
+    std::vector<DiagGroup> groups;
+    std::vector<uint8_t> terms;
+    int n_nondiag = 0;
+    int rescale_exp = 0;            // divide by 2^rescale_exp at the end of the pass
+    bool needs_slot_path = false;   // has path-dependent terms
+};
+
+// All passes of one block over one segment, for a given slot count 2^p.
+struct SegmentPlan {
+    std::vector<PassPlan> passes;
+    bool ok = true;      // false if some operation could not be scheduled
+};
+
+struct HalfProgram {
+    int q = 0;                                  // qubits in the block
+    uint64_t init_h_mask = 0;                   // local qubits whose opening H is folded into the initial state
+    std::vector<std::vector<HalfOp>> segments;  // one per tree level (segment 0 = root)
+    std::vector<std::complex<double>> seg_scale;  // scalar of each segment's unnormalised gates incl. rescaling
+    std::vector<int> seg_rescale_exp;           // power of two divided out at the end of each segment
+    std::complex<double> init_scale = 1.0;      // 2^{-h/2} for the folded opening H gates
+};
+
+struct Level {
+    int cycle;          // clock cycle of this level's crossing CZs
+    int first_cut;      // crossing-CZ indices [first_cut, first_cut + n_cut)
+    int n_cut;
+    int bits_after;     // path bits decided once this level's branch operators are applied
+};
+
+struct Circuit {
+    int rows = 0, cols = 0, n = 0;
+    std::vector<sf_gate_t> gates;
+
+    // cut
+    bool has_cut = false;
+    uint64_t mask_a = 0, mask_b = 0;
+    int k = 0;
+    std::vector<int> cut_gate;        // gate index of crossing CZ j (path-bit order)
+    std::vector<Level> levels;        // levels[0] is the root (no crossing CZ)
+    HalfProgram half[2];              // 0 = A, 1 = B
+
+    // tuning
+    sf_tuning_t tuning{};
+    std::map<std::tuple<int, int, int, int>, SegmentPlan> plan_cache;  // (half, level, p, R)
+
+    // device resources owned by the circuit
+    void *dev_ws = nullptr;
+    size_t dev_ws_bytes = 0;
+    int device_cus = 0;
+
+    sf_run_stats_t stats{};
+};
+
+// planner.cpp
+int build_programs(Circuit &c, std::string &err);
+const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R);
+
+// executor.cpp
+int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
+            const uint64_t *bits, size_t n_bits, double *amps, uint32_t flags, void *stream,
+            void *workspace, size_t workspace_bytes, std::string &err);
+int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32_t flags, size_t *bytes);
+
+}  // namespace sf

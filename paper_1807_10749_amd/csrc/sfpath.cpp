@@ -1,0 +1,259 @@
+// C ABI entry points (include/sfpath.h).  Every function catches C++
+// exceptions and reports errors through return codes and last_error().
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_set>
+
+#include "sf_host.hpp"
+
+using sf::Circuit;
+
+struct sf_circuit : Circuit {};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int ok()
+{
+    g_err.clear();
+    return SF_OK;
+}
+
+template <typename F>
+int guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ERR_OOM, "host out of memory");
+    } catch (const std::exception &e) {
+        return fail(SF_ERR_INVALID, std::string("internal error: ") + e.what());
+    } catch (...) {
+        return fail(SF_ERR_INVALID, "internal error");
+    }
+}
+
+int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+// SplitMix64 (Steele, Lea, Flood 2014).
+uint64_t splitmix_next(uint64_t &s)
+{
+    s += 0x9E3779B97F4A7C15ULL;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+int count_crossing(const Circuit &c, uint64_t mask_a)
+{
+    int k = 0;
+    for (const sf_gate_t &g : c.gates)
+        if (g.kind == 4 && (((mask_a >> g.q0) & 1) != ((mask_a >> g.q1) & 1))) ++k;
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *last_error(void) { return g_err.c_str(); }
+
+int create_circuit(int rows, int cols, const sf_gate_t *gates, size_t n_gates, sf_circuit_t **out)
+{
+    return guarded([&]() -> int {
+        if (!out) return fail(SF_ERR_INVALID, "out is NULL");
+        *out = nullptr;
+        if (rows < 1 || cols < 1) return fail(SF_ERR_INVALID, "grid must be at least 1 x 1");
+        if ((int64_t)rows * cols > 64) return fail(SF_ERR_UNSUPPORTED, "more than 64 qubits");
+        if (n_gates && !gates) return fail(SF_ERR_INVALID, "gates is NULL");
+        const int n = rows * cols;
+        int last_cycle = -1;
+        std::vector<int> seen(n, -1);
+        for (size_t i = 0; i < n_gates; ++i) {
+            const sf_gate_t &g = gates[i];
+            if (g.kind > 4) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": unknown kind");
+            if (g.q0 >= n) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": qubit outside the grid");
+            if (g.cycle < last_cycle) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": cycle decreases");
+            last_cycle = g.cycle;
+            if (g.kind == 4) {
+                if (g.q1 >= n || g.q1 == g.q0) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": bad CZ qubits");
+                const int r0 = g.q0 / cols, c0 = g.q0 % cols, r1 = g.q1 / cols, c1 = g.q1 % cols;
+                if (std::abs(r0 - r1) + std::abs(c0 - c1) != 1)
+                    return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": CZ on non-adjacent qubits");
+            }
+            const int qs[2] = {g.q0, g.kind == 4 ? (int)g.q1 : -1};
+            for (int q : qs) {
+                if (q < 0) continue;
+                if (seen[q] == g.cycle)
+                    return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": qubit used twice in one cycle");
+                seen[q] = g.cycle;
+            }
+        }
+        sf_circuit *c = new sf_circuit();
+        c->rows = rows;
+        c->cols = cols;
+        c->n = n;
+        c->gates.assign(gates, gates + n_gates);
+        *out = c;
+        return ok();
+    });
+}
+
+int destroy_circuit(sf_circuit_t *c)
+{
+    return guarded([&]() -> int {
+        if (!c) return ok();
+        if (c->dev_ws) (void)hipFree(c->dev_ws);
+        delete c;
+        return ok();
+    });
+}
+
+int set_cut(sf_circuit_t *c, uint64_t mask_a, uint32_t *k_out)
+{
+    return guarded([&]() -> int {
+        if (!c) return fail(SF_ERR_INVALID, "circuit is NULL");
+        const uint64_t all = c->n == 64 ? ~uint64_t(0) : ((uint64_t(1) << c->n) - 1);
+        if (!(mask_a & 1)) return fail(SF_ERR_INVALID, "block A must hold qubit 0");
+        if (mask_a & ~all) return fail(SF_ERR_INVALID, "mask has bits outside the grid");
+        if (mask_a == all) return fail(SF_ERR_INVALID, "block B is empty");
+        const int qa = popcount64(mask_a), qb = c->n - qa;
+        if (qa > 30 || qb > 30) return fail(SF_ERR_UNSUPPORTED, "a block has more than 30 qubits");
+        c->mask_a = mask_a;
+        c->mask_b = all & ~mask_a;
+        c->has_cut = false;
+        std::string err;
+        const int rc = sf::build_programs(*c, err);
+        if (rc) return fail(rc, err);
+        c->has_cut = true;
+        if (k_out) *k_out = (uint32_t)c->k;
+        return ok();
+    });
+}
+
+int choose_cut(const sf_circuit_t *c, uint64_t *block_a_mask)
+{
+    return guarded([&]() -> int {
+        if (!c || !block_a_mask) return fail(SF_ERR_INVALID, "NULL argument");
+        // candidates: (larger block, crossing CZs, horizontal?, index, mask)
+        bool found = false;
+        std::tuple<int, int, int, int> best{};
+        uint64_t best_mask = 0;
+        for (int orient = 0; orient < 2; ++orient) {
+            const int lim = orient == 0 ? c->cols - 1 : c->rows - 1;
+            for (int i = 0; i < lim; ++i) {
+                uint64_t m = 0;
+                for (int r = 0; r < c->rows; ++r)
+                    for (int col = 0; col < c->cols; ++col)
+                        if (orient == 0 ? col <= i : r <= i) m |= uint64_t(1) << (r * c->cols + col);
+                const int qa = popcount64(m), qb = c->n - qa;
+                auto key = std::make_tuple(std::max(qa, qb), count_crossing(*c, m), orient, i);
+                if (!found || key < best) { best = key; best_mask = m; found = true; }
+            }
+        }
+        if (!found) return fail(SF_ERR_UNSUPPORTED, "grid has no straight-line cut");
+        if (std::get<0>(best) > 30) return fail(SF_ERR_UNSUPPORTED, "every straight cut leaves a block above 30 qubits");
+        *block_a_mask = best_mask;
+        return ok();
+    });
+}
+
+int num_paths(uint32_t k, double f, uint64_t *n_out)
+{
+    if (!n_out) return fail(SF_ERR_INVALID, "n_out is NULL");
+    if (k > 62) return fail(SF_ERR_UNSUPPORTED, "k > 62");
+    if (!(f > 0.0) || f > 1.0) return fail(SF_ERR_INVALID, "f must lie in (0, 1]");
+    *n_out = (uint64_t)std::ceil(std::ldexp(f, (int)k));
+    return ok();
+}
+
+int sample_paths(uint32_t k, double f, uint64_t seed, uint64_t *out, uint64_t cap, uint64_t *n_out)
+{
+    return guarded([&]() -> int {
+        uint64_t m = 0;
+        int rc = num_paths(k, f, &m);
+        if (rc) return rc;
+        if (!out || m > cap) return fail(SF_ERR_INVALID, "output array too small");
+        const uint64_t N = uint64_t(1) << k;
+        std::unordered_set<uint64_t> chosen;
+        chosen.reserve((size_t)m * 2);
+        uint64_t s = seed, filled = 0;
+        for (uint64_t j = N - m; j < N; ++j) {
+            const uint64_t r = splitmix_next(s);
+            const uint64_t t = (uint64_t)(((unsigned __int128)r * (unsigned __int128)(j + 1)) >> 64);
+            const uint64_t pick = chosen.insert(t).second ? t : j;
+            if (pick == j) chosen.insert(j);
+            out[filled++] = pick;
+        }
+        std::sort(out, out + m);
+        if (n_out) *n_out = m;
+        return ok();
+    });
+}
+
+int workspace_size(const sf_circuit_t *c, uint64_t n_paths, size_t n_bits, uint32_t flags, size_t *bytes)
+{
+    return guarded([&]() -> int {
+        if (!c || !bytes) return fail(SF_ERR_INVALID, "NULL argument");
+        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
+        return sf::estimate_workspace(*c, n_paths, n_bits, flags, bytes) ? fail(SF_ERR_INVALID, "estimate failed") : ok();
+    });
+}
+
+int run_paths(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
+              const uint64_t *bitstrings, size_t n_bits, double *amps, uint32_t flags, void *hip_stream,
+              void *workspace, size_t workspace_bytes)
+{
+    return guarded([&]() -> int {
+        if (!c) return fail(SF_ERR_INVALID, "circuit is NULL");
+        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
+        if (n_bits && (!bitstrings || !amps)) return fail(SF_ERR_INVALID, "bitstrings or amps is NULL");
+        if (flags & ~uint32_t(63)) return fail(SF_ERR_INVALID, "unknown flag");
+        if (workspace && workspace_bytes < (size_t(1) << 28)) return fail(SF_ERR_OOM, "workspace smaller than 256 MiB");
+        if (n_bits > (size_t(1) << 32)) return fail(SF_ERR_UNSUPPORTED, "more than 2^32 bitstrings");
+        std::string err;
+        const int rc = sf::execute(*c, path_ids, path_begin, n_paths, bitstrings, n_bits, amps, flags, hip_stream,
+                                   workspace, workspace_bytes, err);
+        return rc ? fail(rc, err) : ok();
+    });
+}
+
+int set_tuning(sf_circuit_t *c, const sf_tuning_t *t)
+{
+    if (!c || !t) return fail(SF_ERR_INVALID, "NULL argument");
+    if (t->reg_qubits > 5) return fail(SF_ERR_INVALID, "reg_qubits must be at most 5");
+    auto pow2ok = [](uint32_t v) { return v == 0 || (v & (v - 1)) == 0; };
+    if (!pow2ok(t->leaf_batch) || !pow2ok(t->max_slots)) return fail(SF_ERR_INVALID, "batch sizes must be powers of two");
+    c->tuning = *t;
+    c->plan_cache.clear();
+    return ok();
+}
+
+int get_tuning(const sf_circuit_t *c, sf_tuning_t *t)
+{
+    if (!c || !t) return fail(SF_ERR_INVALID, "NULL argument");
+    *t = c->tuning;
+    return ok();
+}
+
+int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s)
+{
+    if (!c || !s) return fail(SF_ERR_INVALID, "NULL argument");
+    *s = c->stats;
+    return ok();
+}
+
+}  // extern "C"

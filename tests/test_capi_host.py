@@ -1,0 +1,154 @@
+"""Host-only checks of the C-ABI library: exports, validation, cut, path selection.
+
+No GPU compute is called here: run_paths is only exercised on argument
+errors that the library rejects before touching the device.
+"""
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from workload import CONFIGS, CZ, GATE_DTYPE, H, grid_circuit, make_workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfpath.h")
+
+
+@pytest.fixture(scope="module")
+def sf():
+    from paper_1807_10749_amd import binding
+    return binding
+
+
+def test_library_exports_every_declared_function(sf):
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^(?:int|const char \*)\s*(\w+)\(", text, re.M))
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(sf.lib, name), name
+    assert declared == set(sf.EXPORTS)
+
+
+def test_create_circuit_validation(sf):
+    ok = np.array([(H, 0, 0, 0, 0), (CZ, 0, 1, 0, 1)], dtype=GATE_DTYPE)
+    c = sf.create_circuit(2, 2, ok)
+    sf.destroy_circuit(c)
+    bad = [
+        np.array([(7, 0, 0, 0, 0)], dtype=GATE_DTYPE),                       # unknown kind
+        np.array([(H, 0, 0, 4, 0)], dtype=GATE_DTYPE),                       # outside grid
+        np.array([(CZ, 0, 0, 0, 3)], dtype=GATE_DTYPE),                      # not neighbours (diagonal)
+        np.array([(H, 0, 2, 0, 0), (H, 0, 1, 1, 0)], dtype=GATE_DTYPE),      # cycle decreases
+        np.array([(H, 0, 1, 0, 0), (CZ, 0, 1, 0, 1)], dtype=GATE_DTYPE),     # qubit twice in a cycle
+    ]
+    for g in bad:
+        with pytest.raises(sf.SFError) as e:
+            sf.create_circuit(2, 2, g)
+        assert e.value.code == sf.SF_ERR_INVALID
+    with pytest.raises(sf.SFError) as e:
+        sf.create_circuit(9, 8, ok)
+    assert e.value.code == sf.SF_ERR_UNSUPPORTED
+
+
+def test_set_cut_counts_match_oracle(sf):
+    for name, cfg in CONFIGS.items():
+        g = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed)
+        c = sf.create_circuit(cfg.rows, cfg.cols, g)
+        k = sf.set_cut(c, cfg.cut_mask())
+        assert k == oracle.num_cut(cfg.n_qubits, g, cfg.cut_mask()), name
+        sf.destroy_circuit(c)
+
+
+def test_set_cut_validation(sf):
+    g = grid_circuit(4, 4, 8, 1)
+    c = sf.create_circuit(4, 4, g)
+    for mask, code in [(0b10, sf.SF_ERR_INVALID), ((1 << 16) - 1, sf.SF_ERR_INVALID),
+                       (1 << 20 | 1, sf.SF_ERR_INVALID)]:
+        with pytest.raises(sf.SFError) as e:
+            sf.set_cut(c, mask)
+        assert e.value.code == code
+    sf.destroy_circuit(c)
+    g = grid_circuit(8, 8, 8, 1)
+    c = sf.create_circuit(8, 8, g)
+    with pytest.raises(sf.SFError) as e:
+        sf.set_cut(c, (1 << 40) - 1)     # block A of 40 qubits
+    assert e.value.code == sf.SF_ERR_UNSUPPORTED
+    sf.destroy_circuit(c)
+
+
+def test_choose_cut_straight_line(sf):
+    """Section 9: a single straight cut minimising the larger block, then crossing CZs."""
+    expect = {(4, 4): ("col", 2), (5, 6): ("col", 3), (6, 7): ("row", 3), (7, 8): ("col", 4)}
+    for (r, cc), (kind, nn) in expect.items():
+        g = grid_circuit(r, cc, 16, 3)
+        c = sf.create_circuit(r, cc, g)
+        m = sf.choose_cut(c)
+        n = r * cc
+        assert bin(m).count("1") * 2 == n and m & 1
+        from workload import column_cut_mask, row_cut_mask
+        want = column_cut_mask(r, cc, nn) if kind == "col" else row_cut_mask(r, cc, nn)
+        assert m == want, (r, cc)
+        sf.destroy_circuit(c)
+
+
+def test_num_paths_matches_paper_logs(sf):
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_numbers.json")))
+    for e in gold["path_counts"]:
+        f = e.get("f", None)
+        if f is None:
+            f = e["f_num"] / e["f_den"] if "f_den" in e else 2.0 ** e["f_pow2"]
+        assert sf.num_paths(e["prefix_bits"], f) == e["count"], e["cite"]
+    with pytest.raises(sf.SFError):
+        sf.num_paths(10, 0.0)
+    with pytest.raises(sf.SFError):
+        sf.num_paths(10, 1.5)
+
+
+@pytest.mark.parametrize("k,f,seed", [(8, 1.0, 3), (15, 0.1, 7), (28, 0.001, 3003), (35, 1e-7, 11),
+                                      (20, 0.5, 0)])
+def test_sample_paths_bit_exact_with_oracle(sf, k, f, seed):
+    a = sf.sample_paths(k, f, seed)
+    b = oracle.sample_paths(k, f, seed)
+    assert a.size == math.ceil(f * 2 ** k)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_workspace_size_and_run_validation(sf):
+    w = make_workload("grid4x4_d16", n_bits=16)
+    c = sf.create_circuit(4, 4, w["gates"])
+    with pytest.raises(sf.SFError) as e:
+        sf.run_paths(c, None, 0, 1, w["bitstrings"], 16, np.zeros(32))
+    assert e.value.code == sf.SF_ERR_NO_CUT
+    k = sf.set_cut(c, w["mask_a"])
+    assert sf.workspace_size(c, 1 << k, 16) > 0
+    amps = np.zeros(32)
+    bad_bits = w["bitstrings"].copy()
+    bad_bits[3] = 1 << 16
+    with pytest.raises(sf.SFError) as e:
+        sf.run_paths(c, None, 0, 1 << k, bad_bits, 16, amps)
+    assert e.value.code == sf.SF_ERR_INVALID
+    with pytest.raises(sf.SFError) as e:
+        sf.run_paths(c, None, 0, (1 << k) + 1, w["bitstrings"], 16, amps)
+    assert e.value.code == sf.SF_ERR_INVALID
+    with pytest.raises(sf.SFError) as e:
+        sf.run_paths(c, None, 0, 1, w["bitstrings"], 16, amps, flags=1 << 10)
+    assert e.value.code == sf.SF_ERR_INVALID
+    with pytest.raises(sf.SFError) as e:
+        sf.run_paths(c, None, 0, 1, w["bitstrings"], 16, amps, workspace=12345, workspace_bytes=1 << 20)
+    assert e.value.code == sf.SF_ERR_OOM
+    sf.destroy_circuit(c)
+
+
+def test_tuning_roundtrip(sf):
+    w = make_workload("grid4x4_d16", n_bits=4)
+    c = sf.create_circuit(4, 4, w["gates"])
+    sf.set_tuning(c, reg_qubits=3, leaf_batch=64, max_slots=1024, waves_per_cu=16)
+    assert sf.get_tuning(c) == {"reg_qubits": 3, "leaf_batch": 64, "max_slots": 1024, "waves_per_cu": 16}
+    with pytest.raises(sf.SFError):
+        sf.set_tuning(c, leaf_batch=48)
+    with pytest.raises(sf.SFError):
+        sf.set_tuning(c, reg_qubits=9)
+    sf.destroy_circuit(c)

@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance (floating point): for amplitudes a (GPU) and o (oracle) over a set
+of m of the 2^k paths of an n-qubit circuit,
+    e_x = | |a_x|^2 - |o_x|^2 | / max(|o_x|^2, (m / 2^k) 2^-n),
+the floor being the mean |amp|^2 of such a partial sum; max_x e_x <= 1e-5
+for complex64 sweeps and <= 1e-10 for complex128 sweeps.  Path and
+bitstring indexing is exact: single-path runs expose any permutation as an
+O(1) error.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workload import CONFIGS, grid_circuit, make_workload, path_block, random_bitstrings
+
+pytestmark = pytest.mark.gpu
+
+TOL_C64 = 1e-5
+TOL_C128 = 1e-10
+
+
+def c11_error(a, o, m, k, n):
+    floor = (m / 2.0 ** k) * 2.0 ** (-n)
+    return float(np.max(np.abs(np.abs(a) ** 2 - np.abs(o) ** 2) / np.maximum(np.abs(o) ** 2, floor)))
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1807_10749_amd import binding
+    return binding
+
+
+def _circuit(sf, name):
+    cfg = CONFIGS[name]
+    g = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed)
+    return cfg, g, sf.Circuit(cfg.rows, cfg.cols, g, cfg.cut_mask())
+
+
+# ---------------------------------------------------------------- 4x4, 1+16+1, 8+8
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_grid4x4_all_paths(sf, fp64):
+    cfg, g, c = _circuit(sf, "grid4x4_d16")
+    bits = random_bitstrings(16, cfg.n_bits, cfg.bits_seed)
+    say(f"grid4x4_d16 all paths fp64={fp64}")
+    a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS if fp64 else 0)
+    o = oracle.path_sum(16, g, cfg.cut_mask(), np.arange(1 << c.k, dtype=np.uint64), bits)
+    full = oracle.full_state(16, g)[bits.astype(np.int64)]
+    err = c11_error(a, o, 1 << c.k, c.k, 16)
+    assert err <= (TOL_C128 if fp64 else TOL_C64), err
+    assert np.abs(o - full).max() < 1e-14
+
+
+@pytest.mark.parametrize("path", [0, 1, 37, 128, 200, 255])
+def test_grid4x4_single_path_indexing(sf, path):
+    cfg, g, c = _circuit(sf, "grid4x4_d16")
+    bits = random_bitstrings(16, 1024, 5)
+    say(f"grid4x4_d16 single path {path}")
+    a = c.amplitudes(bits, path_begin=path, n_paths=1, flags=sf.SF_FP64_SWEEPS)
+    o = oracle.path_sum(16, g, cfg.cut_mask(), [path], bits)
+    assert c11_error(a, o, 1, c.k, 16) <= TOL_C128
+
+
+def test_grid4x4_plain_equals_batched(sf):
+    cfg, g, c = _circuit(sf, "grid4x4_d16")
+    bits = random_bitstrings(16, 512, 6)
+    ids = np.array([3, 4, 5, 17, 100, 101, 250], dtype=np.uint64)
+    say("grid4x4_d16 plain vs batched")
+    a = c.amplitudes(bits, path_ids=ids, flags=sf.SF_PLAIN)
+    b = c.amplitudes(bits, path_ids=ids)
+    o = oracle.path_sum(16, g, cfg.cut_mask(), ids, bits)
+    assert c11_error(a, o, ids.size, c.k, 16) <= TOL_C64
+    assert c11_error(b, o, ids.size, c.k, 16) <= TOL_C64
+
+
+def test_empty_and_accumulate(sf):
+    import torch
+    cfg, g, c = _circuit(sf, "grid4x4_d16")
+    bits = random_bitstrings(16, 100, 7)
+    say("grid4x4_d16 zero paths / accumulate / device buffers")
+    z = c.amplitudes(bits, path_ids=np.zeros(0, dtype=np.uint64))
+    assert np.all(z == 0)
+    # two halves of the path space accumulated into one device buffer equal the whole
+    dbits = torch.from_numpy(bits.view(np.int64)).cuda()
+    acc = torch.zeros(2 * bits.size, dtype=torch.float64, device="cuda")
+    ws = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    flags = sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
+    sf.run_paths(c.handle, None, 0, 128, dbits, bits.size, acc, flags, torch.cuda.current_stream(), ws, ws.numel())
+    sf.run_paths(c.handle, None, 128, 128, dbits, bits.size, acc, flags | sf.SF_ACCUMULATE,
+                 torch.cuda.current_stream(), ws, ws.numel())
+    a = acc.cpu().numpy().view(np.complex128)
+    o = oracle.path_sum(16, g, cfg.cut_mask(), np.arange(256, dtype=np.uint64), bits)
+    assert c11_error(a, o, 256, c.k, 16) <= TOL_C64
+    # a device bitstring outside the grid is reported after the run
+    bad = dbits.clone()
+    bad[5] = 1 << 20
+    with pytest.raises(sf.SFError):
+        sf.run_paths(c.handle, None, 0, 4, bad, bits.size, acc, flags, None, ws, ws.numel())
+
+
+def test_small_blocks_and_no_crossing(sf):
+    """Blocks below 6 qubits (padded slots) and a circuit without crossing CZs (k = 0)."""
+    g = grid_circuit(2, 4, 10, 44)
+    mask = 0b00110011                    # columns 0-1: 4 + 4 qubits
+    c = sf.Circuit(2, 4, g, mask)
+    bits = np.arange(256, dtype=np.uint64)
+    say("2x4 grid, 4+4 blocks")
+    a = c.amplitudes(bits)
+    o = oracle.full_state(8, g)
+    assert c11_error(a, o, 1, 0, 8) <= TOL_C64
+    g0 = grid_circuit(4, 4, 1, 3)
+    c0 = sf.Circuit(4, 4, g0, (1 << 8) - 1)   # rows 0-1 | rows 2-3, cycle 1 is V(0,0): no crossing
+    assert c0.k == 0
+    bits = random_bitstrings(16, 300, 4)
+    say("4x4 depth 1, k = 0")
+    a = c0.amplitudes(bits)
+    o = oracle.full_state(16, g0)[bits.astype(np.int64)]
+    assert c11_error(a, o, 1, 0, 16) <= TOL_C64
+
+
+def test_register_widths_agree(sf):
+    cfg, g, c = _circuit(sf, "grid4x4_d16")
+    bits = random_bitstrings(16, 256, 8)
+    o = oracle.path_sum(16, g, cfg.cut_mask(), np.arange(256, dtype=np.uint64), bits)
+    for r in (1, 2, 3, 4, 5):
+        say(f"grid4x4_d16 reg_qubits={r}")
+        c.tune(reg_qubits=r)
+        a = c.amplitudes(bits)
+        assert c11_error(a, o, 256, c.k, 16) <= TOL_C64, r
+
+
+# ---------------------------------------------------------------- 5x6, 1+24+1, 15+15
+
+def test_grid5x6_path_subsets(sf):
+    cfg, g, c = _circuit(sf, "grid5x6_d24")
+    bits = random_bitstrings(30, 4000, cfg.bits_seed)
+    rng = np.random.default_rng(1)
+    ids = np.sort(rng.choice(1 << c.k, size=200, replace=False)).astype(np.uint64)
+    say("grid5x6_d24 200 random paths")
+    a = c.amplitudes(bits, path_ids=ids)
+    o = oracle.path_sum(30, g, cfg.cut_mask(), ids, bits)
+    assert c11_error(a, o, ids.size, c.k, 30) <= TOL_C64
+    say("grid5x6_d24 aligned block of 512 paths, tight workspace")
+    import torch
+    ws = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    a = c.amplitudes(bits, path_begin=3 * 512, n_paths=512, workspace=ws)
+    o = oracle.path_sum(30, g, cfg.cut_mask(), np.arange(3 * 512, 4 * 512, dtype=np.uint64), bits)
+    assert c11_error(a, o, 512, c.k, 30) <= TOL_C64
+
+
+@pytest.mark.slow
+def test_grid5x6_full_benchmark_size(sf):
+    """All 2^15 paths, 1e5 bitstrings, default launch configuration (the benchmark's)."""
+    w = make_workload("grid5x6_d24")
+    cfg, g, c = _circuit(sf, "grid5x6_d24")
+    say("grid5x6_d24 all paths, 1e5 bitstrings")
+    a = c.amplitudes(w["bitstrings"])
+    o = oracle.path_sum(30, g, cfg.cut_mask(), np.arange(1 << c.k, dtype=np.uint64), w["bitstrings"])
+    assert c11_error(a, o, 1 << c.k, c.k, 30) <= TOL_C64
+
+
+# ---------------------------------------------------------------- 6x7 and 7x8
+
+def test_grid6x7_sampled_paths(sf):
+    cfg, g, c = _circuit(sf, "grid6x7_d32")
+    ids_all = sf.sample_paths(c.k, cfg.f, cfg.path_seed)
+    assert ids_all.size == 2684355
+    ids = ids_all[:: ids_all.size // 4][:4]
+    bits = random_bitstrings(42, 20000, cfg.bits_seed)
+    say(f"grid6x7_d32 sampled paths {ids.tolist()}")
+    a = c.amplitudes(bits, path_ids=ids)
+    o = oracle.path_sum(42, g, cfg.cut_mask(), ids, bits)
+    assert c11_error(a, o, ids.size, c.k, 42) <= TOL_C64
+    for p in ids[:2]:
+        say(f"grid6x7_d32 single path {int(p)}")
+        a1 = c.amplitudes(bits[:2000], path_ids=[p])
+        o1 = oracle.path_sum(42, g, cfg.cut_mask(), [p], bits[:2000])
+        assert c11_error(a1, o1, 1, c.k, 42) <= TOL_C64
+
+
+def test_grid7x8_block_properties(sf):
+    """Full 28+28 shape: a path block equals the sum of its parts, the plain form, and each
+    single-path term is rank one in (x_A, x_B)."""
+    cfg, g, c = _circuit(sf, "grid7x8_d40")
+    begin, count = path_block(c.k, cfg.block_bits, cfg.path_seed)
+    bits = random_bitstrings(56, 4096, cfg.bits_seed)
+    say("grid7x8_d40 16-path sub-block, tree")
+    a = c.amplitudes(bits, path_begin=begin, n_paths=16)
+    say("grid7x8_d40 two 8-path halves")
+    a1 = c.amplitudes(bits, path_begin=begin, n_paths=8)
+    a2 = c.amplitudes(bits, path_begin=begin + 8, n_paths=8)
+    assert np.abs(a - (a1 + a2)).max() <= 1e-5 * np.abs(a).max()
+    say("grid7x8_d40 plain form, 2 paths")
+    p = c.amplitudes(bits, path_begin=begin, n_paths=2, flags=sf.SF_PLAIN)
+    t = c.amplitudes(bits, path_begin=begin, n_paths=2)
+    assert np.abs(p - t).max() <= 1e-5 * np.abs(t).max()
+    # rank one: amp(a1,b1) amp(a2,b2) = amp(a1,b2) amp(a2,b1) for one path
+    ma, mb = c.mask_a, ((1 << 56) - 1) & ~c.mask_a
+    rng = np.random.default_rng(3)
+    xa = [int(v) & ma for v in rng.integers(0, 1 << 62, 2, dtype=np.int64)]
+    xb = [int(v) & mb for v in rng.integers(0, 1 << 62, 2, dtype=np.int64)]
+    quad = np.array([xa[0] | xb[0], xa[1] | xb[1], xa[0] | xb[1], xa[1] | xb[0]], dtype=np.uint64)
+    say("grid7x8_d40 rank-one check of a single path")
+    q = c.amplitudes(quad, path_begin=begin + 5, n_paths=1)
+    assert abs(q[0] * q[1] - q[2] * q[3]) <= 1e-4 * abs(q[0] * q[1])
