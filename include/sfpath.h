@@ -170,6 +170,15 @@ typedef struct {
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);
 
+/*
+ * describe_plan: human-readable summary of the block programs: per tree level
+ * and block the number of operations and of fused passes, planned for the
+ * slot count an all-paths run uses at that level (2^bits, capped by the
+ * tuning).  Host only, no device work.  Writes a NUL-terminated string of
+ * at most cap bytes.
+ */
+int describe_plan(sf_circuit_t *c, char *out, size_t cap);
+
 /* Message for the last error on the calling thread ("" if none). */
 const char *last_error(void);
 

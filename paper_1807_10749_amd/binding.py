@@ -19,7 +19,8 @@ SF_OK, SF_ERR_INVALID, SF_ERR_OOM, SF_ERR_UNSUPPORTED, SF_ERR_NO_CUT, SF_ERR_DEV
 SF_ACCUMULATE, SF_OUT_ON_DEVICE, SF_FP64_SWEEPS, SF_PLAIN, SF_BITS_ON_DEVICE, SF_TIMING = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_paths", "sample_paths",
-           "run_paths", "workspace_size", "set_tuning", "get_tuning", "get_run_stats", "last_error"]
+           "run_paths", "workspace_size", "set_tuning", "get_tuning", "get_run_stats", "describe_plan",
+           "last_error"]
 
 
 class SFError(RuntimeError):
@@ -62,6 +63,7 @@ def _load():
     lib.set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.get_run_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
+    lib.describe_plan.argtypes = [vp, ctypes.c_char_p, sz]
     lib.last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "last_error":
@@ -173,6 +175,12 @@ def get_run_stats(c: int) -> dict:
     s = RunStats()
     _check(lib.get_run_stats(c, ctypes.byref(s)))
     return s.as_dict()
+
+
+def describe_plan(c: int) -> str:
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib.describe_plan(c, buf, len(buf)))
+    return buf.value.decode()
 
 
 # ---------------------------------------------------------------- convenience wrapper

@@ -92,8 +92,8 @@ struct Launch {
     int R = 0;
     PassArgs pa{};
     GatherArgs ga{};
-    size_t plan_off = 0;      // device offsets of ops/groups/terms inside the plan blob
-    size_t groups_off = 0, terms_off = 0;
+    size_t plan_off = 0;      // device offset of the pass program inside the plan blob
+    uint32_t prog_words = 0, groups_word = 0, terms_word = 0;
     int level = 0;
     size_t dst_off = 0, src_off = 0;
     size_t slot_off = 0;      // element offset into the level's node / parent tables
@@ -102,7 +102,7 @@ struct Launch {
     uint64_t bytes = 0;
 };
 
-struct BlobEntry { size_t ops, groups, terms; };
+struct BlobEntry { size_t off; uint32_t words, groups_word, terms_word; };
 
 }  // namespace
 
@@ -296,6 +296,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
 
     // ---------------------------------------------------------------- launch list
     std::vector<Launch> launches;
+    bool plan_error = false;
     std::vector<char> blob;                    // host image of the plan blob
     std::map<const SegmentPlan *, std::vector<BlobEntry>> blob_index;
     std::complex<double> leaf_scale[2];
@@ -317,10 +318,21 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         if (it != blob_index.end()) return it->second;
         std::vector<BlobEntry> v;
         for (const PassPlan &pp : sp.passes) {
+            // [ops][pad to 8 bytes][groups][term bytes, padded to 4]
+            std::vector<char> img(pp.ops.size() * sizeof(PassOp));
+            if (!pp.ops.empty()) std::memcpy(img.data(), pp.ops.data(), img.size());
+            while (img.size() % 8) img.push_back(0);
             BlobEntry e;
-            e.ops = blob_put(pp.ops.data(), pp.ops.size() * sizeof(PassOp));
-            e.groups = blob_put(pp.groups.data(), pp.groups.size() * sizeof(DiagGroup));
-            e.terms = blob_put(pp.terms.data(), pp.terms.size());
+            e.groups_word = (uint32_t)(img.size() / 4);
+            const size_t g0 = img.size();
+            img.resize(g0 + pp.groups.size() * sizeof(DiagGroup));
+            if (!pp.groups.empty()) std::memcpy(img.data() + g0, pp.groups.data(), pp.groups.size() * sizeof(DiagGroup));
+            e.terms_word = (uint32_t)(img.size() / 4);
+            img.insert(img.end(), pp.terms.begin(), pp.terms.end());
+            while (img.size() % 4) img.push_back(0);
+            e.words = (uint32_t)(img.size() / 4);
+            if (e.words > (uint32_t)kMaxProgWords) { plan_error = true; }
+            e.off = blob_put(img.data(), img.size());
             v.push_back(e);
         }
         return blob_index.emplace(&sp, std::move(v)).first->second;
@@ -328,7 +340,6 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
 
     const unsigned max_grid = (unsigned)std::max(1, c.device_cus) * (c.tuning.waves_per_cu ? c.tuning.waves_per_cu / 4 : 8);
     uint64_t n_batches = 0;
-    bool plan_error = false;
 
     // enqueue the passes of segment `level` for one batch of nslots slots
     auto add_segment = [&](RunPlan &rp, int level, uint64_t nslots, size_t dst_base[2], int src_level,
@@ -372,9 +383,10 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 }
                 ln.slot_off = slot_first;
                 ln.parent_base = parent_base;
-                ln.plan_off = be[i].ops;
-                ln.groups_off = be[i].groups;
-                ln.terms_off = be[i].terms;
+                ln.plan_off = be[i].off;
+                ln.prog_words = be[i].words;
+                ln.groups_word = be[i].groups_word;
+                ln.terms_word = be[i].terms_word;
                 const uint64_t waves = a.n_tiles;
                 ln.grid = (unsigned)std::min<uint64_t>((waves + 3) / 4, max_grid);
                 ln.bytes = (uint64_t(1) << n_ext) * elem * (a.src_mode == SRC_INIT ? 1 : 2);
@@ -534,9 +546,10 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 a.src = ws + ln.src_off;
                 a.slot_path = (const uint64_t *)(ws + off_tables + rp.table_off[ln.level]) + ln.slot_off;
                 a.slot_parent = (const uint32_t *)(ws + off_tables + rp.parent_table_off[ln.level]) + ln.slot_off;
-                a.ops = (const PassOp *)(ws + off_blob + ln.plan_off);
-                a.groups = (const DiagGroup *)(ws + off_blob + ln.groups_off);
-                a.terms = (const uint8_t *)(ws + off_blob + ln.terms_off);
+                a.prog = (const uint32_t *)(ws + off_blob + ln.plan_off);
+                a.prog_words = ln.prog_words;
+                a.groups_word = ln.groups_word;
+                a.terms_word = ln.terms_word;
                 a.slot_parent_base = ln.parent_base;   // parent tables hold level-global indices
                 hipEvent_t *e = ev_pair(0);
                 if (e) (void)hipEventRecord(e[0], stream);

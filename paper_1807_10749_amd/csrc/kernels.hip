@@ -211,6 +211,14 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     for (int k = 0; k < 6; ++k) pos[k] = a.reg_pos[k];
     const uint64_t pmask_dst = ((uint64_t)1 << a.p_dst) - 1u;
 
+    // stage the pass program in LDS
+    __shared__ __align__(16) uint32_t s_prog[kMaxProgWords];
+    for (uint32_t i = threadIdx.x; i < a.prog_words; i += blockDim.x) s_prog[i] = a.prog[i];
+    __syncthreads();
+    const PassOp *ops = (const PassOp *)s_prog;
+    const DiagGroup *groups = (const DiagGroup *)(s_prog + a.groups_word);
+    const uint8_t *terms = (const uint8_t *)(s_prog + a.terms_word);
+
     // the wave index is uniform across a wave; say so, so tile arithmetic stays in scalar registers
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint64_t tile = (uint64_t)blockIdx.x * 4u + wid; tile < a.n_tiles; tile += nwaves) {
@@ -256,13 +264,13 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         }
 
         for (uint32_t i = 0; i < a.n_ops; ++i) {
-            const PassOp op = a.ops[i];
+            const PassOp op = ops[i];
             if (op.type == PO_REG) {
                 reg_dispatch<R>(op.target, op.kind, v);
             } else if (op.type == PO_LANE) {
                 lane_gate<R>(op.target, op.kind, (int)lane, v);
             } else {
-                apply_diag<R, T>(a.groups + op.group, a.terms, eB, sp, v);
+                apply_diag<R, T>(groups + op.group, terms, eB, sp, v);
             }
         }
 

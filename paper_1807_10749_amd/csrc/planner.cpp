@@ -73,18 +73,22 @@ int build_programs(Circuit &c, std::string &err)
         hp.segments.assign(L + 1, {});
         hp.init_h_mask = 0;
     }
-    int seg = 0;   // number of levels whose cycle is below the current gate's cycle
+    // Per block, the operations in list order; a crossing CZ becomes its branch operator
+    // (P_s on the A endpoint, Z^s on the B endpoint), tagged with its tree level.
+    std::vector<HalfOp> ops[2];
+    std::vector<int> own[2];
     for (size_t i = 0; i < c.gates.size(); ++i) {
         const sf_gate_t &g = c.gates[i];
-        while (seg < L && c.levels[seg + 1].cycle < g.cycle) ++seg;
         if (bit_of_gate[i] >= 0) {
             int lvl = 1;
             while (c.levels[lvl].cycle != g.cycle) ++lvl;
             const int qa = in_a(g.q0) ? g.q0 : g.q1;
             const int qb = in_a(g.q0) ? g.q1 : g.q0;
             const uint8_t u = (uint8_t)bit_of_gate[i];
-            c.half[0].segments[lvl].push_back(HalfOp{HK_PROJ, (uint8_t)local[qa], 0, u});
-            c.half[1].segments[lvl].push_back(HalfOp{HK_ZCTL, (uint8_t)local[qb], 0, u});
+            ops[0].push_back(HalfOp{HK_PROJ, (uint8_t)local[qa], 0, u});
+            own[0].push_back(lvl);
+            ops[1].push_back(HalfOp{HK_ZCTL, (uint8_t)local[qb], 0, u});
+            own[1].push_back(lvl);
             continue;
         }
         const int h = in_a(g.q0) ? 0 : 1;
@@ -96,7 +100,31 @@ int build_programs(Circuit &c, std::string &err)
         case 3: op.kind = HK_T; break;
         default: op.kind = HK_CZ; op.q1 = (uint8_t)local[g.q1]; break;
         }
-        c.half[h].segments[seg].push_back(op);
+        ops[h].push_back(op);
+        own[h].push_back(0);
+    }
+    // Each operation runs at the highest tree level its dependencies allow, so work that does
+    // not depend on a level's branch operators is done once per parent instead of once per
+    // child.  Diagonal operators commute with each other (and the branch operators are
+    // diagonal): a diagonal op waits only for earlier non-diagonal ops on its qubits, a
+    // non-diagonal op waits for everything earlier on its qubit.
+    for (int h = 0; h < 2; ++h) {
+        std::vector<int> N(64, 0), D(64, 0);   // level of the last non-diagonal op / of later diagonal ops
+        for (size_t i = 0; i < ops[h].size(); ++i) {
+            const HalfOp &op = ops[h][i];
+            int lvl = own[h][i];
+            if (is_diag(op.kind)) {
+                lvl = std::max(lvl, N[op.q0]);
+                if (op.kind == HK_CZ) lvl = std::max(lvl, N[op.q1]);
+                D[op.q0] = std::max(D[op.q0], lvl);
+                if (op.kind == HK_CZ) D[op.q1] = std::max(D[op.q1], lvl);
+            } else {
+                lvl = std::max(lvl, std::max(N[op.q0], D[op.q0]));
+                N[op.q0] = lvl;
+                D[op.q0] = lvl;
+            }
+            c.half[h].segments[lvl].push_back(op);
+        }
     }
 
     // fold each qubit's opening H (if it is the qubit's first operation) into the initial state,

@@ -58,14 +58,21 @@ struct DiagGroup {
 
 enum SrcMode : int32_t { SRC_SAME = 0, SRC_INIT = 1, SRC_FANOUT = 2 };
 
+// A pass program (ops, then diagonal groups, then term bytes) is one
+// contiguous block of at most kMaxProgWords 32-bit words; the kernel stages
+// it in LDS once per workgroup so the per-tile interpreter never touches
+// global memory for it.
+constexpr int kMaxProgWords = 2048;
+
 struct PassArgs {
     void *dst;
     const void *src;
     const uint64_t *slot_path;    // per destination slot: path id of the node (low bits 0 below its level)
     const uint32_t *slot_parent;  // per destination slot: slot of its parent in src (SRC_FANOUT)
-    const PassOp *ops;
-    const DiagGroup *groups;
-    const uint8_t *terms;
+    const uint32_t *prog;         // pass program in global memory
+    uint32_t prog_words;          // its size
+    uint32_t groups_word;         // word offset of the DiagGroup array (8-byte aligned)
+    uint32_t terms_word;          // word offset of the term bytes
     uint64_t n_tiles;             // 2^(n_ext - 6 - R)
     uint64_t init_zero_mask;      // SRC_INIT: extended bits that must be 0 for a non-zero amplitude
     double rescale;               // multiply every amplitude by this at the end (exact power of 2)

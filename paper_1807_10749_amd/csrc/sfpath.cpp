@@ -256,4 +256,39 @@ int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s)
     return ok();
 }
 
+int describe_plan(sf_circuit_t *c, char *out, size_t cap)
+{
+    return guarded([&]() -> int {
+        if (!c || !out || !cap) return fail(SF_ERR_INVALID, "NULL argument");
+        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
+        std::string s;
+        const int R = c->tuning.reg_qubits ? (int)c->tuning.reg_qubits : 5;
+        const int L = (int)c->levels.size() - 1;
+        s += "k=" + std::to_string(c->k) + " qA=" + std::to_string(c->half[0].q) +
+             " qB=" + std::to_string(c->half[1].q) + " levels=" + std::to_string(L) + "\n";
+        for (int l = 0; l <= L; ++l) {
+            int p = std::min(c->levels[l].bits_after, 20);
+            const int qmin = std::min(c->half[0].q, c->half[1].q);
+            if (qmin + p < 6) p = 6 - qmin;
+            s += "level " + std::to_string(l) + " cycle " + std::to_string(c->levels[l].cycle) +
+                 " bits " + std::to_string(c->levels[l].bits_after) + " p " + std::to_string(p) + ":";
+            for (int h = 0; h < 2; ++h) {
+                const sf::SegmentPlan &sp = sf::get_segment_plan(*c, h, l, p, R);
+                int nd = 0;
+                for (const sf::HalfOp &op : c->half[h].segments[l]) nd += sf::is_diag(op.kind) ? 0 : 1;
+                s += std::string(h ? "  B " : " A ") + std::to_string(c->half[h].segments[l].size()) + " ops (" +
+                     std::to_string(nd) + " non-diag) " + std::to_string(sp.passes.size()) + " passes [";
+                for (size_t i = 0; i < sp.passes.size(); ++i)
+                    s += (i ? "," : "") + std::to_string(sp.passes[i].n_nondiag) + "g/" +
+                         std::to_string(sp.passes[i].groups.size()) + "d";
+                s += "]";
+            }
+            s += "\n";
+        }
+        std::strncpy(out, s.c_str(), cap - 1);
+        out[cap - 1] = 0;
+        return ok();
+    });
+}
+
 }  // extern "C"
