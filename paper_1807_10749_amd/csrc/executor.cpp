@@ -95,12 +95,13 @@ struct Launch {
     size_t plan_off = 0;      // device offset of the pass program inside the plan blob
     uint32_t prog_words = 0, groups_word = 0, terms_word = 0;
     int level = 0;
-    size_t dst_off = 0, src_off = 0;
-    size_t slot_off = 0;      // element offset into the level's node / parent tables
-    uint32_t parent_base = 0;
+    size_t dst_off = 0, src_off = 0;   // buffer offsets inside the buffer region
+    size_t table_off = 0;     // element offset of the batch's slot tables
     unsigned grid = 1;
     uint64_t bytes = 0;
 };
+
+struct BatchRec { int level; size_t table_off; uint64_t slots; };
 
 struct BlobEntry { size_t off; uint32_t words, groups_word, terms_word; };
 
@@ -119,7 +120,8 @@ int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32
         total += next_pow2(std::max<uint64_t>(nodes, 1)) * sigma;
         total += align_up(nodes * 12 + 64 * 12) ;
     }
-    total += align_up(n_bits * 8) * 2 + align_up(n_bits * 16) + (size_t(1) << 22);
+    total += align_up(n_bits * 4) * 5 + align_up(n_bits * 8) + align_up(n_bits * 16) + (size_t(1) << 22);
+    total += align_up(n_bits * 16) + (size_t(1) << 20);   // radix-sort scratch (bound)
     *bytes = total;
     return SF_OK;
 }
@@ -133,22 +135,27 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     const bool fp64 = (flags & SF_FP64_SWEEPS) != 0;
     const bool plain = (flags & SF_PLAIN) != 0;
     const bool timing = (flags & SF_TIMING) != 0;
+    const bool bits_dev = (flags & SF_BITS_ON_DEVICE) != 0;
+    const bool out_dev = (flags & SF_OUT_ON_DEVICE) != 0;
     const size_t elem = fp64 ? 16 : 8;
     const int L = (int)c.levels.size() - 1;
+    const int k = c.k;
     const int qh[2] = {c.half[0].q, c.half[1].q};
     int R = c.tuning.reg_qubits ? (int)c.tuning.reg_qubits : kMaxRegBits;
     R = std::max(1, std::min(R, fp64 ? kMaxRegBitsF64 : kMaxRegBits));
     c.stats = sf_run_stats_t{};
 
-    if (!path_ids && n_paths && c.k < 64 && ((path_begin + n_paths - 1) >> c.k) != 0) {
+    if (!path_ids && n_paths && k < 64 && ((path_begin + n_paths - 1) >> k) != 0) {
         err = "path range exceeds 2^k";
         return SF_ERR_INVALID;
     }
+    if (path_ids)
+        for (uint64_t i = 0; i < n_paths; ++i)
+            if (k < 64 && (path_ids[i] >> k)) { err = "path id >= 2^k"; return SF_ERR_INVALID; }
     const uint64_t all = c.n == 64 ? ~uint64_t(0) : ((uint64_t(1) << c.n) - 1);
-    if (!(flags & SF_BITS_ON_DEVICE)) {
+    if (!bits_dev)
         for (size_t j = 0; j < n_bits; ++j)
             if (bits[j] & ~all) { err = "bitstring has bits outside the grid"; return SF_ERR_INVALID; }
-    }
 
     hipError_t he;
     int dev = 0;
@@ -160,144 +167,97 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
     }
 
-    // ---------------------------------------------------------------- tree
-    // In plain form every path is its own tree (one node per level, no sharing).
-    const uint64_t n_trees = plain ? n_paths : (n_paths ? 1 : 0);
-
-    // min slots so that every block state has at least 6 extended bits (one wave of lanes)
+    // every block state needs at least 6 extended bits (one wave of lanes)
     const int qmin = std::min(qh[0], qh[1]);
     const uint64_t min_slots = qmin >= 6 ? 1 : (uint64_t(1) << (6 - qmin));
+    const size_t sigma = (size_t(1) << qh[0]) * elem + (size_t(1) << qh[1]) * elem;   // bytes per slot, both blocks
 
     // ---------------------------------------------------------------- fixed workspace parts
-    const size_t sigma = (size_t(1) << qh[0]) * elem + (size_t(1) << qh[1]) * elem;
-    const bool bits_dev = (flags & SF_BITS_ON_DEVICE) != 0;
-    const bool out_dev = (flags & SF_OUT_ON_DEVICE) != 0;
     size_t fixed = 0;
     const size_t off_xa = fixed; fixed += align_up(n_bits * 4);
     const size_t off_xb = fixed; fixed += align_up(n_bits * 4);
     const size_t off_bits = fixed; if (!bits_dev) fixed += align_up(n_bits * 8);
     const size_t off_acc = fixed; if (!out_dev) fixed += align_up(n_bits * 16);
     const size_t off_flag = fixed; fixed += kAlign;
+    // visiting order of the bitstrings, sorted by x_A on the device
+    size_t sort_temp = 0;
+    if ((he = sort_by_key_temp_bytes(std::max<uint64_t>(n_bits, 1), &sort_temp)) != hipSuccess) {
+        err = std::string("sort temp size: ") + hipGetErrorString(he);
+        return SF_ERR_DEVICE;
+    }
+    const size_t off_order = fixed; fixed += align_up(n_bits * 4);
+    const size_t off_keys = fixed; fixed += align_up(n_bits * 4);
+    const size_t off_idx = fixed; fixed += align_up(n_bits * 4);
+    const size_t off_sort_tmp = fixed; fixed += align_up(sort_temp);
+    const size_t blob_budget = size_t(1) << 22;
+    const size_t off_blob = fixed; fixed += blob_budget;
 
-    // Builds the launch list for one tree; returns the workspace bytes it needs.
-    struct RunPlan {
-        Tree tree;
-        std::vector<LevelBuf> lb;
-        std::vector<size_t> table_off;        // per level: byte offset of node table, parent table
-        std::vector<size_t> parent_table_off;
-        size_t tables_bytes = 0, buffers_bytes = 0;
-    };
-
-    auto plan_levels = [&](RunPlan &rp, size_t budget) -> int {
-        const Tree &t = rp.tree;
-        rp.lb.assign(L + 1, LevelBuf{});
-        // chain levels (each parent has exactly one child) reuse the parent's buffer in place
-        for (int l = 1; l <= L; ++l)
-            if (t.node[l].size() == t.node[l - 1].size()) rp.lb[l].alias = rp.lb[l - 1].alias >= 0 ? rp.lb[l - 1].alias : l - 1;
-        uint64_t maxs = c.tuning.max_slots ? c.tuning.max_slots : (uint64_t(1) << 20);
-        uint64_t leafmax = c.tuning.leaf_batch ? c.tuning.leaf_batch : maxs;
-        for (int l = 0; l <= L; ++l) {
-            uint64_t want = next_pow2(std::max<uint64_t>(t.node[l].size(), 1));
-            want = std::min(want, l == L ? leafmax : maxs);
-            rp.lb[l].cap = std::max(want, min_slots);
-        }
-        // shrink the largest owned buffers until everything fits
-        for (;;) {
-            for (int l = 1; l <= L; ++l) if (rp.lb[l].alias >= 0) rp.lb[l].cap = rp.lb[rp.lb[l].alias].cap;
-            size_t need = 0;
-            for (int l = 0; l <= L; ++l) if (rp.lb[l].alias < 0) need += rp.lb[l].cap * sigma;
-            if (need + rp.tables_bytes <= budget) { rp.buffers_bytes = need; break; }
-            int big = -1;
-            for (int l = 0; l <= L; ++l)
-                if (rp.lb[l].alias < 0 && rp.lb[l].cap > min_slots && (big < 0 || rp.lb[l].cap >= rp.lb[big].cap)) big = l;
-            if (big < 0) return SF_ERR_OOM;
-            rp.lb[big].cap >>= 1;
-        }
-        return SF_OK;
-    };
-
-    // ---------------------------------------------------------------- workspace
-    std::vector<RunPlan> plans(n_trees ? 1 : 0);
-    int rc;
-    size_t ws_bytes = workspace ? workspace_bytes : 0;
-    if (n_trees) {
-        RunPlan &rp = plans[0];
+    // ---------------------------------------------------------------- tree and batch capacities
+    // In plain form every path is its own one-node-per-level tree, run one after another.
+    Tree tree;
+    std::vector<LevelBuf> lb(L + 1);
+    size_t table_bound = 0;
+    if (n_paths) {
+        int rc;
         if (plain) {
             const uint64_t first = path_ids ? path_ids[0] : path_begin;
-            if ((rc = build_tree(c, &first, 0, 1, rp.tree, err))) return rc;
-            if (path_ids) {
-                for (uint64_t i = 0; i < n_paths; ++i)
-                    if (c.k < 64 && (path_ids[i] >> c.k)) { err = "path id >= 2^k"; return SF_ERR_INVALID; }
-            }
-        } else {
-            if ((rc = build_tree(c, path_ids, path_begin, n_paths, rp.tree, err))) return rc;
+            if ((rc = build_tree(c, &first, 0, 1, tree, err))) return rc;
+        } else if ((rc = build_tree(c, path_ids, path_begin, n_paths, tree, err))) {
+            return rc;
         }
-        rp.tables_bytes = 0;
-        rp.table_off.assign(L + 1, 0);
-        rp.parent_table_off.assign(L + 1, 0);
-    }
-    // tables are padded by the largest batch so padded slots read valid entries
-    auto tables_size = [&](RunPlan &rp) {
-        size_t tb = 0;
+        for (int l = 1; l <= L; ++l)
+            if (tree.node[l].size() == tree.node[l - 1].size()) lb[l].alias = lb[l - 1].alias >= 0 ? lb[l - 1].alias : l - 1;
+        const uint64_t maxs = c.tuning.max_slots ? c.tuning.max_slots : (uint64_t(1) << 20);
+        const uint64_t leafmax = c.tuning.leaf_batch ? c.tuning.leaf_batch : maxs;
         for (int l = 0; l <= L; ++l) {
-            const size_t nn = rp.tree.node[l].size() + rp.lb[l].cap;
-            rp.table_off[l] = tb; tb += align_up(nn * 8);
-            rp.parent_table_off[l] = tb; tb += align_up(nn * 4);
+            uint64_t want = next_pow2(std::max<uint64_t>(tree.node[l].size(), 1));
+            want = std::min(want, l == L ? leafmax : maxs);
+            lb[l].cap = std::max(want, min_slots);
+            // slot tables: at most twice the nodes (power-of-two padding), plus padding to
+            // min_slots for at most one small batch per parent node, plus one padded batch
+            table_bound += 2 * tree.node[l].size() + lb[l].cap + min_slots * (l ? tree.node[l - 1].size() : 1);
         }
-        return tb;
-    };
-
-    size_t plan_blob_budget = size_t(1) << 22;   // grown below if needed
-    if (n_trees) {
-        RunPlan &rp = plans[0];
-        // first guess of the table size with caps of the node counts
-        rp.lb.assign(L + 1, LevelBuf{});
-        for (int l = 0; l <= L; ++l) rp.lb[l].cap = std::max<uint64_t>(next_pow2(std::max<size_t>(rp.tree.node[l].size(), 1)), min_slots);
-        rp.tables_bytes = tables_size(rp);
+        table_bound = align_up(table_bound * 8) + align_up(table_bound * 4);
         size_t budget;
         if (workspace) {
-            if (workspace_bytes < fixed + plan_blob_budget + rp.tables_bytes) { err = "workspace too small"; return SF_ERR_OOM; }
-            budget = workspace_bytes - fixed - plan_blob_budget;
+            if (workspace_bytes < fixed + table_bound) { err = "workspace too small"; return SF_ERR_OOM; }
+            budget = workspace_bytes - fixed - table_bound;
         } else {
             size_t free_b = 0, total_b = 0;
-            if ((he = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) { err = std::string("hipMemGetInfo: ") + hipGetErrorString(he); return SF_ERR_DEVICE; }
+            if ((he = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) return (err = std::string("hipMemGetInfo: ") + hipGetErrorString(he), SF_ERR_DEVICE);
             const size_t avail = c.dev_ws_bytes + (size_t)(0.85 * (double)free_b);
-            if (avail < fixed + plan_blob_budget) { err = "not enough device memory"; return SF_ERR_OOM; }
-            budget = avail - fixed - plan_blob_budget;
+            if (avail < fixed + table_bound) { err = "not enough device memory"; return SF_ERR_OOM; }
+            budget = avail - fixed - table_bound;
         }
-        if ((rc = plan_levels(rp, budget))) { err = "workspace too small for one slot per tree level"; return rc; }
-        rp.tables_bytes = tables_size(rp);
-        ws_bytes = fixed + plan_blob_budget + rp.tables_bytes + rp.buffers_bytes;
-        if (workspace && ws_bytes > workspace_bytes) {
-            // tables grew with the final caps; shrink once more
-            if ((rc = plan_levels(rp, workspace_bytes - fixed - plan_blob_budget))) { err = "workspace too small"; return rc; }
-            rp.tables_bytes = tables_size(rp);
-            ws_bytes = fixed + plan_blob_budget + rp.tables_bytes + rp.buffers_bytes;
-            if (ws_bytes > workspace_bytes) { err = "workspace too small"; return SF_ERR_OOM; }
+        // shrink the largest owned level buffers until all fit
+        for (;;) {
+            for (int l = 1; l <= L; ++l) if (lb[l].alias >= 0) lb[l].cap = lb[lb[l].alias].cap;
+            size_t need = 0;
+            for (int l = 0; l <= L; ++l) if (lb[l].alias < 0) need += align_up(lb[l].cap * (size_t(1) << qh[0]) * elem) + align_up(lb[l].cap * (size_t(1) << qh[1]) * elem);
+            if (need <= budget) break;
+            int big = -1;
+            for (int l = 0; l <= L; ++l)
+                if (lb[l].alias < 0 && lb[l].cap > min_slots && (big < 0 || lb[l].cap >= lb[big].cap)) big = l;
+            if (big < 0) { err = "workspace too small for one slot per tree level"; return SF_ERR_OOM; }
+            lb[big].cap >>= 1;
         }
-    } else {
-        ws_bytes = fixed + kAlign;
+        size_t o = 0;
+        for (int l = 0; l <= L; ++l) {
+            if (lb[l].alias >= 0) continue;
+            for (int h = 0; h < 2; ++h) { lb[l].off[h] = o; o += align_up(lb[l].cap * (size_t(1) << qh[h]) * elem); }
+        }
+        for (int l = 0; l <= L; ++l)
+            if (lb[l].alias >= 0) { lb[l].off[0] = lb[lb[l].alias].off[0]; lb[l].off[1] = lb[lb[l].alias].off[1]; }
     }
+    (void)sigma;
 
-    char *ws = (char *)workspace;
-    if (!ws) {
-        if (c.dev_ws_bytes < ws_bytes) {
-            if (c.dev_ws) { (void)hipFree(c.dev_ws); c.dev_ws = nullptr; c.dev_ws_bytes = 0; }
-            if ((he = hipMalloc(&c.dev_ws, ws_bytes)) != hipSuccess) {
-                err = std::string("hipMalloc: ") + hipGetErrorString(he);
-                return SF_ERR_OOM;
-            }
-            c.dev_ws_bytes = ws_bytes;
-        }
-        ws = (char *)c.dev_ws;
-    }
-    const size_t off_blob = fixed;
-    const size_t off_tables = off_blob + plan_blob_budget;
-
-    // ---------------------------------------------------------------- launch list
+    // ---------------------------------------------------------------- launch list (depth first over batches)
     std::vector<Launch> launches;
+    std::vector<BatchRec> batches;
+    std::vector<uint64_t> tpath;         // per slot of every batch: the node's path id
+    std::vector<uint32_t> tparent;       // per slot: parent slot inside the parent batch
     bool plan_error = false;
-    std::vector<char> blob;                    // host image of the plan blob
+    std::vector<char> blob;
     std::map<const SegmentPlan *, std::vector<BlobEntry>> blob_index;
     std::complex<double> leaf_scale[2];
     for (int h = 0; h < 2; ++h) {
@@ -307,12 +267,6 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
     const std::complex<double> gscale = leaf_scale[0] * leaf_scale[1];
 
-    auto blob_put = [&](const void *p, size_t nbytes) {
-        const size_t o = align_up(blob.size());
-        blob.resize(o + nbytes);
-        if (nbytes) std::memcpy(blob.data() + o, p, nbytes);
-        return o;
-    };
     auto blob_entries = [&](const SegmentPlan &sp) -> const std::vector<BlobEntry> & {
         auto it = blob_index.find(&sp);
         if (it != blob_index.end()) return it->second;
@@ -331,20 +285,31 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             img.insert(img.end(), pp.terms.begin(), pp.terms.end());
             while (img.size() % 4) img.push_back(0);
             e.words = (uint32_t)(img.size() / 4);
-            if (e.words > (uint32_t)kMaxProgWords) { plan_error = true; }
-            e.off = blob_put(img.data(), img.size());
+            if (e.words > (uint32_t)kMaxProgWords) plan_error = true;
+            e.off = align_up(blob.size());
+            blob.resize(e.off + img.size());
+            std::memcpy(blob.data() + e.off, img.data(), img.size());
             v.push_back(e);
         }
         return blob_index.emplace(&sp, std::move(v)).first->second;
     };
 
     const unsigned max_grid = (unsigned)std::max(1, c.device_cus) * (c.tuning.waves_per_cu ? c.tuning.waves_per_cu / 4 : 8);
-    uint64_t n_batches = 0;
+    uint64_t n_leaf_batches = 0;
 
-    // enqueue the passes of segment `level` for one batch of nslots slots
-    auto add_segment = [&](RunPlan &rp, int level, uint64_t nslots, size_t dst_base[2], int src_level,
-                           size_t src_base[2], uint64_t src_slots, size_t slot_first, uint32_t parent_base,
-                           bool first_from_init) {
+    // appends the slot tables of one batch (padded to `slots` entries)
+    auto put_tables = [&](const std::vector<uint64_t> &paths, const std::vector<uint32_t> &parents, uint64_t slots) {
+        const size_t off = tpath.size();
+        for (uint64_t i = 0; i < slots; ++i) {
+            const size_t j = std::min<size_t>(i, paths.size() - 1);
+            tpath.push_back(paths[j]);
+            tparent.push_back(parents[j]);
+        }
+        return off;
+    };
+
+    auto add_segment = [&](int level, uint64_t nslots, const size_t dst[2], int mode, const size_t src[2],
+                           uint64_t src_slots, size_t table_off) {
         const int p = log2u(nslots);
         const int ps = log2u(src_slots);
         for (int h = 0; h < 2; ++h) {
@@ -367,40 +332,39 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 a.p_src = p;
                 a.src_mode = SRC_SAME;
                 a.rescale = std::ldexp(1.0, -pp.rescale_exp);
-                for (int k = 0; k < 6; ++k) a.reg_pos[k] = pp.reg_pos[k];
-                ln.dst_off = dst_base[h];
-                ln.src_off = dst_base[h];
-                if (i == 0 && first_from_init) {
+                for (int kk = 0; kk < 6; ++kk) a.reg_pos[kk] = pp.reg_pos[kk];
+                ln.dst_off = dst[h];
+                ln.src_off = dst[h];
+                if (i == 0 && mode == SRC_INIT) {
                     a.src_mode = SRC_INIT;
                     uint64_t z = 0;
                     for (int t = 0; t < qh[h]; ++t)
                         if (!((c.half[h].init_h_mask >> t) & 1)) z |= uint64_t(1) << (p + t);
                     a.init_zero_mask = z;
-                } else if (i == 0 && src_level >= 0) {
+                } else if (i == 0 && mode == SRC_FANOUT) {
                     a.src_mode = SRC_FANOUT;
                     a.p_src = ps;
-                    ln.src_off = src_base[h];
+                    ln.src_off = src[h];
                 }
-                ln.slot_off = slot_first;
-                ln.parent_base = parent_base;
+                ln.table_off = table_off;
                 ln.plan_off = be[i].off;
                 ln.prog_words = be[i].words;
                 ln.groups_word = be[i].groups_word;
                 ln.terms_word = be[i].terms_word;
-                const uint64_t waves = a.n_tiles;
-                ln.grid = (unsigned)std::min<uint64_t>((waves + 3) / 4, max_grid);
+                ln.grid = (unsigned)std::min<uint64_t>((a.n_tiles + 3) / 4, max_grid);
                 ln.bytes = (uint64_t(1) << n_ext) * elem * (a.src_mode == SRC_INIT ? 1 : 2);
+                if (a.src_mode == SRC_FANOUT)
+                    ln.bytes = (uint64_t(1) << n_ext) * elem + (uint64_t(1) << (ps + qh[h])) * elem;
                 launches.push_back(ln);
             }
         }
     };
 
-    // depth-first over batches
-    std::function<void(RunPlan &, int, uint64_t, uint64_t, uint64_t)> visit;
-    visit = [&](RunPlan &rp, int l, uint64_t lo, uint64_t hi, uint64_t nslots) {
+    // nodes: node indices of this batch in slot order
+    std::function<void(int, const std::vector<uint32_t> &, uint64_t)> visit;
+    visit = [&](int l, const std::vector<uint32_t> &nodes, uint64_t nslots) {
         if (plan_error) return;
-        const LevelBuf &me = rp.lb[l];
-        const int own = me.alias >= 0 ? me.alias : l;
+        const int own = lb[l].alias >= 0 ? lb[l].alias : l;
         if (l == L) {
             Launch ln;
             ln.kind = Launch::GATHER;
@@ -408,74 +372,91 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             GatherArgs &g = ln.ga;
             std::memset(&g, 0, sizeof(g));
             g.n_bits = n_bits;
-            g.n_slots = (uint32_t)(hi - lo);
+            g.n_slots = (uint32_t)nodes.size();
             g.p = log2u(nslots);
             g.scale_re = gscale.real();
             g.scale_im = gscale.imag();
-            ln.dst_off = rp.lb[own].off[0];
-            ln.src_off = rp.lb[own].off[1];
-            ln.bytes = (uint64_t)n_bits * (uint64_t)(hi - lo) * 2 * elem;
+            ln.dst_off = lb[own].off[0];
+            ln.src_off = lb[own].off[1];
+            ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * 2 * elem;
             launches.push_back(ln);
-            ++n_batches;
+            ++n_leaf_batches;
             return;
         }
-        const std::vector<uint64_t> &fc = rp.tree.first_child[l];
-        const uint64_t clo = fc[lo], chi = fc[hi];
-        const LevelBuf &cb = rp.lb[l + 1];
-        if (cb.alias >= 0) {
-            // chain level: same nodes one-to-one, evolve in place
-            size_t base[2] = {rp.lb[own].off[0], rp.lb[own].off[1]};
-            add_segment(rp, l + 1, nslots, base, -1, base, nslots, clo, 0, false);
-            visit(rp, l + 1, clo, chi, nslots);
+        const std::vector<uint64_t> &fc = tree.first_child[l];
+        const std::vector<uint64_t> &cnode = tree.node[l + 1];
+        if (lb[l + 1].alias >= 0) {
+            // chain level: one child per node, evolved in place in the same slots
+            std::vector<uint32_t> ch(nodes.size());
+            std::vector<uint64_t> pv(nodes.size());
+            std::vector<uint32_t> pz(nodes.size(), 0);
+            for (size_t i = 0; i < nodes.size(); ++i) { ch[i] = (uint32_t)fc[nodes[i]]; pv[i] = cnode[ch[i]]; }
+            const size_t toff = put_tables(pv, pz, nslots);
+            batches.push_back(BatchRec{l + 1, toff, nslots});
+            const size_t base[2] = {lb[own].off[0], lb[own].off[1]};
+            add_segment(l + 1, nslots, base, SRC_SAME, base, nslots, toff);
+            visit(l + 1, ch, nslots);
             return;
         }
-        size_t src[2] = {rp.lb[own].off[0], rp.lb[own].off[1]};
-        for (uint64_t a = clo; a < chi; a += cb.cap) {
-            const uint64_t b = std::min(chi, a + cb.cap);
-            const uint64_t ns = std::max<uint64_t>(next_pow2(b - a), min_slots);
-            size_t dst[2] = {cb.off[0], cb.off[1]};
-            add_segment(rp, l + 1, ns, dst, l, src, nslots, a, (uint32_t)lo, false);
-            visit(rp, l + 1, a, b, ns);
+        // children ordered branch-major: (new path bits of the child, parent slot), so that
+        // consecutive slots of one branch value read consecutive parent slots
+        const int shift = k - c.levels[l + 1].bits_after;
+        const uint64_t bmask = (uint64_t(1) << c.levels[l + 1].n_cut) - 1;
+        struct Ch { uint64_t b; uint32_t slot; uint32_t node; };
+        std::vector<Ch> chs;
+        for (size_t i = 0; i < nodes.size(); ++i)
+            for (uint64_t cc = fc[nodes[i]]; cc < fc[nodes[i] + 1]; ++cc)
+                chs.push_back(Ch{shift >= 64 ? 0 : ((cnode[cc] >> shift) & bmask), (uint32_t)i, (uint32_t)cc});
+        std::stable_sort(chs.begin(), chs.end(), [](const Ch &x, const Ch &y) { return x.b != y.b ? x.b < y.b : x.slot < y.slot; });
+        const LevelBuf &cb = lb[l + 1];
+        const size_t src[2] = {lb[own].off[0], lb[own].off[1]};
+        for (size_t a0 = 0; a0 < chs.size(); a0 += cb.cap) {
+            const size_t a1 = std::min(chs.size(), a0 + (size_t)cb.cap);
+            const uint64_t ns = std::max<uint64_t>(next_pow2(a1 - a0), min_slots);
+            std::vector<uint32_t> ch(a1 - a0), par(a1 - a0);
+            std::vector<uint64_t> pv(a1 - a0);
+            for (size_t i = a0; i < a1; ++i) { ch[i - a0] = chs[i].node; par[i - a0] = chs[i].slot; pv[i - a0] = cnode[chs[i].node]; }
+            const size_t toff = put_tables(pv, par, ns);
+            batches.push_back(BatchRec{l + 1, toff, ns});
+            const size_t dst[2] = {cb.off[0], cb.off[1]};
+            add_segment(l + 1, ns, dst, SRC_FANOUT, src, nslots, toff);
+            visit(l + 1, ch, ns);
             if (plan_error) return;
         }
     };
 
-    if (n_trees) {
-        RunPlan &rp = plans[0];
-        size_t o = off_tables + rp.tables_bytes;
-        for (int l = 0; l <= L; ++l) {
-            if (rp.lb[l].alias >= 0) continue;
-            for (int h = 0; h < 2; ++h) {
-                rp.lb[l].off[h] = o;
-                o += align_up(rp.lb[l].cap * (size_t(1) << qh[h]) * elem);
-            }
-        }
-        for (int l = 0; l <= L; ++l)
-            if (rp.lb[l].alias >= 0) { rp.lb[l].off[0] = rp.lb[rp.lb[l].alias].off[0]; rp.lb[l].off[1] = rp.lb[rp.lb[l].alias].off[1]; }
-        // root batch
+    if (n_paths) {
         const uint64_t ns0 = std::max<uint64_t>(1, min_slots);
-        size_t base0[2] = {rp.lb[0].off[0], rp.lb[0].off[1]};
-        add_segment(rp, 0, ns0, base0, -1, base0, ns0, 0, 0, true);
-        visit(rp, 0, 0, 1, ns0);
+        const size_t toff = put_tables(std::vector<uint64_t>{0}, std::vector<uint32_t>{0}, ns0);
+        batches.push_back(BatchRec{0, toff, ns0});
+        const size_t base0[2] = {lb[0].off[0], lb[0].off[1]};
+        add_segment(0, ns0, base0, SRC_INIT, base0, ns0, toff);
+        visit(0, std::vector<uint32_t>{0}, ns0);
     }
     if (plan_error) { err = "internal: a segment could not be scheduled into passes"; return SF_ERR_UNSUPPORTED; }
-    if (blob.size() > plan_blob_budget) { err = "internal: plan blob larger than its reservation"; return SF_ERR_UNSUPPORTED; }
+    if (blob.size() > blob_budget) { err = "internal: pass programs exceed their reservation"; return SF_ERR_UNSUPPORTED; }
+    const size_t tables_bytes = align_up(tpath.size() * 8) + align_up(tparent.size() * 4);
+    if (n_paths && tables_bytes > table_bound) { err = "internal: slot tables exceed their reservation"; return SF_ERR_UNSUPPORTED; }
 
-    // ---------------------------------------------------------------- host images of the tables
-    std::vector<char> tables;
-    if (n_trees) {
-        RunPlan &rp = plans[0];
-        tables.assign(rp.tables_bytes, 0);
-        for (int l = 0; l <= L; ++l) {
-            const std::vector<uint64_t> &nd = rp.tree.node[l];
-            uint64_t *pt = (uint64_t *)(tables.data() + rp.table_off[l]);
-            uint32_t *pp = (uint32_t *)(tables.data() + rp.parent_table_off[l]);
-            const size_t nn = nd.size() + rp.lb[l].cap;
-            for (size_t i = 0; i < nn; ++i) {
-                pt[i] = nd[std::min(i, nd.size() - 1)];
-                pp[i] = l ? rp.tree.parent[l][std::min(i, nd.size() - 1)] : 0;
-            }
+    // ---------------------------------------------------------------- workspace
+    const size_t off_tpath = fixed;
+    const size_t off_tparent = off_tpath + align_up(tpath.size() * 8);
+    const size_t off_buffers = fixed + table_bound;
+    size_t buffers_bytes = 0;
+    for (int l = 0; l <= L; ++l)
+        if (n_paths && lb[l].alias < 0)
+            buffers_bytes = std::max(buffers_bytes, lb[l].off[1] + align_up(lb[l].cap * (size_t(1) << qh[1]) * elem));
+    const size_t ws_bytes = off_buffers + buffers_bytes;
+    char *ws = (char *)workspace;
+    if (ws) {
+        if (ws_bytes > workspace_bytes) { err = "workspace too small"; return SF_ERR_OOM; }
+    } else {
+        if (c.dev_ws_bytes < ws_bytes) {
+            if (c.dev_ws) { (void)hipFree(c.dev_ws); c.dev_ws = nullptr; c.dev_ws_bytes = 0; }
+            if ((he = hipMalloc(&c.dev_ws, ws_bytes)) != hipSuccess) { err = std::string("hipMalloc: ") + hipGetErrorString(he); return SF_ERR_OOM; }
+            c.dev_ws_bytes = ws_bytes;
         }
+        ws = (char *)c.dev_ws;
     }
 
     // ---------------------------------------------------------------- enqueue
@@ -487,6 +468,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     double *d_acc = out_dev ? amps : (double *)(ws + off_acc);
     int *d_flag = (int *)(ws + off_flag);
     uint32_t *d_xa = (uint32_t *)(ws + off_xa), *d_xb = (uint32_t *)(ws + off_xb);
+    uint32_t *d_order = (uint32_t *)(ws + off_order);
 
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_cat;    // 0 sweep, 1 gather, 2 other
@@ -504,53 +486,54 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         if ((he = hipMemcpyAsync((void *)d_bits, bits, n_bits * 8, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy bitstrings", he);
     if (!blob.empty())
         if ((he = hipMemcpyAsync(ws + off_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy plan", he);
-    if (!tables.empty())
-        if ((he = hipMemcpyAsync(ws + off_tables, tables.data(), tables.size(), hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy tables", he);
+    if (!tpath.empty()) {
+        if ((he = hipMemcpyAsync(ws + off_tpath, tpath.data(), tpath.size() * 8, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy tables", he);
+        if ((he = hipMemcpyAsync(ws + off_tparent, tparent.data(), tparent.size() * 4, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy tables", he);
+    }
     {
         hipEvent_t *e = ev_pair(2);
         if (e) (void)hipEventRecord(e[0], stream);
         if ((he = launch_fill_zero_i32(d_flag, 1, stream)) != hipSuccess) return dev_err("fill", he);
         if ((he = launch_pext(d_bits, n_bits, c.mask_a, c.mask_b, all, d_xa, d_xb, d_flag, stream)) != hipSuccess) return dev_err("pext", he);
+        if ((he = launch_order_by_key(d_xa, (uint32_t *)(ws + off_keys), (uint32_t *)(ws + off_idx), d_order, n_bits,
+                                      qh[0], ws + off_sort_tmp, sort_temp, stream)) != hipSuccess)
+            return dev_err("sort", he);
         if (flags & SF_ACCUMULATE) {
             if (!out_dev && n_bits)
                 if ((he = hipMemcpyAsync(d_acc, amps, n_bits * 16, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy amps", he);
-        } else {
-            if ((he = launch_fill_zero(d_acc, 2 * (uint64_t)n_bits, stream)) != hipSuccess) return dev_err("fill", he);
+        } else if ((he = launch_fill_zero(d_acc, 2 * (uint64_t)n_bits, stream)) != hipSuccess) {
+            return dev_err("fill", he);
         }
         if (e) (void)hipEventRecord(e[1], stream);
     }
 
-    const uint64_t trees_to_run = n_trees;
-    for (uint64_t tr = 0; tr < trees_to_run; ++tr) {
-        RunPlan &rp = plans[0];
-        if (plain && tr > 0) {
-            // same launch sequence, slot tables of the next path
-            const uint64_t pid = path_ids ? path_ids[tr] : path_begin + tr;
-            std::vector<char> tb(rp.tables_bytes, 0);
-            for (int l = 0; l <= L; ++l) {
-                const int drop = c.k - c.levels[l].bits_after;
+    char *buf = ws + off_buffers;
+    const uint64_t rounds = n_paths ? (plain ? n_paths : 1) : 0;
+    for (uint64_t r = 0; r < rounds; ++r) {
+        if (plain && r > 0) {
+            // same launch sequence with the slot tables of the next path
+            const uint64_t pid = path_ids ? path_ids[r] : path_begin + r;
+            for (const BatchRec &b : batches) {
+                const int drop = k - c.levels[b.level].bits_after;
                 const uint64_t v = drop >= 64 ? 0 : ((pid >> drop) << drop);
-                uint64_t *pt = (uint64_t *)(tb.data() + rp.table_off[l]);
-                uint32_t *pp = (uint32_t *)(tb.data() + rp.parent_table_off[l]);
-                const size_t nn = 1 + rp.lb[l].cap;
-                for (size_t i = 0; i < nn; ++i) { pt[i] = v; pp[i] = 0; }
+                for (uint64_t i = 0; i < b.slots; ++i) tpath[b.table_off + i] = v;
             }
-            // synchronous copy: the previous path's launches must have consumed the old tables
+            // the previous path's launches must be done with the old tables
             if ((he = hipStreamSynchronize(stream)) != hipSuccess) return dev_err("sync", he);
-            if ((he = hipMemcpy(ws + off_tables, tb.data(), tb.size(), hipMemcpyHostToDevice)) != hipSuccess) return dev_err("copy tables", he);
+            if ((he = hipMemcpy(ws + off_tpath, tpath.data(), tpath.size() * 8, hipMemcpyHostToDevice)) != hipSuccess) return dev_err("copy tables", he);
         }
         for (Launch &ln : launches) {
             if (ln.kind == Launch::PASS) {
                 PassArgs a = ln.pa;
-                a.dst = ws + ln.dst_off;
-                a.src = ws + ln.src_off;
-                a.slot_path = (const uint64_t *)(ws + off_tables + rp.table_off[ln.level]) + ln.slot_off;
-                a.slot_parent = (const uint32_t *)(ws + off_tables + rp.parent_table_off[ln.level]) + ln.slot_off;
+                a.dst = buf + ln.dst_off;
+                a.src = buf + ln.src_off;
+                a.slot_path = (const uint64_t *)(ws + off_tpath) + ln.table_off;
+                a.slot_parent = (const uint32_t *)(ws + off_tparent) + ln.table_off;
+                a.slot_parent_base = 0;
                 a.prog = (const uint32_t *)(ws + off_blob + ln.plan_off);
                 a.prog_words = ln.prog_words;
                 a.groups_word = ln.groups_word;
                 a.terms_word = ln.terms_word;
-                a.slot_parent_base = ln.parent_base;   // parent tables hold level-global indices
                 hipEvent_t *e = ev_pair(0);
                 if (e) (void)hipEventRecord(e[0], stream);
                 if ((he = launch_pass(fp64, ln.R, a, ln.grid, stream)) != hipSuccess) return dev_err("pass", he);
@@ -559,10 +542,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 c.stats.sweep_bytes += ln.bytes;
             } else {
                 GatherArgs g = ln.ga;
-                g.a = ws + ln.dst_off;
-                g.b = ws + ln.src_off;
+                g.a = buf + ln.dst_off;
+                g.b = buf + ln.src_off;
                 g.xa = d_xa;
                 g.xb = d_xb;
+                g.order = d_order;
                 g.acc = d_acc;
                 hipEvent_t *e = ev_pair(1);
                 if (e) (void)hipEventRecord(e[0], stream);
@@ -590,13 +574,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
-    c.stats.n_batches = n_batches * (plain ? n_paths : 1);
-    {
-        uint64_t pa = 0, pb = 0;
-        for (const Launch &ln : launches) if (ln.kind == Launch::PASS) (ln.half ? pb : pa)++;
-        c.stats.n_passes_a = pa;
-        c.stats.n_passes_b = pb;
-    }
+    c.stats.n_batches = n_leaf_batches * (plain ? n_paths : 1);
+    for (const Launch &ln : launches)
+        if (ln.kind == Launch::PASS) (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
     c.stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SF_OK;
 }

@@ -8,6 +8,7 @@
 // register index by the 64 lanes are 64 consecutive complex values (512 B
 // in complex64), i.e. whole cache lines.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include "kernels.hpp"
 
@@ -221,7 +222,9 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 
     // the wave index is uniform across a wave; say so, so tile arithmetic stays in scalar registers
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (uint64_t tile = (uint64_t)blockIdx.x * 4u + wid; tile < a.n_tiles; tile += nwaves) {
+    const bool fan = a.src_mode == SRC_FANOUT;
+    const uint32_t pmax = (1u << a.p_src) - 1u;
+    auto tile_base = [&](uint64_t tile) {
         // wave-uniform part of the extended index: tile bits spread around the register positions
         uint64_t et = tile << 6;
 #pragma unroll
@@ -229,9 +232,23 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
             const int p = pos[k];
             et = ((et >> p) << (p + 1)) | (et & (((uint64_t)1 << p) - 1u));
         }
+        return et;
+    };
+    // per-lane slot tables of a tile are fetched one tile ahead, so the data loads of a
+    // fan-out pass do not wait behind a dependent table load
+    uint64_t tile = (uint64_t)blockIdx.x * 4u + wid;
+    uint64_t nx_sp = 0;
+    uint32_t nx_par = 0;
+    if (tile < a.n_tiles) {
+        const uint64_t slot = (tile_base(tile) | lane) & pmask_dst;
+        nx_sp = a.slot_path[slot];
+        if (fan) nx_par = a.slot_parent[slot];
+    }
+    for (; tile < a.n_tiles; tile += nwaves) {
+        const uint64_t et = tile_base(tile);
         const uint64_t eB = et | (uint64_t)lane;     // this lane's amplitude with register bits 0
-        const uint64_t slot = eB & pmask_dst;
-        const uint64_t sp = a.slot_path ? a.slot_path[slot] : 0u;
+        const uint64_t sp = nx_sp;
+        const uint32_t par = nx_par;
 
         C v[N];
         if (a.src_mode == SRC_INIT) {
@@ -241,10 +258,9 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                 v[j].x = (ej & a.init_zero_mask) ? T(0) : T(1);
                 v[j].y = T(0);
             }
-        } else if (a.src_mode == SRC_FANOUT) {
+        } else if (fan) {
             // parent slot inside the source batch; clamped so padded slots stay in bounds
-            uint32_t ps = a.slot_parent[slot] - a.slot_parent_base;
-            const uint32_t pmax = (1u << a.p_src) - 1u;
+            uint32_t ps = par - a.slot_parent_base;
             ps = ps > pmax ? pmax : ps;
             // source index = ((et >> p_dst) << p_src) + ((lane >> p_dst) << p_src) + ps: the first
             // term is wave-uniform (et has zeros in bits 0..5), the rest a small per-lane offset
@@ -260,6 +276,14 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
             for (int j = 0; j < N; ++j) {
                 const C *row = (const C *)a.src + (et + reg_offset<R>(pos, j, 0, 0));   // uniform
                 v[j] = row[lane];
+            }
+        }
+        {
+            const uint64_t nt = tile + nwaves;
+            if (nt < a.n_tiles) {
+                const uint64_t slot = (tile_base(nt) | lane) & pmask_dst;
+                nx_sp = a.slot_path[slot];
+                if (fan) nx_par = a.slot_parent[slot];
             }
         }
 
@@ -323,8 +347,11 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs g)
     const uint32_t L = P < 64u ? P : 64u;
     const uint32_t G = 64u / L;
     const uint64_t wave = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
-    const uint64_t j = wave * G + (uint32_t)lane / L;
+    const uint64_t jj = wave * G + (uint32_t)lane / L;
     const uint32_t sl = (uint32_t)lane % L;
+    // bitstrings are visited in x_A order when `order` is given, so waves that share a
+    // block-A row run close together and find it in cache
+    const uint64_t j = (jj < g.n_bits && g.order) ? (uint64_t)g.order[jj] : jj;
     double re = 0.0, im = 0.0;
     if (j < g.n_bits) {
         const C *ra = (const C *)g.a + ((uint64_t)g.xa[j] << g.p);
@@ -358,6 +385,32 @@ hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s)
     if (fp64) gather_kernel<double><<<(unsigned)blocks, 256, 0, s>>>(g);
     else gather_kernel<float><<<(unsigned)blocks, 256, 0, s>>>(g);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- x_A ordering of bitstrings
+
+__global__ void iota_kernel(uint32_t *p, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (uint32_t)i;
+}
+
+hipError_t sort_by_key_temp_bytes(uint64_t n, size_t *bytes)
+{
+    *bytes = 0;
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                              (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 32);
+}
+
+hipError_t launch_order_by_key(const uint32_t *keys, uint32_t *keys_sorted, uint32_t *idx, uint32_t *order,
+                               uint64_t n, int key_bits, void *temp, size_t temp_bytes, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    iota_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(idx, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, idx, order, (int)n, 0,
+                                              key_bits < 1 ? 1 : key_bits, s);
 }
 
 // ---------------------------------------------------------------- small helpers

@@ -24,6 +24,12 @@ hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s);
 hipError_t launch_pext(const uint64_t *bits, uint64_t n, uint64_t mask_a, uint64_t mask_b,
                        uint64_t all, uint32_t *xa, uint32_t *xb, int *bad, hipStream_t s);
 
+// order = indices 0..n-1 sorted by keys[i] (stable radix sort over key_bits bits); keys_sorted
+// and idx are n-entry scratch arrays, temp a scratch area of sort_by_key_temp_bytes(n).
+hipError_t sort_by_key_temp_bytes(uint64_t n, size_t *bytes);
+hipError_t launch_order_by_key(const uint32_t *keys, uint32_t *keys_sorted, uint32_t *idx, uint32_t *order,
+                               uint64_t n, int key_bits, void *temp, size_t temp_bytes, hipStream_t s);
+
 // Fill n doubles with zero (a kernel, so it can also sit inside a captured graph).
 hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t s);
 hipError_t launch_fill_zero_i32(int *p, uint64_t n, hipStream_t s);

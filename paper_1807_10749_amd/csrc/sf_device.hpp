@@ -87,6 +87,7 @@ struct GatherArgs {
     const void *a;                // block-A leaf states, 2^(p+qA) complex
     const void *b;                // block-B leaf states, 2^(p+qB) complex
     const uint32_t *xa, *xb;      // per bitstring: x_A, x_B
+    const uint32_t *order;        // visiting order of the bitstrings (NULL = as given)
     double *acc;                  // 2 * n_bits doubles (re, im), accumulated
     uint64_t n_bits;
     uint32_t n_slots;             // real slots (<= 2^p)
