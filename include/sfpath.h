@@ -153,6 +153,25 @@ typedef struct {
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);
 int get_tuning(const sf_circuit_t *c, sf_tuning_t *t);
 
+/*
+ * autotune: choose the tuning for requests shaped like this one.  Every
+ * candidate (register qubits per pass x leaf-batch size x grid size per
+ * compute unit) is first planned without device work and ranked by a cost
+ * model of the form of Section 9, Eq. (t_tot): the planned sweep bytes and
+ * gather bytes over measured bandwidths plus a per-launch cost (the paper's
+ * C1 2^x_p (q1 2^q1 + q2 2^q2)(d_p + C2 2^x_b d_b) + C3 2^(x_p+x_b) n_a
+ * with the constants taken from the device).  The n_measure best-ranked
+ * candidates, plus the current tuning, are then timed with real run_paths
+ * calls on this request (same argument rules as run_paths; amps is
+ * overwritten) and the fastest is kept on the circuit and written to *best.
+ * Results are cached for the process per (block sizes, k, number of paths,
+ * number of bitstrings, flags).
+ */
+int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
+             const uint64_t *bitstrings, size_t n_bits, double *amps, uint32_t flags,
+             void *hip_stream, void *workspace, size_t workspace_bytes, uint32_t n_measure,
+             sf_tuning_t *best);
+
 /* Statistics of the last run_paths call on this circuit. Times are only
  * filled when the run used SF_TIMING. */
 typedef struct {
@@ -181,6 +200,72 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char *last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* Serving: jobs arrive at any time and share one GPU.                 */
+/* ------------------------------------------------------------------ */
+#define SF_PENDING 1   /* server_poll: the job has not finished yet */
+
+typedef struct sf_server sf_server_t;   /* opaque */
+
+/* One request: circuit, cut (0 = choose_cut), host bitstrings, fidelity f.
+ * f >= 1 runs all 2^k paths; 0 < f < 1 runs sample_paths(k, f, path_seed)
+ * (Section 3, Eq. (fid)).  The server copies everything it needs. */
+typedef struct {
+    int rows, cols;
+    const sf_gate_t *gates;
+    size_t n_gates;
+    uint64_t block_a_mask;
+    const uint64_t *bitstrings;
+    size_t n_bits;
+    double f;
+    uint64_t path_seed;
+    uint32_t flags;          /* 0 or SF_FP64_SWEEPS */
+} sf_job_t;
+
+typedef struct {
+    double t_submit, t_admit, t_done;   /* seconds since server_create */
+    uint64_t n_paths;
+    uint32_t k;
+    uint32_t chunks;                    /* path chunks run so far */
+    int status;                         /* SF_PENDING, SF_OK or an error code */
+} sf_job_info_t;
+
+typedef struct {
+    uint64_t arena_bytes, peak_bytes, in_use_bytes;
+    uint64_t chunks;                    /* path chunks run */
+    uint32_t max_concurrent_chunks;     /* most chunks in flight at once */
+    uint32_t waiting, active;           /* jobs not yet admitted / admitted and unfinished */
+} sf_server_stats_t;
+
+/*
+ * server_create: a serving runtime over one device-memory arena of
+ * arena_bytes (caller memory `arena`, or NULL to let the server allocate it)
+ * with n_workers workers (1..16), each owning a HIP stream of default
+ * priority.  A job is admitted when its memory (bitstrings, FP64 partial
+ * sums and a run_paths workspace, in the form of Section 9's M_proc) fits
+ * in the arena; jobs that do not fit wait (later, smaller ones may pass).
+ * Admitted jobs are worked on in chunks of chunk_paths paths (0 = 4096),
+ * round-robin over all admitted jobs, one chunk per job at a time, so jobs
+ * admitted while others run start at once and their kernels overlap on the
+ * device.  Partial sums stay on the device until the job's last chunk.
+ */
+int server_create(size_t arena_bytes, void *arena, uint32_t n_workers, uint64_t chunk_paths,
+                  sf_server_t **out);
+/* server_submit: enqueue a job (host-side setup: cut, path sample); returns at once. */
+int server_submit(sf_server_t *s, const sf_job_t *job, uint64_t *job_id);
+/* server_poll: SF_PENDING while running; SF_OK when done (copies 2*n_bits doubles
+ * into amps if not NULL), or the job's error code. */
+int server_poll(sf_server_t *s, uint64_t job_id, double *amps, sf_job_info_t *info);
+/* server_release: forget a finished job and its host result. */
+int server_release(sf_server_t *s, uint64_t job_id);
+/* server_drain: block until every submitted job has finished. */
+int server_drain(sf_server_t *s);
+int server_stats(sf_server_t *s, sf_server_stats_t *out);
+/* server_destroy: finish running chunks, stop the workers, free the server. */
+int server_destroy(sf_server_t *s);
+/* Message for the last server_* error on the calling thread. */
+const char *server_last_error(void);
 
 #ifdef __cplusplus
 }

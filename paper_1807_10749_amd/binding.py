@@ -19,8 +19,10 @@ SF_OK, SF_ERR_INVALID, SF_ERR_OOM, SF_ERR_UNSUPPORTED, SF_ERR_NO_CUT, SF_ERR_DEV
 SF_ACCUMULATE, SF_OUT_ON_DEVICE, SF_FP64_SWEEPS, SF_PLAIN, SF_BITS_ON_DEVICE, SF_TIMING = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_paths", "sample_paths",
-           "run_paths", "workspace_size", "set_tuning", "get_tuning", "get_run_stats", "describe_plan",
-           "last_error"]
+           "run_paths", "workspace_size", "set_tuning", "get_tuning", "autotune", "get_run_stats",
+           "describe_plan", "last_error", "server_create", "server_submit", "server_poll", "server_release",
+           "server_drain", "server_stats", "server_destroy", "server_last_error"]
+SF_PENDING = 1
 
 
 class SFError(RuntimeError):
@@ -46,6 +48,25 @@ class RunStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int), ("cols", ctypes.c_int), ("gates", ctypes.c_void_p),
+                ("n_gates", ctypes.c_size_t), ("block_a_mask", ctypes.c_uint64), ("bitstrings", ctypes.c_void_p),
+                ("n_bits", ctypes.c_size_t), ("f", ctypes.c_double), ("path_seed", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("n_paths", ctypes.c_uint64), ("k", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
+                ("status", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64), ("in_use_bytes", ctypes.c_uint64),
+                ("chunks", ctypes.c_uint64), ("max_concurrent_chunks", ctypes.c_uint32),
+                ("waiting", ctypes.c_uint32), ("active", ctypes.c_uint32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1807_10749_amd.build")
@@ -64,9 +85,18 @@ def _load():
     lib.get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.get_run_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
     lib.describe_plan.argtypes = [vp, ctypes.c_char_p, sz]
+    lib.autotune.argtypes = [vp, vp, u64, u64, vp, sz, vp, u32, vp, vp, sz, u32, ctypes.POINTER(Tuning)]
+    lib.server_create.argtypes = [sz, vp, u32, u64, ctypes.POINTER(vp)]
+    lib.server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
+    lib.server_poll.argtypes = [vp, u64, vp, ctypes.POINTER(JobInfo)]
+    lib.server_release.argtypes = [vp, u64]
+    lib.server_drain.argtypes = [vp]
+    lib.server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.server_destroy.argtypes = [vp]
+    lib.server_last_error.restype = ctypes.c_char_p
     lib.last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name != "last_error":
+        if name not in ("last_error", "server_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -171,6 +201,18 @@ def get_tuning(c: int) -> dict:
     return {name: getattr(t, name) for name, _ in Tuning._fields_}
 
 
+def autotune(c: int, path_ids, path_begin: int, n_paths: int, bitstrings, n_bits: int, amps, flags: int = 0,
+             stream=None, workspace=None, workspace_bytes: int = 0, n_measure: int = 6) -> dict:
+    ids = None
+    if path_ids is not None:
+        ids = np.ascontiguousarray(path_ids, dtype=np.uint64)
+        n_paths = ids.size
+    t = Tuning()
+    _check(lib.autotune(c, _ptr(ids), path_begin, n_paths, _ptr(bitstrings), n_bits, _ptr(amps), flags,
+                        _stream_handle(stream), _ptr(workspace), workspace_bytes, n_measure, ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in Tuning._fields_}
+
+
 def get_run_stats(c: int) -> dict:
     s = RunStats()
     _check(lib.get_run_stats(c, ctypes.byref(s)))
@@ -181,6 +223,62 @@ def describe_plan(c: int) -> str:
     buf = ctypes.create_string_buffer(1 << 16)
     _check(lib.describe_plan(c, buf, len(buf)))
     return buf.value.decode()
+
+
+def server_last_error() -> str:
+    return lib.server_last_error().decode()
+
+
+def _scheck(rc: int):
+    if rc not in (SF_OK, SF_PENDING):
+        raise SFError(rc, server_last_error())
+    return rc
+
+
+def server_create(arena_bytes: int, arena=None, n_workers: int = 4, chunk_paths: int = 0) -> int:
+    out = ctypes.c_void_p()
+    _scheck(lib.server_create(arena_bytes, _ptr(arena), n_workers, chunk_paths, ctypes.byref(out)))
+    return out.value
+
+
+def server_submit(s: int, rows: int, cols: int, gates: np.ndarray, bitstrings: np.ndarray, f: float = 1.0,
+                  path_seed: int = 0, block_a_mask: int = 0, flags: int = 0) -> int:
+    g = np.ascontiguousarray(gates)
+    b = np.ascontiguousarray(bitstrings, dtype=np.uint64)
+    job = Job(rows, cols, g.ctypes.data, g.size, block_a_mask, b.ctypes.data if b.size else None, b.size, f,
+              path_seed, flags)
+    jid = ctypes.c_uint64()
+    _scheck(lib.server_submit(s, ctypes.byref(job), ctypes.byref(jid)))
+    return jid.value
+
+
+def server_poll(s: int, job_id: int, n_bits: Optional[int] = None):
+    """(done, amplitudes or None, info dict)."""
+    info = JobInfo()
+    amps = np.zeros(2 * max(n_bits or 0, 1)) if n_bits is not None else None
+    rc = _scheck(lib.server_poll(s, job_id, _ptr(amps), ctypes.byref(info)))
+    d = {name: getattr(info, name) for name, _ in JobInfo._fields_}
+    if rc == SF_PENDING:
+        return False, None, d
+    return True, (amps.view(np.complex128)[: n_bits] if amps is not None else None), d
+
+
+def server_release(s: int, job_id: int):
+    _scheck(lib.server_release(s, job_id))
+
+
+def server_drain(s: int):
+    _scheck(lib.server_drain(s))
+
+
+def server_stats(s: int) -> dict:
+    st = ServerStats()
+    _scheck(lib.server_stats(s, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+
+def server_destroy(s: int):
+    _scheck(lib.server_destroy(s))
 
 
 # ---------------------------------------------------------------- convenience wrapper

@@ -128,7 +128,7 @@ int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32
 
 int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
             const uint64_t *bits, size_t n_bits, double *amps, uint32_t flags, void *stream_v,
-            void *workspace, size_t workspace_bytes, std::string &err)
+            void *workspace, size_t workspace_bytes, std::string &err, bool dry_run)
 {
     const auto t_start = std::chrono::steady_clock::now();
     hipStream_t stream = (hipStream_t)stream_v;
@@ -153,7 +153,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         for (uint64_t i = 0; i < n_paths; ++i)
             if (k < 64 && (path_ids[i] >> k)) { err = "path id >= 2^k"; return SF_ERR_INVALID; }
     const uint64_t all = c.n == 64 ? ~uint64_t(0) : ((uint64_t(1) << c.n) - 1);
-    if (!bits_dev)
+    if (!bits_dev && !dry_run)
         for (size_t j = 0; j < n_bits; ++j)
             if (bits[j] & ~all) { err = "bitstring has bits outside the grid"; return SF_ERR_INVALID; }
 
@@ -436,6 +436,21 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     if (plan_error) { err = "internal: a segment could not be scheduled into passes"; return SF_ERR_UNSUPPORTED; }
     if (blob.size() > blob_budget) { err = "internal: pass programs exceed their reservation"; return SF_ERR_UNSUPPORTED; }
     const size_t tables_bytes = align_up(tpath.size() * 8) + align_up(tparent.size() * 4);
+    if (dry_run) {
+        const uint64_t rounds = n_paths ? (plain ? n_paths : 1) : 0;
+        for (const Launch &ln : launches) {
+            if (ln.kind == Launch::PASS) {
+                c.stats.n_sweep_launches += rounds;
+                c.stats.sweep_bytes += rounds * ln.bytes;
+                (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
+            } else {
+                c.stats.n_gather_launches += rounds;
+                c.stats.gather_bytes += rounds * ln.bytes;
+            }
+        }
+        c.stats.n_batches = n_leaf_batches * rounds;
+        return SF_OK;
+    }
     if (n_paths && tables_bytes > table_bound) { err = "internal: slot tables exceed their reservation"; return SF_ERR_UNSUPPORTED; }
 
     // ---------------------------------------------------------------- workspace

@@ -89,9 +89,11 @@ int build_programs(Circuit &c, std::string &err);
 const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R);
 
 // executor.cpp
+// dry_run: plan the request (tree, batches, passes) and fill the launch and byte counts of
+// c.stats without touching device memory.
 int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
             const uint64_t *bits, size_t n_bits, double *amps, uint32_t flags, void *stream,
-            void *workspace, size_t workspace_bytes, std::string &err);
+            void *workspace, size_t workspace_bytes, std::string &err, bool dry_run = false);
 int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32_t flags, size_t *bytes);
 
 }  // namespace sf

@@ -3,8 +3,11 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_set>
@@ -247,6 +250,87 @@ int get_tuning(const sf_circuit_t *c, sf_tuning_t *t)
     if (!c || !t) return fail(SF_ERR_INVALID, "NULL argument");
     *t = c->tuning;
     return ok();
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, sf_tuning_t> g_tune_cache;
+
+// Effective rates of the cost model (bytes/s, s per launch) on one MI355X, from
+// measured pass and gather kernels; only the ranking of candidates depends on them.
+constexpr double kSweepRate = 5.0e12, kGatherRate = 6.0e12, kLaunchCost = 4e-6;
+}  // namespace
+
+int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
+             const uint64_t *bitstrings, size_t n_bits, double *amps, uint32_t flags, void *hip_stream,
+             void *workspace, size_t workspace_bytes, uint32_t n_measure, sf_tuning_t *best)
+{
+    return guarded([&]() -> int {
+        if (!c || !best) return fail(SF_ERR_INVALID, "NULL argument");
+        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
+        if (flags & ~uint32_t(63)) return fail(SF_ERR_INVALID, "unknown flag");
+        const bool fp64 = (flags & SF_FP64_SWEEPS) != 0;
+        const std::string key = std::to_string(c->half[0].q) + "/" + std::to_string(c->half[1].q) + "/" +
+                                std::to_string(c->k) + "/" + std::to_string(c->levels.size()) + "/" +
+                                std::to_string(n_paths) + "/" + std::to_string(n_bits) + "/" +
+                                std::to_string(flags & (SF_FP64_SWEEPS | SF_PLAIN));
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                c->tuning = it->second;
+                *best = it->second;
+                return ok();
+            }
+        }
+        const sf_tuning_t start = c->tuning;
+        std::vector<sf_tuning_t> cands;
+        const uint32_t regs[3] = {fp64 ? 4u : 5u, fp64 ? 3u : 4u, fp64 ? 2u : 3u};
+        const uint32_t leafs[4] = {0u, 4096u, 1024u, 256u};
+        const uint32_t wpcs[3] = {32u, 16u, 64u};
+        for (uint32_t r : regs)
+            for (uint32_t lf : leafs)
+                for (uint32_t w : wpcs) cands.push_back(sf_tuning_t{r, lf, 0, w});
+        // rank by the planned cost
+        std::vector<std::pair<double, size_t>> ranked;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            c->tuning = cands[i];
+            std::string err;
+            if (sf::execute(*c, path_ids, path_begin, n_paths, bitstrings, n_bits, amps, flags, hip_stream, workspace,
+                            workspace_bytes, err, true))
+                continue;
+            const sf_run_stats_t &st = c->stats;
+            const double model = (double)st.sweep_bytes / kSweepRate + (double)st.gather_bytes / kGatherRate +
+                                 (double)(st.n_sweep_launches + st.n_gather_launches) * kLaunchCost;
+            ranked.push_back({model, i});
+        }
+        if (ranked.empty()) { c->tuning = start; return fail(SF_ERR_UNSUPPORTED, "no tuning candidate could be planned"); }
+        std::sort(ranked.begin(), ranked.end());
+        std::vector<sf_tuning_t> measure;
+        measure.push_back(start);
+        for (size_t i = 0; i < ranked.size() && measure.size() < (size_t)std::max(1u, n_measure) + 1; ++i)
+            measure.push_back(cands[ranked[i].second]);
+        double best_t = 1e300;
+        sf_tuning_t best_t_cfg = start;
+        for (const sf_tuning_t &t : measure) {
+            c->tuning = t;
+            double tmin = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                std::string err;
+                const auto t0 = std::chrono::steady_clock::now();
+                const int rc = sf::execute(*c, path_ids, path_begin, n_paths, bitstrings, n_bits, amps, flags, hip_stream,
+                                           workspace, workspace_bytes, err);
+                if (rc) { c->tuning = start; return fail(rc, err); }
+                tmin = std::min(tmin, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            }
+            if (tmin < best_t) { best_t = tmin; best_t_cfg = t; }
+        }
+        c->tuning = best_t_cfg;
+        *best = best_t_cfg;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best_t_cfg;
+        return ok();
+    });
 }
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s)
