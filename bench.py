@@ -33,6 +33,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-paths", type=int, default=64)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving mix (0 = skip)")
+    ap.add_argument("--tuning", default="", help="fixed tuning R,leaf_batch,waves_per_cu (skips autotune)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (known HBM traffic for counter scaling)")
     return ap.parse_args()
 
 
@@ -44,6 +49,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.calibrate_copy:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": x.numel(), "calibrate_copy_bytes_written": y.numel()}))
+        return
     from paper_1807_10749_amd import binding as sf
     from workload import CONFIGS, make_workload, path_block
 
@@ -74,6 +87,15 @@ def main():
 
     def step(extra=0):
         sf.run_paths(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags | extra, stream, ws, ws_bytes)
+
+    tuning = None
+    if args.tuning:
+        r, lb, wpc = (int(v) for v in args.tuning.split(","))
+        sf.set_tuning(c.handle, reg_qubits=r, leaf_batch=lb, waves_per_cu=wpc)
+        tuning = sf.get_tuning(c.handle)
+    elif not args.no_autotune:
+        tuning = sf.autotune(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,
+                             n_measure=6)
 
     for _ in range(args.warmup):
         step()
@@ -106,14 +128,21 @@ def main():
     achieved = (dom_bytes / max(dom_n, 1)) / (avg_launch_ms * 1e-3) / 1e9 if dom_n else 0.0
 
     # plain one-path-per-launch GPU form on a subset of the same paths
+    plain = None
     plain_n = min(args.plain_paths, npaths)
-    plain_ids = ids[:plain_n] if ids is not None else None
-    sf.run_paths(c.handle, plain_ids, begin, plain_n, d_bits, bits.size, d_amps, flags | sf.SF_PLAIN, stream, ws, ws_bytes)
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    sf.run_paths(c.handle, plain_ids, begin, plain_n, d_bits, bits.size, d_amps, flags | sf.SF_PLAIN, stream, ws, ws_bytes)
-    torch.cuda.synchronize()
-    plain_paths_per_s = plain_n / (time.perf_counter() - tp)
+    if plain_n > 0:
+        plain_ids = ids[:plain_n] if ids is not None else None
+        sf.run_paths(c.handle, plain_ids, begin, plain_n, d_bits, bits.size, d_amps, flags | sf.SF_PLAIN, stream, ws,
+                     ws_bytes)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        sf.run_paths(c.handle, plain_ids, begin, plain_n, d_bits, bits.size, d_amps, flags | sf.SF_PLAIN, stream, ws,
+                     ws_bytes)
+        torch.cuda.synchronize()
+        plain_paths_per_s = plain_n / (time.perf_counter() - tp)
+        plain = {"paths_per_s": plain_paths_per_s, "paths": plain_n, "speedup_of_batched": paths_per_s / plain_paths_per_s}
+
+    serving = serving_bench(args.serve_jobs) if args.serve_jobs > 0 else None
 
     cpu = None
     if not args.no_cpu:
@@ -135,19 +164,109 @@ def main():
         "config": {"workload": args.workload, "grid": f"{cfg.rows}x{cfg.cols}", "depth": f"1+{cfg.depth}+1",
                    "cut": f"{bin(cfg.cut_mask()).count('1')}+{n - bin(cfg.cut_mask()).count('1')}",
                    "k": c.k, "paths": npaths, "f": cfg.f if cfg.paths == "sample" else npaths / 2.0 ** c.k,
-                   "bitstrings": int(bits.size)},
+                   "bitstrings": int(bits.size), "tuning": tuning or sf.get_tuning(c.handle)},
         "amps_per_s": amps_per_s,
-        "plain_form": {"paths_per_s": plain_paths_per_s, "paths": plain_n,
-                       "speedup_of_batched": paths_per_s / plain_paths_per_s},
+        "plain_form": plain,
         "kernel_ms_per_step": {"sweep": sweep_ms / args.steps, "gather": gather_ms / args.steps},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_ms": avg_launch_ms, "launches_per_step": dom_n / args.steps,
                      "bytes_per_launch": dom_bytes / max(dom_n, 1)},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     c.close()
+
+
+def serving_bench(n_jobs, workers=4, chunk_paths=16384, seed=5005):
+    """Serving mix: Poisson arrivals at 0.7 of the sequential service rate.
+
+    Jobs (grid 4x5..6x6, depth 1+16+1..1+32+1, 1e3..1e5 bitstrings, f in
+    {0.01, 0.1, 1}) are served by the library's server (continuous batching over
+    `workers` streams).  References on the same jobs: the batched form run one
+    job at a time, and the plain one-path-per-launch form run one job at a time
+    (timed on up to 8 paths per job and scaled to the job's path count).
+    """
+    import math
+    from paper_1807_10749_amd import binding as sf
+    from workload import SplitMix64, grid_circuit, random_bitstrings, serving_mix
+
+    specs = serving_mix(n_jobs, seed)
+    inputs = []
+    for j in specs:
+        g = grid_circuit(j["rows"], j["cols"], j["depth"], j["circuit_seed"])
+        b = random_bitstrings(j["rows"] * j["cols"], j["n_bits"], j["bits_seed"])
+        inputs.append((g, b))
+    arena = 32 << 30
+
+    def submit(srv, i):
+        j = specs[i]
+        g, b = inputs[i]
+        return sf.server_submit(srv, j["rows"], j["cols"], g, b, f=j["f"], path_seed=j["path_seed"])
+
+    # one job at a time (batched form)
+    srv = sf.server_create(arena, None, 1, chunk_paths)
+    seq_res, seq_t, n_paths = [], [], []
+    for i in range(n_jobs):
+        jid = submit(srv, i)
+        sf.server_drain(srv)
+        done, a, info = sf.server_poll(srv, jid, specs[i]["n_bits"])
+        seq_res.append(a.copy())
+        seq_t.append(info["t_done"] - info["t_admit"])
+        n_paths.append(info["n_paths"])
+        sf.server_release(srv, jid)
+    sf.server_destroy(srv)
+    total_paths = sum(n_paths)
+    mean_s = sum(seq_t) / n_jobs
+
+    # plain form, one job at a time, timed on a few paths per job
+    plain_total = 0.0
+    for i, j in enumerate(specs):
+        g, b = inputs[i]
+        c = sf.Circuit(j["rows"], j["cols"], g)
+        m = min(8, n_paths[i])
+        ids = (np.arange(m, dtype=np.uint64) if j["f"] >= 1 else sf.sample_paths(c.k, j["f"], j["path_seed"])[:m])
+        t0 = time.perf_counter()
+        c.amplitudes(b, path_ids=ids, flags=sf.SF_PLAIN)
+        plain_total += (time.perf_counter() - t0) / m * n_paths[i]
+        c.close()
+
+    # served: Poisson arrivals at 0.7 of the sequential service rate
+    rate = 0.7 / mean_s
+    rng = SplitMix64(seed + 1)
+    arrivals, t = [], 0.0
+    for _ in range(n_jobs):
+        u = ((rng.next() >> 11) + 1) * (1.0 / (1 << 53))
+        t += -math.log(u) / rate
+        arrivals.append(t)
+    srv = sf.server_create(arena, None, workers, chunk_paths)
+    t0 = time.perf_counter()
+    jids = []
+    for i in range(n_jobs):
+        dt = arrivals[i] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        jids.append(submit(srv, i))
+    sf.server_drain(srv)
+    lat, first, last, dev = [], 1e300, 0.0, 0.0
+    for i, jid in enumerate(jids):
+        done, a, info = sf.server_poll(srv, jid, specs[i]["n_bits"])
+        lat.append(info["t_done"] - info["t_submit"])
+        first, last = min(first, info["t_submit"]), max(last, info["t_done"])
+        ref = seq_res[i]
+        dev = max(dev, float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)))
+    st = sf.server_stats(srv)
+    sf.server_destroy(srv)
+    lat.sort()
+    pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+    return {"jobs": n_jobs, "workers": workers, "arrival_rate_jobs_per_s": rate, "total_paths": total_paths,
+            "p50_latency_ms": 1e3 * pct(0.50), "p99_latency_ms": 1e3 * pct(0.99),
+            "served_paths_per_s": total_paths / (last - first), "makespan_s": last - first,
+            "sequential_paths_per_s": total_paths / sum(seq_t),
+            "plain_sequential_paths_per_s": total_paths / plain_total, "plain_extrapolated": True,
+            "max_concurrent_chunks": st["max_concurrent_chunks"], "peak_arena_bytes": st["peak_bytes"],
+            "alone_vs_mix_max_rel_diff": dev}
 
 
 def cpu_baseline(cfg, gates, bits, k, ids, begin, npaths, budget_s):

@@ -309,7 +309,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     };
 
     auto add_segment = [&](int level, uint64_t nslots, const size_t dst[2], int mode, const size_t src[2],
-                           uint64_t src_slots, size_t table_off) {
+                           uint64_t src_slots, size_t table_off, int n_low = 0, int low_first = 0) {
         const int p = log2u(nslots);
         const int ps = log2u(src_slots);
         for (int h = 0; h < 2; ++h) {
@@ -333,6 +333,19 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 a.src_mode = SRC_SAME;
                 a.rescale = std::ldexp(1.0, -pp.rescale_exp);
                 for (int kk = 0; kk < 6; ++kk) a.reg_pos[kk] = pp.reg_pos[kk];
+                {
+                    // sibling bits as the lowest tile bits (first pass of a regular fan-out only)
+                    std::vector<int> skip(pp.reg_pos, pp.reg_pos + pp.R);
+                    a.n_low = 0;
+                    if (i == 0 && mode == SRC_FANOUT && n_low > 0)
+                        for (int t = 0; t < n_low; ++t) {
+                            a.low_pos[a.n_low++] = low_first + t;
+                            skip.push_back(low_first + t);
+                        }
+                    std::sort(skip.begin(), skip.end());
+                    a.n_skip = (int)skip.size();
+                    for (size_t t = 0; t < skip.size(); ++t) a.skip_pos[t] = skip[t];
+                }
                 ln.dst_off = dst[h];
                 ln.src_off = dst[h];
                 if (i == 0 && mode == SRC_INIT) {
@@ -410,16 +423,25 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         std::stable_sort(chs.begin(), chs.end(), [](const Ch &x, const Ch &y) { return x.b != y.b ? x.b < y.b : x.slot < y.slot; });
         const LevelBuf &cb = lb[l + 1];
         const size_t src[2] = {lb[own].off[0], lb[own].off[1]};
+        // regular fan-out: every parent slot has all 2^n_cut children and the parent batch is
+        // unpadded, so chunk slot = (branch value - first) * nslots + parent slot
+        const bool regular = nodes.size() == nslots && nslots >= 64 &&
+                             chs.size() == nodes.size() << c.levels[l + 1].n_cut;
         for (size_t a0 = 0; a0 < chs.size(); a0 += cb.cap) {
             const size_t a1 = std::min(chs.size(), a0 + (size_t)cb.cap);
             const uint64_t ns = std::max<uint64_t>(next_pow2(a1 - a0), min_slots);
+            int n_low = 0;
+            if (regular && (a1 - a0) % nslots == 0 && a0 % nslots == 0) {
+                const uint64_t sib = (a1 - a0) / nslots;           // branch values in this chunk
+                if ((sib & (sib - 1)) == 0) n_low = std::min(3, log2u(sib));
+            }
             std::vector<uint32_t> ch(a1 - a0), par(a1 - a0);
             std::vector<uint64_t> pv(a1 - a0);
             for (size_t i = a0; i < a1; ++i) { ch[i - a0] = chs[i].node; par[i - a0] = chs[i].slot; pv[i - a0] = cnode[chs[i].node]; }
             const size_t toff = put_tables(pv, par, ns);
             batches.push_back(BatchRec{l + 1, toff, ns});
             const size_t dst[2] = {cb.off[0], cb.off[1]};
-            add_segment(l + 1, ns, dst, SRC_FANOUT, src, nslots, toff);
+            add_segment(l + 1, ns, dst, SRC_FANOUT, src, nslots, toff, n_low, log2u(nslots));
             visit(l + 1, ch, ns);
             if (plan_error) return;
         }

@@ -225,13 +225,14 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     const bool fan = a.src_mode == SRC_FANOUT;
     const uint32_t pmax = (1u << a.p_src) - 1u;
     auto tile_base = [&](uint64_t tile) {
-        // wave-uniform part of the extended index: tile bits spread around the register positions
-        uint64_t et = tile << 6;
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int p = pos[k];
+        // wave-uniform part of the extended index: the low tile bits go to low_pos, the rest
+        // is spread around the register and low positions
+        uint64_t et = (tile >> a.n_low) << 6;
+        for (int k = 0; k < a.n_skip; ++k) {
+            const int p = a.skip_pos[k];
             et = ((et >> p) << (p + 1)) | (et & (((uint64_t)1 << p) - 1u));
         }
+        for (int k = 0; k < a.n_low; ++k) et |= ((tile >> k) & 1u) << a.low_pos[k];
         return et;
     };
     // per-lane slot tables of a tile are fetched one tile ahead, so the data loads of a

@@ -81,6 +81,13 @@ struct PassArgs {
     int32_t p_dst, p_src;         // slot bits of destination and source
     int32_t src_mode;
     int32_t reg_pos[6];           // extended bit positions of register bits, ascending
+    // Tile enumeration: the n_low lowest bits of a tile index go to extended bits low_pos[]
+    // (sibling bits of a fan-out, so the children of one parent are handled by neighbouring
+    // waves and the parent is read from cache), the other tile bits fill the remaining free
+    // bits in ascending order.  skip_pos = register and low positions, ascending.
+    int32_t n_low, n_skip;
+    int32_t low_pos[4];
+    int32_t skip_pos[10];
 };
 
 struct GatherArgs {

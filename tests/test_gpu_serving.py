@@ -124,7 +124,7 @@ def test_autotune_keeps_parity(sf):
     amps = np.zeros(2 * bits.size)
     say("autotune grid5x6_d24, 1024 paths")
     t = sf.autotune(c.handle, ids, 0, ids.size, bits, bits.size, amps, n_measure=3)
-    assert 1 <= t["reg_qubits"] <= 5
+    assert 0 <= t["reg_qubits"] <= 5   # 0 = library default
     a = c.amplitudes(bits, path_ids=ids)
     o = oracle.path_sum(30, g, cfg.cut_mask(), ids, bits)
     floor = (ids.size / 2.0 ** c.k) * 2.0 ** (-30)

@@ -9,5 +9,5 @@ from .generator import (  # noqa: F401
     GATE_DTYPE, H, XH, YH, T, CZ, GATE_NAMES,
     SplitMix64, splitmix64_array,
     cz_pattern_edges, grid_circuit, random_bitstrings, path_block,
-    column_cut_mask, row_cut_mask, CONFIGS, WorkloadConfig, make_workload,
+    column_cut_mask, row_cut_mask, CONFIGS, WorkloadConfig, make_workload, serving_mix,
 )

@@ -236,3 +236,27 @@ def make_workload(name: str, n_bits: Optional[int] = None) -> dict:
     nb = cfg.n_bits if n_bits is None else n_bits
     bits = random_bitstrings(cfg.n_qubits, nb, cfg.bits_seed)
     return {"cfg": cfg, "gates": gates, "mask_a": cfg.cut_mask(), "bitstrings": bits}
+
+
+def serving_mix(n_jobs: int, seed: int):
+    """Jobs of the serving workload: grid rows in {4,5,6}, cols in {5,6}, depth
+    1+D+1 with D uniform in 16..32, a bitstring count log-uniform in 1e3..1e5 and
+    fidelity f uniform in {0.01, 0.1, 1}; every choice is a SplitMix64 draw."""
+    rng = SplitMix64(seed)
+
+    def uniform_int(lo, hi):   # inclusive
+        return lo + (rng.next() * (hi - lo + 1) >> 64)
+
+    def uniform01():
+        return (rng.next() >> 11) * (1.0 / (1 << 53))
+
+    jobs = []
+    for i in range(n_jobs):
+        rows = uniform_int(4, 6)
+        cols = uniform_int(5, 6)
+        depth = uniform_int(16, 32)
+        n_bits = int(round(10 ** (3 + 2 * uniform01())))
+        f = (0.01, 0.1, 1.0)[uniform_int(0, 2)]
+        jobs.append({"rows": rows, "cols": cols, "depth": depth, "n_bits": n_bits, "f": f,
+                     "circuit_seed": 10_000 + i, "bits_seed": 20_000 + i, "path_seed": 30_000 + i})
+    return jobs
