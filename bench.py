@@ -126,6 +126,7 @@ def main():
         dom, dom_ms, dom_n, dom_bytes = "gather_kernel (path sum)", gather_ms, gather_launches, gather_bytes
     avg_launch_ms = dom_ms / max(dom_n, 1)
     achieved = (dom_bytes / max(dom_n, 1)) / (avg_launch_ms * 1e-3) / 1e9 if dom_n else 0.0
+    traffic = measured_traffic(args.workload, "pass_kernel" if dom.startswith("pass") else "gather_kernel")
 
     # plain one-path-per-launch GPU form on a subset of the same paths
     plain = None
@@ -169,7 +170,7 @@ def main():
         "plain_form": plain,
         "kernel_ms_per_step": {"sweep": sweep_ms / args.steps, "gather": gather_ms / args.steps},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_launch_ms, "launches_per_step": dom_n / args.steps,
                      "bytes_per_launch": dom_bytes / max(dom_n, 1)},
         "cpu_baseline": cpu,
@@ -177,6 +178,21 @@ def main():
     }
     print(json.dumps(out), flush=True)
     c.close()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of
+    this workload, or None if there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1807_10749_amd", "csrc", "kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes_per_launch"]
 
 
 def serving_bench(n_jobs, workers=4, chunk_paths=16384, seed=5005):
