@@ -148,6 +148,9 @@ typedef struct {
     uint32_t leaf_batch;     /* max paths per leaf batch (power of two) */
     uint32_t max_slots;      /* max slots of any batch (power of two) */
     uint32_t waves_per_cu;   /* persistent-grid size per compute unit */
+    uint32_t dense_qubits;   /* 0: gates on registers and lanes only; 2..4: also fuse windows of up to
+                                this many qubits into dense 16 x 16 blocks applied on matrix cores
+                                (complex64 sweeps only) */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);

@@ -33,7 +33,8 @@ class SFError(RuntimeError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("reg_qubits", ctypes.c_uint32), ("leaf_batch", ctypes.c_uint32),
-                ("max_slots", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32)]
+                ("max_slots", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
+                ("dense_qubits", ctypes.c_uint32)]
 
 
 class RunStats(ctypes.Structure):
@@ -190,8 +191,8 @@ def workspace_size(c: int, n_paths: int, n_bits: int, flags: int = 0) -> int:
     return b.value
 
 
-def set_tuning(c: int, reg_qubits=0, leaf_batch=0, max_slots=0, waves_per_cu=0):
-    t = Tuning(reg_qubits, leaf_batch, max_slots, waves_per_cu)
+def set_tuning(c: int, reg_qubits=0, leaf_batch=0, max_slots=0, waves_per_cu=0, dense_qubits=0):
+    t = Tuning(reg_qubits, leaf_batch, max_slots, waves_per_cu, dense_qubits)
     _check(lib.set_tuning(c, ctypes.byref(t)))
 
 

@@ -87,7 +87,8 @@ struct LevelBuf {
 };
 
 struct Launch {
-    enum Kind { PASS, GATHER } kind;
+    enum Kind { PASS, GATHER, DENSE } kind;
+    DenseArgs da{};
     int half = 0;
     int R = 0;
     PassArgs pa{};
@@ -272,6 +273,14 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         if (it != blob_index.end()) return it->second;
         std::vector<BlobEntry> v;
         for (const PassPlan &pp : sp.passes) {
+            if (pp.dense) {
+                BlobEntry e{};
+                e.off = align_up(blob.size());
+                blob.resize(e.off + pp.mat.size() * sizeof(float));
+                std::memcpy(blob.data() + e.off, pp.mat.data(), pp.mat.size() * sizeof(float));
+                v.push_back(e);
+                continue;
+            }
             // [ops][pad to 8 bytes][groups][term bytes, padded to 4]
             std::vector<char> img(pp.ops.size() * sizeof(PassOp));
             if (!pp.ops.empty()) std::memcpy(img.data(), pp.ops.data(), img.size());
@@ -313,12 +322,29 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         const int p = log2u(nslots);
         const int ps = log2u(src_slots);
         for (int h = 0; h < 2; ++h) {
-            const SegmentPlan &sp = get_segment_plan(c, h, level, p, R);
+            const SegmentPlan &sp = get_segment_plan(c, h, level, p, R, fp64 ? 0 : (int)c.tuning.dense_qubits);
             if (!sp.ok) { plan_error = true; return; }
             const std::vector<BlobEntry> &be = blob_entries(sp);
             const int n_ext = p + qh[h];
             for (size_t i = 0; i < sp.passes.size(); ++i) {
                 const PassPlan &pp = sp.passes[i];
+                if (pp.dense) {
+                    Launch ln;
+                    ln.kind = Launch::DENSE;
+                    ln.half = h;
+                    ln.level = level;
+                    std::memset(&ln.da, 0, sizeof(ln.da));
+                    ln.da.n_groups = uint64_t(1) << (n_ext - 9);
+                    ln.da.rescale = std::ldexp(1.0, -pp.rescale_exp);
+                    for (int t = 0; t < 4; ++t) ln.da.bpos[t] = pp.bpos[t];
+                    ln.dst_off = dst[h];
+                    ln.src_off = dst[h];
+                    ln.plan_off = be[i].off;
+                    ln.grid = (unsigned)std::min<uint64_t>((ln.da.n_groups + 3) / 4, max_grid);
+                    ln.bytes = (uint64_t(1) << n_ext) * elem * 2;
+                    launches.push_back(ln);
+                    continue;
+                }
                 Launch ln;
                 ln.kind = Launch::PASS;
                 ln.half = h;
@@ -461,7 +487,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     if (dry_run) {
         const uint64_t rounds = n_paths ? (plain ? n_paths : 1) : 0;
         for (const Launch &ln : launches) {
-            if (ln.kind == Launch::PASS) {
+            if (ln.kind != Launch::GATHER) {
                 c.stats.n_sweep_launches += rounds;
                 c.stats.sweep_bytes += rounds * ln.bytes;
                 (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
@@ -560,7 +586,18 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             if ((he = hipMemcpy(ws + off_tpath, tpath.data(), tpath.size() * 8, hipMemcpyHostToDevice)) != hipSuccess) return dev_err("copy tables", he);
         }
         for (Launch &ln : launches) {
-            if (ln.kind == Launch::PASS) {
+            if (ln.kind == Launch::DENSE) {
+                DenseArgs d = ln.da;
+                d.dst = buf + ln.dst_off;
+                d.src = buf + ln.src_off;
+                d.mat = (const float *)(ws + off_blob + ln.plan_off);
+                hipEvent_t *e = ev_pair(0);
+                if (e) (void)hipEventRecord(e[0], stream);
+                if ((he = launch_dense(d, ln.grid, stream)) != hipSuccess) return dev_err("dense", he);
+                if (e) (void)hipEventRecord(e[1], stream);
+                c.stats.n_sweep_launches++;
+                c.stats.sweep_bytes += ln.bytes;
+            } else if (ln.kind == Launch::PASS) {
                 PassArgs a = ln.pa;
                 a.dst = buf + ln.dst_off;
                 a.src = buf + ln.src_off;
@@ -613,7 +650,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
     c.stats.n_batches = n_leaf_batches * (plain ? n_paths : 1);
     for (const Launch &ln : launches)
-        if (ln.kind == Launch::PASS) (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
+        if (ln.kind != Launch::GATHER) (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
     c.stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SF_OK;
 }

@@ -333,6 +333,69 @@ hipError_t launch_pass(bool fp64, int R, const PassArgs &a, unsigned grid, hipSt
     return fp64 ? launch_pass_t<double>(R, a, grid, s) : launch_pass_t<float>(R, a, grid, s);
 }
 
+// ---------------------------------------------------------------- dense block on matrix cores
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// out = U in for every column: a 32x32 real matrix times the real embedding [Re; Im] of
+// the 16 block amplitudes of 32 columns, with v_mfma_f32_32x32x2f32 (K = 2 per step).
+// Operand layout of that instruction: A[i][k] in lane i + 32k, B[k][j] in lane j + 32k,
+// D[i][j] in lane j + 32*((i/4)%2), register 4*(i/8) + i%4.  Lane j + 32h therefore loads
+// the complex rows 2r + h (r = 0..7) of column j: for step kk the B value is the real part
+// of its row r = kk (kk < 8) or the imaginary part of row r = kk - 8, with no cross-lane
+// exchange.  The accumulator holds real rows 8*(r/4) + 4h + r%4: registers 0..7 are real
+// parts and 8..15 the imaginary parts of the complex rows 8*(r/4) + 4h + r%4.
+__global__ __launch_bounds__(256) void dense_kernel(DenseArgs a)
+{
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned h = lane >> 5, col = lane & 31u;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * 4u;
+    float am[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) am[kk] = a.mat[col * 32u + 2u * kk + h];
+    uint64_t bs[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) bs[t] = (uint64_t)1 << a.bpos[t];
+    auto rowoff = [&](unsigned r) {
+        return ((r & 1u) ? bs[0] : 0u) + ((r & 2u) ? bs[1] : 0u) + ((r & 4u) ? bs[2] : 0u) + ((r & 8u) ? bs[3] : 0u);
+    };
+    const float sc = (float)a.rescale;
+    for (uint64_t g = (uint64_t)blockIdx.x * 4u + wid; g < a.n_groups; g += nwaves) {
+        uint64_t et = g << 5;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int p = a.bpos[t];
+            et = ((et >> p) << (p + 1)) | (et & (((uint64_t)1 << p) - 1u));
+        }
+        const float2 *src = (const float2 *)a.src + et + col;
+        float2 v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = src[rowoff(2u * r + h)];
+        f32x16 acc = {};
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const float b = kk < 8 ? v[kk].x : v[kk - 8].y;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(am[kk], b, acc, 0, 0, 0);
+        }
+        float2 *dst = (float2 *)a.dst + et + col;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const unsigned row = 8u * (r / 4) + 4u * h + (r % 4);
+            float2 o;
+            o.x = acc[r] * sc;
+            o.y = acc[r + 8] * sc;
+            dst[rowoff(row)] = o;
+        }
+    }
+}
+
+hipError_t launch_dense(const DenseArgs &a, unsigned grid, hipStream_t s)
+{
+    dense_kernel<<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- gather + FP64 path sum
 
 // amp[j] += scale * sum_{slot < n_slots} A[x_A(j) * P + slot] * B[x_B(j) * P + slot]

@@ -16,6 +16,9 @@ constexpr int kMaxRegBitsF64 = 4;
 // (0..kMaxRegBits), fp64 selects complex128 states.
 hipError_t launch_pass(bool fp64, int R, const PassArgs &a, unsigned grid, hipStream_t s);
 
+// Dense 4-qubit block on matrix cores (complex64 states only).
+hipError_t launch_dense(const DenseArgs &a, unsigned grid, hipStream_t s);
+
 // Gather + FP64 path sum for one leaf batch.
 hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s);
 

@@ -264,9 +264,64 @@ void flush(PendingDiag &pd, PassPlan &pp, const int (&kidx)[64])
 
 }  // namespace
 
-const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R)
+namespace {
+
+// Unnormalised one-qubit forms (the kernels use the same; the host scalars cover the rest).
+void gate2x2(uint8_t kind, std::complex<double> g[4])
 {
-    const auto key = std::make_tuple(half, level, p, R);
+    const std::complex<double> I(0, 1);
+    if (kind == HK_H) { g[0] = 1; g[1] = 1; g[2] = 1; g[3] = -1; }
+    else if (kind == HK_X) { g[0] = 1; g[1] = -I; g[2] = -I; g[3] = 1; }
+    else { g[0] = 1; g[1] = -1; g[2] = 1; g[3] = 1; }
+}
+
+// Dense block: ops (all inside the four block qubits qs, ascending local ids) multiplied into a
+// 16 x 16 complex matrix, returned as its 32 x 32 real embedding [[Ur, -Ui], [Ui, Ur]].
+std::vector<float> dense_matrix(const std::vector<HalfOp> &ops, const int qs[4])
+{
+    std::complex<double> M[16][16];
+    for (int r = 0; r < 16; ++r)
+        for (int c2 = 0; c2 < 16; ++c2) M[r][c2] = r == c2 ? 1.0 : 0.0;
+    auto idx = [&](int q) { for (int t = 0; t < 4; ++t) if (qs[t] == q) return t; return -1; };
+    const std::complex<double> omega(std::cos(M_PI / 4), std::sin(M_PI / 4));
+    for (const HalfOp &op : ops) {
+        if (op.kind == HK_T) {
+            const int t = idx(op.q0);
+            for (int r = 0; r < 16; ++r) if ((r >> t) & 1) for (int c2 = 0; c2 < 16; ++c2) M[r][c2] *= omega;
+        } else if (op.kind == HK_CZ) {
+            const int t1 = idx(op.q0), t2 = idx(op.q1);
+            for (int r = 0; r < 16; ++r) if (((r >> t1) & 1) && ((r >> t2) & 1)) for (int c2 = 0; c2 < 16; ++c2) M[r][c2] = -M[r][c2];
+        } else {
+            std::complex<double> g[4];
+            gate2x2(op.kind, g);
+            const int t = idx(op.q0);
+            for (int r = 0; r < 16; ++r) {
+                if ((r >> t) & 1) continue;
+                const int r1 = r | (1 << t);
+                for (int c2 = 0; c2 < 16; ++c2) {
+                    const std::complex<double> a = M[r][c2], b = M[r1][c2];
+                    M[r][c2] = g[0] * a + g[1] * b;
+                    M[r1][c2] = g[2] * a + g[3] * b;
+                }
+            }
+        }
+    }
+    std::vector<float> m(32 * 32);
+    for (int i = 0; i < 16; ++i)
+        for (int k = 0; k < 16; ++k) {
+            m[i * 32 + k] = (float)M[i][k].real();
+            m[i * 32 + 16 + k] = (float)-M[i][k].imag();
+            m[(16 + i) * 32 + k] = (float)M[i][k].imag();
+            m[(16 + i) * 32 + 16 + k] = (float)M[i][k].real();
+        }
+    return m;
+}
+
+}  // namespace
+
+const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m)
+{
+    const auto key = std::make_tuple(half, level, p, R, dense_m);
     auto it = c.plan_cache.find(key);
     if (it != c.plan_cache.end()) return it->second;
 
@@ -290,7 +345,59 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
     const int seg_exp = hp.seg_rescale_exp[level];
 
     bool first = true;
+    const bool dense_ok = dense_m >= 2 && n_ext >= 9 && q >= 4;
     while (first || !rem.empty()) {
+        // a dense block on matrix cores (never the first pass of a segment, which reads the
+        // parent batch or writes the initial state)
+        if (!first && dense_ok) {
+            std::vector<int> Q;
+            std::vector<HalfOp> blk, dfr;
+            uint64_t blocked = 0;
+            int nd = 0;
+            for (const HalfOp &op : rem) {
+                const uint64_t qm = (uint64_t(1) << op.q0) | (op.kind == HK_CZ ? uint64_t(1) << op.q1 : 0);
+                bool take = !(qm & blocked) && op.kind != HK_PROJ && op.kind != HK_ZCTL;
+                std::vector<int> nq = Q;
+                if (take) {
+                    const int qq[2] = {op.q0, op.kind == HK_CZ ? (int)op.q1 : -1};
+                    for (int x : qq) {
+                        if (x < 0) continue;
+                        if (p + x < 5) take = false;
+                        if (std::find(nq.begin(), nq.end(), x) == nq.end()) nq.push_back(x);
+                    }
+                    if ((int)nq.size() > dense_m) take = false;
+                }
+                if (take) {
+                    Q = nq;
+                    blk.push_back(op);
+                    if (!is_diag(op.kind)) ++nd;
+                } else {
+                    dfr.push_back(op);
+                    blocked |= qm;
+                }
+            }
+            if (nd >= 2) {
+                for (int t = q - 1; t >= 0 && Q.size() < 4; --t)
+                    if (p + t >= 5 && std::find(Q.begin(), Q.end(), t) == Q.end()) Q.push_back(t);
+                std::sort(Q.begin(), Q.end());
+                PassPlan pp;
+                pp.dense = true;
+                int qs[4];
+                for (int t = 0; t < 4; ++t) { qs[t] = Q[t]; pp.bpos[t] = p + Q[t]; }
+                pp.mat = dense_matrix(blk, qs);
+                pp.n_nondiag = nd;
+                carry += pp.n_nondiag;
+                if (carry >= 32) {
+                    const int e = std::min(carry / 2, seg_exp - taken);
+                    pp.rescale_exp = e;
+                    taken += e;
+                    carry -= 2 * e;
+                }
+                sp.passes.push_back(std::move(pp));
+                rem.swap(dfr);
+                continue;
+            }
+        }
         first = false;
         PassPlan pp;
         std::vector<int> regq;

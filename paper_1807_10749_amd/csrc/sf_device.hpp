@@ -90,6 +90,19 @@ struct PassArgs {
     int32_t skip_pos[10];
 };
 
+// Dense fused block: a 2^4 x 2^4 complex matrix U applied to four qubits (extended bit
+// positions bpos[0] < ... < bpos[3], all >= 5), on matrix cores.  `mat` is the real
+// embedding [[Ur, -Ui], [Ui, Ur]] (32 x 32, row-major, FP32).  The 5 lowest extended
+// bits index 32 columns that are contiguous in memory.
+struct DenseArgs {
+    void *dst;
+    const void *src;
+    const float *mat;
+    uint64_t n_groups;            // 2^(n_ext - 9): groups of 32 columns
+    double rescale;
+    int32_t bpos[4];
+};
+
 struct GatherArgs {
     const void *a;                // block-A leaf states, 2^(p+qA) complex
     const void *b;                // block-B leaf states, 2^(p+qB) complex

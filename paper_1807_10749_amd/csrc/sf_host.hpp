@@ -36,6 +36,10 @@ struct PassPlan {
     int n_nondiag = 0;
     int rescale_exp = 0;            // divide by 2^rescale_exp at the end of the pass
     bool needs_slot_path = false;   // has path-dependent terms
+    // dense pass (matrix cores): a 16 x 16 block on four qubits instead of the op list
+    bool dense = false;
+    int bpos[4] = {0, 0, 0, 0};     // extended bit positions, ascending
+    std::vector<float> mat;         // 32 x 32 real embedding, row-major
 };
 
 // All passes of one block over one segment, for a given slot count 2^p.
@@ -74,7 +78,7 @@ struct Circuit {
 
     // tuning
     sf_tuning_t tuning{};
-    std::map<std::tuple<int, int, int, int>, SegmentPlan> plan_cache;  // (half, level, p, R)
+    std::map<std::tuple<int, int, int, int, int>, SegmentPlan> plan_cache;  // (half, level, p, R, dense)
 
     // device resources owned by the circuit
     void *dev_ws = nullptr;
@@ -86,7 +90,9 @@ struct Circuit {
 
 // planner.cpp
 int build_programs(Circuit &c, std::string &err);
-const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R);
+// dense_m: 0 = register/lane passes only; 2..4 = also fuse windows of up to dense_m qubits
+// into dense 4-qubit blocks applied on matrix cores.
+const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m = 0);
 
 // executor.cpp
 // dry_run: plan the request (tree, batches, passes) and fill the launch and byte counts of

@@ -238,6 +238,7 @@ int set_tuning(sf_circuit_t *c, const sf_tuning_t *t)
 {
     if (!c || !t) return fail(SF_ERR_INVALID, "NULL argument");
     if (t->reg_qubits > 5) return fail(SF_ERR_INVALID, "reg_qubits must be at most 5");
+    if (t->dense_qubits == 1 || t->dense_qubits > 4) return fail(SF_ERR_INVALID, "dense_qubits must be 0 or 2..4");
     auto pow2ok = [](uint32_t v) { return v == 0 || (v & (v - 1)) == 0; };
     if (!pow2ok(t->leaf_batch) || !pow2ok(t->max_slots)) return fail(SF_ERR_INVALID, "batch sizes must be powers of two");
     c->tuning = *t;
@@ -290,7 +291,10 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
         const uint32_t wpcs[3] = {32u, 16u, 64u};
         for (uint32_t r : regs)
             for (uint32_t lf : leafs)
-                for (uint32_t w : wpcs) cands.push_back(sf_tuning_t{r, lf, 0, w});
+                for (uint32_t w : wpcs) {
+                    cands.push_back(sf_tuning_t{r, lf, 0, w, 0});
+                    if (!fp64) cands.push_back(sf_tuning_t{r, lf, 0, w, 4});   // dense blocks on matrix cores
+                }
         // rank by the planned cost
         std::vector<std::pair<double, size_t>> ranked;
         for (size_t i = 0; i < cands.size(); ++i) {
@@ -357,14 +361,14 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
             s += "level " + std::to_string(l) + " cycle " + std::to_string(c->levels[l].cycle) +
                  " bits " + std::to_string(c->levels[l].bits_after) + " p " + std::to_string(p) + ":";
             for (int h = 0; h < 2; ++h) {
-                const sf::SegmentPlan &sp = sf::get_segment_plan(*c, h, l, p, R);
+                const sf::SegmentPlan &sp = sf::get_segment_plan(*c, h, l, p, R, (int)c->tuning.dense_qubits);
                 int nd = 0;
                 for (const sf::HalfOp &op : c->half[h].segments[l]) nd += sf::is_diag(op.kind) ? 0 : 1;
                 s += std::string(h ? "  B " : " A ") + std::to_string(c->half[h].segments[l].size()) + " ops (" +
                      std::to_string(nd) + " non-diag) " + std::to_string(sp.passes.size()) + " passes [";
                 for (size_t i = 0; i < sp.passes.size(); ++i)
                     s += (i ? "," : "") + std::to_string(sp.passes[i].n_nondiag) + "g/" +
-                         std::to_string(sp.passes[i].groups.size()) + "d";
+                         (sp.passes[i].dense ? std::string("dense") : std::to_string(sp.passes[i].groups.size()) + "d");
                 s += "]";
             }
             s += "\n";

@@ -142,11 +142,26 @@ def test_workspace_size_and_run_validation(sf):
     sf.destroy_circuit(c)
 
 
+def test_dense_plan_uses_matrix_core_blocks(sf):
+    """With dense_qubits set, the planner packs four-qubit windows into dense blocks."""
+    w = make_workload("grid5x6_d24", n_bits=4)
+    c = sf.create_circuit(5, 6, w["gates"])
+    sf.set_cut(c, w["mask_a"])
+    plain = sf.describe_plan(c)
+    sf.set_tuning(c, dense_qubits=4)
+    dense = sf.describe_plan(c)
+    assert "dense" not in plain and "dense" in dense
+    sf.destroy_circuit(c)
+
+
 def test_tuning_roundtrip(sf):
     w = make_workload("grid4x4_d16", n_bits=4)
     c = sf.create_circuit(4, 4, w["gates"])
-    sf.set_tuning(c, reg_qubits=3, leaf_batch=64, max_slots=1024, waves_per_cu=16)
-    assert sf.get_tuning(c) == {"reg_qubits": 3, "leaf_batch": 64, "max_slots": 1024, "waves_per_cu": 16}
+    sf.set_tuning(c, reg_qubits=3, leaf_batch=64, max_slots=1024, waves_per_cu=16, dense_qubits=4)
+    assert sf.get_tuning(c) == {"reg_qubits": 3, "leaf_batch": 64, "max_slots": 1024, "waves_per_cu": 16,
+                                "dense_qubits": 4}
+    with pytest.raises(sf.SFError):
+        sf.set_tuning(c, dense_qubits=1)
     with pytest.raises(sf.SFError):
         sf.set_tuning(c, leaf_batch=48)
     with pytest.raises(sf.SFError):

@@ -210,3 +210,20 @@ def test_grid7x8_block_properties(sf):
     say("grid7x8_d40 rank-one check of a single path")
     q = c.amplitudes(quad, path_begin=begin + 5, n_paths=1)
     assert abs(q[0] * q[1] - q[2] * q[3]) <= 1e-4 * abs(q[0] * q[1])
+
+
+# ---------------------------------------------------------------- dense blocks on matrix cores
+
+@pytest.mark.parametrize("name,npaths", [("grid5x6_d24", 300), ("grid6x7_d32", 3)])
+def test_dense_blocks_parity(sf, name, npaths):
+    """Four-qubit windows applied as dense 16 x 16 blocks with MFMA give the oracle's result."""
+    cfg, g, c = _circuit(sf, name)
+    c.tune(dense_qubits=4)
+    assert "dense" in sf.describe_plan(c.handle)
+    rng = np.random.default_rng(11)
+    ids = np.sort(rng.choice(1 << min(c.k, 40), size=npaths, replace=False)).astype(np.uint64)
+    bits = random_bitstrings(cfg.n_qubits, 3000, 12)
+    say(f"{name} dense blocks, {npaths} paths")
+    a = c.amplitudes(bits, path_ids=ids)
+    o = oracle.path_sum(cfg.n_qubits, g, cfg.cut_mask(), ids, bits)
+    assert c11_error(a, o, ids.size, c.k, cfg.n_qubits) <= TOL_C64
