@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--plain-paths", type=int, default=64)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving mix (0 = skip)")
-    ap.add_argument("--tuning", default="", help="fixed tuning R,leaf_batch,waves_per_cu (skips autotune)")
+    ap.add_argument("--tuning", default="",
+                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold]] (skips autotune)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (known HBM traffic for counter scaling)")
     return ap.parse_args()
@@ -79,7 +80,10 @@ def main():
 
     d_bits = torch.from_numpy(bits.view(np.int64)).cuda()
     d_amps = torch.zeros(2 * bits.size, dtype=torch.float64, device="cuda")
+    # room for every tuning the autotuner may try, materialised leaf states included
+    sf.set_tuning(c.handle, no_leaf_fold=1)
     ws_bytes = sf.workspace_size(c.handle, npaths, bits.size, flags_base)
+    sf.set_tuning(c.handle)
     free_b, _ = torch.cuda.mem_get_info()
     ws_bytes = min(ws_bytes, int(free_b * 0.85))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
@@ -90,8 +94,12 @@ def main():
 
     tuning = None
     if args.tuning:
-        r, lb, wpc = (int(v) for v in args.tuning.split(","))
-        sf.set_tuning(c.handle, reg_qubits=r, leaf_batch=lb, waves_per_cu=wpc)
+        vals = [int(v) for v in args.tuning.split(",")]
+        r, lb, wpc = vals[:3]
+        dense = vals[3] if len(vals) > 3 else 0
+        nofold = vals[4] if len(vals) > 4 else 0
+        sf.set_tuning(c.handle, reg_qubits=r, leaf_batch=lb, waves_per_cu=wpc, dense_qubits=dense,
+                      no_leaf_fold=nofold)
         tuning = sf.get_tuning(c.handle)
     elif not args.no_autotune:
         tuning = sf.autotune(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,
@@ -100,19 +108,22 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    sweep_ms = gather_ms = 0.0
+    sweep_ms = gather_ms = other_ms = host_ms = 0.0
     sweep_launches = gather_launches = 0
-    sweep_bytes = gather_bytes = 0
+    sweep_bytes = gather_bytes = gather_row_bytes = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(sf.SF_TIMING)
         st = c.stats()
         sweep_ms += st["ms_sweep"]
         gather_ms += st["ms_gather"]
+        other_ms += st["ms_other"]
+        host_ms += st["ms_total"]
         sweep_launches += st["n_sweep_launches"]
         gather_launches += st["n_gather_launches"]
         sweep_bytes += st["sweep_bytes"]
         gather_bytes += st["gather_bytes"]
+        gather_row_bytes += st["gather_row_bytes"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -120,13 +131,16 @@ def main():
     amps_per_s = bits.size * args.steps / elapsed
 
     # dominant kernel category by measured time
+    folded = "folded" in sf.describe_plan(c.handle)
     if sweep_ms >= gather_ms:
         dom, dom_ms, dom_n, dom_bytes = "pass_kernel (gate sweep)", sweep_ms, sweep_launches, sweep_bytes
+    elif folded:
+        dom, dom_ms, dom_n, dom_bytes = "fold_kernel (last level + path sum)", gather_ms, gather_launches, gather_bytes
     else:
         dom, dom_ms, dom_n, dom_bytes = "gather_kernel (path sum)", gather_ms, gather_launches, gather_bytes
     avg_launch_ms = dom_ms / max(dom_n, 1)
     achieved = (dom_bytes / max(dom_n, 1)) / (avg_launch_ms * 1e-3) / 1e9 if dom_n else 0.0
-    traffic = measured_traffic(args.workload, "pass_kernel" if dom.startswith("pass") else "gather_kernel")
+    traffic = measured_traffic(args.workload, dom.split(" ")[0])
 
     # plain one-path-per-launch GPU form on a subset of the same paths
     plain = None
@@ -168,11 +182,16 @@ def main():
                    "bitstrings": int(bits.size), "tuning": tuning or sf.get_tuning(c.handle)},
         "amps_per_s": amps_per_s,
         "plain_form": plain,
-        "kernel_ms_per_step": {"sweep": sweep_ms / args.steps, "gather": gather_ms / args.steps},
+        "kernel_ms_per_step": {"sweep": sweep_ms / args.steps, "gather": gather_ms / args.steps,
+                               "other": other_ms / args.steps},
+        "run_paths_wall_ms_per_step": host_ms / args.steps,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_launch_ms, "launches_per_step": dom_n / args.steps,
-                     "bytes_per_launch": dom_bytes / max(dom_n, 1)},
+                     "bytes_per_launch": dom_bytes / max(dom_n, 1),
+                     "row_bytes_per_launch": (gather_row_bytes / max(gather_launches, 1)
+                                              if not dom.startswith("pass") else None),
+                     "a_groups": st["a_groups"]},
         "cpu_baseline": cpu,
         "serving": serving,
     }

@@ -151,6 +151,10 @@ typedef struct {
     uint32_t dense_qubits;   /* 0: gates on registers and lanes only; 2..4: also fuse windows of up to
                                 this many qubits into dense 16 x 16 blocks applied on matrix cores
                                 (complex64 sweeps only) */
+    uint32_t no_leaf_fold;   /* 0: when every non-diagonal gate of the last tree level acts on a
+                                branch qubit of that level, the gather reads the level above and
+                                applies the last level itself (leaf states are never written);
+                                1: always write the leaf states and gather from them */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);
@@ -185,9 +189,15 @@ typedef struct {
     uint64_t n_sweep_launches;
     uint64_t n_gather_launches;
     uint64_t sweep_bytes;    /* algorithmic bytes: read + written by sweep passes */
-    uint64_t gather_bytes;   /* algorithmic bytes read by gather launches */
+    uint64_t gather_bytes;   /* algorithmic bytes of gather launches in their visiting order:
+                                block-A rows once per group of bitstrings that read the same
+                                block-A rows, block-B rows once per bitstring, plus indices
+                                and the amplitudes read and written */
     uint64_t n_batches;      /* leaf batches */
     uint64_t n_passes_a, n_passes_b;  /* passes per leaf path of block A / B (full plan) */
+    uint64_t gather_row_bytes;  /* rows of both blocks read once per bitstring (no reuse) */
+    uint64_t a_groups;       /* groups of bitstrings that share their block-A rows (estimated
+                                from the bitstring count in a planning-only run) */
 } sf_run_stats_t;
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);

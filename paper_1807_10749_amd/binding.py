@@ -34,7 +34,7 @@ class SFError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [("reg_qubits", ctypes.c_uint32), ("leaf_batch", ctypes.c_uint32),
                 ("max_slots", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
-                ("dense_qubits", ctypes.c_uint32)]
+                ("dense_qubits", ctypes.c_uint32), ("no_leaf_fold", ctypes.c_uint32)]
 
 
 class RunStats(ctypes.Structure):
@@ -43,7 +43,8 @@ class RunStats(ctypes.Structure):
                 ("n_sweep_launches", ctypes.c_uint64), ("n_gather_launches", ctypes.c_uint64),
                 ("sweep_bytes", ctypes.c_uint64), ("gather_bytes", ctypes.c_uint64),
                 ("n_batches", ctypes.c_uint64), ("n_passes_a", ctypes.c_uint64),
-                ("n_passes_b", ctypes.c_uint64)]
+                ("n_passes_b", ctypes.c_uint64), ("gather_row_bytes", ctypes.c_uint64),
+                ("a_groups", ctypes.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -191,8 +192,8 @@ def workspace_size(c: int, n_paths: int, n_bits: int, flags: int = 0) -> int:
     return b.value
 
 
-def set_tuning(c: int, reg_qubits=0, leaf_batch=0, max_slots=0, waves_per_cu=0, dense_qubits=0):
-    t = Tuning(reg_qubits, leaf_batch, max_slots, waves_per_cu, dense_qubits)
+def set_tuning(c: int, reg_qubits=0, leaf_batch=0, max_slots=0, waves_per_cu=0, dense_qubits=0, no_leaf_fold=0):
+    t = Tuning(reg_qubits, leaf_batch, max_slots, waves_per_cu, dense_qubits, no_leaf_fold)
     _check(lib.set_tuning(c, ctypes.byref(t)))
 
 

@@ -81,14 +81,17 @@ int build_tree(const Circuit &c, const uint64_t *ids, uint64_t begin, uint64_t n
 }
 
 struct LevelBuf {
+    bool none = false;    // no buffer (leaf level folded into the gather)
     int alias = -1;       // level whose buffer this level reuses in place (chain levels)
     uint64_t cap = 1;     // slots
     size_t off[2] = {0, 0};
 };
 
 struct Launch {
-    enum Kind { PASS, GATHER, DENSE } kind;
+    enum Kind { PASS, GATHER, DENSE, FOLD } kind;
     DenseArgs da{};
+    FoldArgs fa{};
+    size_t mask_off = 0;          // FOLD: element offset of the batch's child masks
     int half = 0;
     int R = 0;
     PassArgs pa{};
@@ -106,6 +109,12 @@ struct BatchRec { int level; size_t table_off; uint64_t slots; };
 
 struct BlobEntry { size_t off; uint32_t words, groups_word, terms_word; };
 
+// The leaf level is folded into the gather (see LeafFold) unless the tuning says otherwise.
+bool fold_active(const Circuit &c)
+{
+    return c.levels.size() > 1 && c.tuning.no_leaf_fold == 0 && c.half[0].fold.ok && c.half[1].fold.ok;
+}
+
 }  // namespace
 
 int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32_t flags, size_t *bytes)
@@ -113,15 +122,20 @@ int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32
     const size_t elem = (flags & SF_FP64_SWEEPS) ? 16 : 8;
     const size_t sigma = (size_t(1) << c.half[0].q) * elem + (size_t(1) << c.half[1].q) * elem;
     const int L = (int)c.levels.size() - 1;
+    const bool fold = fold_active(c);
     // upper bound: every level resident with min(2^bits, n_paths) nodes
     size_t total = 0;
     for (int l = 0; l <= L; ++l) {
+        if (fold && l == L) {
+            total += align_up(n_paths * 4 + 64 * 4);   // child masks instead of leaf states
+            continue;
+        }
         const int b = c.levels[l].bits_after;
         uint64_t nodes = b >= 63 ? n_paths : std::min<uint64_t>(uint64_t(1) << b, n_paths);
         total += next_pow2(std::max<uint64_t>(nodes, 1)) * sigma;
         total += align_up(nodes * 12 + 64 * 12) ;
     }
-    total += align_up(n_bits * 4) * 5 + align_up(n_bits * 8) + align_up(n_bits * 16) + (size_t(1) << 22);
+    total += align_up(n_bits * 4) * 6 + align_up(n_bits * 8) + align_up(n_bits * 16) + (size_t(1) << 22);
     total += align_up(n_bits * 16) + (size_t(1) << 20);   // radix-sort scratch (bound)
     *bytes = total;
     return SF_OK;
@@ -144,6 +158,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     const int qh[2] = {c.half[0].q, c.half[1].q};
     int R = c.tuning.reg_qubits ? (int)c.tuning.reg_qubits : kMaxRegBits;
     R = std::max(1, std::min(R, fp64 ? kMaxRegBitsF64 : kMaxRegBits));
+    const bool fold = fold_active(c);
     c.stats = sf_run_stats_t{};
 
     if (!path_ids && n_paths && k < 64 && ((path_begin + n_paths - 1) >> k) != 0) {
@@ -159,9 +174,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             if (bits[j] & ~all) { err = "bitstring has bits outside the grid"; return SF_ERR_INVALID; }
 
     hipError_t he;
-    int dev = 0;
-    if ((he = hipGetDevice(&dev)) != hipSuccess) { err = std::string("hipGetDevice: ") + hipGetErrorString(he); return SF_ERR_DEVICE; }
     if (!c.device_cus) {
+        int dev = 0;
+        if ((he = hipGetDevice(&dev)) != hipSuccess) { err = std::string("hipGetDevice: ") + hipGetErrorString(he); return SF_ERR_DEVICE; }
         if ((he = hipDeviceGetAttribute(&c.device_cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
             err = std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he);
             return SF_ERR_DEVICE;
@@ -189,6 +204,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     const size_t off_order = fixed; fixed += align_up(n_bits * 4);
     const size_t off_keys = fixed; fixed += align_up(n_bits * 4);
     const size_t off_idx = fixed; fixed += align_up(n_bits * 4);
+    const size_t off_fkey = fixed; if (fold) fixed += align_up(n_bits * 4);
     const size_t off_sort_tmp = fixed; fixed += align_up(sort_temp);
     const size_t blob_budget = size_t(1) << 22;
     const size_t off_blob = fixed; fixed += blob_budget;
@@ -208,6 +224,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
         for (int l = 1; l <= L; ++l)
             if (tree.node[l].size() == tree.node[l - 1].size()) lb[l].alias = lb[l - 1].alias >= 0 ? lb[l - 1].alias : l - 1;
+        if (fold) { lb[L].none = true; lb[L].alias = -1; }
         const uint64_t maxs = c.tuning.max_slots ? c.tuning.max_slots : (uint64_t(1) << 20);
         const uint64_t leafmax = c.tuning.leaf_batch ? c.tuning.leaf_batch : maxs;
         for (int l = 0; l <= L; ++l) {
@@ -219,6 +236,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             table_bound += 2 * tree.node[l].size() + lb[l].cap + min_slots * (l ? tree.node[l - 1].size() : 1);
         }
         table_bound = align_up(table_bound * 8) + align_up(table_bound * 4);
+        if (fold) table_bound += align_up(tree.node[L - 1].size() * 4);   // child masks
         size_t budget;
         if (workspace) {
             if (workspace_bytes < fixed + table_bound) { err = "workspace too small"; return SF_ERR_OOM; }
@@ -234,17 +252,17 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         for (;;) {
             for (int l = 1; l <= L; ++l) if (lb[l].alias >= 0) lb[l].cap = lb[lb[l].alias].cap;
             size_t need = 0;
-            for (int l = 0; l <= L; ++l) if (lb[l].alias < 0) need += align_up(lb[l].cap * (size_t(1) << qh[0]) * elem) + align_up(lb[l].cap * (size_t(1) << qh[1]) * elem);
+            for (int l = 0; l <= L; ++l) if (lb[l].alias < 0 && !lb[l].none) need += align_up(lb[l].cap * (size_t(1) << qh[0]) * elem) + align_up(lb[l].cap * (size_t(1) << qh[1]) * elem);
             if (need <= budget) break;
             int big = -1;
             for (int l = 0; l <= L; ++l)
-                if (lb[l].alias < 0 && lb[l].cap > min_slots && (big < 0 || lb[l].cap >= lb[big].cap)) big = l;
+                if (lb[l].alias < 0 && !lb[l].none && lb[l].cap > min_slots && (big < 0 || lb[l].cap >= lb[big].cap)) big = l;
             if (big < 0) { err = "workspace too small for one slot per tree level"; return SF_ERR_OOM; }
             lb[big].cap >>= 1;
         }
         size_t o = 0;
         for (int l = 0; l <= L; ++l) {
-            if (lb[l].alias >= 0) continue;
+            if (lb[l].alias >= 0 || lb[l].none) continue;
             for (int h = 0; h < 2; ++h) { lb[l].off[h] = o; o += align_up(lb[l].cap * (size_t(1) << qh[h]) * elem); }
         }
         for (int l = 0; l <= L; ++l)
@@ -267,6 +285,16 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         leaf_scale[h] = s;
     }
     const std::complex<double> gscale = leaf_scale[0] * leaf_scale[1];
+    // folded leaf: the last segment is applied with its exact matrix, so its scalar is not tracked
+    std::complex<double> fscale = 1.0;
+    for (int h = 0; h < 2; ++h) {
+        std::complex<double> s = c.half[h].init_scale;
+        for (int l = 0; l < L; ++l) s *= c.half[h].seg_scale[l];
+        fscale *= s;
+    }
+    std::vector<uint32_t> tmaskv;        // child masks of folded parent batches
+    size_t fold_tab_off[2] = {0, 0};
+    size_t plain_mask_idx = SIZE_MAX;
 
     auto blob_entries = [&](const SegmentPlan &sp) -> const std::vector<BlobEntry> & {
         auto it = blob_index.find(&sp);
@@ -301,6 +329,22 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             v.push_back(e);
         }
         return blob_index.emplace(&sp, std::move(v)).first->second;
+    };
+
+    // gather byte accounting (see sf_run_stats_t): a_groups = distinct block-A keys of the visit
+    auto account_gather = [&](const std::vector<Launch> &ls, uint64_t rounds, uint64_t a_groups) {
+        c.stats.a_groups = a_groups;
+        for (const Launch &ln : ls) {
+            if (ln.kind != Launch::GATHER && ln.kind != Launch::FOLD) continue;
+            const uint64_t slots = ln.kind == Launch::FOLD ? ln.fa.n_slots : ln.ga.n_slots;
+            const uint64_t ra = ln.kind == Launch::FOLD ? uint64_t(1) << c.half[0].fold.n_s : 1;
+            const uint64_t rb = ln.kind == Launch::FOLD ? uint64_t(1) << c.half[1].fold.n_s : 1;
+            const uint64_t per = slots * elem * (a_groups * ra + (uint64_t)n_bits * rb) + (uint64_t)n_bits * 44 +
+                                 (ln.kind == Launch::FOLD ? slots * 4 : 0);
+            c.stats.n_gather_launches += rounds;
+            c.stats.gather_bytes += rounds * per;
+            c.stats.gather_row_bytes += rounds * ln.bytes;
+        }
     };
 
     const unsigned max_grid = (unsigned)std::max(1, c.device_cus) * (c.tuning.waves_per_cu ? c.tuning.waves_per_cu / 4 : 8);
@@ -404,6 +448,45 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     visit = [&](int l, const std::vector<uint32_t> &nodes, uint64_t nslots) {
         if (plan_error) return;
         const int own = lb[l].alias >= 0 ? lb[l].alias : l;
+        if (fold && l == L - 1) {
+            // the gather reads this batch and applies the leaf segment itself
+            Launch ln;
+            ln.kind = Launch::FOLD;
+            ln.level = l;
+            FoldArgs &f = ln.fa;
+            std::memset(&f, 0, sizeof(f));
+            for (int h = 0; h < 2; ++h) {
+                const LeafFold &lf = c.half[h].fold;
+                FoldHalf &fh = f.h[h];
+                fh.smask = lf.smask;
+                fh.tmask = lf.tmask;
+                fh.dmask = lf.dmask;
+                fh.n_s = lf.n_s;
+                for (int i = 0; i < 16; ++i) { fh.sdep[i] = lf.sdep[i]; fh.dval[i] = lf.dval[i]; fh.ymap[i] = lf.ymap[i]; }
+            }
+            f.n_bits = n_bits;
+            f.n_slots = (uint32_t)nodes.size();
+            f.p = log2u(nslots);
+            f.scale_re = fscale.real();
+            f.scale_im = fscale.imag();
+            const int nb = c.levels[L].n_cut;
+            const uint32_t full = (1u << nb) - 1;
+            const std::vector<uint64_t> &fc = tree.first_child[l];
+            const std::vector<uint64_t> &cnode = tree.node[L];
+            std::vector<uint32_t> m(nodes.size(), 0);
+            for (size_t i = 0; i < nodes.size(); ++i)
+                for (uint64_t cc = fc[nodes[i]]; cc < fc[nodes[i] + 1]; ++cc) m[i] |= 1u << (cnode[cc] & full);
+            ln.mask_off = tmaskv.size();
+            if (plain) plain_mask_idx = tmaskv.size();
+            tmaskv.insert(tmaskv.end(), m.begin(), m.end());
+            ln.dst_off = lb[own].off[0];
+            ln.src_off = lb[own].off[1];
+            ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem *
+                       ((uint64_t(1) << c.half[0].fold.n_s) + (uint64_t(1) << c.half[1].fold.n_s));
+            launches.push_back(ln);
+            ++n_leaf_batches;
+            return;
+        }
         if (l == L) {
             Launch ln;
             ln.kind = Launch::GATHER;
@@ -473,6 +556,17 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
     };
 
+    if (n_paths && fold) {
+        for (int h = 0; h < 2; ++h) {
+            const std::vector<std::complex<double>> &tab = c.half[h].fold.tab;
+            fold_tab_off[h] = align_up(blob.size());
+            blob.resize(fold_tab_off[h] + tab.size() * 16);
+            for (size_t i = 0; i < tab.size(); ++i) {
+                const double v[2] = {tab[i].real(), tab[i].imag()};
+                std::memcpy(blob.data() + fold_tab_off[h] + 16 * i, v, 16);
+            }
+        }
+    }
     if (n_paths) {
         const uint64_t ns0 = std::max<uint64_t>(1, min_slots);
         const size_t toff = put_tables(std::vector<uint64_t>{0}, std::vector<uint32_t>{0}, ns0);
@@ -483,19 +577,19 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
     if (plan_error) { err = "internal: a segment could not be scheduled into passes"; return SF_ERR_UNSUPPORTED; }
     if (blob.size() > blob_budget) { err = "internal: pass programs exceed their reservation"; return SF_ERR_UNSUPPORTED; }
-    const size_t tables_bytes = align_up(tpath.size() * 8) + align_up(tparent.size() * 4);
+    const size_t tables_bytes = align_up(tpath.size() * 8) + align_up(tparent.size() * 4) + align_up(tmaskv.size() * 4);
     if (dry_run) {
         const uint64_t rounds = n_paths ? (plain ? n_paths : 1) : 0;
         for (const Launch &ln : launches) {
-            if (ln.kind != Launch::GATHER) {
+            if (ln.kind != Launch::GATHER && ln.kind != Launch::FOLD) {
                 c.stats.n_sweep_launches += rounds;
                 c.stats.sweep_bytes += rounds * ln.bytes;
                 (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
-            } else {
-                c.stats.n_gather_launches += rounds;
-                c.stats.gather_bytes += rounds * ln.bytes;
             }
         }
+        // planning only: every bitstring its own block-A group unless there are fewer rows
+        const int kb = fold ? qh[0] - c.half[0].fold.n_s : qh[0];
+        account_gather(launches, rounds, std::min<uint64_t>(n_bits, kb >= 32 ? n_bits : (uint64_t(1) << kb)));
         c.stats.n_batches = n_leaf_batches * rounds;
         return SF_OK;
     }
@@ -504,10 +598,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     // ---------------------------------------------------------------- workspace
     const size_t off_tpath = fixed;
     const size_t off_tparent = off_tpath + align_up(tpath.size() * 8);
+    const size_t off_tmask = off_tparent + align_up(tparent.size() * 4);
     const size_t off_buffers = fixed + table_bound;
     size_t buffers_bytes = 0;
     for (int l = 0; l <= L; ++l)
-        if (n_paths && lb[l].alias < 0)
+        if (n_paths && lb[l].alias < 0 && !lb[l].none)
             buffers_bytes = std::max(buffers_bytes, lb[l].off[1] + align_up(lb[l].cap * (size_t(1) << qh[1]) * elem));
     const size_t ws_bytes = off_buffers + buffers_bytes;
     char *ws = (char *)workspace;
@@ -553,14 +648,29 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         if ((he = hipMemcpyAsync(ws + off_tpath, tpath.data(), tpath.size() * 8, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy tables", he);
         if ((he = hipMemcpyAsync(ws + off_tparent, tparent.data(), tparent.size() * 4, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy tables", he);
     }
+    if (!tmaskv.empty())
+        if ((he = hipMemcpyAsync(ws + off_tmask, tmaskv.data(), tmaskv.size() * 4, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy masks", he);
     {
         hipEvent_t *e = ev_pair(2);
         if (e) (void)hipEventRecord(e[0], stream);
-        if ((he = launch_fill_zero_i32(d_flag, 1, stream)) != hipSuccess) return dev_err("fill", he);
+        if ((he = launch_fill_zero_i32(d_flag, 2, stream)) != hipSuccess) return dev_err("fill", he);
         if ((he = launch_pext(d_bits, n_bits, c.mask_a, c.mask_b, all, d_xa, d_xb, d_flag, stream)) != hipSuccess) return dev_err("pext", he);
-        if ((he = launch_order_by_key(d_xa, (uint32_t *)(ws + off_keys), (uint32_t *)(ws + off_idx), d_order, n_bits,
-                                      qh[0], ws + off_sort_tmp, sort_temp, stream)) != hipSuccess)
+        const uint32_t *keys = d_xa;
+        int key_bits = qh[0];
+        if (fold) {
+            // bitstrings that share their block-A bits outside the fold's S qubits read the same
+            // parent rows of block A: visit them together
+            const uint32_t kmask = (qh[0] >= 32 ? ~0u : ((1u << qh[0]) - 1)) & ~c.half[0].fold.smask;
+            if ((he = launch_key(d_xa, n_bits, kmask, (uint32_t *)(ws + off_fkey), stream)) != hipSuccess) return dev_err("key", he);
+            keys = (const uint32_t *)(ws + off_fkey);
+            key_bits = __builtin_popcount(kmask);
+        }
+        if ((he = launch_order_by_key(keys, (uint32_t *)(ws + off_keys), (uint32_t *)(ws + off_idx), d_order, n_bits,
+                                      key_bits, ws + off_sort_tmp, sort_temp, stream)) != hipSuccess)
             return dev_err("sort", he);
+        // groups of bitstrings that read the same block-A rows, for the byte accounting
+        if ((he = launch_count_runs((const uint32_t *)(ws + off_keys), n_bits, d_flag + 1, stream)) != hipSuccess)
+            return dev_err("count", he);
         if (flags & SF_ACCUMULATE) {
             if (!out_dev && n_bits)
                 if ((he = hipMemcpyAsync(d_acc, amps, n_bits * 16, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy amps", he);
@@ -581,9 +691,12 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 const uint64_t v = drop >= 64 ? 0 : ((pid >> drop) << drop);
                 for (uint64_t i = 0; i < b.slots; ++i) tpath[b.table_off + i] = v;
             }
+            if (plain_mask_idx != SIZE_MAX) tmaskv[plain_mask_idx] = 1u << (pid & ((uint64_t(1) << c.levels[L].n_cut) - 1));
             // the previous path's launches must be done with the old tables
             if ((he = hipStreamSynchronize(stream)) != hipSuccess) return dev_err("sync", he);
             if ((he = hipMemcpy(ws + off_tpath, tpath.data(), tpath.size() * 8, hipMemcpyHostToDevice)) != hipSuccess) return dev_err("copy tables", he);
+            if (!tmaskv.empty())
+                if ((he = hipMemcpy(ws + off_tmask, tmaskv.data(), tmaskv.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return dev_err("copy masks", he);
         }
         for (Launch &ln : launches) {
             if (ln.kind == Launch::DENSE) {
@@ -614,6 +727,20 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 if (e) (void)hipEventRecord(e[1], stream);
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;
+            } else if (ln.kind == Launch::FOLD) {
+                FoldArgs f = ln.fa;
+                f.h[0].par = buf + ln.dst_off;
+                f.h[1].par = buf + ln.src_off;
+                for (int h = 0; h < 2; ++h) f.h[h].tab = (const double *)(ws + off_blob + fold_tab_off[h]);
+                f.xa = d_xa;
+                f.xb = d_xb;
+                f.order = d_order;
+                f.acc = d_acc;
+                f.child_mask = (const uint32_t *)(ws + off_tmask) + ln.mask_off;
+                hipEvent_t *e = ev_pair(1);
+                if (e) (void)hipEventRecord(e[0], stream);
+                if ((he = launch_fold(fp64, c.levels[L].n_cut, f, stream)) != hipSuccess) return dev_err("fold", he);
+                if (e) (void)hipEventRecord(e[1], stream);
             } else {
                 GatherArgs g = ln.ga;
                 g.a = buf + ln.dst_off;
@@ -626,17 +753,16 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 if (e) (void)hipEventRecord(e[0], stream);
                 if ((he = launch_gather(fp64, g, stream)) != hipSuccess) return dev_err("gather", he);
                 if (e) (void)hipEventRecord(e[1], stream);
-                c.stats.n_gather_launches++;
-                c.stats.gather_bytes += ln.bytes;
             }
         }
     }
     if (!out_dev && n_bits)
         if ((he = hipMemcpyAsync(amps, d_acc, n_bits * 16, hipMemcpyDeviceToHost, stream)) != hipSuccess) return dev_err("copy amps", he);
-    int flag = 0;
-    if ((he = hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, stream)) != hipSuccess) return dev_err("copy flag", he);
+    int flag[2] = {0, 0};
+    if ((he = hipMemcpyAsync(flag, d_flag, sizeof(flag), hipMemcpyDeviceToHost, stream)) != hipSuccess) return dev_err("copy flag", he);
     if ((he = hipStreamSynchronize(stream)) != hipSuccess) return dev_err("synchronize", he);
-    if (flag) { err = "bitstring has bits outside the grid"; return SF_ERR_INVALID; }
+    if (flag[0]) { err = "bitstring has bits outside the grid"; return SF_ERR_INVALID; }
+    account_gather(launches, rounds, (uint64_t)flag[1]);
 
     if (timing) {
         for (size_t i = 0; i < ev_cat.size(); ++i) {
@@ -650,7 +776,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
     c.stats.n_batches = n_leaf_batches * (plain ? n_paths : 1);
     for (const Launch &ln : launches)
-        if (ln.kind != Launch::GATHER) (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
+        if (ln.kind != Launch::GATHER && ln.kind != Launch::FOLD) (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
     c.stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SF_OK;
 }

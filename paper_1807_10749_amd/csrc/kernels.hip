@@ -18,6 +18,15 @@ template <typename T> struct Cplx;
 template <> struct Cplx<float> { using type = float2; };
 template <> struct Cplx<double> { using type = double2; };
 
+// Workgroups are dispatched to the 8 XCDs round-robin, and each XCD has its own L2.  For a grid
+// that is a multiple of 8, this maps the hardware block index to a logical one so that XCD x runs
+// the contiguous logical range [x * n / 8, (x + 1) * n / 8): neighbouring bitstrings in the
+// visiting order (which share rows) then meet in one L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n)
+{
+    return (b & 7u) * (n >> 3) + (b >> 3);
+}
+
 template <typename T>
 __device__ __forceinline__ T inv_sqrt2() { return T(0.70710678118654752440084436210485); }
 
@@ -410,11 +419,11 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs g)
     const uint32_t P = 1u << g.p;
     const uint32_t L = P < 64u ? P : 64u;
     const uint32_t G = 64u / L;
-    const uint64_t wave = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint64_t wave = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
     const uint64_t jj = wave * G + (uint32_t)lane / L;
     const uint32_t sl = (uint32_t)lane % L;
     // bitstrings are visited in x_A order when `order` is given, so waves that share a
-    // block-A row run close together and find it in cache
+    // block-A row run close together, on one XCD, and find it in its L2
     const uint64_t j = (jj < g.n_bits && g.order) ? (uint64_t)g.order[jj] : jj;
     double re = 0.0, im = 0.0;
     if (j < g.n_bits) {
@@ -445,7 +454,7 @@ hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s)
     const uint64_t L = P < 64 ? P : 64;
     const uint64_t per_wave = 64 / L;
     const uint64_t waves = (g.n_bits + per_wave - 1) / per_wave;
-    const uint64_t blocks = (waves + 3) / 4;
+    const uint64_t blocks = ((waves + 3) / 4 + 7) / 8 * 8;   // a multiple of 8 (xcd_block)
     if (fp64) gather_kernel<double><<<(unsigned)blocks, 256, 0, s>>>(g);
     else gather_kernel<float><<<(unsigned)blocks, 256, 0, s>>>(g);
     return hipGetLastError();
@@ -508,6 +517,167 @@ hipError_t launch_pext(const uint64_t *bits, uint64_t n, uint64_t mask_a, uint64
 {
     if (n == 0) return hipSuccess;
     pext_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(bits, n, mask_a, mask_b, all, xa, xb, bad);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- leaf fold + FP64 path sum
+
+__device__ __forceinline__ uint32_t pext32(uint32_t x, uint32_t m)
+{
+    uint32_t r = 0;
+    int k = 0;
+    while (m) {
+        const int q = __ffs((int)m) - 1;
+        r |= ((x >> q) & 1u) << k;
+        ++k;
+        m &= m - 1;
+    }
+    return r;
+}
+
+// amp[j] += scale * sum_{slot < n_slots} sum_{i in child_mask[slot]} c_A[i] * WHT(c_B)[i]
+// with c_h[i] read from the parent level as described with FoldArgs.  WIDE: one bitstring per
+// wave, lanes over slots (P >= 64); otherwise P lanes per bitstring.  The leaf gates are applied
+// in the state precision, the products and sums over slots in FP64.
+template <typename T, int NB, bool WIDE>
+__global__ __launch_bounds__(256) void fold_kernel(FoldArgs g)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int V = 1 << NB;
+    const int lane = threadIdx.x & 63;
+    const uint32_t P = 1u << g.p;
+    const uint32_t L = WIDE ? 64u : P;
+    const uint32_t G = 64u / L;
+    const uint64_t wave = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t jj = wave * G + (uint32_t)lane / L;
+    const uint32_t sl = (uint32_t)lane % L;
+    uint64_t j = jj < g.n_bits ? (uint64_t)g.order[jj] : g.n_bits;
+    if (WIDE) {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)j);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(j >> 32));
+        j = ((uint64_t)hi << 32) | lo;
+    }
+    double re = 0.0, im = 0.0;
+    if (j < g.n_bits) {
+        const C *row[2][V];
+        T vr[2][V], vi[2][V];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const FoldHalf &f = g.h[h];
+            const uint32_t x = h ? g.xb[j] : g.xa[j];
+            const double *tr = f.tab + 2 * ((uint64_t)pext32(x, f.tmask) << f.n_s);
+            const uint32_t base = x & ~f.smask;
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                // a virtual slot whose branch bits outside S disagree with x contributes zero; its
+                // row is the row of the slot that agrees (rows depend on the S bits only), so
+                // every load below is unconditional and in bounds
+                const bool ok = (x & f.dmask) == f.dval[i];
+                row[h][i] = (const C *)f.par + ((uint64_t)(base | f.sdep[i]) << g.p);
+                vr[h][i] = ok ? (T)tr[2 * f.ymap[i]] : T(0);
+                vi[h][i] = ok ? (T)tr[2 * f.ymap[i] + 1] : T(0);
+            }
+        }
+        for (uint32_t s = sl; s < g.n_slots; s += L) {
+            C ta[V], tb[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                ta[i] = row[0][i][s];
+                tb[i] = row[1][i][s];
+            }
+            const uint32_t m = g.child_mask[s];
+            C a[V], b[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                a[i].x = vr[0][i] * ta[i].x - vi[0][i] * ta[i].y;
+                a[i].y = vr[0][i] * ta[i].y + vi[0][i] * ta[i].x;
+                b[i].x = vr[1][i] * tb[i].x - vi[1][i] * tb[i].y;
+                b[i].y = vr[1][i] * tb[i].y + vi[1][i] * tb[i].x;
+            }
+            // block B: the child's Z^b signs summed over the input branch bits
+#pragma unroll
+            for (int st = 1; st < V; st <<= 1)
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+                    if (!(i & st)) {
+                        const C u = b[i], w = b[i | st];
+                        b[i].x = u.x + w.x;
+                        b[i].y = u.y + w.y;
+                        b[i | st].x = u.x - w.x;
+                        b[i | st].y = u.y - w.y;
+                    }
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const double ar = a[i].x, ai = a[i].y, br = b[i].x, bi = b[i].y;
+                const double pr = ar * br - ai * bi, pi = ar * bi + ai * br;
+                const bool on = (m >> i) & 1u;     // a select, not a branch
+                re += on ? pr : 0.0;
+                im += on ? pi : 0.0;
+            }
+        }
+    }
+    for (uint32_t mm = 1; mm < L; mm <<= 1) {
+        re += __shfl_xor(re, (int)mm);
+        im += __shfl_xor(im, (int)mm);
+    }
+    if (j < g.n_bits && sl == 0) {
+        double *o = g.acc + 2 * j;
+        o[0] += g.scale_re * re - g.scale_im * im;
+        o[1] += g.scale_re * im + g.scale_im * re;
+    }
+}
+
+template <typename T, int NB>
+static void fold_launch(const FoldArgs &g, unsigned blocks, bool wide, hipStream_t s)
+{
+    if (wide) fold_kernel<T, NB, true><<<blocks, 256, 0, s>>>(g);
+    else fold_kernel<T, NB, false><<<blocks, 256, 0, s>>>(g);
+}
+
+hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s)
+{
+    if (g.n_bits == 0) return hipSuccess;
+    if (nb < 1 || nb > 4 || g.p < 0 || g.p > 31 || !g.order || !g.child_mask) return hipErrorInvalidValue;
+    const uint64_t P = (uint64_t)1 << g.p;
+    const bool wide = P >= 64;
+    const uint64_t per_wave = wide ? 1 : 64 / P;
+    const uint64_t waves = (g.n_bits + per_wave - 1) / per_wave;
+    const unsigned blocks = (unsigned)(((waves + 3) / 4 + 7) / 8 * 8);   // a multiple of 8 (xcd_block)
+    switch (nb) {
+    case 1: fp64 ? fold_launch<double, 1>(g, blocks, wide, s) : fold_launch<float, 1>(g, blocks, wide, s); break;
+    case 2: fp64 ? fold_launch<double, 2>(g, blocks, wide, s) : fold_launch<float, 2>(g, blocks, wide, s); break;
+    case 3: fp64 ? fold_launch<double, 3>(g, blocks, wide, s) : fold_launch<float, 3>(g, blocks, wide, s); break;
+    default: fp64 ? fold_launch<double, 4>(g, blocks, wide, s) : fold_launch<float, 4>(g, blocks, wide, s); break;
+    }
+    return hipGetLastError();
+}
+
+// key[i] = pext(x[i], mask): visiting key of the leaf fold (bitstrings that share their block-A
+// bits outside the fold's S qubits read the same parent rows)
+__global__ void key_kernel(const uint32_t *x, uint64_t n, uint32_t mask, uint32_t *key)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) key[i] = pext32(x[i], mask);
+}
+
+hipError_t launch_key(const uint32_t *x, uint64_t n, uint32_t mask, uint32_t *key, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    key_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, mask, key);
+    return hipGetLastError();
+}
+
+// *count += number of i with i == 0 or keys[i] != keys[i - 1] (distinct values of a sorted array)
+__global__ void count_runs_kernel(const uint32_t *keys, uint64_t n, int *count)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (i == 0 || keys[i] != keys[i - 1])) atomicAdd(count, 1);
+}
+
+hipError_t launch_count_runs(const uint32_t *keys, uint64_t n, int *count, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    count_runs_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(keys, n, count);
     return hipGetLastError();
 }
 

@@ -22,6 +22,16 @@ hipError_t launch_dense(const DenseArgs &a, unsigned grid, hipStream_t s);
 // Gather + FP64 path sum for one leaf batch.
 hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s);
 
+// Leaf fold + FP64 path sum for one parent batch (see FoldArgs); nb = branch bits of the leaf
+// level (1..4).  g.order and g.child_mask must be given.
+hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s);
+
+// key[i] = pext(x[i], mask) (32-bit).
+hipError_t launch_key(const uint32_t *x, uint64_t n, uint32_t mask, uint32_t *key, hipStream_t s);
+
+// *count += number of distinct values in the sorted array keys[0..n).
+hipError_t launch_count_runs(const uint32_t *keys, uint64_t n, int *count, hipStream_t s);
+
 // x_A = pext(x, mask_a), x_B = pext(x, mask_b) per bitstring; *bad is set to
 // 1 if some bitstring has bits outside `all`.
 hipError_t launch_pext(const uint64_t *bits, uint64_t n, uint64_t mask_a, uint64_t mask_b,

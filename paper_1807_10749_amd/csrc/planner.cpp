@@ -25,6 +25,124 @@ namespace sf {
 
 static int popcount64(uint64_t x) { return __builtin_popcountll(x); }
 
+namespace {
+void gate2x2(uint8_t kind, std::complex<double> g[4]);
+}  // namespace
+
+// Leaf segment of block h as V * D(b) (see LeafFold).  The branch operators of the leaf level
+// are diagonal, so they commute with every diagonal leaf gate; the form holds when no
+// non-diagonal gate precedes a branch operator on its qubit, and it is used when every
+// non-diagonal leaf gate acts on a branch qubit (then a child reads no more parent rows than
+// it has branch values).  V is multiplied out exactly with the normalised gates.
+static void build_leaf_fold(Circuit &c, int h)
+{
+    LeafFold &f = c.half[h].fold;
+    f = LeafFold();
+    const int L = (int)c.levels.size() - 1;
+    if (L < 1) return;
+    const int nb = c.levels[L].n_cut;
+    if (nb < 1 || nb > 4) return;
+    const std::vector<HalfOp> &seg = c.half[h].segments[L];
+    int bq[4] = {-1, -1, -1, -1};       // local qubit of the branch operator of path bit u
+    uint32_t nondiag_seen = 0, smask = 0, tmask = 0;
+    std::vector<HalfOp> rest;
+    for (const HalfOp &op : seg) {
+        if (op.kind == HK_PROJ || op.kind == HK_ZCTL) {
+            if (op.bit >= nb || bq[op.bit] >= 0 || ((nondiag_seen >> op.q0) & 1)) return;
+            bq[op.bit] = op.q0;
+            continue;
+        }
+        if (op.q0 >= 32 || (op.kind == HK_CZ && op.q1 >= 32)) return;
+        if (!is_diag(op.kind)) {
+            nondiag_seen |= 1u << op.q0;
+            smask |= 1u << op.q0;
+        }
+        tmask |= 1u << op.q0;
+        if (op.kind == HK_CZ) tmask |= 1u << op.q1;
+        rest.push_back(op);
+    }
+    uint32_t bmask = 0;
+    for (int u = 0; u < nb; ++u) {
+        if (bq[u] < 0 || bq[u] >= 32) return;
+        bmask |= 1u << bq[u];
+    }
+    if ((smask & ~bmask) != 0) return;            // a non-diagonal gate off the branch qubits
+    const int n_t = __builtin_popcount(tmask), n_s = __builtin_popcount(smask);
+    if (n_t > 8) return;
+    // T-local index of each local qubit in T, S-local index of each qubit in S
+    int tpos[32], spos[32];
+    for (int t = 0, a = 0, b = 0; t < 32; ++t) {
+        tpos[t] = ((tmask >> t) & 1) ? a++ : -1;
+        spos[t] = ((smask >> t) & 1) ? b++ : -1;
+    }
+    // V as a 2^n_t x 2^n_t matrix, column by column
+    const int D = 1 << n_t;
+    std::vector<std::complex<double>> M((size_t)D * D);
+    const std::complex<double> I(0, 1), omega(std::cos(M_PI / 4), std::sin(M_PI / 4));
+    const std::complex<double> s_h(1.0 / std::sqrt(2.0), 0.0), s_xy(0.5, 0.5);
+    for (int col = 0; col < D; ++col) {
+        std::vector<std::complex<double>> v(D, 0.0);
+        v[col] = 1.0;
+        for (const HalfOp &op : rest) {
+            const int a = tpos[op.q0];
+            if (op.kind == HK_T) {
+                for (int r = 0; r < D; ++r) if ((r >> a) & 1) v[r] *= omega;
+            } else if (op.kind == HK_CZ) {
+                const int b = tpos[op.q1];
+                for (int r = 0; r < D; ++r) if (((r >> a) & 1) && ((r >> b) & 1)) v[r] = -v[r];
+            } else {
+                std::complex<double> g[4];
+                gate2x2(op.kind, g);
+                const std::complex<double> sc = op.kind == HK_H ? s_h : s_xy;
+                for (int r = 0; r < D; ++r) {
+                    if ((r >> a) & 1) continue;
+                    const int r1 = r | (1 << a);
+                    const std::complex<double> x0 = v[r], x1 = v[r1];
+                    v[r] = sc * (g[0] * x0 + g[1] * x1);
+                    v[r1] = sc * (g[2] * x0 + g[3] * x1);
+                }
+            }
+        }
+        for (int r = 0; r < D; ++r) M[(size_t)r * D + col] = v[r];
+    }
+    // table row x_T, entry y: column = x_T with its S bits replaced by y
+    f.tab.assign((size_t)D << n_s, 0.0);
+    for (int xt = 0; xt < D; ++xt)
+        for (int y = 0; y < (1 << n_s); ++y) {
+            int col = xt;
+            for (int t = 0; t < 32; ++t)
+                if (spos[t] >= 0) {
+                    const int bit = (y >> spos[t]) & 1;
+                    col = (col & ~(1 << tpos[t])) | (bit << tpos[t]);
+                }
+            f.tab[((size_t)xt << n_s) + y] = M[(size_t)xt * D + col];
+        }
+    // virtual slots: child branch value i sets the branch qubits' input bits
+    for (int i = 0; i < (1 << nb); ++i) {
+        uint32_t sdep = 0, dval = 0;
+        int y = 0;
+        for (int u = 0; u < nb; ++u) {
+            const uint32_t bit = (i >> u) & 1;
+            if (spos[bq[u]] >= 0) {
+                sdep |= bit << bq[u];
+                y |= (int)bit << spos[bq[u]];
+            } else {
+                dval |= bit << bq[u];
+            }
+        }
+        f.sdep[i] = sdep;
+        f.dval[i] = dval;
+        f.ymap[i] = (uint8_t)y;
+    }
+    f.nb = nb;
+    f.n_s = n_s;
+    f.n_t = n_t;
+    f.smask = smask;
+    f.tmask = tmask;
+    f.dmask = bmask & ~smask;
+    f.ok = true;
+}
+
 int build_programs(Circuit &c, std::string &err)
 {
     const int n = c.n;
@@ -164,6 +282,7 @@ int build_programs(Circuit &c, std::string &err)
             hp.seg_scale[l] = std::pow(s_h, nh) * std::pow(s_xy, nxy) * std::ldexp(1.0, e);
         }
     }
+    for (int h = 0; h < 2; ++h) build_leaf_fold(c, h);
     c.plan_cache.clear();
     return SF_OK;
 }

@@ -115,4 +115,33 @@ struct GatherArgs {
     double scale_re, scale_im;    // product of both blocks' tracked scalars
 };
 
+// Leaf fold: the gather reads the parent level (level L-1) and applies the leaf segment
+// itself.  For block h, output bits x (local) and child branch value i ("virtual slot"):
+//   c_h[i] = [ (x & dmask) == dval[i] ] * tab[pext(x, tmask) * 2^n_s + ymap[i]]
+//            * parent_h[(x & ~smask) | sdep[i]][slot]
+// Block A's projectors keep exactly child i; block B's Z^b signs become a Walsh-Hadamard
+// transform over i.  Then amp[x] += scale * sum_slot sum_{i in child_mask[slot]} c_A[i] c_B'[i]
+// with c_B' = WHT(c_B).
+struct FoldHalf {
+    const void *par;              // parent states of the block, 2^(p+q) complex
+    const double *tab;            // complex (re, im) table of V
+    uint32_t smask, tmask, dmask;
+    int32_t n_s;
+    uint32_t sdep[16];
+    uint32_t dval[16];
+    uint8_t ymap[16];
+};
+
+struct FoldArgs {
+    FoldHalf h[2];
+    const uint32_t *xa, *xb;      // per bitstring: x_A, x_B
+    const uint32_t *order;        // visiting order of the bitstrings
+    const uint32_t *child_mask;   // per parent slot: bit i set if child i is requested
+    double *acc;                  // 2 * n_bits doubles, accumulated
+    uint64_t n_bits;
+    uint32_t n_slots;             // real parent slots (<= 2^p)
+    int32_t p;                    // parent slot bits
+    double scale_re, scale_im;
+};
+
 }  // namespace sf

@@ -48,6 +48,21 @@ struct SegmentPlan {
     bool ok = true;      // false if some operation could not be scheduled
 };
 
+// The leaf segment of one block written as V * D(b): D(b) = the leaf level's branch operators
+// for child branch value b (diagonal), V = the block's remaining leaf gates (independent of b).
+// When every non-diagonal leaf gate acts on a branch qubit, a child's amplitude at x is one
+// parent amplitude per "virtual slot" i (child branch value i, see FoldHalf) times an entry of
+// V, so the gather can read the parent level and the leaf states are never written.
+struct LeafFold {
+    bool ok = false;
+    int nb = 0;                 // branch bits of the leaf level
+    int n_s = 0, n_t = 0;       // |S| (qubits of non-diagonal leaf gates), |T| (all qubits V touches)
+    uint32_t smask = 0, tmask = 0, dmask = 0;   // local masks of S, T, and branch qubits outside S
+    uint32_t sdep[16] = {0}, dval[16] = {0};
+    uint8_t ymap[16] = {0};
+    std::vector<std::complex<double>> tab;      // [2^n_t][2^n_s]: <x_T| V |x_T with S bits := y>
+};
+
 struct HalfProgram {
     int q = 0;                                  // qubits in the block
     uint64_t init_h_mask = 0;                   // local qubits whose opening H is folded into the initial state
@@ -55,6 +70,7 @@ struct HalfProgram {
     std::vector<std::complex<double>> seg_scale;  // scalar of each segment's unnormalised gates incl. rescaling
     std::vector<int> seg_rescale_exp;           // power of two divided out at the end of each segment
     std::complex<double> init_scale = 1.0;      // 2^{-h/2} for the folded opening H gates
+    LeafFold fold;                              // leaf segment as V * D(b), if it qualifies
 };
 
 struct Level {

@@ -239,6 +239,7 @@ int set_tuning(sf_circuit_t *c, const sf_tuning_t *t)
     if (!c || !t) return fail(SF_ERR_INVALID, "NULL argument");
     if (t->reg_qubits > 5) return fail(SF_ERR_INVALID, "reg_qubits must be at most 5");
     if (t->dense_qubits == 1 || t->dense_qubits > 4) return fail(SF_ERR_INVALID, "dense_qubits must be 0 or 2..4");
+    if (t->no_leaf_fold > 1) return fail(SF_ERR_INVALID, "no_leaf_fold must be 0 or 1");
     auto pow2ok = [](uint32_t v) { return v == 0 || (v & (v - 1)) == 0; };
     if (!pow2ok(t->leaf_batch) || !pow2ok(t->max_slots)) return fail(SF_ERR_INVALID, "batch sizes must be powers of two");
     c->tuning = *t;
@@ -289,11 +290,13 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
         const uint32_t regs[3] = {fp64 ? 4u : 5u, fp64 ? 3u : 4u, fp64 ? 2u : 3u};
         const uint32_t leafs[4] = {0u, 4096u, 1024u, 256u};
         const uint32_t wpcs[3] = {32u, 16u, 64u};
+        const bool foldable = c->levels.size() > 1 && c->half[0].fold.ok && c->half[1].fold.ok;
         for (uint32_t r : regs)
-            for (uint32_t lf : leafs)
-                for (uint32_t w : wpcs) {
-                    cands.push_back(sf_tuning_t{r, lf, 0, w, 0});
-                    if (!fp64) cands.push_back(sf_tuning_t{r, lf, 0, w, 4});   // dense blocks on matrix cores
+            for (uint32_t w : wpcs)
+                for (uint32_t dq : {0u, 4u}) {
+                    if (dq && fp64) continue;                 // dense blocks on matrix cores: complex64 only
+                    if (foldable) cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0});
+                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1});
                 }
         // rank by the planned cost
         std::vector<std::pair<double, size_t>> ranked;
@@ -360,6 +363,15 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
             if (qmin + p < 6) p = 6 - qmin;
             s += "level " + std::to_string(l) + " cycle " + std::to_string(c->levels[l].cycle) +
                  " bits " + std::to_string(c->levels[l].bits_after) + " p " + std::to_string(p) + ":";
+            if (l == L && L > 0 && c->tuning.no_leaf_fold == 0 && c->half[0].fold.ok && c->half[1].fold.ok) {
+                for (int h = 0; h < 2; ++h)
+                    s += std::string(h ? "  B " : " A ") + std::to_string(c->half[h].segments[l].size()) +
+                         " ops folded into the gather (branch bits " + std::to_string(c->half[h].fold.nb) +
+                         ", S " + std::to_string(c->half[h].fold.n_s) + " qubits, T " +
+                         std::to_string(c->half[h].fold.n_t) + ")";
+                s += "\n";
+                continue;
+            }
             for (int h = 0; h < 2; ++h) {
                 const sf::SegmentPlan &sp = sf::get_segment_plan(*c, h, l, p, R, (int)c->tuning.dense_qubits);
                 int nd = 0;

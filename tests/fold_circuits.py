@@ -1,0 +1,39 @@
+"""Hand-built circuits whose last tree level has the shapes the folded leaf gather handles.
+
+Only gate lists (no arithmetic of the method): a random grid circuit without its closing H
+layer, then one cycle of CZs crossing the column cut between columns 1 and 2 in every row (one
+tree level with `rows` branch bits), then a tail of gates chosen so that the last level mixes
+sqrt(X)/sqrt(Y)/H on branch qubits, T and CZ phases after them (one CZ reaching a qubit that only
+diagonal gates touch), and branch qubits that no non-diagonal gate touches after the crossing.
+"""
+import numpy as np
+
+from workload import CZ, GATE_DTYPE, H, T, XH, YH, grid_circuit
+
+
+def crossing_tail_circuit(rows=4, depth=8, seed=5):
+    cols = 4
+    base = grid_circuit(rows, cols, depth, seed)
+    gates = [tuple(g) for g in base if g["cycle"] <= depth]
+    q = lambda r, c: r * cols + c
+    c1, c2, c3, c4 = depth + 1, depth + 2, depth + 3, depth + 4
+    for r in range(rows):
+        gates.append((CZ, 0, c1, q(r, 1), q(r, 2)))      # crossing: block A = columns 0-1
+    # block A: sqrt(X), then CZ to the non-branch qubit (0,0), then H on (0,1); H, T, H on (1,1);
+    # H on (2,1); nothing after the crossing on (3,1)
+    gates += [(XH, 0, c2, q(0, 1), 0), (H, 0, c2, q(1, 1), 0), (H, 0, c2, q(2, 1), 0)]
+    gates += [(CZ, 0, c3, q(0, 1), q(0, 0)), (T, 0, c3, q(1, 1), 0)]
+    gates += [(H, 0, c4, q(0, 1), 0), (H, 0, c4, q(1, 1), 0)]
+    # block B: sqrt(Y), T, H on (0,2); H, then CZ to the non-branch qubit (1,3) on (1,2); only a
+    # T (diagonal) on (2,2); nothing on (3,2)
+    gates += [(YH, 0, c2, q(0, 2), 0), (H, 0, c2, q(1, 2), 0), (T, 0, c2, q(2, 2), 0)]
+    gates += [(T, 0, c3, q(0, 2), 0), (CZ, 0, c3, q(1, 2), q(1, 3))]
+    gates += [(H, 0, c4, q(0, 2), 0)]
+    # the other qubits of columns 0 and 3 end with an H (not part of the last level)
+    gates += [(H, 0, c4, q(r, 0), 0) for r in range(1, rows)]
+    gates += [(H, 0, c4, q(r, 3), 0) for r in range(rows) if r != 1]
+    mask_a = 0
+    for r in range(rows):
+        mask_a |= (1 << q(r, 0)) | (1 << q(r, 1))
+    gates.sort(key=lambda g: g[2])           # stable: list order within a cycle is kept
+    return rows, cols, np.array(gates, dtype=GATE_DTYPE), mask_a

@@ -154,12 +154,51 @@ def test_dense_plan_uses_matrix_core_blocks(sf):
     sf.destroy_circuit(c)
 
 
+def test_leaf_fold_eligibility(sf):
+    """The last tree level is folded into the gather exactly when every non-diagonal gate of it
+    acts on a branch qubit of that level."""
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from fold_circuits import crossing_tail_circuit
+    expect = {"grid4x4_d16": False, "grid5x6_d24": True, "grid6x7_d32": False, "grid7x8_d40": False}
+    for name, folded in expect.items():
+        cfg = CONFIGS[name]
+        c = sf.create_circuit(cfg.rows, cfg.cols, grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed))
+        sf.set_cut(c, cfg.cut_mask())
+        last = sf.describe_plan(c).strip().splitlines()[-1]
+        assert ("folded" in last) == folded, name
+        if folded:
+            assert last.count("branch bits 3, S 3 qubits, T 3") == 2
+            # without the fold the leaf states are written: the workspace bound grows by them
+            small = sf.workspace_size(c, 1 << 15, 100000)
+            sf.set_tuning(c, no_leaf_fold=1)
+            assert "folded" not in sf.describe_plan(c)
+            assert sf.workspace_size(c, 1 << 15, 100000) - small >= 2 * (1 << 30) * 8
+        sf.destroy_circuit(c)
+    for rows, nb in ((3, 3), (4, 4)):
+        r, cc, g, m = crossing_tail_circuit(rows=rows)
+        c = sf.create_circuit(r, cc, g)
+        assert sf.set_cut(c, m) >= nb
+        last = sf.describe_plan(c).strip().splitlines()[-1]
+        assert f"branch bits {nb}, S 3 qubits, T 4" in last and f"branch bits {nb}, S 2 qubits, T 3" in last
+        sf.destroy_circuit(c)
+    # a non-diagonal gate on a non-branch qubit in the last level: not folded
+    r, cc, g, m = crossing_tail_circuit(rows=3)
+    extra = np.array([(H, 0, int(g["cycle"].max()) + 1, 0, 0)], dtype=GATE_DTYPE)   # H on (0,0) after its CZ
+    c = sf.create_circuit(r, cc, np.concatenate([g, extra]))
+    sf.set_cut(c, m)
+    assert "folded" not in sf.describe_plan(c)
+    sf.destroy_circuit(c)
+
+
 def test_tuning_roundtrip(sf):
     w = make_workload("grid4x4_d16", n_bits=4)
     c = sf.create_circuit(4, 4, w["gates"])
-    sf.set_tuning(c, reg_qubits=3, leaf_batch=64, max_slots=1024, waves_per_cu=16, dense_qubits=4)
+    sf.set_tuning(c, reg_qubits=3, leaf_batch=64, max_slots=1024, waves_per_cu=16, dense_qubits=4, no_leaf_fold=1)
     assert sf.get_tuning(c) == {"reg_qubits": 3, "leaf_batch": 64, "max_slots": 1024, "waves_per_cu": 16,
-                                "dense_qubits": 4}
+                                "dense_qubits": 4, "no_leaf_fold": 1}
+    with pytest.raises(sf.SFError):
+        sf.set_tuning(c, no_leaf_fold=2)
     with pytest.raises(sf.SFError):
         sf.set_tuning(c, dense_qubits=1)
     with pytest.raises(sf.SFError):

@@ -138,8 +138,11 @@ def test_register_widths_agree(sf):
 
 # ---------------------------------------------------------------- 5x6, 1+24+1, 15+15
 
-def test_grid5x6_path_subsets(sf):
+@pytest.mark.parametrize("no_fold", [0, 1])
+def test_grid5x6_path_subsets(sf, no_fold):
     cfg, g, c = _circuit(sf, "grid5x6_d24")
+    c.tune(no_leaf_fold=no_fold)
+    say(f"grid5x6_d24 no_leaf_fold={no_fold}")
     bits = random_bitstrings(30, 4000, cfg.bits_seed)
     rng = np.random.default_rng(1)
     ids = np.sort(rng.choice(1 << c.k, size=200, replace=False)).astype(np.uint64)
@@ -227,3 +230,71 @@ def test_dense_blocks_parity(sf, name, npaths):
     a = c.amplitudes(bits, path_ids=ids)
     o = oracle.path_sum(cfg.n_qubits, g, cfg.cut_mask(), ids, bits)
     assert c11_error(a, o, ids.size, c.k, cfg.n_qubits) <= TOL_C64
+
+
+# ---------------------------------------------------------------- last level folded into the gather
+
+def _tail(sf, rows):
+    import sys, os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from fold_circuits import crossing_tail_circuit
+    r, cc, g, m = crossing_tail_circuit(rows=rows)
+    return r * cc, g, m, sf.Circuit(r, cc, g, m)
+
+
+@pytest.mark.parametrize("rows", [3, 4])
+def test_leaf_fold_tail_circuits(sf, rows):
+    """Leaf levels with 3 and 4 branch bits, phases after the branch gates, and branch qubits that
+    only diagonal gates touch: folded and materialised leaves both give the oracle's result."""
+    n, g, m, c = _tail(sf, rows)
+    assert "folded" in sf.describe_plan(c.handle)
+    bits = random_bitstrings(n, 3000, 21 + rows)
+    ids = np.arange(1 << c.k, dtype=np.uint64)
+    o = oracle.path_sum(n, g, m, ids, bits)
+    assert np.abs(o - oracle.full_state(n, g)[bits.astype(np.int64)]).max() < 1e-13
+    for no_fold in (0, 1):
+        c.tune(no_leaf_fold=no_fold)
+        say(f"tail circuit rows={rows} all paths no_leaf_fold={no_fold}")
+        a = c.amplitudes(bits)
+        assert c11_error(a, o, ids.size, c.k, n) <= TOL_C64, no_fold
+        say(f"tail circuit rows={rows} all paths complex128 no_leaf_fold={no_fold}")
+        a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS)
+        assert c11_error(a, o, ids.size, c.k, n) <= TOL_C128, no_fold
+    c.tune(no_leaf_fold=0)
+    # sampled paths: parents with some of their children only
+    sub = sf.sample_paths(c.k, 0.3, 77)
+    say(f"tail circuit rows={rows} {sub.size} sampled paths")
+    a = c.amplitudes(bits, path_ids=sub)
+    o = oracle.path_sum(n, g, m, sub, bits)
+    assert c11_error(a, o, sub.size, c.k, n) <= TOL_C64
+    # one path at a time (plain form) and single-path indexing
+    ids3 = np.array([1, (1 << c.k) - 2, (1 << c.k) // 3 + 1], dtype=np.uint64)
+    say(f"tail circuit rows={rows} plain form {ids3.tolist()}")
+    a = c.amplitudes(bits, path_ids=ids3, flags=sf.SF_PLAIN)
+    o = oracle.path_sum(n, g, m, ids3, bits)
+    assert c11_error(a, o, ids3.size, c.k, n) <= TOL_C64
+    for p in ids3:
+        a = c.amplitudes(bits[:500], path_ids=[p], flags=sf.SF_FP64_SWEEPS)
+        o = oracle.path_sum(n, g, m, [p], bits[:500])
+        assert c11_error(a, o, 1, c.k, n) <= TOL_C128, int(p)
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 3, 0), (2, 3, 5, 0), (2, 3, 21, 0), (4, 5, 7, 0), (4, 5, 15, 0)])
+def test_leaf_fold_grid_circuits(sf, shape):
+    """Grid circuits whose last level qualifies, from one slot per parent batch (fewer slots than
+    lanes) to 2^7; every bitstring of the smaller ones."""
+    rows, cols, depth, seed = shape
+    n = rows * cols
+    g = grid_circuit(rows, cols, depth, seed)
+    h = sf.create_circuit(rows, cols, g)
+    m = sf.choose_cut(h)
+    sf.destroy_circuit(h)
+    c = sf.Circuit(rows, cols, g, m)
+    assert "folded" in sf.describe_plan(c.handle)
+    bits = np.arange(1 << n, dtype=np.uint64) if n <= 12 else random_bitstrings(n, 5000, 31)
+    say(f"grid {rows}x{cols} depth {depth} seed {seed} folded leaf, {bits.size} bitstrings")
+    a = c.amplitudes(bits)
+    o = oracle.full_state(n, g)[bits.astype(np.int64)]
+    assert c11_error(a, o, 1, 0, n) <= TOL_C64
+    a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS)
+    assert c11_error(a, o, 1, 0, n) <= TOL_C128
