@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving mix (0 = skip)")
     ap.add_argument("--tuning", default="",
-                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold]] (skips autotune)")
+                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels]]] "
+                         "(skips autotune)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (known HBM traffic for counter scaling)")
     return ap.parse_args()
@@ -98,8 +99,9 @@ def main():
         r, lb, wpc = vals[:3]
         dense = vals[3] if len(vals) > 3 else 0
         nofold = vals[4] if len(vals) > 4 else 0
+        flev = vals[5] if len(vals) > 5 else 0
         sf.set_tuning(c.handle, reg_qubits=r, leaf_batch=lb, waves_per_cu=wpc, dense_qubits=dense,
-                      no_leaf_fold=nofold)
+                      no_leaf_fold=nofold, fold_levels=flev)
         tuning = sf.get_tuning(c.handle)
     elif not args.no_autotune:
         tuning = sf.autotune(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,
@@ -108,7 +110,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    sweep_ms = gather_ms = other_ms = host_ms = 0.0
+    sweep_ms = gather_ms = other_ms = host_ms = plan_ms = 0.0
     sweep_launches = gather_launches = 0
     sweep_bytes = gather_bytes = gather_row_bytes = 0
     t0 = time.perf_counter()
@@ -119,6 +121,7 @@ def main():
         gather_ms += st["ms_gather"]
         other_ms += st["ms_other"]
         host_ms += st["ms_total"]
+        plan_ms += st["ms_plan"]
         sweep_launches += st["n_sweep_launches"]
         gather_launches += st["n_gather_launches"]
         sweep_bytes += st["sweep_bytes"]
@@ -185,6 +188,7 @@ def main():
         "kernel_ms_per_step": {"sweep": sweep_ms / args.steps, "gather": gather_ms / args.steps,
                                "other": other_ms / args.steps},
         "run_paths_wall_ms_per_step": host_ms / args.steps,
+        "host_plan_ms_per_step": plan_ms / args.steps,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_launch_ms, "launches_per_step": dom_n / args.steps,

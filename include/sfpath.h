@@ -151,10 +151,13 @@ typedef struct {
     uint32_t dense_qubits;   /* 0: gates on registers and lanes only; 2..4: also fuse windows of up to
                                 this many qubits into dense 16 x 16 blocks applied on matrix cores
                                 (complex64 sweeps only) */
-    uint32_t no_leaf_fold;   /* 0: when every non-diagonal gate of the last tree level acts on a
-                                branch qubit of that level, the gather reads the level above and
-                                applies the last level itself (leaf states are never written);
+    uint32_t no_leaf_fold;   /* 0: when every non-diagonal gate of the last tree level(s) acts
+                                on a branch qubit of those levels, the gather reads the level
+                                above and applies them itself (their states are never written);
                                 1: always write the leaf states and gather from them */
+    uint32_t fold_levels;    /* most trailing tree levels folded into the gather (0: as many as
+                                qualify, up to 5 path bits; a group of levels qualifies when all
+                                its non-diagonal gates act on its branch qubits) */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);
@@ -167,8 +170,10 @@ int get_tuning(const sf_circuit_t *c, sf_tuning_t *t);
  * model of the form of Section 9, Eq. (t_tot): the planned sweep bytes and
  * gather bytes over measured bandwidths plus a per-launch cost (the paper's
  * C1 2^x_p (q1 2^q1 + q2 2^q2)(d_p + C2 2^x_b d_b) + C3 2^(x_p+x_b) n_a
- * with the constants taken from the device).  The n_measure best-ranked
- * candidates, plus the current tuning, are then timed with real run_paths
+ * with the constants taken from the device).  The best-ranked candidate of
+ * every kind (folded levels or written leaves, dense blocks or not), more
+ * candidates by rank up to n_measure, and the current tuning are then timed
+ * with real run_paths
  * calls on this request (same argument rules as run_paths; amps is
  * overwritten) and the fastest is kept on the circuit and written to *best.
  * Results are cached for the process per (block sizes, k, number of paths,
@@ -198,6 +203,7 @@ typedef struct {
     uint64_t gather_row_bytes;  /* rows of both blocks read once per bitstring (no reuse) */
     uint64_t a_groups;       /* groups of bitstrings that share their block-A rows (estimated
                                 from the bitstring count in a planning-only run) */
+    double ms_plan;          /* host time from entry to the first enqueued device operation */
 } sf_run_stats_t;
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);

@@ -109,12 +109,6 @@ struct BatchRec { int level; size_t table_off; uint64_t slots; };
 
 struct BlobEntry { size_t off; uint32_t words, groups_word, terms_word; };
 
-// The leaf level is folded into the gather (see LeafFold) unless the tuning says otherwise.
-bool fold_active(const Circuit &c)
-{
-    return c.levels.size() > 1 && c.tuning.no_leaf_fold == 0 && c.half[0].fold.ok && c.half[1].fold.ok;
-}
-
 }  // namespace
 
 int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32_t flags, size_t *bytes)
@@ -122,14 +116,12 @@ int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32
     const size_t elem = (flags & SF_FP64_SWEEPS) ? 16 : 8;
     const size_t sigma = (size_t(1) << c.half[0].q) * elem + (size_t(1) << c.half[1].q) * elem;
     const int L = (int)c.levels.size() - 1;
-    const bool fold = fold_active(c);
+    const int FD = fold_depth(c);
     // upper bound: every level resident with min(2^bits, n_paths) nodes
     size_t total = 0;
+    if (FD) total += align_up(n_paths * 4 + 64 * 4);   // descendant masks instead of folded levels
     for (int l = 0; l <= L; ++l) {
-        if (fold && l == L) {
-            total += align_up(n_paths * 4 + 64 * 4);   // child masks instead of leaf states
-            continue;
-        }
+        if (l > L - FD) continue;
         const int b = c.levels[l].bits_after;
         uint64_t nodes = b >= 63 ? n_paths : std::min<uint64_t>(uint64_t(1) << b, n_paths);
         total += next_pow2(std::max<uint64_t>(nodes, 1)) * sigma;
@@ -158,7 +150,10 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     const int qh[2] = {c.half[0].q, c.half[1].q};
     int R = c.tuning.reg_qubits ? (int)c.tuning.reg_qubits : kMaxRegBits;
     R = std::max(1, std::min(R, fp64 ? kMaxRegBitsF64 : kMaxRegBits));
-    const bool fold = fold_active(c);
+    const int FD = fold_depth(c);          // trailing levels folded into the gather
+    const bool fold = FD > 0;
+    const int fold_at = L - FD;            // the level the gather reads
+    const LeafFold *fh[2] = {fold ? &c.half[0].folds[FD - 1] : nullptr, fold ? &c.half[1].folds[FD - 1] : nullptr};
     c.stats = sf_run_stats_t{};
 
     if (!path_ids && n_paths && k < 64 && ((path_begin + n_paths - 1) >> k) != 0) {
@@ -224,7 +219,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
         for (int l = 1; l <= L; ++l)
             if (tree.node[l].size() == tree.node[l - 1].size()) lb[l].alias = lb[l - 1].alias >= 0 ? lb[l - 1].alias : l - 1;
-        if (fold) { lb[L].none = true; lb[L].alias = -1; }
+        for (int l = fold_at + 1; fold && l <= L; ++l) { lb[l].none = true; lb[l].alias = -1; }
         const uint64_t maxs = c.tuning.max_slots ? c.tuning.max_slots : (uint64_t(1) << 20);
         const uint64_t leafmax = c.tuning.leaf_batch ? c.tuning.leaf_batch : maxs;
         for (int l = 0; l <= L; ++l) {
@@ -236,7 +231,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             table_bound += 2 * tree.node[l].size() + lb[l].cap + min_slots * (l ? tree.node[l - 1].size() : 1);
         }
         table_bound = align_up(table_bound * 8) + align_up(table_bound * 4);
-        if (fold) table_bound += align_up(tree.node[L - 1].size() * 4);   // child masks
+        if (fold) table_bound += align_up(tree.node[fold_at].size() * 4);   // descendant masks
         size_t budget;
         if (workspace) {
             if (workspace_bytes < fixed + table_bound) { err = "workspace too small"; return SF_ERR_OOM; }
@@ -285,14 +280,15 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         leaf_scale[h] = s;
     }
     const std::complex<double> gscale = leaf_scale[0] * leaf_scale[1];
-    // folded leaf: the last segment is applied with its exact matrix, so its scalar is not tracked
+    // folded levels are applied with their exact matrices, so their scalars are not tracked
     std::complex<double> fscale = 1.0;
     for (int h = 0; h < 2; ++h) {
         std::complex<double> s = c.half[h].init_scale;
-        for (int l = 0; l < L; ++l) s *= c.half[h].seg_scale[l];
+        for (int l = 0; l <= fold_at; ++l) s *= c.half[h].seg_scale[l];
         fscale *= s;
     }
-    std::vector<uint32_t> tmaskv;        // child masks of folded parent batches
+    std::vector<uint32_t> tmaskv;        // descendant masks of the batches the fold reads
+    std::vector<uint32_t> node_mask;     // per node of that level (filled below)
     size_t fold_tab_off[2] = {0, 0};
     size_t plain_mask_idx = SIZE_MAX;
 
@@ -337,8 +333,8 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         for (const Launch &ln : ls) {
             if (ln.kind != Launch::GATHER && ln.kind != Launch::FOLD) continue;
             const uint64_t slots = ln.kind == Launch::FOLD ? ln.fa.n_slots : ln.ga.n_slots;
-            const uint64_t ra = ln.kind == Launch::FOLD ? uint64_t(1) << c.half[0].fold.n_s : 1;
-            const uint64_t rb = ln.kind == Launch::FOLD ? uint64_t(1) << c.half[1].fold.n_s : 1;
+            const uint64_t ra = ln.kind == Launch::FOLD ? uint64_t(1) << fh[0]->n_s : 1;
+            const uint64_t rb = ln.kind == Launch::FOLD ? uint64_t(1) << fh[1]->n_s : 1;
             const uint64_t per = slots * elem * (a_groups * ra + (uint64_t)n_bits * rb) + (uint64_t)n_bits * 44 +
                                  (ln.kind == Launch::FOLD ? slots * 4 : 0);
             c.stats.n_gather_launches += rounds;
@@ -448,41 +444,49 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     visit = [&](int l, const std::vector<uint32_t> &nodes, uint64_t nslots) {
         if (plan_error) return;
         const int own = lb[l].alias >= 0 ? lb[l].alias : l;
-        if (fold && l == L - 1) {
-            // the gather reads this batch and applies the leaf segment itself
+        if (fold && l == fold_at) {
+            // the gather reads this batch and applies the folded levels itself
             Launch ln;
             ln.kind = Launch::FOLD;
             ln.level = l;
             FoldArgs &f = ln.fa;
             std::memset(&f, 0, sizeof(f));
             for (int h = 0; h < 2; ++h) {
-                const LeafFold &lf = c.half[h].fold;
-                FoldHalf &fh = f.h[h];
-                fh.smask = lf.smask;
-                fh.tmask = lf.tmask;
-                fh.dmask = lf.dmask;
-                fh.n_s = lf.n_s;
-                for (int i = 0; i < 16; ++i) { fh.sdep[i] = lf.sdep[i]; fh.dval[i] = lf.dval[i]; fh.ymap[i] = lf.ymap[i]; }
+                const LeafFold &lf = *fh[h];
+                FoldHalf &d = f.h[h];
+                d.smask = lf.smask;
+                d.tmask = lf.tmask;
+                d.n_s = lf.n_s;
+                d.dsel = 0;
+                for (int u = 0; u < lf.nb; ++u) {
+                    d.bq[u] = (uint8_t)lf.bq[u];
+                    if (lf.ypos[u] >= 0) {
+                        d.sstride[u] = 1u << lf.bq[u];
+                        d.ypos[u] = (uint8_t)lf.ypos[u];
+                    } else {
+                        d.dsel |= 1u << u;
+                    }
+                }
             }
             f.n_bits = n_bits;
             f.n_slots = (uint32_t)nodes.size();
             f.p = log2u(nslots);
             f.scale_re = fscale.real();
             f.scale_im = fscale.imag();
-            const int nb = c.levels[L].n_cut;
-            const uint32_t full = (1u << nb) - 1;
-            const std::vector<uint64_t> &fc = tree.first_child[l];
-            const std::vector<uint64_t> &cnode = tree.node[L];
-            std::vector<uint32_t> m(nodes.size(), 0);
-            for (size_t i = 0; i < nodes.size(); ++i)
-                for (uint64_t cc = fc[nodes[i]]; cc < fc[nodes[i] + 1]; ++cc) m[i] |= 1u << (cnode[cc] & full);
+            const int nd = 1 << fh[0]->nb;                       // descendants per node (one mask bit each)
+            const uint32_t full = nd >= 32 ? ~0u : (1u << nd) - 1;
+            bool all = true;
             ln.mask_off = tmaskv.size();
             if (plain) plain_mask_idx = tmaskv.size();
-            tmaskv.insert(tmaskv.end(), m.begin(), m.end());
+            for (size_t i = 0; i < nodes.size(); ++i) {
+                tmaskv.push_back(node_mask[nodes[i]]);
+                all = all && node_mask[nodes[i]] == full;
+            }
+            f.all_children = all && !plain ? 1 : 0;
             ln.dst_off = lb[own].off[0];
             ln.src_off = lb[own].off[1];
             ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem *
-                       ((uint64_t(1) << c.half[0].fold.n_s) + (uint64_t(1) << c.half[1].fold.n_s));
+                       ((uint64_t(1) << fh[0]->n_s) + (uint64_t(1) << fh[1]->n_s));
             launches.push_back(ln);
             ++n_leaf_batches;
             return;
@@ -556,9 +560,20 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
     };
 
+    // per node of the level the gather reads: bit i set if its descendant with branch value i
+    // (the low path bits decided by the folded levels) is requested
+    if (n_paths && fold) {
+        node_mask.assign(tree.node[fold_at].size(), 0);
+        const uint64_t low = (uint64_t(1) << fh[0]->nb) - 1;
+        for (size_t i = 0; i < tree.node[L].size(); ++i) {
+            size_t a = i;
+            for (int l = L; l > fold_at; --l) a = tree.parent[l][a];
+            node_mask[a] |= 1u << (tree.node[L][i] & low);
+        }
+    }
     if (n_paths && fold) {
         for (int h = 0; h < 2; ++h) {
-            const std::vector<std::complex<double>> &tab = c.half[h].fold.tab;
+            const std::vector<std::complex<double>> &tab = fh[h]->tab;
             fold_tab_off[h] = align_up(blob.size());
             blob.resize(fold_tab_off[h] + tab.size() * 16);
             for (size_t i = 0; i < tab.size(); ++i) {
@@ -588,7 +603,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             }
         }
         // planning only: every bitstring its own block-A group unless there are fewer rows
-        const int kb = fold ? qh[0] - c.half[0].fold.n_s : qh[0];
+        const int kb = fold ? qh[0] - fh[0]->n_s : qh[0];
         account_gather(launches, rounds, std::min<uint64_t>(n_bits, kb >= 32 ? n_bits : (uint64_t(1) << kb)));
         c.stats.n_batches = n_leaf_batches * rounds;
         return SF_OK;
@@ -628,18 +643,27 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     uint32_t *d_xa = (uint32_t *)(ws + off_xa), *d_xb = (uint32_t *)(ws + off_xb);
     uint32_t *d_order = (uint32_t *)(ws + off_order);
 
+    // timed runs: event pairs from the circuit's pool (created once, reused by later calls)
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_cat;    // 0 sweep, 1 gather, 2 other
+    if (timing) {
+        const size_t need = 2 * (launches.size() * (plain ? n_paths : 1) + 1);
+        while (c.events.size() < need) {
+            hipEvent_t e;
+            if ((he = hipEventCreate(&e)) != hipSuccess) return dev_err("event", he);
+            c.events.push_back((void *)e);
+        }
+        ev.reserve(need);
+    }
     auto ev_pair = [&](int cat) -> hipEvent_t * {
         if (!timing) return nullptr;
-        ev.emplace_back();
-        ev.emplace_back();
-        (void)hipEventCreate(&ev[ev.size() - 2]);
-        (void)hipEventCreate(&ev[ev.size() - 1]);
+        ev.push_back((hipEvent_t)c.events[ev.size()]);
+        ev.push_back((hipEvent_t)c.events[ev.size()]);
         ev_cat.push_back(cat);
         return &ev[ev.size() - 2];
     };
 
+    c.stats.ms_plan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (!bits_dev && n_bits)
         if ((he = hipMemcpyAsync((void *)d_bits, bits, n_bits * 8, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy bitstrings", he);
     if (!blob.empty())
@@ -660,7 +684,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         if (fold) {
             // bitstrings that share their block-A bits outside the fold's S qubits read the same
             // parent rows of block A: visit them together
-            const uint32_t kmask = (qh[0] >= 32 ? ~0u : ((1u << qh[0]) - 1)) & ~c.half[0].fold.smask;
+            const uint32_t kmask = (qh[0] >= 32 ? ~0u : ((1u << qh[0]) - 1)) & ~fh[0]->smask;
             if ((he = launch_key(d_xa, n_bits, kmask, (uint32_t *)(ws + off_fkey), stream)) != hipSuccess) return dev_err("key", he);
             keys = (const uint32_t *)(ws + off_fkey);
             key_bits = __builtin_popcount(kmask);
@@ -691,7 +715,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 const uint64_t v = drop >= 64 ? 0 : ((pid >> drop) << drop);
                 for (uint64_t i = 0; i < b.slots; ++i) tpath[b.table_off + i] = v;
             }
-            if (plain_mask_idx != SIZE_MAX) tmaskv[plain_mask_idx] = 1u << (pid & ((uint64_t(1) << c.levels[L].n_cut) - 1));
+            if (plain_mask_idx != SIZE_MAX) tmaskv[plain_mask_idx] = 1u << (pid & ((uint64_t(1) << fh[0]->nb) - 1));
             // the previous path's launches must be done with the old tables
             if ((he = hipStreamSynchronize(stream)) != hipSuccess) return dev_err("sync", he);
             if ((he = hipMemcpy(ws + off_tpath, tpath.data(), tpath.size() * 8, hipMemcpyHostToDevice)) != hipSuccess) return dev_err("copy tables", he);
@@ -739,7 +763,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 f.child_mask = (const uint32_t *)(ws + off_tmask) + ln.mask_off;
                 hipEvent_t *e = ev_pair(1);
                 if (e) (void)hipEventRecord(e[0], stream);
-                if ((he = launch_fold(fp64, c.levels[L].n_cut, f, stream)) != hipSuccess) return dev_err("fold", he);
+                if ((he = launch_fold(fp64, fh[0]->nb, f, stream)) != hipSuccess) return dev_err("fold", he);
                 if (e) (void)hipEventRecord(e[1], stream);
             } else {
                 GatherArgs g = ln.ga;
@@ -772,7 +796,6 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             else if (ev_cat[i] == 1) c.stats.ms_gather += ms;
             else c.stats.ms_other += ms;
         }
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
     c.stats.n_batches = n_leaf_batches * (plain ? n_paths : 1);
     for (const Launch &ln : launches)

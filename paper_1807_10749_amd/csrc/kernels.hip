@@ -536,19 +536,31 @@ __device__ __forceinline__ uint32_t pext32(uint32_t x, uint32_t m)
 }
 
 // amp[j] += scale * sum_{slot < n_slots} sum_{i in child_mask[slot]} c_A[i] * WHT(c_B)[i]
-// with c_h[i] read from the parent level as described with FoldArgs.  WIDE: one bitstring per
-// wave, lanes over slots (P >= 64); otherwise P lanes per bitstring.  The leaf gates are applied
-// in the state precision, the products and sums over slots in FP64.
-template <typename T, int NB, bool WIDE>
-__global__ __launch_bounds__(256) void fold_kernel(FoldArgs g)
+// with c_h[i] read from level L-F as described with FoldArgs.  WIDE: one bitstring per wave,
+// lanes over slots (P >= 64), so every per-bitstring quantity is wave-uniform; else P lanes per
+// bitstring.  Per slot, block B's 2^NB values are formed and transformed first, then block A's
+// are streamed against them.  The folded gates are applied in the state precision, the
+// products and sums over slots in FP64.
+//
+// With NB >= 4 there are too many per-bitstring constants (2 x 2^NB entries of V and row
+// offsets) to keep in registers: the V entries of each wave's bitstring go to LDS and are read
+// back every iteration, and the row offsets are re-added from the per-bit strides every
+// iteration (the empty asm statements only hide loop invariance from the compiler).
+// At most 4 waves per SIMD (2 with NB >= 4): the register budget then lets the scheduler issue
+// every row load of an iteration before the first use (with a tighter budget it serialises them).
+template <typename T, int NB, bool WIDE, bool MASKED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, NB >= 4 ? 2 : 4))) void fold_kernel(FoldArgs g)
 {
     using C = typename Cplx<T>::type;
     constexpr int V = 1 << NB;
+    constexpr bool LDSV = WIDE && NB >= 4;
+    __shared__ C sv[LDSV ? 4 * 2 * V : 1];
     const int lane = threadIdx.x & 63;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t P = 1u << g.p;
     const uint32_t L = WIDE ? 64u : P;
     const uint32_t G = 64u / L;
-    const uint64_t wave = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t wave = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 4u + wid;
     const uint64_t jj = wave * G + (uint32_t)lane / L;
     const uint32_t sl = (uint32_t)lane % L;
     uint64_t j = jj < g.n_bits ? (uint64_t)g.order[jj] : g.n_bits;
@@ -559,60 +571,101 @@ __global__ __launch_bounds__(256) void fold_kernel(FoldArgs g)
     }
     double re = 0.0, im = 0.0;
     if (j < g.n_bits) {
-        const C *row[2][V];
-        T vr[2][V], vi[2][V];
+        const C *base[2];             // row (x & ~smask) of each block
+        const double *tr[2];          // table row of x_T
+        uint32_t xd[2];               // x at the branch qubits outside S, as path bits
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const FoldHalf &f = g.h[h];
             const uint32_t x = h ? g.xb[j] : g.xa[j];
-            const double *tr = f.tab + 2 * ((uint64_t)pext32(x, f.tmask) << f.n_s);
-            const uint32_t base = x & ~f.smask;
+            tr[h] = f.tab + 2 * ((uint64_t)pext32(x, f.tmask) << f.n_s);
+            base[h] = (const C *)f.par + ((uint64_t)(x & ~f.smask) << g.p);
+            uint32_t d = 0;
 #pragma unroll
-            for (int i = 0; i < V; ++i) {
-                // a virtual slot whose branch bits outside S disagree with x contributes zero; its
-                // row is the row of the slot that agrees (rows depend on the S bits only), so
-                // every load below is unconditional and in bounds
-                const bool ok = (x & f.dmask) == f.dval[i];
-                row[h][i] = (const C *)f.par + ((uint64_t)(base | f.sdep[i]) << g.p);
-                vr[h][i] = ok ? (T)tr[2 * f.ymap[i]] : T(0);
-                vi[h][i] = ok ? (T)tr[2 * f.ymap[i] + 1] : T(0);
+            for (int u = 0; u < NB; ++u)
+                if ((f.dsel >> u) & 1u) d |= ((x >> f.bq[u]) & 1u) << u;
+            xd[h] = d;
+        }
+        // V entry of virtual slot i: zero if i disagrees with x outside S
+        auto vval = [&](int h, int i) -> C {
+            const FoldHalf &f = g.h[h];
+            C v;
+            v.x = v.y = T(0);
+            if (((uint32_t)i & f.dsel) == xd[h]) {
+                uint32_t y = 0;
+                for (int u = 0; u < NB; ++u)
+                    if (!((f.dsel >> u) & 1u)) y |= (((uint32_t)i >> u) & 1u) << f.ypos[u];
+                v.x = (T)tr[h][2 * y];
+                v.y = (T)tr[h][2 * y + 1];
             }
+            return v;
+        };
+        C *wv = sv + (LDSV ? wid * 2 * V : 0);
+        if (LDSV) {
+            if (lane < V) {
+                wv[lane] = vval(0, lane);
+                wv[V + lane] = vval(1, lane);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         for (uint32_t s = sl; s < g.n_slots; s += L) {
-            C ta[V], tb[V];
+            uint32_t st[2][NB];       // row strides per path bit
+            int voff = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    st[h][u] = g.h[h].sstride[u];
+                    if (NB >= 4) asm volatile("" : "+s"(st[h][u]));
+                }
+            if (LDSV) asm volatile("" : "+v"(voff));
+            auto row_of = [&](int h, int i) -> uint64_t {
+                uint32_t r = 0;
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    if ((i >> u) & 1) r += st[h][u];
+                return (uint64_t)r << g.p;
+            };
+            // a virtual slot that disagrees with x contributes zero; its row is the row of the
+            // slot that agrees (rows depend on the S bits only), so every load is in bounds
+            C b[V];
 #pragma unroll
             for (int i = 0; i < V; ++i) {
-                ta[i] = row[0][i][s];
-                tb[i] = row[1][i][s];
+                const C t = base[1][row_of(1, i) + s];
+                const C v = LDSV ? wv[V + i + voff] : vval(1, i);
+                b[i].x = v.x * t.x - v.y * t.y;
+                b[i].y = v.x * t.y + v.y * t.x;
             }
-            const uint32_t m = g.child_mask[s];
-            C a[V], b[V];
+            // block B: the descendant's Z^b signs summed over the input branch bits
 #pragma unroll
-            for (int i = 0; i < V; ++i) {
-                a[i].x = vr[0][i] * ta[i].x - vi[0][i] * ta[i].y;
-                a[i].y = vr[0][i] * ta[i].y + vi[0][i] * ta[i].x;
-                b[i].x = vr[1][i] * tb[i].x - vi[1][i] * tb[i].y;
-                b[i].y = vr[1][i] * tb[i].y + vi[1][i] * tb[i].x;
-            }
-            // block B: the child's Z^b signs summed over the input branch bits
-#pragma unroll
-            for (int st = 1; st < V; st <<= 1)
+            for (int stp = 1; stp < V; stp <<= 1)
 #pragma unroll
                 for (int i = 0; i < V; ++i)
-                    if (!(i & st)) {
-                        const C u = b[i], w = b[i | st];
+                    if (!(i & stp)) {
+                        const C u = b[i], w = b[i | stp];
                         b[i].x = u.x + w.x;
                         b[i].y = u.y + w.y;
-                        b[i | st].x = u.x - w.x;
-                        b[i | st].y = u.y - w.y;
+                        b[i | stp].x = u.x - w.x;
+                        b[i | stp].y = u.y - w.y;
                     }
+            const uint32_t m = MASKED ? g.child_mask[s] : 0xffffffffu;
 #pragma unroll
             for (int i = 0; i < V; ++i) {
-                const double ar = a[i].x, ai = a[i].y, br = b[i].x, bi = b[i].y;
+                const C t = base[0][row_of(0, i) + s];
+                const C v = LDSV ? wv[i + voff] : vval(0, i);
+                const double ar = (double)(v.x * t.x - v.y * t.y), ai = (double)(v.x * t.y + v.y * t.x);
+                const double br = b[i].x, bi = b[i].y;
                 const double pr = ar * br - ai * bi, pi = ar * bi + ai * br;
-                const bool on = (m >> i) & 1u;     // a select, not a branch
-                re += on ? pr : 0.0;
-                im += on ? pi : 0.0;
+                if (MASKED) {
+                    const bool use = (m >> i) & 1u;    // a select, not a branch
+                    re += use ? pr : 0.0;
+                    im += use ? pi : 0.0;
+                } else {
+                    re += pr;
+                    im += pi;
+                }
             }
         }
     }
@@ -630,14 +683,19 @@ __global__ __launch_bounds__(256) void fold_kernel(FoldArgs g)
 template <typename T, int NB>
 static void fold_launch(const FoldArgs &g, unsigned blocks, bool wide, hipStream_t s)
 {
-    if (wide) fold_kernel<T, NB, true><<<blocks, 256, 0, s>>>(g);
-    else fold_kernel<T, NB, false><<<blocks, 256, 0, s>>>(g);
+    if (g.all_children) {
+        if (wide) fold_kernel<T, NB, true, false><<<blocks, 256, 0, s>>>(g);
+        else fold_kernel<T, NB, false, false><<<blocks, 256, 0, s>>>(g);
+    } else {
+        if (wide) fold_kernel<T, NB, true, true><<<blocks, 256, 0, s>>>(g);
+        else fold_kernel<T, NB, false, true><<<blocks, 256, 0, s>>>(g);
+    }
 }
 
 hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s)
 {
     if (g.n_bits == 0) return hipSuccess;
-    if (nb < 1 || nb > 4 || g.p < 0 || g.p > 31 || !g.order || !g.child_mask) return hipErrorInvalidValue;
+    if (nb < 1 || nb > 5 || g.p < 0 || g.p > 31 || !g.order || !g.child_mask) return hipErrorInvalidValue;
     const uint64_t P = (uint64_t)1 << g.p;
     const bool wide = P >= 64;
     const uint64_t per_wave = wide ? 1 : 64 / P;
@@ -647,7 +705,8 @@ hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s)
     case 1: fp64 ? fold_launch<double, 1>(g, blocks, wide, s) : fold_launch<float, 1>(g, blocks, wide, s); break;
     case 2: fp64 ? fold_launch<double, 2>(g, blocks, wide, s) : fold_launch<float, 2>(g, blocks, wide, s); break;
     case 3: fp64 ? fold_launch<double, 3>(g, blocks, wide, s) : fold_launch<float, 3>(g, blocks, wide, s); break;
-    default: fp64 ? fold_launch<double, 4>(g, blocks, wide, s) : fold_launch<float, 4>(g, blocks, wide, s); break;
+    case 4: fp64 ? fold_launch<double, 4>(g, blocks, wide, s) : fold_launch<float, 4>(g, blocks, wide, s); break;
+    default: fp64 ? fold_launch<double, 5>(g, blocks, wide, s) : fold_launch<float, 5>(g, blocks, wide, s); break;
     }
     return hipGetLastError();
 }

@@ -22,8 +22,9 @@ hipError_t launch_dense(const DenseArgs &a, unsigned grid, hipStream_t s);
 // Gather + FP64 path sum for one leaf batch.
 hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s);
 
-// Leaf fold + FP64 path sum for one parent batch (see FoldArgs); nb = branch bits of the leaf
-// level (1..4).  g.order and g.child_mask must be given.
+// Fold of the last tree levels + FP64 path sum for one batch of the level it reads (see
+// FoldArgs); nb = path bits decided by the folded levels (1..5).  g.order and g.child_mask must
+// be given.
 hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s);
 
 // key[i] = pext(x[i], mask) (32-bit).

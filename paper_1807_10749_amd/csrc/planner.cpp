@@ -29,46 +29,48 @@ namespace {
 void gate2x2(uint8_t kind, std::complex<double> g[4]);
 }  // namespace
 
-// Leaf segment of block h as V * D(b) (see LeafFold).  The branch operators of the leaf level
-// are diagonal, so they commute with every diagonal leaf gate; the form holds when no
-// non-diagonal gate precedes a branch operator on its qubit, and it is used when every
-// non-diagonal leaf gate acts on a branch qubit (then a child reads no more parent rows than
-// it has branch values).  V is multiplied out exactly with the normalised gates.
-static void build_leaf_fold(Circuit &c, int h)
+// The last F tree levels of block h as V * D(b) (see LeafFold).  Their segments, in order, are
+// applied to the state of the level above; the branch operators are diagonal, so each one can
+// be moved to the right of every earlier gate of these segments that is diagonal or acts on
+// other qubits.  The form holds when no non-diagonal gate precedes a branch operator on its
+// qubit, and it is used when every non-diagonal gate of the segments acts on a branch qubit
+// (then a descendant reads no more rows of the level above than it has branch values).  V is
+// multiplied out exactly with the normalised gates.
+static LeafFold make_fold(const Circuit &c, int h, int F)
 {
-    LeafFold &f = c.half[h].fold;
-    f = LeafFold();
+    LeafFold f;
     const int L = (int)c.levels.size() - 1;
-    if (L < 1) return;
-    const int nb = c.levels[L].n_cut;
-    if (nb < 1 || nb > 4) return;
-    const std::vector<HalfOp> &seg = c.half[h].segments[L];
-    int bq[4] = {-1, -1, -1, -1};       // local qubit of the branch operator of path bit u
+    if (F < 1 || F > L) return f;
+    const int nb = c.k - c.levels[L - F].bits_after;     // path bits decided by the F levels
+    if (nb < 1 || nb > kMaxFoldBits) return f;
+    int bq[kMaxFoldBits];
+    for (int u = 0; u < kMaxFoldBits; ++u) bq[u] = -1;  // local qubit of the branch operator of path bit u
     uint32_t nondiag_seen = 0, smask = 0, tmask = 0;
     std::vector<HalfOp> rest;
-    for (const HalfOp &op : seg) {
-        if (op.kind == HK_PROJ || op.kind == HK_ZCTL) {
-            if (op.bit >= nb || bq[op.bit] >= 0 || ((nondiag_seen >> op.q0) & 1)) return;
-            bq[op.bit] = op.q0;
-            continue;
+    for (int l = L - F + 1; l <= L; ++l)
+        for (const HalfOp &op : c.half[h].segments[l]) {
+            if (op.kind == HK_PROJ || op.kind == HK_ZCTL) {
+                if (op.bit >= nb || bq[op.bit] >= 0 || op.q0 >= 32 || ((nondiag_seen >> op.q0) & 1)) return f;
+                bq[op.bit] = op.q0;
+                continue;
+            }
+            if (op.q0 >= 32 || (op.kind == HK_CZ && op.q1 >= 32)) return f;
+            if (!is_diag(op.kind)) {
+                nondiag_seen |= 1u << op.q0;
+                smask |= 1u << op.q0;
+            }
+            tmask |= 1u << op.q0;
+            if (op.kind == HK_CZ) tmask |= 1u << op.q1;
+            rest.push_back(op);
         }
-        if (op.q0 >= 32 || (op.kind == HK_CZ && op.q1 >= 32)) return;
-        if (!is_diag(op.kind)) {
-            nondiag_seen |= 1u << op.q0;
-            smask |= 1u << op.q0;
-        }
-        tmask |= 1u << op.q0;
-        if (op.kind == HK_CZ) tmask |= 1u << op.q1;
-        rest.push_back(op);
-    }
     uint32_t bmask = 0;
     for (int u = 0; u < nb; ++u) {
-        if (bq[u] < 0 || bq[u] >= 32) return;
+        if (bq[u] < 0) return f;
         bmask |= 1u << bq[u];
     }
-    if ((smask & ~bmask) != 0) return;            // a non-diagonal gate off the branch qubits
+    if ((smask & ~bmask) != 0) return f;            // a non-diagonal gate off the branch qubits
     const int n_t = __builtin_popcount(tmask), n_s = __builtin_popcount(smask);
-    if (n_t > 8) return;
+    if (n_t > 8) return f;
     // T-local index of each local qubit in T, S-local index of each qubit in S
     int tpos[32], spos[32];
     for (int t = 0, a = 0, b = 0; t < 32; ++t) {
@@ -117,23 +119,11 @@ static void build_leaf_fold(Circuit &c, int h)
                 }
             f.tab[((size_t)xt << n_s) + y] = M[(size_t)xt * D + col];
         }
-    // virtual slots: child branch value i sets the branch qubits' input bits
-    for (int i = 0; i < (1 << nb); ++i) {
-        uint32_t sdep = 0, dval = 0;
-        int y = 0;
-        for (int u = 0; u < nb; ++u) {
-            const uint32_t bit = (i >> u) & 1;
-            if (spos[bq[u]] >= 0) {
-                sdep |= bit << bq[u];
-                y |= (int)bit << spos[bq[u]];
-            } else {
-                dval |= bit << bq[u];
-            }
-        }
-        f.sdep[i] = sdep;
-        f.dval[i] = dval;
-        f.ymap[i] = (uint8_t)y;
+    for (int u = 0; u < nb; ++u) {
+        f.bq[u] = bq[u];
+        f.ypos[u] = spos[bq[u]];
     }
+    f.levels = F;
     f.nb = nb;
     f.n_s = n_s;
     f.n_t = n_t;
@@ -141,6 +131,19 @@ static void build_leaf_fold(Circuit &c, int h)
     f.tmask = tmask;
     f.dmask = bmask & ~smask;
     f.ok = true;
+    return f;
+}
+
+int fold_depth(const Circuit &c)
+{
+    if (c.tuning.no_leaf_fold) return 0;
+    int best = 0;
+    const int n = (int)std::min(c.half[0].folds.size(), c.half[1].folds.size());
+    for (int F = 1; F <= n; ++F) {
+        if (c.tuning.fold_levels && F > (int)c.tuning.fold_levels) break;
+        if (c.half[0].folds[F - 1].ok && c.half[1].folds[F - 1].ok) best = F;
+    }
+    return best;
 }
 
 int build_programs(Circuit &c, std::string &err)
@@ -282,7 +285,10 @@ int build_programs(Circuit &c, std::string &err)
             hp.seg_scale[l] = std::pow(s_h, nh) * std::pow(s_xy, nxy) * std::ldexp(1.0, e);
         }
     }
-    for (int h = 0; h < 2; ++h) build_leaf_fold(c, h);
+    for (int h = 0; h < 2; ++h) {
+        c.half[h].folds.clear();
+        for (int F = 1; F <= L; ++F) c.half[h].folds.push_back(make_fold(c, h, F));
+    }
     c.plan_cache.clear();
     return SF_OK;
 }

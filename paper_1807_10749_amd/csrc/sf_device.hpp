@@ -115,32 +115,37 @@ struct GatherArgs {
     double scale_re, scale_im;    // product of both blocks' tracked scalars
 };
 
-// Leaf fold: the gather reads the parent level (level L-1) and applies the leaf segment
-// itself.  For block h, output bits x (local) and child branch value i ("virtual slot"):
-//   c_h[i] = [ (x & dmask) == dval[i] ] * tab[pext(x, tmask) * 2^n_s + ymap[i]]
-//            * parent_h[(x & ~smask) | sdep[i]][slot]
-// Block A's projectors keep exactly child i; block B's Z^b signs become a Walsh-Hadamard
+// Fold of the last F tree levels: the gather reads level L-F and applies the F levels itself.
+// The nb path bits these levels decide index the "virtual slots" i of a descendant; path bit u
+// belongs to a branch operator on local qubit bq[u].  For block h and output bits x (local):
+//   c_h[i] = [ bits u of i outside S equal x at bq[u] ] * tab[pext(x, tmask) * 2^n_s + y(i)]
+//            * parent_h[(x & ~smask) + sum_u i_u * sstride[u]][slot],
+//   y(i) = sum over u with bq[u] in S of i_u << ypos[u]   (i's S pattern, an index of tab's row).
+// Block A's projectors keep exactly descendant i; block B's Z^b signs become a Walsh-Hadamard
 // transform over i.  Then amp[x] += scale * sum_slot sum_{i in child_mask[slot]} c_A[i] c_B'[i]
 // with c_B' = WHT(c_B).
 struct FoldHalf {
-    const void *par;              // parent states of the block, 2^(p+q) complex
-    const double *tab;            // complex (re, im) table of V
-    uint32_t smask, tmask, dmask;
+    const void *par;              // states of the block at level L-F, 2^(p+q) complex
+    const double *tab;            // complex (re, im) table of V, [2^|T|][2^n_s]
+    uint32_t smask, tmask;        // local qubits of S (non-diagonal gates), of T (all of V)
+    uint32_t dsel;                // bit u set if bq[u] is outside S
     int32_t n_s;
-    uint32_t sdep[16];
-    uint32_t dval[16];
-    uint8_t ymap[16];
+    uint32_t sstride[5];          // 1 << bq[u] if bq[u] is in S, else 0
+    uint8_t bq[5];
+    uint8_t ypos[5];              // S index of bq[u] (unused if outside S)
+    uint8_t pad[6];
 };
 
 struct FoldArgs {
     FoldHalf h[2];
     const uint32_t *xa, *xb;      // per bitstring: x_A, x_B
     const uint32_t *order;        // visiting order of the bitstrings
-    const uint32_t *child_mask;   // per parent slot: bit i set if child i is requested
+    const uint32_t *child_mask;   // per parent slot: bit i set if descendant i is requested
     double *acc;                  // 2 * n_bits doubles, accumulated
     uint64_t n_bits;
     uint32_t n_slots;             // real parent slots (<= 2^p)
     int32_t p;                    // parent slot bits
+    int32_t all_children;         // 1: every parent slot has all 2^nb descendants (masks not read)
     double scale_re, scale_im;
 };
 

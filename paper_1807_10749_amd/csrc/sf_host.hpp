@@ -48,18 +48,23 @@ struct SegmentPlan {
     bool ok = true;      // false if some operation could not be scheduled
 };
 
-// The leaf segment of one block written as V * D(b): D(b) = the leaf level's branch operators
-// for child branch value b (diagonal), V = the block's remaining leaf gates (independent of b).
-// When every non-diagonal leaf gate acts on a branch qubit, a child's amplitude at x is one
-// parent amplitude per "virtual slot" i (child branch value i, see FoldHalf) times an entry of
-// V, so the gather can read the parent level and the leaf states are never written.
+// Most path bits the folded levels may decide (virtual slots per parent slot = 2^bits).
+constexpr int kMaxFoldBits = 5;
+
+// The last F tree levels of one block written as V * D(b): D(b) = their branch operators for
+// descendant branch value b (diagonal), V = the block's remaining gates of those levels
+// (independent of b).  When every non-diagonal gate among them acts on a branch qubit, a
+// descendant's amplitude at x is one amplitude of the level above per "virtual slot" i
+// (descendant branch value i, see FoldHalf) times an entry of V, so the gather can read the
+// level above and the states of the F levels are never written.
 struct LeafFold {
     bool ok = false;
-    int nb = 0;                 // branch bits of the leaf level
-    int n_s = 0, n_t = 0;       // |S| (qubits of non-diagonal leaf gates), |T| (all qubits V touches)
+    int levels = 0;             // F
+    int nb = 0;                 // path bits decided by the F levels
+    int n_s = 0, n_t = 0;       // |S| (qubits of non-diagonal gates), |T| (all qubits V touches)
     uint32_t smask = 0, tmask = 0, dmask = 0;   // local masks of S, T, and branch qubits outside S
-    uint32_t sdep[16] = {0}, dval[16] = {0};
-    uint8_t ymap[16] = {0};
+    int bq[kMaxFoldBits] = {0};                 // local qubit of the branch operator of path bit u
+    int ypos[kMaxFoldBits] = {0};               // its index in S (-1 if outside S)
     std::vector<std::complex<double>> tab;      // [2^n_t][2^n_s]: <x_T| V |x_T with S bits := y>
 };
 
@@ -70,7 +75,7 @@ struct HalfProgram {
     std::vector<std::complex<double>> seg_scale;  // scalar of each segment's unnormalised gates incl. rescaling
     std::vector<int> seg_rescale_exp;           // power of two divided out at the end of each segment
     std::complex<double> init_scale = 1.0;      // 2^{-h/2} for the folded opening H gates
-    LeafFold fold;                              // leaf segment as V * D(b), if it qualifies
+    std::vector<LeafFold> folds;                // folds[F-1]: the last F levels as V * D(b)
 };
 
 struct Level {
@@ -99,6 +104,7 @@ struct Circuit {
     // device resources owned by the circuit
     void *dev_ws = nullptr;
     size_t dev_ws_bytes = 0;
+    std::vector<void *> events;       // hipEvent_t pool of timed runs, reused across calls
     int device_cus = 0;
 
     sf_run_stats_t stats{};
@@ -106,6 +112,9 @@ struct Circuit {
 
 // planner.cpp
 int build_programs(Circuit &c, std::string &err);
+// Number of trailing tree levels folded into the gather with the current tuning (0 = none):
+// the largest F for which both blocks' folds[F-1] qualify, capped by tuning.fold_levels.
+int fold_depth(const Circuit &c);
 // dense_m: 0 = register/lane passes only; 2..4 = also fuse windows of up to dense_m qubits
 // into dense 4-qubit blocks applied on matrix cores.
 const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m = 0);

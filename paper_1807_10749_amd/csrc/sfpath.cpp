@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
+#include <tuple>
 #include <mutex>
 #include <new>
 #include <string>
@@ -120,6 +122,7 @@ int destroy_circuit(sf_circuit_t *c)
     return guarded([&]() -> int {
         if (!c) return ok();
         if (c->dev_ws) (void)hipFree(c->dev_ws);
+        for (void *e : c->events) (void)hipEventDestroy((hipEvent_t)e);
         delete c;
         return ok();
     });
@@ -240,6 +243,7 @@ int set_tuning(sf_circuit_t *c, const sf_tuning_t *t)
     if (t->reg_qubits > 5) return fail(SF_ERR_INVALID, "reg_qubits must be at most 5");
     if (t->dense_qubits == 1 || t->dense_qubits > 4) return fail(SF_ERR_INVALID, "dense_qubits must be 0 or 2..4");
     if (t->no_leaf_fold > 1) return fail(SF_ERR_INVALID, "no_leaf_fold must be 0 or 1");
+    if (t->fold_levels > 62) return fail(SF_ERR_INVALID, "fold_levels must be at most 62");
     auto pow2ok = [](uint32_t v) { return v == 0 || (v & (v - 1)) == 0; };
     if (!pow2ok(t->leaf_batch) || !pow2ok(t->max_slots)) return fail(SF_ERR_INVALID, "batch sizes must be powers of two");
     c->tuning = *t;
@@ -290,13 +294,22 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
         const uint32_t regs[3] = {fp64 ? 4u : 5u, fp64 ? 3u : 4u, fp64 ? 2u : 3u};
         const uint32_t leafs[4] = {0u, 4096u, 1024u, 256u};
         const uint32_t wpcs[3] = {32u, 16u, 64u};
-        const bool foldable = c->levels.size() > 1 && c->half[0].fold.ok && c->half[1].fold.ok;
+        sf_tuning_t probe = c->tuning;
+        probe.no_leaf_fold = 0;
+        probe.fold_levels = 0;
+        std::swap(probe, c->tuning);
+        const int max_fold = sf::fold_depth(*c);
+        std::swap(probe, c->tuning);
         for (uint32_t r : regs)
             for (uint32_t w : wpcs)
                 for (uint32_t dq : {0u, 4u}) {
                     if (dq && fp64) continue;                 // dense blocks on matrix cores: complex64 only
-                    if (foldable) cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0});
-                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1});
+                    for (int F = 1; F <= max_fold; ++F) {     // F trailing levels folded into the gather
+                        const int Fp = max_fold > 1 ? max_fold - 1 : 1;
+                        if (F != max_fold && F != Fp) continue;
+                        cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0, (uint32_t)F});
+                    }
+                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1, 0});
                 }
         // rank by the planned cost
         std::vector<std::pair<double, size_t>> ranked;
@@ -313,10 +326,20 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
         }
         if (ranked.empty()) { c->tuning = start; return fail(SF_ERR_UNSUPPORTED, "no tuning candidate could be planned"); }
         std::sort(ranked.begin(), ranked.end());
+        // time the best-ranked candidate of every kind (leaf handling x dense blocks) first, since
+        // the model compares kinds less reliably than tunings of one kind; then fill by rank
         std::vector<sf_tuning_t> measure;
         measure.push_back(start);
-        for (size_t i = 0; i < ranked.size() && measure.size() < (size_t)std::max(1u, n_measure) + 1; ++i)
-            measure.push_back(cands[ranked[i].second]);
+        std::vector<size_t> picked;
+        std::set<std::tuple<uint32_t, uint32_t, uint32_t>> kinds;
+        for (size_t i = 0; i < ranked.size(); ++i) {
+            const sf_tuning_t &t = cands[ranked[i].second];
+            if (kinds.insert({t.no_leaf_fold, t.fold_levels, t.dense_qubits}).second) picked.push_back(i);
+        }
+        for (size_t i = 0; i < ranked.size() && picked.size() < (size_t)std::max(1u, n_measure); ++i)
+            if (std::find(picked.begin(), picked.end(), i) == picked.end()) picked.push_back(i);
+        std::sort(picked.begin(), picked.end());
+        for (size_t i : picked) measure.push_back(cands[ranked[i].second]);
         double best_t = 1e300;
         sf_tuning_t best_t_cfg = start;
         for (const sf_tuning_t &t : measure) {
@@ -363,12 +386,15 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
             if (qmin + p < 6) p = 6 - qmin;
             s += "level " + std::to_string(l) + " cycle " + std::to_string(c->levels[l].cycle) +
                  " bits " + std::to_string(c->levels[l].bits_after) + " p " + std::to_string(p) + ":";
-            if (l == L && L > 0 && c->tuning.no_leaf_fold == 0 && c->half[0].fold.ok && c->half[1].fold.ok) {
-                for (int h = 0; h < 2; ++h)
-                    s += std::string(h ? "  B " : " A ") + std::to_string(c->half[h].segments[l].size()) +
-                         " ops folded into the gather (branch bits " + std::to_string(c->half[h].fold.nb) +
-                         ", S " + std::to_string(c->half[h].fold.n_s) + " qubits, T " +
-                         std::to_string(c->half[h].fold.n_t) + ")";
+            const int FD = sf::fold_depth(*c);
+            if (FD && l > L - FD) {
+                const sf::LeafFold &f0 = c->half[0].folds[FD - 1], &f1 = c->half[1].folds[FD - 1];
+                s += " A " + std::to_string(c->half[0].segments[l].size()) + " ops, B " +
+                     std::to_string(c->half[1].segments[l].size()) + " ops folded into the gather";
+                if (l == L)
+                    s += " (" + std::to_string(FD) + " levels, branch bits " + std::to_string(f0.nb) + "; A: S " +
+                         std::to_string(f0.n_s) + " qubits, T " + std::to_string(f0.n_t) + "; B: S " +
+                         std::to_string(f1.n_s) + " qubits, T " + std::to_string(f1.n_t) + ")";
                 s += "\n";
                 continue;
             }

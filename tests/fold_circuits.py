@@ -37,3 +37,29 @@ def crossing_tail_circuit(rows=4, depth=8, seed=5):
         mask_a |= (1 << q(r, 0)) | (1 << q(r, 1))
     gates.sort(key=lambda g: g[2])           # stable: list order within a cycle is kept
     return rows, cols, np.array(gates, dtype=GATE_DTYPE), mask_a
+
+
+def two_level_tail_circuit(depth=8, seed=5):
+    """Two crossing cycles at the end on a 4 x 4 grid (cut between columns 1 and 2): rows 0-1
+    cross first, rows 2-3 two cycles later.  Between and after them: non-diagonal gates on
+    some branch qubits only, T and CZ phases (one CZ reaching a non-branch qubit on each side),
+    and branch qubits that no non-diagonal gate touches afterwards; so the last two tree levels
+    fold together (4 path bits)."""
+    rows, cols = 4, 4
+    base = grid_circuit(rows, cols, depth, seed)
+    gates = [tuple(g) for g in base if g["cycle"] <= depth]
+    q = lambda r, c: r * cols + c
+    c1, c2, c3, c4, c5, c6 = (depth + i for i in range(1, 7))
+    gates += [(CZ, 0, c1, q(0, 1), q(0, 2)), (CZ, 0, c1, q(1, 1), q(1, 2))]
+    gates += [(XH, 0, c2, q(0, 1), 0), (H, 0, c2, q(1, 1), 0), (YH, 0, c2, q(0, 2), 0), (T, 0, c2, q(1, 2), 0)]
+    gates += [(CZ, 0, c3, q(0, 1), q(0, 0)), (CZ, 0, c3, q(2, 1), q(2, 2)), (CZ, 0, c3, q(3, 1), q(3, 2))]
+    gates += [(H, 0, c4, q(0, 1), 0), (T, 0, c4, q(2, 1), 0), (H, 0, c4, q(3, 1), 0), (H, 0, c4, q(0, 2), 0),
+              (YH, 0, c4, q(2, 2), 0)]
+    gates += [(CZ, 0, c5, q(2, 2), q(2, 3)), (CZ, 0, c5, q(3, 2), q(3, 3))]
+    gates += [(H, 0, c6, q(2, 2), 0)]
+    gates += [(H, 0, c6, q(r, 0), 0) for r in (1, 2, 3)] + [(H, 0, c6, q(r, 3), 0) for r in (0, 1)]
+    gates.sort(key=lambda g: g[2])
+    mask_a = 0
+    for r in range(rows):
+        mask_a |= (1 << q(r, 0)) | (1 << q(r, 1))
+    return rows, cols, np.array(gates, dtype=GATE_DTYPE), mask_a

@@ -155,32 +155,37 @@ def test_dense_plan_uses_matrix_core_blocks(sf):
 
 
 def test_leaf_fold_eligibility(sf):
-    """The last tree level is folded into the gather exactly when every non-diagonal gate of it
-    acts on a branch qubit of that level."""
+    """Trailing tree levels are folded into the gather when every non-diagonal gate among them
+    acts on one of their branch qubits (at most 5 path bits); fold_levels caps how many."""
     import sys
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from fold_circuits import crossing_tail_circuit
-    expect = {"grid4x4_d16": False, "grid5x6_d24": True, "grid6x7_d32": False, "grid7x8_d40": False}
-    for name, folded in expect.items():
+    from fold_circuits import crossing_tail_circuit, two_level_tail_circuit
+    expect = {"grid4x4_d16": None, "grid6x7_d32": None, "grid7x8_d40": None,
+              "grid5x6_d24": "2 levels, branch bits 5; A: S 5 qubits, T 5; B: S 5 qubits, T 5"}
+    for name, fold in expect.items():
         cfg = CONFIGS[name]
         c = sf.create_circuit(cfg.rows, cfg.cols, grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed))
         sf.set_cut(c, cfg.cut_mask())
-        last = sf.describe_plan(c).strip().splitlines()[-1]
-        assert ("folded" in last) == folded, name
-        if folded:
-            assert last.count("branch bits 3, S 3 qubits, T 3") == 2
+        plan = sf.describe_plan(c)
+        if fold is None:
+            assert "folded" not in plan, name
+        else:
+            assert fold in plan, plan
+            sf.set_tuning(c, fold_levels=1)
+            assert "1 levels, branch bits 3; A: S 3 qubits, T 3; B: S 3 qubits, T 3" in sf.describe_plan(c)
             # without the fold the leaf states are written: the workspace bound grows by them
             small = sf.workspace_size(c, 1 << 15, 100000)
             sf.set_tuning(c, no_leaf_fold=1)
             assert "folded" not in sf.describe_plan(c)
             assert sf.workspace_size(c, 1 << 15, 100000) - small >= 2 * (1 << 30) * 8
         sf.destroy_circuit(c)
-    for rows, nb in ((3, 3), (4, 4)):
-        r, cc, g, m = crossing_tail_circuit(rows=rows)
+    cases = [(crossing_tail_circuit(rows=3), "1 levels, branch bits 3; A: S 3 qubits, T 4; B: S 2 qubits, T 3"),
+             (crossing_tail_circuit(rows=4), "1 levels, branch bits 4; A: S 3 qubits, T 4; B: S 2 qubits, T 3"),
+             (two_level_tail_circuit(), "2 levels, branch bits 4; A: S 3 qubits, T 4; B: S 2 qubits, T 3")]
+    for (r, cc, g, m), want in cases:
         c = sf.create_circuit(r, cc, g)
-        assert sf.set_cut(c, m) >= nb
-        last = sf.describe_plan(c).strip().splitlines()[-1]
-        assert f"branch bits {nb}, S 3 qubits, T 4" in last and f"branch bits {nb}, S 2 qubits, T 3" in last
+        sf.set_cut(c, m)
+        assert want in sf.describe_plan(c)
         sf.destroy_circuit(c)
     # a non-diagonal gate on a non-branch qubit in the last level: not folded
     r, cc, g, m = crossing_tail_circuit(rows=3)
@@ -194,9 +199,10 @@ def test_leaf_fold_eligibility(sf):
 def test_tuning_roundtrip(sf):
     w = make_workload("grid4x4_d16", n_bits=4)
     c = sf.create_circuit(4, 4, w["gates"])
-    sf.set_tuning(c, reg_qubits=3, leaf_batch=64, max_slots=1024, waves_per_cu=16, dense_qubits=4, no_leaf_fold=1)
+    sf.set_tuning(c, reg_qubits=3, leaf_batch=64, max_slots=1024, waves_per_cu=16, dense_qubits=4, no_leaf_fold=1,
+                  fold_levels=2)
     assert sf.get_tuning(c) == {"reg_qubits": 3, "leaf_batch": 64, "max_slots": 1024, "waves_per_cu": 16,
-                                "dense_qubits": 4, "no_leaf_fold": 1}
+                                "dense_qubits": 4, "no_leaf_fold": 1, "fold_levels": 2}
     with pytest.raises(sf.SFError):
         sf.set_tuning(c, no_leaf_fold=2)
     with pytest.raises(sf.SFError):

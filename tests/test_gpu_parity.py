@@ -232,44 +232,45 @@ def test_dense_blocks_parity(sf, name, npaths):
     assert c11_error(a, o, ids.size, c.k, cfg.n_qubits) <= TOL_C64
 
 
-# ---------------------------------------------------------------- last level folded into the gather
+# ---------------------------------------------------------------- trailing levels folded into the gather
 
-def _tail(sf, rows):
+def _hand_built(sf, which):
     import sys, os
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-    from fold_circuits import crossing_tail_circuit
-    r, cc, g, m = crossing_tail_circuit(rows=rows)
+    from fold_circuits import crossing_tail_circuit, two_level_tail_circuit
+    r, cc, g, m = two_level_tail_circuit() if which == "two" else crossing_tail_circuit(rows=which)
     return r * cc, g, m, sf.Circuit(r, cc, g, m)
 
 
-@pytest.mark.parametrize("rows", [3, 4])
-def test_leaf_fold_tail_circuits(sf, rows):
-    """Leaf levels with 3 and 4 branch bits, phases after the branch gates, and branch qubits that
-    only diagonal gates touch: folded and materialised leaves both give the oracle's result."""
-    n, g, m, c = _tail(sf, rows)
+@pytest.mark.parametrize("which", [3, 4, "two"])
+def test_leaf_fold_tail_circuits(sf, which):
+    """Folded levels with 3 and 4 branch bits (one level) and 4 bits over two levels, phases
+    after the branch gates, and branch qubits that only diagonal gates touch: every fold depth
+    and the materialised leaves give the oracle's result."""
+    n, g, m, c = _hand_built(sf, which)
     assert "folded" in sf.describe_plan(c.handle)
-    bits = random_bitstrings(n, 3000, 21 + rows)
+    bits = random_bitstrings(n, 3000, 21 + (which if which != "two" else 9))
     ids = np.arange(1 << c.k, dtype=np.uint64)
     o = oracle.path_sum(n, g, m, ids, bits)
     assert np.abs(o - oracle.full_state(n, g)[bits.astype(np.int64)]).max() < 1e-13
-    for no_fold in (0, 1):
-        c.tune(no_leaf_fold=no_fold)
-        say(f"tail circuit rows={rows} all paths no_leaf_fold={no_fold}")
+    for tune in ({"no_leaf_fold": 0}, {"fold_levels": 1}, {"no_leaf_fold": 1}):
+        c.tune(**tune)
+        say(f"hand-built circuit {which} all paths {tune}")
         a = c.amplitudes(bits)
-        assert c11_error(a, o, ids.size, c.k, n) <= TOL_C64, no_fold
-        say(f"tail circuit rows={rows} all paths complex128 no_leaf_fold={no_fold}")
+        assert c11_error(a, o, ids.size, c.k, n) <= TOL_C64, tune
+        say(f"hand-built circuit {which} all paths complex128 {tune}")
         a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS)
-        assert c11_error(a, o, ids.size, c.k, n) <= TOL_C128, no_fold
+        assert c11_error(a, o, ids.size, c.k, n) <= TOL_C128, tune
     c.tune(no_leaf_fold=0)
-    # sampled paths: parents with some of their children only
+    # sampled paths: parents with some of their descendants only
     sub = sf.sample_paths(c.k, 0.3, 77)
-    say(f"tail circuit rows={rows} {sub.size} sampled paths")
+    say(f"hand-built circuit {which} {sub.size} sampled paths")
     a = c.amplitudes(bits, path_ids=sub)
     o = oracle.path_sum(n, g, m, sub, bits)
     assert c11_error(a, o, sub.size, c.k, n) <= TOL_C64
     # one path at a time (plain form) and single-path indexing
     ids3 = np.array([1, (1 << c.k) - 2, (1 << c.k) // 3 + 1], dtype=np.uint64)
-    say(f"tail circuit rows={rows} plain form {ids3.tolist()}")
+    say(f"hand-built circuit {which} plain form {ids3.tolist()}")
     a = c.amplitudes(bits, path_ids=ids3, flags=sf.SF_PLAIN)
     o = oracle.path_sum(n, g, m, ids3, bits)
     assert c11_error(a, o, ids3.size, c.k, n) <= TOL_C64
@@ -281,8 +282,8 @@ def test_leaf_fold_tail_circuits(sf, rows):
 
 @pytest.mark.parametrize("shape", [(2, 3, 3, 0), (2, 3, 5, 0), (2, 3, 21, 0), (4, 5, 7, 0), (4, 5, 15, 0)])
 def test_leaf_fold_grid_circuits(sf, shape):
-    """Grid circuits whose last level qualifies, from one slot per parent batch (fewer slots than
-    lanes) to 2^7; every bitstring of the smaller ones."""
+    """Grid circuits whose trailing levels qualify (one or two levels, 2 to 5 path bits), from
+    one slot per batch (fewer slots than lanes) to 2^5; every bitstring of the smaller ones."""
     rows, cols, depth, seed = shape
     n = rows * cols
     g = grid_circuit(rows, cols, depth, seed)
@@ -292,9 +293,36 @@ def test_leaf_fold_grid_circuits(sf, shape):
     c = sf.Circuit(rows, cols, g, m)
     assert "folded" in sf.describe_plan(c.handle)
     bits = np.arange(1 << n, dtype=np.uint64) if n <= 12 else random_bitstrings(n, 5000, 31)
-    say(f"grid {rows}x{cols} depth {depth} seed {seed} folded leaf, {bits.size} bitstrings")
-    a = c.amplitudes(bits)
     o = oracle.full_state(n, g)[bits.astype(np.int64)]
-    assert c11_error(a, o, 1, 0, n) <= TOL_C64
-    a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS)
-    assert c11_error(a, o, 1, 0, n) <= TOL_C128
+    for tune in ({"fold_levels": 0}, {"fold_levels": 1}):
+        c.tune(**tune)
+        say(f"grid {rows}x{cols} depth {depth} seed {seed} {tune}, {bits.size} bitstrings")
+        a = c.amplitudes(bits)
+        assert c11_error(a, o, 1, 0, n) <= TOL_C64, tune
+        a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS)
+        assert c11_error(a, o, 1, 0, n) <= TOL_C128, tune
+
+
+def test_grid5x6_fold_depths_tight_workspace(sf):
+    """The benchmark circuit with two and one folded levels and with materialised leaves: an
+    aligned block of 4096 paths against the oracle, and all 2^15 paths in a 256 MiB workspace
+    (several batches of the level the gather reads) against each other."""
+    import torch
+    cfg, g, c = _circuit(sf, "grid5x6_d24")
+    bits = random_bitstrings(30, 2000, cfg.bits_seed)
+    o = oracle.path_sum(30, g, cfg.cut_mask(), np.arange(8192, 8192 + 4096, dtype=np.uint64), bits)
+    ws = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    full = {}
+    for tune in ({"fold_levels": 2}, {"fold_levels": 1}, {"no_leaf_fold": 1}):
+        c.tune(**tune)
+        say(f"grid5x6_d24 {tune} 4096 paths")
+        a = c.amplitudes(bits, path_begin=8192, n_paths=4096)
+        assert c11_error(a, o, 4096, c.k, 30) <= TOL_C64, tune
+        say(f"grid5x6_d24 {tune} 4096 paths, 256 MiB workspace")
+        a = c.amplitudes(bits, path_begin=8192, n_paths=4096, workspace=ws)
+        assert c11_error(a, o, 4096, c.k, 30) <= TOL_C64, tune
+        say(f"grid5x6_d24 {tune} all paths, 256 MiB workspace")
+        full[str(tune)] = c.amplitudes(bits, workspace=ws)
+    ref = full[str({"no_leaf_fold": 1})]
+    for k, a in full.items():
+        assert c11_error(a, ref, 1 << c.k, c.k, 30) <= 2 * TOL_C64, k
