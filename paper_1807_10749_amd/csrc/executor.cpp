@@ -204,6 +204,73 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     const size_t blob_budget = size_t(1) << 22;
     const size_t off_blob = fixed; fixed += blob_budget;
 
+    auto dev_err = [&](const char *what, hipError_t e) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return SF_ERR_DEVICE;
+    };
+    // timed runs: event pairs from the circuit's pool (created on first use, reused by later
+    // calls); pair i = pool entries 2i, 2i+1, bracketing a run of launches of one category
+    std::vector<int> ev_cat;    // 0 sweep, 1 gather, 2 other
+    auto ev_get = [&](size_t i) -> hipEvent_t {
+        while (c.events.size() <= i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            c.events.push_back((void *)e);
+        }
+        return (hipEvent_t)c.events[i];
+    };
+    auto ev_begin = [&](int cat) -> int {
+        if (!timing) return -1;
+        const int id = (int)ev_cat.size();
+        hipEvent_t e = ev_get(2 * (size_t)id);
+        if (!e || !ev_get(2 * (size_t)id + 1)) return -1;
+        ev_cat.push_back(cat);
+        (void)hipEventRecord(e, stream);
+        return id;
+    };
+    auto ev_end = [&](int id) {
+        if (id >= 0) (void)hipEventRecord((hipEvent_t)c.events[2 * (size_t)id + 1], stream);
+    };
+
+    // Bitstring preprocessing (upload, x_A / x_B, bad-bit flag, visiting order, group count).
+    // It needs only the fixed part of the workspace, so with a caller's workspace it is enqueued
+    // before the host plans the request and runs on the device meanwhile.
+    bool pre_done = false;
+    auto enqueue_pre = [&](char *wsp) -> int {
+        pre_done = true;
+        const uint64_t *d_bits = bits_dev ? bits : (const uint64_t *)(wsp + off_bits);
+        int *d_flag = (int *)(wsp + off_flag);
+        uint32_t *d_xa = (uint32_t *)(wsp + off_xa), *d_xb = (uint32_t *)(wsp + off_xb);
+        const int id = ev_begin(2);
+        if (!bits_dev && n_bits)
+            if ((he = hipMemcpyAsync((void *)d_bits, bits, n_bits * 8, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy bitstrings", he);
+        if ((he = launch_fill_zero_i32(d_flag, 2, stream)) != hipSuccess) return dev_err("fill", he);
+        if ((he = launch_pext(d_bits, n_bits, c.mask_a, c.mask_b, all, d_xa, d_xb, d_flag, stream)) != hipSuccess) return dev_err("pext", he);
+        const uint32_t *keys = d_xa;
+        int key_bits = qh[0];
+        if (fold) {
+            // bitstrings that share their block-A bits outside the fold's S qubits read the same
+            // rows of block A: visit them together
+            const uint32_t kmask = (qh[0] >= 32 ? ~0u : ((1u << qh[0]) - 1)) & ~fh[0]->smask;
+            if ((he = launch_key(d_xa, n_bits, kmask, (uint32_t *)(wsp + off_fkey), stream)) != hipSuccess) return dev_err("key", he);
+            keys = (const uint32_t *)(wsp + off_fkey);
+            key_bits = __builtin_popcount(kmask);
+        }
+        if ((he = launch_order_by_key(keys, (uint32_t *)(wsp + off_keys), (uint32_t *)(wsp + off_idx),
+                                      (uint32_t *)(wsp + off_order), n_bits, key_bits, wsp + off_sort_tmp, sort_temp,
+                                      stream)) != hipSuccess)
+            return dev_err("sort", he);
+        // groups of bitstrings that read the same block-A rows, for the byte accounting
+        if ((he = launch_count_runs((const uint32_t *)(wsp + off_keys), n_bits, d_flag + 1, stream)) != hipSuccess)
+            return dev_err("count", he);
+        ev_end(id);
+        return SF_OK;
+    };
+    if (workspace && !dry_run && workspace_bytes >= fixed) {
+        const int rc = enqueue_pre((char *)workspace);
+        if (rc) return rc;
+    }
+
     // ---------------------------------------------------------------- tree and batch capacities
     // In plain form every path is its own one-node-per-level tree, run one after another.
     Tree tree;
@@ -633,39 +700,15 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
 
     // ---------------------------------------------------------------- enqueue
-    auto dev_err = [&](const char *what, hipError_t e) {
-        err = std::string(what) + ": " + hipGetErrorString(e);
-        return SF_ERR_DEVICE;
-    };
-    const uint64_t *d_bits = bits_dev ? bits : (const uint64_t *)(ws + off_bits);
+    c.stats.ms_plan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (!pre_done) {
+        const int rc = enqueue_pre(ws);
+        if (rc) return rc;
+    }
     double *d_acc = out_dev ? amps : (double *)(ws + off_acc);
     int *d_flag = (int *)(ws + off_flag);
     uint32_t *d_xa = (uint32_t *)(ws + off_xa), *d_xb = (uint32_t *)(ws + off_xb);
     uint32_t *d_order = (uint32_t *)(ws + off_order);
-
-    // timed runs: event pairs from the circuit's pool (created once, reused by later calls)
-    std::vector<hipEvent_t> ev;
-    std::vector<int> ev_cat;    // 0 sweep, 1 gather, 2 other
-    if (timing) {
-        const size_t need = 2 * (launches.size() * (plain ? n_paths : 1) + 1);
-        while (c.events.size() < need) {
-            hipEvent_t e;
-            if ((he = hipEventCreate(&e)) != hipSuccess) return dev_err("event", he);
-            c.events.push_back((void *)e);
-        }
-        ev.reserve(need);
-    }
-    auto ev_pair = [&](int cat) -> hipEvent_t * {
-        if (!timing) return nullptr;
-        ev.push_back((hipEvent_t)c.events[ev.size()]);
-        ev.push_back((hipEvent_t)c.events[ev.size()]);
-        ev_cat.push_back(cat);
-        return &ev[ev.size() - 2];
-    };
-
-    c.stats.ms_plan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    if (!bits_dev && n_bits)
-        if ((he = hipMemcpyAsync((void *)d_bits, bits, n_bits * 8, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy bitstrings", he);
     if (!blob.empty())
         if ((he = hipMemcpyAsync(ws + off_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy plan", he);
     if (!tpath.empty()) {
@@ -674,34 +717,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
     if (!tmaskv.empty())
         if ((he = hipMemcpyAsync(ws + off_tmask, tmaskv.data(), tmaskv.size() * 4, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy masks", he);
-    {
-        hipEvent_t *e = ev_pair(2);
-        if (e) (void)hipEventRecord(e[0], stream);
-        if ((he = launch_fill_zero_i32(d_flag, 2, stream)) != hipSuccess) return dev_err("fill", he);
-        if ((he = launch_pext(d_bits, n_bits, c.mask_a, c.mask_b, all, d_xa, d_xb, d_flag, stream)) != hipSuccess) return dev_err("pext", he);
-        const uint32_t *keys = d_xa;
-        int key_bits = qh[0];
-        if (fold) {
-            // bitstrings that share their block-A bits outside the fold's S qubits read the same
-            // parent rows of block A: visit them together
-            const uint32_t kmask = (qh[0] >= 32 ? ~0u : ((1u << qh[0]) - 1)) & ~fh[0]->smask;
-            if ((he = launch_key(d_xa, n_bits, kmask, (uint32_t *)(ws + off_fkey), stream)) != hipSuccess) return dev_err("key", he);
-            keys = (const uint32_t *)(ws + off_fkey);
-            key_bits = __builtin_popcount(kmask);
-        }
-        if ((he = launch_order_by_key(keys, (uint32_t *)(ws + off_keys), (uint32_t *)(ws + off_idx), d_order, n_bits,
-                                      key_bits, ws + off_sort_tmp, sort_temp, stream)) != hipSuccess)
-            return dev_err("sort", he);
-        // groups of bitstrings that read the same block-A rows, for the byte accounting
-        if ((he = launch_count_runs((const uint32_t *)(ws + off_keys), n_bits, d_flag + 1, stream)) != hipSuccess)
-            return dev_err("count", he);
-        if (flags & SF_ACCUMULATE) {
-            if (!out_dev && n_bits)
-                if ((he = hipMemcpyAsync(d_acc, amps, n_bits * 16, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy amps", he);
-        } else if ((he = launch_fill_zero(d_acc, 2 * (uint64_t)n_bits, stream)) != hipSuccess) {
-            return dev_err("fill", he);
-        }
-        if (e) (void)hipEventRecord(e[1], stream);
+    if (flags & SF_ACCUMULATE) {
+        if (!out_dev && n_bits)
+            if ((he = hipMemcpyAsync(d_acc, amps, n_bits * 16, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy amps", he);
+    } else if ((he = launch_fill_zero(d_acc, 2 * (uint64_t)n_bits, stream)) != hipSuccess) {
+        return dev_err("fill", he);
     }
 
     char *buf = ws + off_buffers;
@@ -722,16 +742,21 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             if (!tmaskv.empty())
                 if ((he = hipMemcpy(ws + off_tmask, tmaskv.data(), tmaskv.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return dev_err("copy masks", he);
         }
+        int cur_cat = -1, cur_id = -1;     // open event pair: a run of launches of one category
+        auto timed = [&](int cat) {
+            if (!timing || cat == cur_cat) return;
+            ev_end(cur_id);
+            cur_id = ev_begin(cat);
+            cur_cat = cat;
+        };
         for (Launch &ln : launches) {
             if (ln.kind == Launch::DENSE) {
                 DenseArgs d = ln.da;
                 d.dst = buf + ln.dst_off;
                 d.src = buf + ln.src_off;
                 d.mat = (const float *)(ws + off_blob + ln.plan_off);
-                hipEvent_t *e = ev_pair(0);
-                if (e) (void)hipEventRecord(e[0], stream);
+                timed(0);
                 if ((he = launch_dense(d, ln.grid, stream)) != hipSuccess) return dev_err("dense", he);
-                if (e) (void)hipEventRecord(e[1], stream);
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;
             } else if (ln.kind == Launch::PASS) {
@@ -745,10 +770,8 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 a.prog_words = ln.prog_words;
                 a.groups_word = ln.groups_word;
                 a.terms_word = ln.terms_word;
-                hipEvent_t *e = ev_pair(0);
-                if (e) (void)hipEventRecord(e[0], stream);
+                timed(0);
                 if ((he = launch_pass(fp64, ln.R, a, ln.grid, stream)) != hipSuccess) return dev_err("pass", he);
-                if (e) (void)hipEventRecord(e[1], stream);
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;
             } else if (ln.kind == Launch::FOLD) {
@@ -761,10 +784,8 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 f.order = d_order;
                 f.acc = d_acc;
                 f.child_mask = (const uint32_t *)(ws + off_tmask) + ln.mask_off;
-                hipEvent_t *e = ev_pair(1);
-                if (e) (void)hipEventRecord(e[0], stream);
+                timed(1);
                 if ((he = launch_fold(fp64, fh[0]->nb, f, stream)) != hipSuccess) return dev_err("fold", he);
-                if (e) (void)hipEventRecord(e[1], stream);
             } else {
                 GatherArgs g = ln.ga;
                 g.a = buf + ln.dst_off;
@@ -773,12 +794,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 g.xb = d_xb;
                 g.order = d_order;
                 g.acc = d_acc;
-                hipEvent_t *e = ev_pair(1);
-                if (e) (void)hipEventRecord(e[0], stream);
+                timed(1);
                 if ((he = launch_gather(fp64, g, stream)) != hipSuccess) return dev_err("gather", he);
-                if (e) (void)hipEventRecord(e[1], stream);
             }
         }
+        ev_end(cur_id);
     }
     if (!out_dev && n_bits)
         if ((he = hipMemcpyAsync(amps, d_acc, n_bits * 16, hipMemcpyDeviceToHost, stream)) != hipSuccess) return dev_err("copy amps", he);
@@ -791,7 +811,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     if (timing) {
         for (size_t i = 0; i < ev_cat.size(); ++i) {
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+            (void)hipEventElapsedTime(&ms, (hipEvent_t)c.events[2 * i], (hipEvent_t)c.events[2 * i + 1]);
             if (ev_cat[i] == 0) c.stats.ms_sweep += ms;
             else if (ev_cat[i] == 1) c.stats.ms_gather += ms;
             else c.stats.ms_other += ms;

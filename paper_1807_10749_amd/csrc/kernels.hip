@@ -730,7 +730,9 @@ hipError_t launch_key(const uint32_t *x, uint64_t n, uint32_t mask, uint32_t *ke
 __global__ void count_runs_kernel(const uint32_t *keys, uint64_t n, int *count)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && (i == 0 || keys[i] != keys[i - 1])) atomicAdd(count, 1);
+    const bool first = i < n && (i == 0 || keys[i] != keys[i - 1]);
+    const uint64_t b = __ballot(first);      // one atomic per wave
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (int)__popcll(b));
 }
 
 hipError_t launch_count_runs(const uint32_t *keys, uint64_t n, int *count, hipStream_t s)
