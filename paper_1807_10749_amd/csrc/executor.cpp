@@ -40,7 +40,11 @@ int build_tree(const Circuit &c, const uint64_t *ids, uint64_t begin, uint64_t n
 {
     const int L = (int)c.levels.size() - 1;
     const int k = c.k;
-    std::vector<uint64_t> leaf(n);
+    t.node.assign(L + 1, {});
+    t.parent.assign(L + 1, {});
+    t.first_child.assign(L + 1, {});
+    std::vector<uint64_t> &leaf = t.node[L];     // the last level decides every path bit
+    leaf.resize(n);
     if (ids) {
         std::copy(ids, ids + n, leaf.begin());
         std::sort(leaf.begin(), leaf.end());
@@ -50,32 +54,23 @@ int build_tree(const Circuit &c, const uint64_t *ids, uint64_t begin, uint64_t n
         for (uint64_t i = 0; i < n; ++i) leaf[i] = begin + i;
     }
     if (n && (k < 64) && (leaf.back() >> k) != 0) { err = "path id >= 2^k"; return SF_ERR_INVALID; }
-    t.node.assign(L + 1, {});
-    t.parent.assign(L + 1, {});
-    t.first_child.assign(L + 1, {});
-    for (int l = 0; l <= L; ++l) {
+    // bottom-up: a level's nodes are the distinct prefixes of the level below (sorted input,
+    // so equal prefixes are adjacent); the cost is the total node count, not leaves x levels
+    for (int l = L - 1; l >= 0; --l) {
         const int drop = k - c.levels[l].bits_after;   // bits not yet decided at this level
+        const std::vector<uint64_t> &below = t.node[l + 1];
         std::vector<uint64_t> &nd = t.node[l];
-        for (uint64_t i = 0; i < n; ++i) {
-            const uint64_t v = drop >= 64 ? 0 : ((leaf[i] >> drop) << drop);
+        std::vector<uint32_t> &par = t.parent[l + 1];
+        par.resize(below.size());
+        for (size_t i = 0; i < below.size(); ++i) {
+            const uint64_t v = drop >= 64 ? 0 : ((below[i] >> drop) << drop);
             if (nd.empty() || nd.back() != v) nd.push_back(v);
+            par[i] = (uint32_t)(nd.size() - 1);
         }
-        if (l > 0) {
-            const int pdrop = k - c.levels[l - 1].bits_after;
-            std::vector<uint32_t> &par = t.parent[l];
-            par.resize(nd.size());
-            const std::vector<uint64_t> &pn = t.node[l - 1];
-            size_t pi = 0;
-            for (size_t i = 0; i < nd.size(); ++i) {
-                const uint64_t pv = pdrop >= 64 ? 0 : ((nd[i] >> pdrop) << pdrop);
-                while (pn[pi] != pv) ++pi;
-                par[i] = (uint32_t)pi;
-            }
-            std::vector<uint64_t> &fc = t.first_child[l - 1];
-            fc.assign(pn.size() + 1, 0);
-            for (size_t i = 0; i < nd.size(); ++i) fc[par[i] + 1]++;
-            for (size_t i = 0; i < pn.size(); ++i) fc[i + 1] += fc[i];
-        }
+        std::vector<uint64_t> &fc = t.first_child[l];
+        fc.assign(nd.size() + 1, 0);
+        for (size_t i = 0; i < below.size(); ++i) fc[par[i] + 1]++;
+        for (size_t i = 0; i < nd.size(); ++i) fc[i + 1] += fc[i];
     }
     return SF_OK;
 }
