@@ -17,6 +17,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 
 #include "kernels.hpp"
 #include "sf_host.hpp"
@@ -103,6 +104,38 @@ struct Launch {
 struct BatchRec { int level; size_t table_off; uint64_t slots; };
 
 struct BlobEntry { size_t off; uint32_t words, groups_word, terms_word; };
+
+// Host-side result of planning one request: everything the enqueue step needs besides the
+// device pointers of the call.
+struct Planned {
+    std::vector<LevelBuf> lb;
+    size_t table_bound = 0;
+    std::vector<Launch> launches;
+    std::vector<BatchRec> batches;
+    std::vector<uint64_t> tpath;          // per slot of every batch: the node's path id
+    std::vector<uint32_t> tparent;        // per slot: parent slot inside the parent batch
+    std::vector<uint32_t> tmaskv;         // descendant masks of the batches the fold reads
+    std::vector<char> blob;               // pass programs, dense matrices, fold tables
+    size_t fold_tab_off[2] = {0, 0};
+    size_t plain_mask_idx = SIZE_MAX;
+    uint64_t n_leaf_batches = 0;
+};
+
+// The circuit's last planned request; the next call reuses the plan if it is the same request
+// (paths, bitstring count, layout flags, tuning, caller workspace).
+struct ExecCache {
+    bool valid = false;
+    uint64_t n_paths = 0, path_begin = 0;
+    size_t n_bits = 0;
+    uint32_t flags = 0;
+    bool has_ids = false;
+    std::vector<uint64_t> ids;
+    const void *ws = nullptr;
+    size_t ws_bytes = 0;
+    sf_tuning_t tuning{};
+    int device_cus = 0;
+    Planned plan;
+};
 
 }  // namespace
 
@@ -268,10 +301,26 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
 
     // ---------------------------------------------------------------- tree and batch capacities
     // In plain form every path is its own one-node-per-level tree, run one after another.
+    // A request identical to the circuit's previous one reuses its plan (launch list, slot
+    // tables, programs); everything is still uploaded and enqueued.  Plain form rewrites its
+    // tables per path and is planned every time.
+    if (!c.exec_cache) c.exec_cache = std::make_shared<ExecCache>();
+    ExecCache &cache = *static_cast<ExecCache *>(c.exec_cache.get());
+    const uint32_t layout_flags = flags & ~uint32_t(SF_TIMING | SF_ACCUMULATE);
+    const bool cacheable = n_paths && !plain && !dry_run && workspace;
+    const bool hit = cacheable && cache.valid && cache.n_paths == n_paths && cache.n_bits == n_bits &&
+                     cache.flags == layout_flags && cache.ws == workspace && cache.ws_bytes == workspace_bytes &&
+                     cache.device_cus == c.device_cus && cache.has_ids == (path_ids != nullptr) &&
+                     (path_ids ? std::equal(path_ids, path_ids + n_paths, cache.ids.begin())
+                               : cache.path_begin == path_begin) &&
+                     std::memcmp(&cache.tuning, &c.tuning, sizeof(sf_tuning_t)) == 0;
+    Planned fresh;
+    Planned &PL = hit ? cache.plan : fresh;
+    std::vector<LevelBuf> &lb = PL.lb;
+    size_t &table_bound = PL.table_bound;
+    if (!hit) lb.assign(L + 1, LevelBuf());
     Tree tree;
-    std::vector<LevelBuf> lb(L + 1);
-    size_t table_bound = 0;
-    if (n_paths) {
+    if (n_paths && !hit) {
         int rc;
         if (plain) {
             const uint64_t first = path_ids ? path_ids[0] : path_begin;
@@ -328,12 +377,12 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     (void)sigma;
 
     // ---------------------------------------------------------------- launch list (depth first over batches)
-    std::vector<Launch> launches;
-    std::vector<BatchRec> batches;
-    std::vector<uint64_t> tpath;         // per slot of every batch: the node's path id
-    std::vector<uint32_t> tparent;       // per slot: parent slot inside the parent batch
+    std::vector<Launch> &launches = PL.launches;
+    std::vector<BatchRec> &batches = PL.batches;
+    std::vector<uint64_t> &tpath = PL.tpath;
+    std::vector<uint32_t> &tparent = PL.tparent;
     bool plan_error = false;
-    std::vector<char> blob;
+    std::vector<char> &blob = PL.blob;
     std::map<const SegmentPlan *, std::vector<BlobEntry>> blob_index;
     std::complex<double> leaf_scale[2];
     for (int h = 0; h < 2; ++h) {
@@ -349,10 +398,10 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         for (int l = 0; l <= fold_at; ++l) s *= c.half[h].seg_scale[l];
         fscale *= s;
     }
-    std::vector<uint32_t> tmaskv;        // descendant masks of the batches the fold reads
-    std::vector<uint32_t> node_mask;     // per node of that level (filled below)
-    size_t fold_tab_off[2] = {0, 0};
-    size_t plain_mask_idx = SIZE_MAX;
+    std::vector<uint32_t> &tmaskv = PL.tmaskv;
+    std::vector<uint32_t> node_mask;     // per node of the level the fold reads (filled below)
+    size_t (&fold_tab_off)[2] = PL.fold_tab_off;
+    size_t &plain_mask_idx = PL.plain_mask_idx;
 
     auto blob_entries = [&](const SegmentPlan &sp) -> const std::vector<BlobEntry> & {
         auto it = blob_index.find(&sp);
@@ -406,7 +455,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     };
 
     const unsigned max_grid = (unsigned)std::max(1, c.device_cus) * (c.tuning.waves_per_cu ? c.tuning.waves_per_cu / 4 : 8);
-    uint64_t n_leaf_batches = 0;
+    uint64_t &n_leaf_batches = PL.n_leaf_batches;
 
     // appends the slot tables of one batch (padded to `slots` entries)
     auto put_tables = [&](const std::vector<uint64_t> &paths, const std::vector<uint32_t> &parents, uint64_t slots) {
@@ -624,7 +673,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
 
     // per node of the level the gather reads: bit i set if its descendant with branch value i
     // (the low path bits decided by the folded levels) is requested
-    if (n_paths && fold) {
+    if (n_paths && fold && !hit) {
         node_mask.assign(tree.node[fold_at].size(), 0);
         const uint64_t low = (uint64_t(1) << fh[0]->nb) - 1;
         for (size_t i = 0; i < tree.node[L].size(); ++i) {
@@ -633,7 +682,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             node_mask[a] |= 1u << (tree.node[L][i] & low);
         }
     }
-    if (n_paths && fold) {
+    if (n_paths && fold && !hit) {
         for (int h = 0; h < 2; ++h) {
             const std::vector<std::complex<double>> &tab = fh[h]->tab;
             fold_tab_off[h] = align_up(blob.size());
@@ -644,7 +693,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             }
         }
     }
-    if (n_paths) {
+    if (n_paths && !hit) {
         const uint64_t ns0 = std::max<uint64_t>(1, min_slots);
         const size_t toff = put_tables(std::vector<uint64_t>{0}, std::vector<uint32_t>{0}, ns0);
         batches.push_back(BatchRec{0, toff, ns0});
@@ -671,6 +720,22 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         return SF_OK;
     }
     if (n_paths && tables_bytes > table_bound) { err = "internal: slot tables exceed their reservation"; return SF_ERR_UNSUPPORTED; }
+    if (cacheable && !hit) {
+        cache.valid = false;
+        cache.plan = fresh;
+        cache.n_paths = n_paths;
+        cache.path_begin = path_begin;
+        cache.n_bits = n_bits;
+        cache.flags = layout_flags;
+        cache.has_ids = path_ids != nullptr;
+        if (path_ids) cache.ids.assign(path_ids, path_ids + n_paths);
+        else cache.ids.clear();
+        cache.ws = workspace;
+        cache.ws_bytes = workspace_bytes;
+        cache.tuning = c.tuning;
+        cache.device_cus = c.device_cus;
+        cache.valid = true;
+    }
 
     // ---------------------------------------------------------------- workspace
     const size_t off_tpath = fixed;

@@ -285,6 +285,7 @@ int build_programs(Circuit &c, std::string &err)
             hp.seg_scale[l] = std::pow(s_h, nh) * std::pow(s_xy, nxy) * std::ldexp(1.0, e);
         }
     }
+    c.exec_cache.reset();
     for (int h = 0; h < 2; ++h) {
         c.half[h].folds.clear();
         for (int F = 1; F <= L; ++F) c.half[h].folds.push_back(make_fold(c, h, F));

@@ -2,6 +2,7 @@
 #pragma once
 #include <complex>
 #include <map>
+#include <memory>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -105,6 +106,7 @@ struct Circuit {
     void *dev_ws = nullptr;
     size_t dev_ws_bytes = 0;
     std::vector<void *> events;       // hipEvent_t pool of timed runs, reused across calls
+    std::shared_ptr<void> exec_cache; // the last planned request (executor.cpp)
     int device_cus = 0;
 
     sf_run_stats_t stats{};

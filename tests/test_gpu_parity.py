@@ -326,3 +326,71 @@ def test_grid5x6_fold_depths_tight_workspace(sf):
     ref = full[str({"no_leaf_fold": 1})]
     for k, a in full.items():
         assert c11_error(a, ref, 1 << c.k, c.k, 30) <= 2 * TOL_C64, k
+
+
+def test_fold_empty_accumulate_device_buffers(sf):
+    """Folded gather with device buffers and a caller's workspace (bitstring preprocessing is
+    enqueued before planning): zero paths, two path blocks accumulated, a bad device bitstring,
+    and a duplicated bitstring."""
+    import torch
+    cfg, g, c = _circuit(sf, "grid5x6_d24")
+    assert "folded" in sf.describe_plan(c.handle)
+    bits = random_bitstrings(30, 300, 17)
+    bits = np.concatenate([bits, bits[:3]])               # repeated bitstrings get the same amplitude
+    dbits = torch.from_numpy(bits.view(np.int64)).cuda()
+    acc = torch.full((2 * bits.size,), 7.0, dtype=torch.float64, device="cuda")
+    ws = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    flags = sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
+    stream = torch.cuda.current_stream()
+    say("grid5x6_d24 folded: zero paths")
+    sf.run_paths(c.handle, np.zeros(0, dtype=np.uint64), 0, 0, dbits, bits.size, acc, flags, stream, ws, ws.numel())
+    assert torch.all(acc == 0)
+    say("grid5x6_d24 folded: two blocks of 256 paths accumulated")
+    sf.run_paths(c.handle, None, 1024, 256, dbits, bits.size, acc, flags, stream, ws, ws.numel())
+    sf.run_paths(c.handle, None, 1280, 256, dbits, bits.size, acc, flags | sf.SF_ACCUMULATE, stream, ws, ws.numel())
+    a = acc.cpu().numpy().view(np.complex128)
+    o = oracle.path_sum(30, g, cfg.cut_mask(), np.arange(1024, 1536, dtype=np.uint64), bits)
+    assert c11_error(a, o, 512, c.k, 30) <= TOL_C64
+    assert np.array_equal(a[-3:], a[:3])
+    say("grid5x6_d24 folded: bad device bitstring")
+    bad = dbits.clone()
+    bad[5] = 1 << 40
+    with pytest.raises(sf.SFError):
+        sf.run_paths(c.handle, None, 0, 64, bad, bits.size, acc, flags, stream, ws, ws.numel())
+    # the library still works afterwards on the same workspace
+    sf.run_paths(c.handle, None, 1024, 512, dbits, bits.size, acc, flags, stream, ws, ws.numel())
+    a = acc.cpu().numpy().view(np.complex128)
+    assert c11_error(a, o, 512, c.k, 30) <= TOL_C64
+
+
+def test_repeated_request_reuses_plan(sf):
+    """A call identical to the previous one reuses its plan: results are unchanged, ACCUMULATE
+    still adds, and a different path list, bitstring count or tuning is planned afresh."""
+    import torch
+    cfg, g, c = _circuit(sf, "grid5x6_d24")
+    bits = random_bitstrings(30, 500, 23)
+    dbits = torch.from_numpy(bits.view(np.int64)).cuda()
+    acc = torch.zeros(2 * bits.size, dtype=torch.float64, device="cuda")
+    ws = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+    flags = sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
+    stream = torch.cuda.current_stream()
+    ids = np.sort(np.random.default_rng(4).choice(1 << c.k, 700, replace=False)).astype(np.uint64)
+    o = oracle.path_sum(30, g, cfg.cut_mask(), ids, bits)
+    runs = []
+    for rep in range(3):
+        say(f"grid5x6_d24 repeated request {rep}")
+        sf.run_paths(c.handle, ids, 0, ids.size, dbits, bits.size, acc, flags, stream, ws, ws.numel())
+        runs.append(acc.cpu().numpy().view(np.complex128).copy())
+    assert c11_error(runs[0], o, ids.size, c.k, 30) <= TOL_C64
+    assert np.array_equal(runs[0], runs[1]) and np.array_equal(runs[0], runs[2])
+    sf.run_paths(c.handle, ids, 0, ids.size, dbits, bits.size, acc, flags | sf.SF_ACCUMULATE, stream, ws, ws.numel())
+    assert np.allclose(acc.cpu().numpy().view(np.complex128), 2 * runs[0], rtol=1e-12, atol=0)
+    ids2 = ids[::2].copy()
+    say("grid5x6_d24 other path list after a repeated request")
+    sf.run_paths(c.handle, ids2, 0, ids2.size, dbits, bits.size, acc, flags, stream, ws, ws.numel())
+    o2 = oracle.path_sum(30, g, cfg.cut_mask(), ids2, bits)
+    assert c11_error(acc.cpu().numpy().view(np.complex128), o2, ids2.size, c.k, 30) <= TOL_C64
+    say("grid5x6_d24 fewer bitstrings, other tuning")
+    c.tune(fold_levels=1)
+    sf.run_paths(c.handle, ids2, 0, ids2.size, dbits, 200, acc, flags, stream, ws, ws.numel())
+    assert c11_error(acc.cpu().numpy().view(np.complex128)[:200], o2[:200], ids2.size, c.k, 30) <= TOL_C64
