@@ -7,4 +7,5 @@ import this package.  It is built from ``oracle/sf_oracle.c`` by
 from .oracle import (  # noqa: F401
     lib_path, load, gate_matrix, full_state, path_sum, num_cut, cut_gates,
     sample_paths, num_paths, pext, num_threads,
+    rejection_m, sample_bitstrings, splitmix64_at, rejection_accept,
 )

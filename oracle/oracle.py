@@ -39,6 +39,11 @@ def load():
     lib.or_num_paths.restype = ctypes.c_int64
     lib.or_sample_paths.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, c_u64p,
                                     ctypes.c_int64, c_i64p]
+    lib.or_sample_bitstrings.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, c_u64p]
+    lib.or_splitmix64_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.or_splitmix64_at.restype = ctypes.c_uint64
+    lib.or_rejection_accept.argtypes = [c_dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_uint8), c_dp]
     _LIB = lib
     return lib
 
@@ -125,3 +130,45 @@ def sample_paths(k: int, f: float, seed: int) -> np.ndarray:
     if load().or_sample_paths(k, f, seed, _ptr(out, ctypes.c_uint64), m, ctypes.byref(n_out)):
         raise ValueError("sampling failed")
     return out[: n_out.value]
+
+
+# ---------------------------------------------------------------- rejection sampling
+# Section "Frugal rejection sampling" and its figure (Algorithm 1 basic, Algorithm 2 frugal).
+
+def rejection_m(n_qubits: int, eps: float, basic: bool = False) -> float:
+    """Step 1.  Algorithm 1: M = ceil(ln(N / eps)), N = 2^n.  Algorithm 2 under Porter-Thomas
+    statistics: the smallest integer M' >= 1 with sum_{p > M'/N} p = e^{-M'} (1 + M') <= eps."""
+    import math
+    if not (eps > 0.0) or n_qubits < 1:
+        raise ValueError("bad eps or n")
+    if basic:
+        return float(math.ceil(n_qubits * math.log(2.0) - math.log(eps)))
+    m = 1
+    while math.exp(-m) * (1.0 + m) > eps:
+        m += 1
+    return float(m)
+
+
+def sample_bitstrings(n_qubits: int, count: int, seed: int) -> np.ndarray:
+    """Step 2: count distinct uniform n-qubit bitstrings in SplitMix64 draw order."""
+    out = np.zeros(count, dtype=np.uint64)
+    if load().or_sample_bitstrings(n_qubits, count, seed, _ptr(out, ctypes.c_uint64)):
+        raise ValueError("bad n or count")
+    return out
+
+
+def splitmix64_at(seed: int, j: int) -> int:
+    return int(load().or_splitmix64_at(seed, j))
+
+
+def rejection_accept(amps, n_qubits: int, m: float, seed: int, basic: bool = False):
+    """Step 4 (Algorithm 2; Algorithm 1 steps 4-5 with basic=True) on a batch of amplitudes.
+    Returns (accept flags as bool array, batch estimate of the mass above M/N)."""
+    a = np.ascontiguousarray(np.asarray(amps, dtype=np.complex128))
+    flat = a.view(np.float64)
+    acc = np.zeros(a.size, dtype=np.uint8)
+    err = ctypes.c_double(0.0)
+    if load().or_rejection_accept(_ptr(flat, ctypes.c_double), a.size, n_qubits, m, seed, int(basic),
+                                  _ptr(acc, ctypes.c_uint8), ctypes.byref(err)):
+        raise ValueError("bad arguments")
+    return acc.astype(bool), err.value

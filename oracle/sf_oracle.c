@@ -19,6 +19,9 @@
  *       amplitudes", end of Section 2).
  *   Path selection for fidelity f (Section 3, Eq. (fid)): ceil(f 2^k)
  *   distinct path ids drawn with Floyd's algorithm over SplitMix64.
+ *   Rejection sampling of bitstrings from a batch of output probabilities
+ *   (Section "Frugal rejection sampling", Algorithms 1 and 2): candidate
+ *   bitstrings, acceptance and the per-batch sampling-error estimate.
  *
  * Readings of points the paper leaves open (kept identical in the GPU path
  * by definition, never by shared code):
@@ -434,5 +437,74 @@ int or_sample_paths(int k, double f, uint64_t seed, uint64_t *out, int64_t cap, 
     free(s.slot);
     qsort(out, (size_t)m, sizeof(uint64_t), cmp_u64);
     *n_out = m;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Rejection sampling from a batch of output probabilities            */
+/* (Section "Frugal rejection sampling" and its figure: Algorithm 1,   */
+/* basic; Algorithm 2, frugal).                                        */
+/*                                                                     */
+/* Step 2 (candidates): count distinct uniform n-qubit bitstrings;     */
+/* draw i is output i of SplitMix64(seed) masked to n bits, repeats    */
+/* are skipped, the kept draws stay in draw order.                     */
+/* Step 4 (acceptance) for candidate j with amplitude a_j:             */
+/*   p_j = re^2 + im^2 (two products and a sum, each rounded),         */
+/*   t_j = p_j * s with s = 2^n / M (N p_j / M),                       */
+/*   u_j = (output j of SplitMix64(seed_u) >> 11) * 2^-53;             */
+/*   Algorithm 2 accepts when u_j < t_j, i.e. with probability         */
+/*   min{1, p_j N / M'}; Algorithm 1 first removes candidates with     */
+/*   p_j > M / N (t_j > 1) and accepts the rest when u_j < t_j.        */
+/* The batch's sampling error (the probability mass above M/N, which   */
+/* the paper computes per batch when Porter-Thomas statistics are not  */
+/* assumed) is estimated from the uniform candidates as                */
+/*   (N / n) * sum_{j : t_j > 1} p_j.                                  */
+/* ------------------------------------------------------------------ */
+int or_sample_bitstrings(int n_qubits, uint64_t count, uint64_t seed, uint64_t *out)
+{
+    if (n_qubits < 1 || n_qubits > 64) return -1;
+    if (n_qubits < 64 && count > ((uint64_t)1 << n_qubits)) return -1;
+    const uint64_t mask = n_qubits == 64 ? ~(uint64_t)0 : (((uint64_t)1 << n_qubits) - 1);
+    u64set s;
+    s.cap = 1;
+    while (s.cap < 2 * count + 2) s.cap <<= 1;
+    s.slot = (uint64_t *)calloc(s.cap, sizeof(uint64_t));
+    if (!s.slot) return -1;
+    uint64_t st = seed, got = 0;
+    while (got < count) {
+        const uint64_t x = splitmix_next(&st) & mask;
+        if (set_insert(&s, x)) out[got++] = x;
+    }
+    free(s.slot);
+    return 0;
+}
+
+/* output j (0-based) of SplitMix64(seed) */
+uint64_t or_splitmix64_at(uint64_t seed, uint64_t j)
+{
+    uint64_t st = seed + j * 0x9E3779B97F4A7C15ULL;
+    return splitmix_next(&st);
+}
+
+int or_rejection_accept(const double *amps, int64_t n, int n_qubits, double m, uint64_t seed_u,
+                        int basic, uint8_t *accept, double *err_est)
+{
+    if (n < 0 || n_qubits < 1 || n_qubits > 64 || !(m > 0.0)) return -1;
+    const double s = ldexp(1.0, n_qubits) / m;
+    double excess = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double re = amps[2 * j], im = amps[2 * j + 1];
+        const double rr = re * re;
+        const double ii = im * im;
+        const double p = rr + ii;
+        const double t = p * s;
+        const double u = (double)(or_splitmix64_at(seed_u, (uint64_t)j) >> 11) * 0x1p-53;
+        int acc;
+        if (basic) acc = (t <= 1.0) && (u < t);
+        else acc = u < t;
+        accept[j] = (uint8_t)acc;
+        if (t > 1.0) excess += p;
+    }
+    *err_est = n ? excess * ldexp(1.0, n_qubits) / (double)n : 0.0;
     return 0;
 }
