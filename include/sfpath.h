@@ -63,6 +63,9 @@ typedef struct sf_circuit sf_circuit_t;   /* opaque, library-owned */
 #define SF_BITS_ON_DEVICE 16u  /* bitstrings is a device pointer */
 #define SF_TIMING         32u  /* time every kernel with HIP events (see get_run_stats) */
 
+/* rejection-sampling flag (rejection_m, rejection_accept, frugal_sample) */
+#define SF_SAMPLE_BASIC   256u /* Algorithm 1 instead of Algorithm 2 */
+
 /*
  * create_circuit: copy a gate list on an R x C grid (rows*cols <= 64).
  * Gates must act on grid qubits; a CZ must join grid neighbours; cycles
@@ -219,6 +222,68 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char *last_error(void);
+
+/*
+ * Rejection sampling of bitstrings from a batch of output probabilities
+ * (Section "Frugal rejection sampling" and its figure: Algorithm 1, basic;
+ * Algorithm 2, frugal).  N = 2^n for n qubits.
+ *
+ * rejection_m: step 1.  Algorithm 2 (flags 0): the smallest integer M' >= 1
+ * with e^{-M'} (1 + M') <= eps, the probability mass above M'/N under
+ * Porter-Thomas statistics (M' = 10 for eps = 5e-4).  Algorithm 1
+ * (SF_SAMPLE_BASIC): M = ceil(ln(N / eps)) (41 for eps = 1e-3, n = 49).
+ * Host only; SF_ERR_INVALID for n outside 1..64 or eps outside (0, 1).
+ */
+int rejection_m(uint32_t n_qubits, double eps, uint32_t flags, double *m);
+
+/*
+ * sample_bitstrings: step 2.  count distinct uniform n-qubit bitstrings into
+ * the host array out (bit q = qubit q): draw i is output i of
+ * SplitMix64(seed) masked to n bits, repeats are skipped, the kept draws stay
+ * in draw order.  SF_ERR_INVALID if count exceeds 2^n.
+ */
+int sample_bitstrings(uint32_t n_qubits, uint64_t count, uint64_t seed, uint64_t *out);
+
+/* rejection_workspace_size: device bytes rejection_accept needs for n candidates. */
+int rejection_workspace_size(uint64_t n, size_t *bytes);
+
+/*
+ * rejection_accept: step 4 of Algorithm 2 (steps 4-5 of Algorithm 1 with
+ * SF_SAMPLE_BASIC) on the device.  amps: n FP64 complex amplitudes (re, im
+ * interleaved, device, as run_paths writes them with SF_OUT_ON_DEVICE) of
+ * candidates drawn uniformly.  For candidate j: p = re^2 + im^2, t = p N / M,
+ * u = (output j of SplitMix64(seed) >> 11) * 2^-53, every product and sum
+ * rounded on its own in FP64; Algorithm 2 accepts when u < t, i.e. with
+ * probability min{1, p N / M'}; Algorithm 1 removes candidates with t > 1
+ * (p > M/N) and accepts the others when u < t.  accepted (device, capacity
+ * n) receives the indices of the accepted candidates in ascending order,
+ * *n_accepted (host) their number, *err_est (host) the batch estimate
+ * (N / n) sum_{t > 1} p of the probability mass above M/N (the sampling error
+ * the paper computes per batch when Porter-Thomas statistics are not
+ * assumed).  workspace: device scratch of rejection_workspace_size(n) bytes,
+ * owned by the caller.  Synchronizes hip_stream before returning.
+ */
+int rejection_accept(const double *amps, uint64_t n, uint32_t n_qubits, double m, uint64_t seed,
+                     uint32_t flags, uint32_t *accepted, uint64_t *n_accepted, double *err_est,
+                     void *hip_stream, void *workspace, size_t workspace_bytes);
+
+/*
+ * frugal_sample: Algorithm 2 (Algorithm 1 with SF_SAMPLE_BASIC) end to end:
+ * n_candidates candidates from sample_bitstrings(seed_candidates), their
+ * amplitudes by run_paths over the given paths (path_ids / path_begin /
+ * n_paths as in run_paths; flags may add SF_FP64_SWEEPS or SF_PLAIN), and
+ * rejection_accept with m and seed_accept.  The accepted bitstrings go to the
+ * host array out (capacity n_candidates) in candidate order, their number to
+ * *n_out, the batch's error estimate to *err_est.  With a caller workspace,
+ * 28 B per candidate plus the acceptance scratch are taken from its end and
+ * run_paths gets the rest (at least 256 MiB must remain); without one the
+ * library allocates.  The probability of a path-sum subset is |amp|^2 of the
+ * partial sum (Section 3: the sum over a fraction f of the paths).
+ */
+int frugal_sample(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
+                  uint64_t n_candidates, double m, uint64_t seed_candidates, uint64_t seed_accept,
+                  uint32_t flags, void *hip_stream, void *workspace, size_t workspace_bytes,
+                  uint64_t *out, uint64_t *n_out, double *err_est);
 
 /* ------------------------------------------------------------------ */
 /* Serving: jobs arrive at any time and share one GPU.                 */

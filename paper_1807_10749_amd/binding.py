@@ -17,11 +17,13 @@ LIB_PATH = os.path.join(_HERE, "libsfpath.so")
 
 SF_OK, SF_ERR_INVALID, SF_ERR_OOM, SF_ERR_UNSUPPORTED, SF_ERR_NO_CUT, SF_ERR_DEVICE = 0, -1, -2, -3, -4, -5
 SF_ACCUMULATE, SF_OUT_ON_DEVICE, SF_FP64_SWEEPS, SF_PLAIN, SF_BITS_ON_DEVICE, SF_TIMING = 1, 2, 4, 8, 16, 32
+SF_SAMPLE_BASIC = 256
 
 EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_paths", "sample_paths",
            "run_paths", "workspace_size", "set_tuning", "get_tuning", "autotune", "get_run_stats",
            "describe_plan", "last_error", "server_create", "server_submit", "server_poll", "server_release",
-           "server_drain", "server_stats", "server_destroy", "server_last_error"]
+           "server_drain", "server_stats", "server_destroy", "server_last_error", "rejection_m",
+           "sample_bitstrings", "rejection_workspace_size", "rejection_accept", "frugal_sample"]
 SF_PENDING = 1
 
 
@@ -96,6 +98,13 @@ def _load():
     lib.server_drain.argtypes = [vp]
     lib.server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.server_destroy.argtypes = [vp]
+    lib.rejection_m.argtypes = [u32, ctypes.c_double, u32, ctypes.POINTER(ctypes.c_double)]
+    lib.sample_bitstrings.argtypes = [u32, u64, u64, vp]
+    lib.rejection_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
+    lib.rejection_accept.argtypes = [vp, u64, u32, ctypes.c_double, u64, u32, vp, pu64,
+                                     ctypes.POINTER(ctypes.c_double), vp, vp, sz]
+    lib.frugal_sample.argtypes = [vp, vp, u64, u64, u64, ctypes.c_double, u64, u64, u32, vp, vp, sz, vp, pu64,
+                                  ctypes.POINTER(ctypes.c_double)]
     lib.server_last_error.restype = ctypes.c_char_p
     lib.last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -174,6 +183,51 @@ def sample_paths(k: int, f: float, seed: int) -> np.ndarray:
     n = ctypes.c_uint64()
     _check(lib.sample_paths(k, f, seed, out.ctypes.data, m, ctypes.byref(n)))
     return out[: n.value]
+
+
+def rejection_m(n_qubits: int, eps: float, flags: int = 0) -> float:
+    m = ctypes.c_double()
+    _check(lib.rejection_m(n_qubits, eps, flags, ctypes.byref(m)))
+    return m.value
+
+
+def sample_bitstrings(n_qubits: int, count: int, seed: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    _check(lib.sample_bitstrings(n_qubits, count, seed, out.ctypes.data))
+    return out
+
+
+def rejection_workspace_size(n: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib.rejection_workspace_size(n, ctypes.byref(b)))
+    return b.value
+
+
+def rejection_accept(amps, n: int, n_qubits: int, m: float, seed: int, accepted, flags: int = 0, stream=None,
+                     workspace=None, workspace_bytes: int = 0):
+    """Raw call (device buffers as torch tensors or addresses); returns (n_accepted, err_est)."""
+    na = ctypes.c_uint64()
+    err = ctypes.c_double()
+    _check(lib.rejection_accept(_ptr(amps), n, n_qubits, m, seed, flags, _ptr(accepted), ctypes.byref(na),
+                                ctypes.byref(err), _stream_handle(stream), _ptr(workspace), workspace_bytes))
+    return na.value, err.value
+
+
+def frugal_sample(c: int, path_ids, path_begin: int, n_paths: int, n_candidates: int, m: float,
+                  seed_candidates: int, seed_accept: int, flags: int = 0, stream=None, workspace=None,
+                  workspace_bytes: int = 0):
+    """Returns (accepted bitstrings as uint64 array, error estimate)."""
+    ids = None
+    if path_ids is not None:
+        ids = np.ascontiguousarray(path_ids, dtype=np.uint64)
+        n_paths = ids.size
+    out = np.empty(max(n_candidates, 1), dtype=np.uint64)
+    n = ctypes.c_uint64()
+    err = ctypes.c_double()
+    _check(lib.frugal_sample(c, _ptr(ids), path_begin, n_paths, n_candidates, m, seed_candidates, seed_accept, flags,
+                             _stream_handle(stream), _ptr(workspace), workspace_bytes, out.ctypes.data,
+                             ctypes.byref(n), ctypes.byref(err)))
+    return out[: n.value], err.value
 
 
 def run_paths(c: int, path_ids, path_begin: int, n_paths: int, bitstrings, n_bits: int, amps,

@@ -742,6 +742,62 @@ hipError_t launch_count_runs(const uint32_t *keys, uint64_t n, int *count, hipSt
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- rejection sampling
+
+// Candidate j of a batch (Algorithms 1 and 2 of the rejection-sampling section): p = re^2 + im^2,
+// t = p * scale (scale = 2^n / M), u = (output j of SplitMix64(seed) >> 11) * 2^-53.  Algorithm 2
+// accepts when u < t; Algorithm 1 (basic) removes t > 1 first.  excess[j] = p when t > 1.
+// Every product and sum is rounded on its own (no contraction), so the decision is the same FP64
+// computation on any device.
+__global__ void accept_kernel(const double *amps, uint64_t n, double scale, uint64_t seed, int basic,
+                              uint8_t *flag, double *excess)
+{
+#pragma clang fp contract(off)
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double re = amps[2 * j], im = amps[2 * j + 1];
+    const double rr = re * re;
+    const double ii = im * im;
+    const double p = rr + ii;
+    const double t = p * scale;
+    uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = (double)(z >> 11) * 0x1p-53;
+    const bool acc = basic ? (t <= 1.0 && u < t) : (u < t);
+    flag[j] = acc ? 1 : 0;
+    excess[j] = t > 1.0 ? p : 0.0;
+}
+
+hipError_t reject_temp_bytes(uint64_t n, size_t *bytes)
+{
+    size_t a = 0, b = 0;
+    hipError_t e = hipcub::DeviceSelect::Flagged(nullptr, a, hipcub::CountingInputIterator<uint32_t>(0),
+                                                 (const uint8_t *)nullptr, (uint32_t *)nullptr,
+                                                 (uint64_t *)nullptr, (int)n);
+    if (e != hipSuccess) return e;
+    e = hipcub::DeviceReduce::Sum(nullptr, b, (const double *)nullptr, (double *)nullptr, (int)n);
+    *bytes = a > b ? a : b;
+    return e;
+}
+
+hipError_t launch_accept(const double *amps, uint64_t n, double scale, uint64_t seed, int basic, uint8_t *flag,
+                         double *excess, uint32_t *accepted, uint64_t *n_accepted, double *excess_sum,
+                         void *temp, size_t temp_bytes, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    accept_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(amps, n, scale, seed, basic, flag, excess);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t tb = temp_bytes;
+    e = hipcub::DeviceSelect::Flagged(temp, tb, hipcub::CountingInputIterator<uint32_t>(0), flag, accepted,
+                                      n_accepted, (int)n, s);
+    if (e != hipSuccess) return e;
+    tb = temp_bytes;
+    return hipcub::DeviceReduce::Sum(temp, tb, excess, excess_sum, (int)n, s);
+}
+
 __global__ void fill_zero_kernel(double *p, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -33,6 +33,15 @@ hipError_t launch_key(const uint32_t *x, uint64_t n, uint32_t mask, uint32_t *ke
 // *count += number of distinct values in the sorted array keys[0..n).
 hipError_t launch_count_runs(const uint32_t *keys, uint64_t n, int *count, hipStream_t s);
 
+// Rejection-sampling decisions for a batch of n FP64 complex amplitudes (see accept_kernel):
+// flag[j] (0/1) and excess[j] per candidate, then the indices of accepted candidates in
+// ascending order into accepted, their number into *n_accepted (device), and the sum of excess
+// into *excess_sum (device).  temp: reject_temp_bytes(n) bytes.
+hipError_t reject_temp_bytes(uint64_t n, size_t *bytes);
+hipError_t launch_accept(const double *amps, uint64_t n, double scale, uint64_t seed, int basic, uint8_t *flag,
+                         double *excess, uint32_t *accepted, uint64_t *n_accepted, double *excess_sum,
+                         void *temp, size_t temp_bytes, hipStream_t s);
+
 // x_A = pext(x, mask_a), x_B = pext(x, mask_b) per bitstring; *bad is set to
 // 1 if some bitstring has bits outside `all`.
 hipError_t launch_pext(const uint64_t *bits, uint64_t n, uint64_t mask_a, uint64_t mask_b,

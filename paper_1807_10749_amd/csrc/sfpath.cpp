@@ -14,6 +14,7 @@
 #include <string>
 #include <unordered_set>
 
+#include "kernels.hpp"
 #include "sf_host.hpp"
 
 using sf::Circuit;
@@ -414,6 +415,166 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
         std::strncpy(out, s.c_str(), cap - 1);
         out[cap - 1] = 0;
         return ok();
+    });
+}
+
+
+// ------------------------------------------------------------------ rejection sampling
+// Section "Frugal rejection sampling" and its figure: Algorithm 1 (basic) and Algorithm 2
+// (frugal) turn a batch of output probabilities of uniformly drawn candidates into samples.
+
+int rejection_m(uint32_t n_qubits, double eps, uint32_t flags, double *m)
+{
+    if (!m) return fail(SF_ERR_INVALID, "m is NULL");
+    if (n_qubits < 1 || n_qubits > 64 || !(eps > 0.0) || !(eps < 1.0)) return fail(SF_ERR_INVALID, "bad n_qubits or eps");
+    if (flags & ~uint32_t(SF_SAMPLE_BASIC)) return fail(SF_ERR_INVALID, "unknown flag");
+    if (flags & SF_SAMPLE_BASIC) {
+        *m = std::ceil(n_qubits * std::log(2.0) - std::log(eps));     // M = ceil(ln(N / eps))
+    } else {
+        int mp = 1;                                                     // e^{-M'} (1 + M') <= eps
+        while (std::exp(-(double)mp) * (1.0 + mp) > eps) ++mp;
+        *m = mp;
+    }
+    return ok();
+}
+
+int sample_bitstrings(uint32_t n_qubits, uint64_t count, uint64_t seed, uint64_t *out)
+{
+    return guarded([&]() -> int {
+        if (count && !out) return fail(SF_ERR_INVALID, "out is NULL");
+        if (n_qubits < 1 || n_qubits > 64) return fail(SF_ERR_INVALID, "n_qubits must be 1..64");
+        if (n_qubits < 64 && count > (uint64_t(1) << n_qubits)) return fail(SF_ERR_INVALID, "more bitstrings than exist");
+        const uint64_t mask = n_qubits == 64 ? ~uint64_t(0) : ((uint64_t(1) << n_qubits) - 1);
+        std::unordered_set<uint64_t> seen;
+        seen.reserve((size_t)count * 2);
+        uint64_t st = seed, got = 0;
+        while (got < count) {
+            const uint64_t x = splitmix_next(st) & mask;
+            if (seen.insert(x).second) out[got++] = x;
+        }
+        return ok();
+    });
+}
+
+int rejection_workspace_size(uint64_t n, size_t *bytes)
+{
+    return guarded([&]() -> int {
+        if (!bytes) return fail(SF_ERR_INVALID, "bytes is NULL");
+        if (n > (uint64_t(1) << 31)) return fail(SF_ERR_UNSUPPORTED, "more than 2^31 candidates");
+        size_t temp = 0;
+        hipError_t e = sf::reject_temp_bytes(std::max<uint64_t>(n, 1), &temp);
+        if (e != hipSuccess) return fail(SF_ERR_DEVICE, std::string("temp size: ") + hipGetErrorString(e));
+        auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+        *bytes = al(n) + al(n * 8) + 256 + al(temp);
+        return ok();
+    });
+}
+
+int rejection_accept(const double *amps, uint64_t n, uint32_t n_qubits, double m, uint64_t seed, uint32_t flags,
+                     uint32_t *accepted, uint64_t *n_accepted, double *err_est, void *hip_stream,
+                     void *workspace, size_t workspace_bytes)
+{
+    return guarded([&]() -> int {
+        if (!n_accepted || !err_est) return fail(SF_ERR_INVALID, "NULL argument");
+        if (n && (!amps || !accepted || !workspace)) return fail(SF_ERR_INVALID, "NULL device buffer");
+        if (n_qubits < 1 || n_qubits > 64 || !(m > 0.0)) return fail(SF_ERR_INVALID, "bad n_qubits or m");
+        if (flags & ~uint32_t(SF_SAMPLE_BASIC)) return fail(SF_ERR_INVALID, "unknown flag");
+        size_t need = 0;
+        int rc = rejection_workspace_size(n, &need);
+        if (rc) return rc;
+        if (n && workspace_bytes < need) return fail(SF_ERR_OOM, "workspace too small");
+        *n_accepted = 0;
+        *err_est = 0.0;
+        if (!n) return ok();
+        hipStream_t s = (hipStream_t)hip_stream;
+        auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+        char *w = (char *)workspace;
+        uint8_t *flag = (uint8_t *)w;
+        double *excess = (double *)(w + al(n));
+        uint64_t *d_count = (uint64_t *)(w + al(n) + al(n * 8));
+        double *d_sum = (double *)(w + al(n) + al(n * 8) + 8);
+        char *temp = w + al(n) + al(n * 8) + 256;
+        const size_t temp_bytes = workspace_bytes - (al(n) + al(n * 8) + 256);
+        const double scale = std::ldexp(1.0, (int)n_qubits) / m;        // t = p N / M
+        hipError_t e = sf::launch_accept(amps, n, scale, seed, (flags & SF_SAMPLE_BASIC) ? 1 : 0, flag, excess,
+                                         accepted, d_count, d_sum, temp, temp_bytes, s);
+        if (e != hipSuccess) return fail(SF_ERR_DEVICE, std::string("accept: ") + hipGetErrorString(e));
+        uint64_t cnt = 0;
+        double sum = 0.0;
+        if ((e = hipMemcpyAsync(&cnt, d_count, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(&sum, d_sum, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return fail(SF_ERR_DEVICE, std::string("accept: ") + hipGetErrorString(e));
+        *n_accepted = cnt;
+        *err_est = sum * std::ldexp(1.0, (int)n_qubits) / (double)n;   // (N / n) sum_{t > 1} p
+        return ok();
+    });
+}
+
+int frugal_sample(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
+                  uint64_t n_candidates, double m, uint64_t seed_candidates, uint64_t seed_accept, uint32_t flags,
+                  void *hip_stream, void *workspace, size_t workspace_bytes, uint64_t *out, uint64_t *n_out,
+                  double *err_est)
+{
+    return guarded([&]() -> int {
+        if (!c || !n_out || !err_est) return fail(SF_ERR_INVALID, "NULL argument");
+        if (n_candidates && !out) return fail(SF_ERR_INVALID, "out is NULL");
+        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
+        const uint32_t run_flags = flags & (SF_FP64_SWEEPS | SF_PLAIN);
+        if (flags & ~uint32_t(SF_FP64_SWEEPS | SF_PLAIN | SF_SAMPLE_BASIC)) return fail(SF_ERR_INVALID, "unknown flag");
+        if (n_candidates > (uint64_t(1) << 31)) return fail(SF_ERR_UNSUPPORTED, "more than 2^31 candidates");
+        *n_out = 0;
+        *err_est = 0.0;
+        // Step 2: candidates
+        std::vector<uint64_t> cand(n_candidates);
+        int rc = sample_bitstrings((uint32_t)c->n, n_candidates, seed_candidates, cand.data());
+        if (rc) return rc;
+        if (!n_candidates) return ok();
+        size_t rws = 0;
+        if ((rc = rejection_workspace_size(n_candidates, &rws))) return rc;
+        auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+        const size_t own = al(n_candidates * 8) + al(n_candidates * 16) + al(n_candidates * 4) + al(rws);
+        // device arrays: carved from the end of the caller's workspace, else allocated here
+        char *base = nullptr;
+        void *run_ws = nullptr;
+        size_t run_ws_bytes = 0;
+        bool allocated = false;
+        hipError_t e;
+        if (workspace) {
+            if (workspace_bytes < own + (size_t(1) << 28)) return fail(SF_ERR_OOM, "workspace too small");
+            base = (char *)workspace + (workspace_bytes - own) / 256 * 256;
+            run_ws = workspace;
+            run_ws_bytes = (size_t)(base - (char *)workspace);
+        } else {
+            if ((e = hipMalloc((void **)&base, own)) != hipSuccess) return fail(SF_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            allocated = true;
+        }
+        uint64_t *d_bits = (uint64_t *)base;
+        double *d_amps = (double *)(base + al(n_candidates * 8));
+        uint32_t *d_acc = (uint32_t *)(base + al(n_candidates * 8) + al(n_candidates * 16));
+        char *d_rws = base + al(n_candidates * 8) + al(n_candidates * 16) + al(n_candidates * 4);
+        hipStream_t s = (hipStream_t)hip_stream;
+        auto finish = [&](int code) {
+            if (allocated) { (void)hipStreamSynchronize(s); (void)hipFree(base); }
+            return code;
+        };
+        if ((e = hipMemcpyAsync(d_bits, cand.data(), n_candidates * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return finish(fail(SF_ERR_DEVICE, std::string("copy candidates: ") + hipGetErrorString(e)));
+        // Step 3: their probabilities at once
+        rc = run_paths(c, path_ids, path_begin, n_paths, d_bits, n_candidates, d_amps,
+                       run_flags | SF_BITS_ON_DEVICE | SF_OUT_ON_DEVICE, hip_stream, run_ws, run_ws_bytes);
+        if (rc) return finish(rc);
+        // Step 4: acceptance
+        uint64_t n_acc = 0;
+        rc = rejection_accept(d_amps, n_candidates, (uint32_t)c->n, m, seed_accept, flags & SF_SAMPLE_BASIC, d_acc,
+                              &n_acc, err_est, hip_stream, d_rws, rws);
+        if (rc) return finish(rc);
+        std::vector<uint32_t> idx(n_acc);
+        if (n_acc && (e = hipMemcpy(idx.data(), d_acc, n_acc * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+            return finish(fail(SF_ERR_DEVICE, std::string("copy accepted: ") + hipGetErrorString(e)));
+        for (uint64_t i = 0; i < n_acc; ++i) out[i] = cand[idx[i]];
+        *n_out = n_acc;
+        return finish(ok());
     });
 }
 

@@ -212,3 +212,19 @@ def test_tuning_roundtrip(sf):
     with pytest.raises(sf.SFError):
         sf.set_tuning(c, reg_qubits=9)
     sf.destroy_circuit(c)
+
+
+def test_rejection_host_entries_match_oracle(sf):
+    """Step 1 and step 2 of the rejection-sampling algorithms run on the host: M and M' as the
+    oracle (and the paper's printed 41 and 10), candidates bit for bit."""
+    assert sf.rejection_m(49, 1e-3, sf.SF_SAMPLE_BASIC) == oracle.rejection_m(49, 1e-3, basic=True) == 41
+    for eps in (1e-2, 5e-4, 1e-6):
+        assert sf.rejection_m(30, eps) == oracle.rejection_m(30, eps)
+    for n, count, seed in ((30, 100000, 2002), (16, 65536, 3), (64, 5000, 9), (1, 2, 4)):
+        np.testing.assert_array_equal(sf.sample_bitstrings(n, count, seed), oracle.sample_bitstrings(n, count, seed))
+    for args in ((0, 1e-3, 0), (65, 1e-3, 0), (20, 0.0, 0), (20, 1.0, 0), (20, 1e-3, 1)):
+        with pytest.raises(sf.SFError) as e:
+            sf.rejection_m(*args)
+        assert e.value.code == sf.SF_ERR_INVALID
+    with pytest.raises(sf.SFError):
+        sf.sample_bitstrings(4, 17, 1)
