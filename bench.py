@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--plain-paths", type=int, default=64)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving mix (0 = skip)")
+    ap.add_argument("--no-sampling", action="store_true", help="skip the rejection-sampling measurement")
     ap.add_argument("--tuning", default="",
                     help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels]]] "
                          "(skips autotune)")
@@ -161,6 +162,7 @@ def main():
         plain = {"paths_per_s": plain_paths_per_s, "paths": plain_n, "speedup_of_batched": paths_per_s / plain_paths_per_s}
 
     serving = serving_bench(args.serve_jobs) if args.serve_jobs > 0 else None
+    sampling = None if args.no_sampling else sampling_bench(c, ids, begin, npaths, bits.size, ws, ws_bytes, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -198,6 +200,7 @@ def main():
                      "a_groups": st["a_groups"]},
         "cpu_baseline": cpu,
         "serving": serving,
+        "sampling": sampling,
     }
     print(json.dumps(out), flush=True)
     c.close()
@@ -216,6 +219,43 @@ def measured_traffic(workload, kernel):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def sampling_bench(c, ids, begin, npaths, n_candidates, ws, ws_bytes, stream, m_prime=10.0, reps=3):
+    """Frugal rejection sampling (Algorithm 2) on the benchmark request: n_candidates = l M'
+    uniform candidates, their amplitudes over the same paths, acceptance on the device; and the
+    acceptance step alone on 1e7 Porter-Thomas-distributed amplitudes resident in HBM."""
+    import torch
+    from paper_1807_10749_amd import binding as sf
+    torch.cuda.synchronize()
+    best = None
+    for r in range(reps):
+        t0 = time.perf_counter()
+        out, err = sf.frugal_sample(c.handle, ids, begin, npaths, n_candidates, m_prime, 9000 + r, 9100 + r, 0,
+                                    stream, ws, ws_bytes)
+        dt = time.perf_counter() - t0
+        if best is None or dt < best[0]:
+            best = (dt, out.size, err)
+    # acceptance step alone: 1e7 candidates
+    n = 10_000_000
+    t = torch.empty(n, dtype=torch.float64, device="cuda").exponential_(1.0, generator=torch.Generator("cuda").manual_seed(3))
+    amps = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    amps[0::2] = torch.sqrt(t / 2.0 ** c.n)
+    acc = torch.empty(n, dtype=torch.int32, device="cuda")
+    rws = torch.empty(sf.rejection_workspace_size(n), dtype=torch.uint8, device="cuda")
+    sf.rejection_accept(amps, n, c.n, m_prime, 1, acc, 0, stream, rws, rws.numel())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for r in range(reps):
+        n_acc, _ = sf.rejection_accept(amps, n, c.n, m_prime, 2 + r, acc, 0, stream, rws, rws.numel())
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"m_prime": m_prime, "candidates": n_candidates, "samples": best[1],
+            "samples_per_s": best[1] / best[0], "ms": best[0] * 1e3, "batch_error_estimate": best[2],
+            "accept_only": {"candidates": n, "ms": ms, "candidates_per_s": n / (ms * 1e-3),
+                            "accepted_fraction": n_acc / n,
+                            "bytes_per_candidate": 34, "GB_per_s": 34 * n / (ms * 1e-3) / 1e9}}
 
 
 def serving_bench(n_jobs, workers=4, chunk_paths=16384, seed=5005):

@@ -445,12 +445,21 @@ int sample_bitstrings(uint32_t n_qubits, uint64_t count, uint64_t seed, uint64_t
         if (n_qubits < 1 || n_qubits > 64) return fail(SF_ERR_INVALID, "n_qubits must be 1..64");
         if (n_qubits < 64 && count > (uint64_t(1) << n_qubits)) return fail(SF_ERR_INVALID, "more bitstrings than exist");
         const uint64_t mask = n_qubits == 64 ? ~uint64_t(0) : ((uint64_t(1) << n_qubits) - 1);
-        std::unordered_set<uint64_t> seen;
-        seen.reserve((size_t)count * 2);
+        // open-addressing set of the values drawn so far (value + 1 stored, 0 = empty), at most
+        // half full; hashed with a Fibonacci multiplier so consecutive values spread out
+        uint64_t cap = 16;
+        while (cap < 2 * count) cap <<= 1;
+        std::vector<uint64_t> slot(cap, 0);
+        const int shift = 64 - __builtin_ctzll(cap);
         uint64_t st = seed, got = 0;
         while (got < count) {
             const uint64_t x = splitmix_next(st) & mask;
-            if (seen.insert(x).second) out[got++] = x;
+            uint64_t i = (x * 0x9E3779B97F4A7C15ULL) >> shift;
+            while (slot[i] && slot[i] != x + 1) i = (i + 1) & (cap - 1);
+            if (!slot[i]) {
+                slot[i] = x + 1;
+                out[got++] = x;
+            }
         }
         return ok();
     });
