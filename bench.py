@@ -163,6 +163,11 @@ def main():
 
     serving = serving_bench(args.serve_jobs) if args.serve_jobs > 0 else None
     sampling = None if args.no_sampling else sampling_bench(c, ids, begin, npaths, bits.size, ws, ws_bytes, stream)
+    validation = None
+    if not args.no_sampling and cfg.paths == "all":
+        step()                      # exact amplitudes again (the plain-form runs overwrote them)
+        torch.cuda.synchronize()
+        validation = validation_bench(c, bits, d_amps, cfg.bits_seed, ws, ws_bytes, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -201,6 +206,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "sampling": sampling,
+        "validation": validation,
     }
     print(json.dumps(out), flush=True)
     c.close()
@@ -256,6 +262,25 @@ def sampling_bench(c, ids, begin, npaths, n_candidates, ws, ws_bytes, stream, m_
             "accept_only": {"candidates": n, "ms": ms, "candidates_per_s": n / (ms * 1e-3),
                             "accepted_fraction": n_acc / n,
                             "bytes_per_candidate": 34, "GB_per_s": 34 * n / (ms * 1e-3) / 1e9}}
+
+
+def validation_bench(c, bits, d_amps, index_seed, ws, ws_bytes, stream, f1=0.25, delta=0.05):
+    """The Verifier's side of the validation protocol on the benchmark circuit: the benchmark's
+    own exact amplitudes (its bitstrings are the protocol's seeded indices) as the honest claim,
+    a fidelity-f1 simulation on the same indices, the overlap estimate and the test."""
+    from paper_1807_10749_amd import binding as sf
+    if not np.array_equal(sf.sample_bitstrings(c.n, bits.size, index_seed), bits):
+        return None
+    claim = d_amps.cpu().numpy().view(np.complex128)
+    best = None
+    for r in range(2):
+        t0 = time.perf_counter()
+        fe, ok = sf.verify_claim(c.handle, claim, index_seed, f1, 3005 + r, delta, 0, stream, ws, ws_bytes)
+        dt = time.perf_counter() - t0
+        if best is None or dt < best[0]:
+            best = (dt, fe, ok)
+    return {"indices": int(bits.size), "f1": f1, "delta": delta, "f_e": best[1], "passed": best[2],
+            "ms": best[0] * 1e3}
 
 
 def serving_bench(n_jobs, workers=4, chunk_paths=16384, seed=5005):

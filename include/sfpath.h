@@ -285,6 +285,40 @@ int frugal_sample(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin
                   uint32_t flags, void *hip_stream, void *workspace, size_t workspace_bytes,
                   uint64_t *out, uint64_t *n_out, double *err_est);
 
+/*
+ * Validation of results (appendix on validating simulation results).
+ *
+ * fidelity_estimate: the state overlap estimated from n amplitudes of two
+ * states at the same indices (device arrays, FP64 complex, re/im
+ * interleaved): f_e = |sum conj(a) b|^2 / (sum |a|^2 sum |b|^2); the sums
+ * are FP64, per block in a fixed order, then over blocks in block order on
+ * the host.  Optionally returns sum |a|^2 and sum |b|^2 (norm_a, norm_b may
+ * be NULL).  Synchronizes hip_stream.
+ */
+int fidelity_estimate(const double *a, const double *b, uint64_t n, void *hip_stream, double *f_e,
+                      double *norm_a, double *norm_b);
+
+/*
+ * xeb_fidelity: linear cross-entropy fidelity N <|a|^2> - 1 of n sampled
+ * bitstrings' ideal amplitudes (device, FP64 complex), N = 2^n_qubits (the
+ * cross-entropy check the paper mentions beside the overlap estimate).
+ */
+int xeb_fidelity(const double *amps, uint64_t n, uint32_t n_qubits, void *hip_stream, double *f);
+
+/*
+ * verify_claim: the Verifier's side of the two-party validation protocol.
+ * Step 1: the k indices are sample_bitstrings(n, k, index_seed); the
+ * Claimant's amplitudes at them (claimed, host, k FP64 complex) are the
+ * input.  Step 3: the Verifier simulates with fidelity f1 (the paths
+ * sample_paths(k_cut, f1, path_seed), run_paths on the k indices).  Steps 5-6:
+ * *f_e = fidelity_estimate(Verifier's, Claimant's amplitudes) and *passed =
+ * |f_e - f1| <= delta.  flags may be SF_FP64_SWEEPS.  The workspace is used
+ * as in frugal_sample (40 B per index taken from its end); NULL allocates.
+ */
+int verify_claim(sf_circuit_t *c, const double *claimed, uint64_t k, uint64_t index_seed, double f1,
+                 uint64_t path_seed, double delta, uint32_t flags, void *hip_stream, void *workspace,
+                 size_t workspace_bytes, double *f_e, int *passed);
+
 /* ------------------------------------------------------------------ */
 /* Serving: jobs arrive at any time and share one GPU.                 */
 /* ------------------------------------------------------------------ */

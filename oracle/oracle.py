@@ -172,3 +172,31 @@ def rejection_accept(amps, n_qubits: int, m: float, seed: int, basic: bool = Fal
                                   _ptr(acc, ctypes.c_uint8), ctypes.byref(err)):
         raise ValueError("bad arguments")
     return acc.astype(bool), err.value
+
+
+# ---------------------------------------------------------------- validation of results
+# Appendix on validating simulation results: the state overlap estimated from k amplitudes at the
+# same indices, and the two-party protocol built on it; cross-entropy fidelity as a comparison.
+
+def fidelity_estimate(a, b):
+    """|sum conj(a) b|^2 / (sum |a|^2 sum |b|^2) over the given amplitudes (FP64 sums in order);
+    returns (f_e, sum |a|^2, sum |b|^2)."""
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    ov = complex(0.0)
+    na = nb = 0.0
+    for x, y in zip(a.tolist(), b.tolist()):
+        ov += x.conjugate() * y
+        na += x.real * x.real + x.imag * x.imag
+        nb += y.real * y.real + y.imag * y.imag
+    f = (ov.real * ov.real + ov.imag * ov.imag) / (na * nb) if na > 0 and nb > 0 else 0.0
+    return f, na, nb
+
+
+def xeb_fidelity(amps, n_qubits: int) -> float:
+    """Linear cross-entropy fidelity N <p(x)> - 1 over the ideal amplitudes of sampled x."""
+    a = np.asarray(amps, dtype=np.complex128)
+    s = 0.0
+    for x in a.tolist():
+        s += x.real * x.real + x.imag * x.imag
+    return 2.0 ** n_qubits * s / len(a) - 1.0 if len(a) else 0.0

@@ -23,7 +23,8 @@ EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_pa
            "run_paths", "workspace_size", "set_tuning", "get_tuning", "autotune", "get_run_stats",
            "describe_plan", "last_error", "server_create", "server_submit", "server_poll", "server_release",
            "server_drain", "server_stats", "server_destroy", "server_last_error", "rejection_m",
-           "sample_bitstrings", "rejection_workspace_size", "rejection_accept", "frugal_sample"]
+           "sample_bitstrings", "rejection_workspace_size", "rejection_accept", "frugal_sample",
+           "fidelity_estimate", "xeb_fidelity", "verify_claim"]
 SF_PENDING = 1
 
 
@@ -105,6 +106,11 @@ def _load():
                                      ctypes.POINTER(ctypes.c_double), vp, vp, sz]
     lib.frugal_sample.argtypes = [vp, vp, u64, u64, u64, ctypes.c_double, u64, u64, u32, vp, vp, sz, vp, pu64,
                                   ctypes.POINTER(ctypes.c_double)]
+    pd = ctypes.POINTER(ctypes.c_double)
+    lib.fidelity_estimate.argtypes = [vp, vp, u64, vp, pd, pd, pd]
+    lib.xeb_fidelity.argtypes = [vp, u64, u32, vp, pd]
+    lib.verify_claim.argtypes = [vp, vp, u64, u64, ctypes.c_double, u64, ctypes.c_double, u32, vp, vp, sz, pd,
+                                 ctypes.POINTER(ctypes.c_int)]
     lib.server_last_error.restype = ctypes.c_char_p
     lib.last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -228,6 +234,30 @@ def frugal_sample(c: int, path_ids, path_begin: int, n_paths: int, n_candidates:
                              _stream_handle(stream), _ptr(workspace), workspace_bytes, out.ctypes.data,
                              ctypes.byref(n), ctypes.byref(err)))
     return out[: n.value], err.value
+
+
+def fidelity_estimate(a, b, n: int, stream=None):
+    """Device arrays; returns (f_e, sum |a|^2, sum |b|^2)."""
+    f, na, nb = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib.fidelity_estimate(_ptr(a), _ptr(b), n, _stream_handle(stream), ctypes.byref(f), ctypes.byref(na),
+                                 ctypes.byref(nb)))
+    return f.value, na.value, nb.value
+
+
+def xeb_fidelity(amps, n: int, n_qubits: int, stream=None) -> float:
+    f = ctypes.c_double()
+    _check(lib.xeb_fidelity(_ptr(amps), n, n_qubits, _stream_handle(stream), ctypes.byref(f)))
+    return f.value
+
+
+def verify_claim(c: int, claimed, index_seed: int, f1: float, path_seed: int, delta: float, flags: int = 0,
+                 stream=None, workspace=None, workspace_bytes: int = 0):
+    """claimed: host complex128 array of the Claimant's amplitudes; returns (f_e, passed)."""
+    a = np.ascontiguousarray(claimed, dtype=np.complex128)
+    f, ok = ctypes.c_double(), ctypes.c_int()
+    _check(lib.verify_claim(c, a.ctypes.data, a.size, index_seed, f1, path_seed, delta, flags, _stream_handle(stream),
+                            _ptr(workspace), workspace_bytes, ctypes.byref(f), ctypes.byref(ok)))
+    return f.value, bool(ok.value)
 
 
 def run_paths(c: int, path_ids, path_begin: int, n_paths: int, bitstrings, n_bits: int, amps,

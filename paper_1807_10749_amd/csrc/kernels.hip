@@ -798,6 +798,46 @@ hipError_t launch_accept(const double *amps, uint64_t n, double scale, uint64_t 
     return hipcub::DeviceReduce::Sum(temp, tb, excess, excess_sum, (int)n, s);
 }
 
+// ---------------------------------------------------------------- validation: overlaps
+
+// Per-block partial sums over n FP64 complex pairs: Re sum conj(a) b, Im sum conj(a) b,
+// sum |a|^2, sum |b|^2 (b == NULL: only sum |a|^2 is meaningful).  Grid-stride, then a fixed
+// tree over the block, so a launch's result does not depend on timing.
+__global__ __launch_bounds__(256) void overlap_kernel(const double *a, const double *b, uint64_t n, double *partial)
+{
+    __shared__ double sh[4][256];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const double ar = a[2 * i], ai = a[2 * i + 1];
+        s2 += ar * ar + ai * ai;
+        if (b) {
+            const double br = b[2 * i], bi = b[2 * i + 1];
+            s0 += ar * br + ai * bi;
+            s1 += ar * bi - ai * br;
+            s3 += br * br + bi * bi;
+        }
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    sh[2][threadIdx.x] = s2;
+    sh[3][threadIdx.x] = s3;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partial[4 * (uint64_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+hipError_t launch_overlap(const double *a, const double *b, uint64_t n, double *partial, unsigned blocks,
+                          hipStream_t s)
+{
+    if (n == 0 || blocks == 0) return hipSuccess;
+    overlap_kernel<<<blocks, 256, 0, s>>>(a, b, n, partial);
+    return hipGetLastError();
+}
+
 __global__ void fill_zero_kernel(double *p, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

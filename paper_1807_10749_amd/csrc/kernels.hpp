@@ -42,6 +42,11 @@ hipError_t launch_accept(const double *amps, uint64_t n, double scale, uint64_t 
                          double *excess, uint32_t *accepted, uint64_t *n_accepted, double *excess_sum,
                          void *temp, size_t temp_bytes, hipStream_t s);
 
+// Per-block partial sums (4 doubles per block: Re and Im of sum conj(a) b, sum |a|^2,
+// sum |b|^2) over n complex FP64 pairs; b may be NULL.  partial: 4 * blocks doubles.
+hipError_t launch_overlap(const double *a, const double *b, uint64_t n, double *partial, unsigned blocks,
+                          hipStream_t s);
+
 // x_A = pext(x, mask_a), x_B = pext(x, mask_b) per bitstring; *bad is set to
 // 1 if some bitstring has bits outside `all`.
 hipError_t launch_pext(const uint64_t *bits, uint64_t n, uint64_t mask_a, uint64_t mask_b,

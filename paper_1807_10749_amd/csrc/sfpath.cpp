@@ -587,4 +587,122 @@ int frugal_sample(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin
     });
 }
 
+
+// ------------------------------------------------------------------ validation of results
+// Appendix on validating simulation results: state overlap from amplitudes at common indices
+// and the Verifier's side of the two-party protocol; linear cross-entropy fidelity.
+
+namespace {
+// sums[0..3] = Re, Im of sum conj(a) b, sum |a|^2, sum |b|^2; partial sums per block are added
+// on the host in block order
+int overlap_sums(const double *a, const double *b, uint64_t n, hipStream_t s, double sums[4])
+{
+    for (int q = 0; q < 4; ++q) sums[q] = 0.0;
+    if (!n) return SF_OK;
+    const unsigned blocks = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
+    double *partial = nullptr;
+    hipError_t e = hipMallocAsync((void **)&partial, (size_t)blocks * 32, s);
+    if (e != hipSuccess) return fail(SF_ERR_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    std::vector<double> h((size_t)blocks * 4);
+    if ((e = sf::launch_overlap(a, b, n, partial, blocks, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(h.data(), partial, h.size() * 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipFreeAsync(partial, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail(SF_ERR_DEVICE, std::string("overlap: ") + hipGetErrorString(e));
+    for (unsigned i = 0; i < blocks; ++i)
+        for (int q = 0; q < 4; ++q) sums[q] += h[4 * (size_t)i + q];
+    return SF_OK;
+}
+}  // namespace
+
+int fidelity_estimate(const double *a, const double *b, uint64_t n, void *hip_stream, double *f_e, double *norm_a,
+                      double *norm_b)
+{
+    return guarded([&]() -> int {
+        if (!f_e) return fail(SF_ERR_INVALID, "f_e is NULL");
+        if (n && (!a || !b)) return fail(SF_ERR_INVALID, "NULL device array");
+        double sm[4];
+        const int rc = overlap_sums(a, b, n, (hipStream_t)hip_stream, sm);
+        if (rc) return rc;
+        *f_e = (sm[2] > 0.0 && sm[3] > 0.0) ? (sm[0] * sm[0] + sm[1] * sm[1]) / (sm[2] * sm[3]) : 0.0;
+        if (norm_a) *norm_a = sm[2];
+        if (norm_b) *norm_b = sm[3];
+        return ok();
+    });
+}
+
+int xeb_fidelity(const double *amps, uint64_t n, uint32_t n_qubits, void *hip_stream, double *f)
+{
+    return guarded([&]() -> int {
+        if (!f) return fail(SF_ERR_INVALID, "f is NULL");
+        if (n && !amps) return fail(SF_ERR_INVALID, "NULL device array");
+        if (n_qubits < 1 || n_qubits > 64) return fail(SF_ERR_INVALID, "n_qubits must be 1..64");
+        double sm[4];
+        const int rc = overlap_sums(amps, nullptr, n, (hipStream_t)hip_stream, sm);
+        if (rc) return rc;
+        *f = n ? std::ldexp(sm[2], (int)n_qubits) / (double)n - 1.0 : 0.0;   // N <p(x)> - 1
+        return ok();
+    });
+}
+
+int verify_claim(sf_circuit_t *c, const double *claimed, uint64_t k, uint64_t index_seed, double f1,
+                 uint64_t path_seed, double delta, uint32_t flags, void *hip_stream, void *workspace,
+                 size_t workspace_bytes, double *f_e, int *passed)
+{
+    return guarded([&]() -> int {
+        if (!c || !f_e || !passed || (k && !claimed)) return fail(SF_ERR_INVALID, "NULL argument");
+        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
+        if (!(f1 > 0.0) || f1 > 1.0 || !(delta >= 0.0)) return fail(SF_ERR_INVALID, "bad f1 or delta");
+        if (flags & ~uint32_t(SF_FP64_SWEEPS)) return fail(SF_ERR_INVALID, "unknown flag");
+        if (k > (uint64_t(1) << 31)) return fail(SF_ERR_UNSUPPORTED, "more than 2^31 amplitudes");
+        *f_e = 0.0;
+        *passed = 0;
+        if (!k) return fail(SF_ERR_INVALID, "no amplitudes");
+        // step 1: the indices the Claimant was given; step 3: a fidelity-f1 simulation on them
+        std::vector<uint64_t> idx(k);
+        int rc = sample_bitstrings((uint32_t)c->n, k, index_seed, idx.data());
+        if (rc) return rc;
+        uint64_t m = 0;
+        if ((rc = num_paths((uint32_t)c->k, f1, &m))) return rc;
+        std::vector<uint64_t> ids(m);
+        uint64_t got = 0;
+        if ((rc = sample_paths((uint32_t)c->k, f1, path_seed, ids.data(), m, &got))) return rc;
+        auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+        const size_t own = al(k * 8) + 2 * al(k * 16);
+        char *base = nullptr;
+        void *run_ws = nullptr;
+        size_t run_ws_bytes = 0;
+        bool allocated = false;
+        hipError_t e;
+        if (workspace) {
+            if (workspace_bytes < own + (size_t(1) << 28)) return fail(SF_ERR_OOM, "workspace too small");
+            base = (char *)workspace + (workspace_bytes - own) / 256 * 256;
+            run_ws = workspace;
+            run_ws_bytes = (size_t)(base - (char *)workspace);
+        } else {
+            if ((e = hipMalloc((void **)&base, own)) != hipSuccess) return fail(SF_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            allocated = true;
+        }
+        hipStream_t s = (hipStream_t)hip_stream;
+        auto finish = [&](int code) {
+            if (allocated) { (void)hipStreamSynchronize(s); (void)hipFree(base); }
+            return code;
+        };
+        uint64_t *d_bits = (uint64_t *)base;
+        double *d_mine = (double *)(base + al(k * 8));
+        double *d_claim = (double *)(base + al(k * 8) + al(k * 16));
+        if ((e = hipMemcpyAsync(d_bits, idx.data(), k * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(d_claim, claimed, k * 16, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return finish(fail(SF_ERR_DEVICE, std::string("copy: ") + hipGetErrorString(e)));
+        rc = run_paths(c, ids.data(), 0, got, d_bits, k, d_mine, flags | SF_BITS_ON_DEVICE | SF_OUT_ON_DEVICE,
+                       hip_stream, run_ws, run_ws_bytes);
+        if (rc) return finish(rc);
+        // steps 5-6: estimate the fidelity between the two states and test it against f1
+        double sm[4];
+        if ((rc = overlap_sums(d_mine, d_claim, k, s, sm))) return finish(rc);
+        *f_e = (sm[2] > 0.0 && sm[3] > 0.0) ? (sm[0] * sm[0] + sm[1] * sm[1]) / (sm[2] * sm[3]) : 0.0;
+        *passed = std::fabs(*f_e - f1) <= delta ? 1 : 0;
+        return finish(ok());
+    });
+}
+
 }  // extern "C"
