@@ -8,5 +8,5 @@ from .oracle import (  # noqa: F401
     lib_path, load, gate_matrix, full_state, path_sum, num_cut, cut_gates,
     sample_paths, num_paths, pext, num_threads,
     rejection_m, sample_bitstrings, splitmix64_at, rejection_accept,
-    fidelity_estimate, xeb_fidelity,
+    fidelity_estimate, xeb_fidelity, gate_matrix2, branch_ops,
 )

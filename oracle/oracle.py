@@ -39,6 +39,8 @@ def load():
     lib.or_num_paths.restype = ctypes.c_int64
     lib.or_sample_paths.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, c_u64p,
                                     ctypes.c_int64, c_i64p]
+    lib.or_gate_matrix2.argtypes = [ctypes.c_int, c_dp]
+    lib.or_branch_ops.argtypes = [ctypes.c_int, ctypes.c_int, c_dp, c_dp]
     lib.or_sample_bitstrings.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, c_u64p]
     lib.or_splitmix64_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.or_splitmix64_at.restype = ctypes.c_uint64
@@ -84,12 +86,15 @@ def num_cut(n: int, gates: np.ndarray, mask_a: int) -> int:
 
 
 def cut_gates(n: int, gates: np.ndarray, mask_a: int) -> np.ndarray:
-    """Indices (into ``gates``) of the crossing CZs in path-bit order."""
+    """Indices (into ``gates``) of the crossing two-qubit gates in path-bit order."""
     g = np.ascontiguousarray(gates)
-    k = num_cut(n, g, mask_a)
-    idx = np.zeros(max(k, 1), dtype=np.int64)
-    load().or_cut_gates(n, g.ctypes.data, g.size, mask_a, _ptr(idx, ctypes.c_int64), k)
-    return idx[:k]
+    lib = load()
+    nc = int(lib.or_cut_gates(n, g.ctypes.data, g.size, mask_a, None, 0))
+    if nc < 0:
+        raise ValueError("bad gates")
+    idx = np.zeros(max(nc, 1), dtype=np.int64)
+    lib.or_cut_gates(n, g.ctypes.data, g.size, mask_a, _ptr(idx, ctypes.c_int64), nc)
+    return idx[:nc]
 
 
 def path_sum(n: int, gates: np.ndarray, mask_a: int, paths, bits, norms: bool = False):
@@ -200,3 +205,23 @@ def xeb_fidelity(amps, n_qubits: int) -> float:
     for x in a.tolist():
         s += x.real * x.real + x.imag * x.imag
     return 2.0 ** n_qubits * s / len(a) - 1.0 if len(a) else 0.0
+
+
+# ---------------------------------------------------------------- two-qubit gates
+# Section on harder benchmarks through two-qubit gates: iSWAP and Eq. (4way).
+
+def gate_matrix2(kind: int) -> np.ndarray:
+    out = np.zeros(32, dtype=np.float64)
+    if load().or_gate_matrix2(kind, _ptr(out, ctypes.c_double)):
+        raise ValueError("not a two-qubit gate kind")
+    return (out[0::2] + 1j * out[1::2]).reshape(4, 4)
+
+
+def branch_ops(kind: int, r: int):
+    """Term r = 2i + j of Eq. (4way) for a crossing gate: (|i><j| on the block-A endpoint,
+    the 2x2 block G_ij on the block-B endpoint)."""
+    ea = np.zeros(8, dtype=np.float64)
+    gb = np.zeros(8, dtype=np.float64)
+    if load().or_branch_ops(kind, r, _ptr(ea, ctypes.c_double), _ptr(gb, ctypes.c_double)):
+        raise ValueError("bad kind or term")
+    return (ea[0::2] + 1j * ea[1::2]).reshape(2, 2), (gb[0::2] + 1j * gb[1::2]).reshape(2, 2)

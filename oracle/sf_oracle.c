@@ -19,6 +19,11 @@
  *       amplitudes", end of Section 2).
  *   Path selection for fidelity f (Section 3, Eq. (fid)): ceil(f 2^k)
  *   distinct path ids drawn with Floyd's algorithm over SplitMix64.
+ *   Two-qubit gates (section on harder benchmarks through two-qubit gates):
+ *   iSWAP inside a block is applied as a 4x4 matrix; a crossing two-qubit
+ *   gate G is split as in Eq. (4way), sum_{i,j} |i><j| (x) G_ij with the
+ *   block-A endpoint first, term r = 2i + j from two path bits (a crossing
+ *   CZ keeps the Section 2 split with one bit).
  *   Rejection sampling of bitstrings from a batch of output probabilities
  *   (Section "Frugal rejection sampling", Algorithms 1 and 2): candidate
  *   bitstrings, acceptance and the per-batch sampling-error estimate.
@@ -52,7 +57,61 @@ typedef struct {
     uint16_t q0, q1;
 } or_gate;
 
-enum { OR_H = 0, OR_XH = 1, OR_YH = 2, OR_T = 3, OR_CZ = 4 };
+enum { OR_H = 0, OR_XH = 1, OR_YH = 2, OR_T = 3, OR_CZ = 4, OR_ISWAP = 5 };
+
+/* Two-qubit gate matrices, row-major 4x4 in the basis |x_q0 x_q1> (index 2 x_q0 + x_q1).
+ * iSWAP (section on two-qubit gates): |00> -> |00>, |01> -> i|10>, |10> -> i|01>, |11> -> |11>. */
+static int gate_matrix2(int kind, double complex m[16])
+{
+    for (int i = 0; i < 16; ++i) m[i] = 0.0;
+    if (kind == OR_CZ) {
+        m[0] = 1.0; m[5] = 1.0; m[10] = 1.0; m[15] = -1.0;
+        return 0;
+    }
+    if (kind == OR_ISWAP) {
+        m[0] = 1.0; m[6] = I; m[9] = I; m[15] = 1.0;
+        return 0;
+    }
+    return -1;
+}
+
+int or_gate_matrix2(int kind, double *out)
+{
+    double complex m[16];
+    if (gate_matrix2(kind, m)) return -1;
+    for (int i = 0; i < 16; ++i) { out[2 * i] = creal(m[i]); out[2 * i + 1] = cimag(m[i]); }
+    return 0;
+}
+
+/* Section on two-qubit gates, Eq. (4way): a two-qubit gate G whose first qubit sits in block A
+ * is  sum_{i,j} |i><j| (x) G_ij  with G_ij the 2x2 block of rows 2i.. and columns 2j..; term
+ * r = 2i + j.  A CZ has only the diagonal terms, which are the Section 2 branches
+ * P0 (x) I + P1 (x) Z; it keeps one path bit, with r = 3 s (s = 0: P0 (x) I, s = 1: P1 (x) Z). */
+static void branch_ops(int kind, int r, double complex ea[4], double complex gb[4])
+{
+    double complex m[16];
+    gate_matrix2(kind, m);
+    const int i = r >> 1, j = r & 1;
+    for (int t = 0; t < 4; ++t) ea[t] = 0.0;
+    ea[2 * i + j] = 1.0;                                   /* |i><j| */
+    for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 2; ++t) gb[2 * s + t] = m[(2 * i + s) * 4 + (2 * j + t)];
+}
+
+int or_branch_ops(int kind, int r, double *ea_out, double *gb_out)
+{
+    if ((kind != OR_CZ && kind != OR_ISWAP) || r < 0 || r > 3) return -1;
+    double complex ea[4], gb[4];
+    branch_ops(kind, r, ea, gb);
+    for (int t = 0; t < 4; ++t) {
+        ea_out[2 * t] = creal(ea[t]); ea_out[2 * t + 1] = cimag(ea[t]);
+        gb_out[2 * t] = creal(gb[t]); gb_out[2 * t + 1] = cimag(gb[t]);
+    }
+    return 0;
+}
+
+/* path bits a crossing two-qubit gate takes: 1 for CZ (two terms), 2 for iSWAP (four) */
+static int branch_bits(int kind) { return kind == OR_ISWAP ? 2 : 1; }
 
 /* ------------------------------------------------------------------ */
 /* Gate matrices, row-major m[0]=u00 m[1]=u01 m[2]=u10 m[3]=u11.        */
@@ -104,6 +163,27 @@ static void apply_1q(double complex *psi, int n, int t, const double complex m[4
     }
 }
 
+/* Two-qubit matrix on bits a (first) and b of a 2^n vector. */
+static void apply_2q(double complex *psi, int n, int a, int b, const double complex m[16])
+{
+    const int64_t quarter = (int64_t)1 << (n - 2);
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+#pragma omp parallel for schedule(static) if (n > 14)
+    for (int64_t i = 0; i < quarter; ++i) {
+        uint64_t x = (uint64_t)i;
+        x = ((x >> lo) << (lo + 1)) | (x & (((uint64_t)1 << lo) - 1));
+        x = ((x >> hi) << (hi + 1)) | (x & (((uint64_t)1 << hi) - 1));
+        uint64_t idx[4];
+        double complex v[4];
+        for (int r = 0; r < 4; ++r) {
+            idx[r] = x | ((uint64_t)(r >> 1) << a) | ((uint64_t)(r & 1) << b);
+            v[r] = psi[idx[r]];
+        }
+        for (int r = 0; r < 4; ++r)
+            psi[idx[r]] = m[4 * r] * v[0] + m[4 * r + 1] * v[1] + m[4 * r + 2] * v[2] + m[4 * r + 3] * v[3];
+    }
+}
+
 /* CZ on bits a, b: negate amplitudes whose bits a and b are both 1. */
 static void apply_cz(double complex *psi, int n, int a, int b)
 {
@@ -131,11 +211,13 @@ static void apply_z(double complex *psi, int n, int b)
         if (((uint64_t)i >> b) & 1) psi[i] = -psi[i];
 }
 
+static int is_2q(int kind) { return kind == OR_CZ || kind == OR_ISWAP; }
+
 static int check_gates(int n, const or_gate *g, size_t ng)
 {
     for (size_t i = 0; i < ng; ++i) {
-        if (g[i].kind > OR_CZ || g[i].q0 >= n) return -1;
-        if (g[i].kind == OR_CZ && (g[i].q1 >= n || g[i].q1 == g[i].q0)) return -1;
+        if (g[i].kind > OR_ISWAP || g[i].q0 >= n) return -1;
+        if (is_2q(g[i].kind) && (g[i].q1 >= n || g[i].q1 == g[i].q0)) return -1;
     }
     return 0;
 }
@@ -154,6 +236,10 @@ int or_full_state(int n, const or_gate *gates, size_t ng, double *psi_out)
     for (size_t i = 0; i < ng; ++i) {
         if (gates[i].kind == OR_CZ) {
             apply_cz(psi, n, gates[i].q0, gates[i].q1);
+        } else if (gates[i].kind == OR_ISWAP) {
+            double complex m[16];
+            gate_matrix2(OR_ISWAP, m);
+            apply_2q(psi, n, gates[i].q0, gates[i].q1, m);
         } else {
             double complex m[4];
             gate_matrix(gates[i].kind, m);
@@ -188,7 +274,7 @@ static int local_index(uint64_t mask, int q)
     return popcount64(mask & (((uint64_t)1 << q) - 1));
 }
 
-/* Crossing CZs ordered by (cycle, smaller qubit); returns k or -1.
+/* Crossing two-qubit gates ordered by (cycle, smaller qubit); returns their number or -1.
  * idx_out (capacity cap) receives gate indices in path-bit order. */
 int or_cut_gates(int n, const or_gate *gates, size_t ng, uint64_t mask_a,
                  int64_t *idx_out, int cap)
@@ -196,7 +282,7 @@ int or_cut_gates(int n, const or_gate *gates, size_t ng, uint64_t mask_a,
     if (check_gates(n, gates, ng)) return -1;
     int k = 0;
     for (size_t i = 0; i < ng; ++i) {
-        if (gates[i].kind != OR_CZ) continue;
+        if (!is_2q(gates[i].kind)) continue;
         int ina = (int)((mask_a >> gates[i].q0) & 1), inb = (int)((mask_a >> gates[i].q1) & 1);
         if (ina == inb) continue;
         if (k < cap && idx_out) idx_out[k] = (int64_t)i;
@@ -230,7 +316,7 @@ typedef struct {
     uint64_t mask_a, mask_b;
     const or_gate *gates;
     size_t ng;
-    int *bit_of_gate;   /* per gate: path bit position deciding it, or -1 */
+    int *bit_of_gate;   /* per gate: lowest path bit of the term index deciding it, or -1 */
 } or_cut_info;
 
 /* Evolve both blocks for one path id.  psiA has 2^qa entries, psiB 2^qb. */
@@ -246,7 +332,7 @@ static void evolve_path(const or_cut_info *c, uint64_t path,
         const or_gate *G = &c->gates[g];
         int q0 = G->q0;
         int a0 = (int)((c->mask_a >> q0) & 1);
-        if (G->kind != OR_CZ) {
+        if (!is_2q(G->kind)) {
             double complex m[4];
             gate_matrix(G->kind, m);
             if (a0) apply_1q(psiA, c->qa, local_index(c->mask_a, q0), m);
@@ -255,16 +341,32 @@ static void evolve_path(const or_cut_info *c, uint64_t path,
         }
         int q1 = G->q1;
         int a1 = (int)((c->mask_a >> q1) & 1);
-        if (a0 && a1) {
-            apply_cz(psiA, c->qa, local_index(c->mask_a, q0), local_index(c->mask_a, q1));
-        } else if (!a0 && !a1) {
-            apply_cz(psiB, c->qb, local_index(c->mask_b, q0), local_index(c->mask_b, q1));
-        } else {
+        if (a0 == a1) {
+            double complex *psi = a0 ? psiA : psiB;
+            const int nq = a0 ? c->qa : c->qb;
+            const uint64_t mk = a0 ? c->mask_a : c->mask_b;
+            if (G->kind == OR_CZ) {
+                apply_cz(psi, nq, local_index(mk, q0), local_index(mk, q1));
+            } else {
+                double complex m[16];
+                gate_matrix2(G->kind, m);
+                apply_2q(psi, nq, local_index(mk, q0), local_index(mk, q1), m);
+            }
+        } else if (G->kind == OR_CZ) {
             /* crossing CZ = P0 (x) I + P1 (x) Z; this path takes term s */
             int s = (int)((path >> c->bit_of_gate[g]) & 1);
             int qa_ = a0 ? q0 : q1, qb_ = a0 ? q1 : q0;
             apply_projector(psiA, c->qa, local_index(c->mask_a, qa_), s);
             if (s) apply_z(psiB, c->qb, local_index(c->mask_b, qb_));
+        } else {
+            /* Eq. (4way) with the block-A endpoint as the first qubit (a symmetric gate such as
+             * iSWAP reads the same either way); this path takes term r = 2i + j */
+            int r = (int)((path >> c->bit_of_gate[g]) & 3);
+            int qa_ = a0 ? q0 : q1, qb_ = a0 ? q1 : q0;
+            double complex ea[4], gb[4];
+            branch_ops(G->kind, r, ea, gb);
+            apply_1q(psiA, c->qa, local_index(c->mask_a, qa_), ea);
+            apply_1q(psiB, c->qb, local_index(c->mask_b, qb_), gb);
         }
     }
 }
@@ -282,13 +384,22 @@ static int make_cut_info(int n, const or_gate *gates, size_t ng, uint64_t mask_a
     c->gates = gates;
     c->ng = ng;
     if (c->qa > 30 || c->qb > 30) return -1;
-    int k = or_cut_gates(n, gates, ng, mask_a, NULL, 0);
-    if (k < 0 || k > 63) return -1;
-    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (k ? k : 1));
+    int nc = or_cut_gates(n, gates, ng, mask_a, NULL, 0);
+    if (nc < 0) return -1;
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (nc ? nc : 1));
     c->bit_of_gate = (int *)malloc(sizeof(int) * (ng ? ng : 1));
     for (size_t i = 0; i < ng; ++i) c->bit_of_gate[i] = -1;
-    or_cut_gates(n, gates, ng, mask_a, idx, k);
-    for (int j = 0; j < k; ++j) c->bit_of_gate[idx[j]] = k - 1 - j;
+    or_cut_gates(n, gates, ng, mask_a, idx, nc);
+    /* the first crossing gate takes the highest path bits: crossing gate j's term index sits
+     * right below the bits of the gates before it */
+    int k = 0;
+    for (int j = 0; j < nc; ++j) k += branch_bits(gates[idx[j]].kind);
+    if (k > 63) { free(idx); free(c->bit_of_gate); return -1; }
+    int top = k;
+    for (int j = 0; j < nc; ++j) {
+        top -= branch_bits(gates[idx[j]].kind);
+        c->bit_of_gate[idx[j]] = top;
+    }
     free(idx);
     c->k = k;
     return 0;
@@ -370,10 +481,17 @@ int or_path_sum(int n, const or_gate *gates, size_t ng, uint64_t mask_a,
     return 0;
 }
 
-/* Number of crossing CZs for a cut, or -1. */
+/* Number of path bits k for a cut (one per crossing CZ, two per crossing iSWAP), or -1. */
 int or_num_cut(int n, const or_gate *gates, size_t ng, uint64_t mask_a)
 {
-    return or_cut_gates(n, gates, ng, mask_a, NULL, 0);
+    const int nc = or_cut_gates(n, gates, ng, mask_a, NULL, 0);
+    if (nc <= 0) return nc;
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * nc);
+    or_cut_gates(n, gates, ng, mask_a, idx, nc);
+    int k = 0;
+    for (int j = 0; j < nc; ++j) k += branch_bits(gates[idx[j]].kind);
+    free(idx);
+    return k;
 }
 
 /* ------------------------------------------------------------------ */

@@ -33,8 +33,8 @@ from typing import Optional
 
 import numpy as np
 
-H, XH, YH, T, CZ = 0, 1, 2, 3, 4
-GATE_NAMES = {H: "H", XH: "X^1/2", YH: "Y^1/2", T: "T", CZ: "CZ"}
+H, XH, YH, T, CZ, ISWAP = 0, 1, 2, 3, 4, 5
+GATE_NAMES = {H: "H", XH: "X^1/2", YH: "Y^1/2", T: "T", CZ: "CZ", ISWAP: "iSWAP"}
 
 GATE_DTYPE = np.dtype([("kind", np.uint8), ("pad", np.uint8), ("cycle", np.uint16),
                        ("q0", np.uint16), ("q1", np.uint16)])
@@ -99,8 +99,11 @@ def cz_pattern_edges(rows: int, cols: int, pattern: int):
     return edges
 
 
-def grid_circuit(rows: int, cols: int, depth: int, seed: int) -> np.ndarray:
-    """Random circuit of depth 1+depth+1 on a rows x cols grid (see module doc)."""
+def grid_circuit(rows: int, cols: int, depth: int, seed: int, two_qubit: int = CZ) -> np.ndarray:
+    """Random circuit of depth 1+depth+1 on a rows x cols grid (see module doc).
+
+    two_qubit = ISWAP gives the harder benchmark variant of the section on two-qubit gates:
+    every CZ of the same circuit replaced by an iSWAP (same layouts, same one-qubit gates)."""
     n = rows * cols
     if n > 64:
         raise ValueError("at most 64 qubits")
@@ -114,7 +117,7 @@ def grid_circuit(rows: int, cols: int, depth: int, seed: int) -> np.ndarray:
         edges = cz_pattern_edges(rows, cols, c % 8)
         cur_cz = [False] * n
         for (a, b) in edges:
-            gates.append((CZ, 0, c, a, b))
+            gates.append((two_qubit, 0, c, a, b))
             cur_cz[a] = cur_cz[b] = True
         for q in range(n):
             if prev_cz[q] and not cur_cz[q]:
