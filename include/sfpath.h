@@ -4,8 +4,9 @@
  * Method (arXiv:1807.10749): the qubit grid is cut into block A (which
  * holds qubit 0) and block B (Section 2; Section 9, "Performance
  * estimation": a single straight-line cut).  Every CZ that crosses the cut
- * is split as P0 (x) I + P1 (x) Z (Section 2, Eq. (CZ)), so k crossing CZs
- * give 2^k paths and |psi> = sum_j |phi_j> (Section 3).  Each path evolves
+ * is split as P0 (x) I + P1 (x) Z (Section 2, Eq. (CZ)) and every crossing
+ * iSWAP into the four terms of Eq. (4way), so crossing gates deciding k path
+ * bits give 2^k paths and |psi> = sum_j |phi_j> (Section 3).  Each path evolves
  * the two blocks separately; requested amplitudes are accumulated over paths
  * as amp(x) = sum_p psiA_p(x_A) psiB_p(x_B) (Section 2, "Final-state
  * amplitudes").  Summing a fraction f of the paths trades fidelity for time
@@ -15,14 +16,18 @@
  *   - qubit id on an R x C grid is r*C + c; bitstring bit q = value of qubit
  *     q (x is a uint64); x_A / x_B are the bits of x at the block's qubits,
  *     packed in ascending qubit order;
- *   - gate kinds 0 H, 1 X^1/2, 2 Y^1/2, 3 T, 4 CZ with
+ *   - gate kinds 0 H, 1 X^1/2, 2 Y^1/2, 3 T, 4 CZ, 5 iSWAP with
  *     H = [[1,1],[1,-1]]/sqrt2, X^1/2 = [[1+i,1-i],[1-i,1+i]]/2,
- *     Y^1/2 = [[1+i,-1-i],[1+i,1+i]]/2, T = diag(1, e^{i pi/4});
- *   - the crossing CZs are ordered by (cycle, smaller qubit id); crossing CZ
- *     j is decided by bit (k-1-j) of a path id (the earliest CZ is the most
- *     significant bit, so an aligned block of 2^b ids shares its prefix);
- *     path bit 0 takes P0 on the A endpoint, bit 1 takes P1 on the A endpoint
- *     and Z on the B endpoint.
+ *     Y^1/2 = [[1+i,-1-i],[1+i,1+i]]/2, T = diag(1, e^{i pi/4}),
+ *     iSWAP: |01> -> i|10>, |10> -> i|01>, |00> and |11> kept (Section 7);
+ *   - the crossing gates are ordered by (cycle, smaller qubit id); a crossing
+ *     CZ takes one path bit, a crossing iSWAP two, and the earliest gate the
+ *     most significant bits (so an aligned block of 2^b ids shares its
+ *     prefix).  CZ bit 0 takes P0 on the A endpoint, bit 1 takes P1 on the A
+ *     endpoint and Z on the B endpoint.  iSWAP bits r = 2i + j take the term
+ *     |i><j| (x) G_ij of Eq. (4way), |i><j| on the A endpoint and the 2x2 block
+ *     G_ij (rows 2i.., columns 2j.. of the matrix in the basis 2 x_A + x_B) on
+ *     the B endpoint.
  *
  * Errors: every function returns 0 on success or a negative code below and
  * never throws; last_error() gives a message for the calling thread.
@@ -39,7 +44,7 @@ extern "C" {
 #endif
 
 #define SF_OK              0
-#define SF_ERR_INVALID   (-1)  /* bad argument: qubit outside the grid, non-adjacent CZ, id >= 2^k ... */
+#define SF_ERR_INVALID   (-1)  /* bad argument: qubit outside the grid, non-adjacent two-qubit gate, id >= 2^k ... */
 #define SF_ERR_OOM       (-2)  /* host or device memory, or a workspace that is too small */
 #define SF_ERR_UNSUPPORTED (-3) /* n > 64, a block > 30 qubits, k > 62, ... */
 #define SF_ERR_NO_CUT    (-4)  /* run_paths before set_cut */
@@ -47,7 +52,7 @@ extern "C" {
 
 /* One gate record, 8 bytes. q1 is ignored for one-qubit gates. */
 typedef struct {
-    uint8_t kind;     /* 0 H, 1 X^1/2, 2 Y^1/2, 3 T, 4 CZ */
+    uint8_t kind;     /* 0 H, 1 X^1/2, 2 Y^1/2, 3 T, 4 CZ, 5 iSWAP */
     uint8_t pad;
     uint16_t cycle;   /* clock cycle; must not decrease along the list */
     uint16_t q0, q1;
@@ -68,7 +73,7 @@ typedef struct sf_circuit sf_circuit_t;   /* opaque, library-owned */
 
 /*
  * create_circuit: copy a gate list on an R x C grid (rows*cols <= 64).
- * Gates must act on grid qubits; a CZ must join grid neighbours; cycles
+ * Gates must act on grid qubits; a CZ or iSWAP must join grid neighbours; cycles
  * must not decrease along the list and a qubit may appear at most once per
  * cycle (Section 1 circuits: one layer of gates per clock cycle).
  * The library owns *out until destroy_circuit.
@@ -82,15 +87,16 @@ int destroy_circuit(sf_circuit_t *c);
 /*
  * set_cut: choose block A as the qubits whose bits are set in block_a_mask
  * (bit 0 must be set; block B is the rest of the grid and must not be empty;
- * each block at most 30 qubits).  Writes the number k of crossing CZs
- * (Section 2: "cross-block" CZ gates, xCZ) to *k_out.  Plans are rebuilt.
+ * each block at most 30 qubits).  Writes the number k of path bits of the
+ * crossing gates (Section 2: "cross-block" CZ gates, xCZ, one bit each; a
+ * crossing iSWAP two, Section 7) to *k_out.  Plans are rebuilt.
  */
 int set_cut(sf_circuit_t *c, uint64_t block_a_mask, uint32_t *k_out);
 
 /*
  * choose_cut: the straight-line cut of Section 9 (Performance estimation):
  * among all vertical and horizontal grid cuts, minimise the larger block,
- * then the number of crossing CZs; ties prefer vertical cuts, then the cut
+ * then the path bits of the crossing gates; ties prefer vertical cuts, then the cut
  * nearest to column/row 0.  Writes block A's mask (holding qubit 0).
  */
 int choose_cut(const sf_circuit_t *c, uint64_t *block_a_mask);

@@ -123,6 +123,54 @@ __device__ __forceinline__ void lane_gate(int b, int kind, int lane, C (&v)[1 <<
     }
 }
 
+// ---------------------------------------------------------------- per-path flips
+
+// Swap the pairs of register qubit K where f (this lane's slot) is set.
+template <int K, int R, typename C>
+__device__ __forceinline__ void reg_flip(bool f, C (&v)[1 << R])
+{
+    constexpr int N = 1 << R;
+    constexpr int B = 1 << K;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j & B) continue;
+        const C a = v[j], b = v[j | B];
+        v[j].x = f ? b.x : a.x; v[j].y = f ? b.y : a.y;
+        v[j | B].x = f ? a.x : b.x; v[j | B].y = f ? a.y : b.y;
+    }
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void reg_flip_dispatch(int k, bool f, C (&v)[1 << R])
+{
+    switch (k) {
+    case 0: if constexpr (R > 0) reg_flip<0, R>(f, v); break;
+    case 1: if constexpr (R > 1) reg_flip<1, R>(f, v); break;
+    case 2: if constexpr (R > 2) reg_flip<2, R>(f, v); break;
+    case 3: if constexpr (R > 3) reg_flip<3, R>(f, v); break;
+    case 4: if constexpr (R > 4) reg_flip<4, R>(f, v); break;
+    default: break;
+    }
+}
+
+// Flip lane bit b where f is set.  The target is a qubit bit (above the slot bits), so the
+// partner lane holds the same slot and takes the same decision.
+template <int R, typename C>
+__device__ __forceinline__ void lane_flip(int b, bool f, C (&v)[1 << R])
+{
+    constexpr int N = 1 << R;
+    const int m = 1 << b;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const C o = v[j];
+        C t;
+        t.x = __shfl_xor(o.x, m);
+        t.y = __shfl_xor(o.y, m);
+        v[j].x = f ? t.x : o.x;
+        v[j].y = f ? t.y : o.y;
+    }
+}
+
 // ---------------------------------------------------------------- diagonal groups
 
 __device__ __forceinline__ int tab_entry(const uint64_t (&tab)[4], int j)
@@ -303,8 +351,20 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                 reg_dispatch<R>(op.target, op.kind, v);
             } else if (op.type == PO_LANE) {
                 lane_gate<R>(op.target, op.kind, (int)lane, v);
-            } else {
+            } else if (op.type == PO_DIAG) {
                 apply_diag<R, T>(groups + op.group, terms, eB, sp, v);
+            } else {
+                const bool f = (((sp >> op.group) ^ (sp >> (op.group + 1))) & 1u) != 0;
+                if (op.type == PO_PFLIP_REG) reg_flip_dispatch<R>(op.target, f, v);
+                else lane_flip<R>(op.target, f, v);
+                if (op.kind && f) {
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {       // times i
+                        const T x = v[j].x;
+                        v[j].x = -v[j].y;
+                        v[j].y = x;
+                    }
+                }
             }
         }
 

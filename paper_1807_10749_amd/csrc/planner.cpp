@@ -1,13 +1,15 @@
 // Planner: cut -> per-block programs -> tree levels -> fused passes.
 //
-// * Crossing CZs (Section 2, "cross-block" CZ) are ordered by (cycle,
-//   smaller qubit) and crossing CZ j is decided by path bit (k-1-j), so an
-//   aligned block of path ids shares a prefix (Section 2: x = x_p + x_b,
-//   processes spawned per x_p-bit prefix).
+// * Crossing gates (Section 2, "cross-block" CZ; iSWAP by Eq. (4way)) are
+//   ordered by (cycle, smaller qubit); a CZ takes one path bit, an iSWAP
+//   two, and the first crossing gate the highest bits, so an aligned block of
+//   path ids shares a prefix (Section 2: x = x_p + x_b, processes spawned
+//   per x_p-bit prefix).
 // * Each block's program is cut into segments at the cycles holding
-//   crossing CZs.  Segment l starts with the branch operators of level l
-//   (P_s on the block-A endpoint, Z^s on the block-B endpoint; Section 2,
-//   Eq. (CZ)); everything between two such cycles is shared by all paths
+//   crossing gates.  Segment l starts with the branch operators of level l
+//   (P_s on the block-A endpoint, Z^s on the block-B endpoint of a CZ,
+//   Section 2, Eq. (CZ); projector plus per-path flip on both endpoints of
+//   an iSWAP); everything between two such cycles is shared by all paths
 //   with the same prefix (the checkpoint/branch scheme of Section 2).
 // * A segment is split into passes: each pass may apply non-diagonal gates
 //   only to qubits held in lane bits or in its R register bits; diagonal
@@ -49,6 +51,7 @@ static LeafFold make_fold(const Circuit &c, int h, int F)
     std::vector<HalfOp> rest;
     for (int l = L - F + 1; l <= L; ++l)
         for (const HalfOp &op : c.half[h].segments[l]) {
+            if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) return f;   // a branch operator that is not diagonal
             if (op.kind == HK_PROJ || op.kind == HK_ZCTL) {
                 if (op.bit >= nb || bq[op.bit] >= 0 || op.q0 >= 32 || ((nondiag_seen >> op.q0) & 1)) return f;
                 bq[op.bit] = op.q0;
@@ -157,34 +160,41 @@ int build_programs(Circuit &c, std::string &err)
     }
     auto in_a = [&](int q) { return ((c.mask_a >> q) & 1) != 0; };
 
-    // crossing CZs in path-bit order
+    // crossing two-qubit gates in path-bit order; a CZ takes one path bit (two terms), an iSWAP
+    // two (the four terms of Eq. (4way)), and the first crossing gate the highest bits
     c.cut_gate.clear();
     for (size_t i = 0; i < c.gates.size(); ++i) {
         const sf_gate_t &g = c.gates[i];
-        if (g.kind == 4 && in_a(g.q0) != in_a(g.q1)) c.cut_gate.push_back((int)i);
+        if ((g.kind == 4 || g.kind == 5) && in_a(g.q0) != in_a(g.q1)) c.cut_gate.push_back((int)i);
     }
     std::stable_sort(c.cut_gate.begin(), c.cut_gate.end(), [&](int a, int b) {
         const sf_gate_t &x = c.gates[a], &y = c.gates[b];
         const int mx = std::min(x.q0, x.q1), my = std::min(y.q0, y.q1);
         return x.cycle != y.cycle ? x.cycle < y.cycle : mx < my;
     });
-    c.k = (int)c.cut_gate.size();
+    auto width = [&](int gi) { return c.gates[gi].kind == 5 ? 2 : 1; };
+    c.k = 0;
+    for (int gi : c.cut_gate) c.k += width(gi);
     if (c.k > 62) {
-        err = "more than 62 crossing CZs";
+        err = "crossing gates take more than 62 path bits";
         return SF_ERR_UNSUPPORTED;
     }
-    std::vector<int> bit_of_gate(c.gates.size(), -1);
-    for (int j = 0; j < c.k; ++j) bit_of_gate[c.cut_gate[j]] = c.k - 1 - j;
+    std::vector<int> bit_of_gate(c.gates.size(), -1);   // lowest path bit of the gate's term index
+    for (int j = 0, top = c.k; j < (int)c.cut_gate.size(); ++j) {
+        top -= width(c.cut_gate[j]);
+        bit_of_gate[c.cut_gate[j]] = top;
+    }
 
-    // tree levels: one per clock cycle that holds crossing CZs
+    // tree levels: one per clock cycle that holds crossing gates
     c.levels.clear();
     c.levels.push_back(Level{-1, 0, 0, 0});
-    for (int j = 0; j < c.k; ++j) {
-        const int cy = c.gates[c.cut_gate[j]].cycle;
+    for (int j = 0; j < (int)c.cut_gate.size(); ++j) {
+        const int gi = c.cut_gate[j];
+        const int cy = c.gates[gi].cycle;
         if (c.levels.size() == 1 || c.levels.back().cycle != cy)
             c.levels.push_back(Level{cy, j, 0, 0});
-        c.levels.back().n_cut++;
-        c.levels.back().bits_after = j + 1;
+        c.levels.back().n_cut += width(gi);
+        c.levels.back().bits_after = c.k - bit_of_gate[gi];
     }
     const int L = (int)c.levels.size() - 1;
 
@@ -194,8 +204,11 @@ int build_programs(Circuit &c, std::string &err)
         hp.segments.assign(L + 1, {});
         hp.init_h_mask = 0;
     }
-    // Per block, the operations in list order; a crossing CZ becomes its branch operator
-    // (P_s on the A endpoint, Z^s on the B endpoint), tagged with its tree level.
+    // Per block, the operations in list order; a crossing gate becomes its branch operators,
+    // tagged with its tree level.  Crossing CZ (Section 2, Eq. (CZ)): P_s on the A endpoint,
+    // Z^s on the B endpoint.  Crossing iSWAP, term r = 2i + j of Eq. (4way) (i = path bit u+1,
+    // j = path bit u): |i><j| = X^{i xor j} P_j on the A endpoint and, by Eq. (iSWAP1),
+    // G_ij = i^{i xor j} X^{i xor j} P_i on the B endpoint.
     std::vector<HalfOp> ops[2];
     std::vector<int> own[2];
     for (size_t i = 0; i < c.gates.size(); ++i) {
@@ -203,17 +216,35 @@ int build_programs(Circuit &c, std::string &err)
         if (bit_of_gate[i] >= 0) {
             int lvl = 1;
             while (c.levels[lvl].cycle != g.cycle) ++lvl;
-            const int qa = in_a(g.q0) ? g.q0 : g.q1;
-            const int qb = in_a(g.q0) ? g.q1 : g.q0;
+            const uint8_t qa = (uint8_t)local[in_a(g.q0) ? g.q0 : g.q1];
+            const uint8_t qb = (uint8_t)local[in_a(g.q0) ? g.q1 : g.q0];
             const uint8_t u = (uint8_t)bit_of_gate[i];
-            ops[0].push_back(HalfOp{HK_PROJ, (uint8_t)local[qa], 0, u});
-            own[0].push_back(lvl);
-            ops[1].push_back(HalfOp{HK_ZCTL, (uint8_t)local[qb], 0, u});
-            own[1].push_back(lvl);
+            if (g.kind == 4) {
+                ops[0].push_back(HalfOp{HK_PROJ, qa, 0, u});
+                ops[1].push_back(HalfOp{HK_ZCTL, qb, 0, u});
+            } else {
+                ops[0].push_back(HalfOp{HK_PROJ, qa, 0, u});
+                ops[0].push_back(HalfOp{HK_PFLIP, qa, 0, u});
+                ops[1].push_back(HalfOp{HK_PROJ, qb, 0, (uint8_t)(u + 1)});
+                ops[1].push_back(HalfOp{HK_PFLIPI, qb, 0, u});
+            }
+            own[0].resize(ops[0].size(), lvl);
+            own[1].resize(ops[1].size(), lvl);
             continue;
         }
         const int h = in_a(g.q0) ? 0 : 1;
-        HalfOp op{0, (uint8_t)local[g.q0], 0, 0};
+        const uint8_t a = (uint8_t)local[g.q0];
+        if (g.kind == 5) {
+            // iSWAP inside a block, exactly: H_b H_a CZ H_a H_b CZ H_b H_a, then S = T^2 on both
+            const uint8_t b = (uint8_t)local[g.q1];
+            const HalfOp seq[] = {{HK_H, b, 0, 0}, {HK_H, a, 0, 0}, {HK_CZ, a, b, 0}, {HK_H, a, 0, 0},
+                                  {HK_H, b, 0, 0}, {HK_CZ, a, b, 0}, {HK_H, b, 0, 0}, {HK_H, a, 0, 0},
+                                  {HK_T, a, 0, 0}, {HK_T, a, 0, 0}, {HK_T, b, 0, 0}, {HK_T, b, 0, 0}};
+            for (const HalfOp &op : seq) ops[h].push_back(op);
+            own[h].resize(ops[h].size(), 0);
+            continue;
+        }
+        HalfOp op{0, a, 0, 0};
         switch (g.kind) {
         case 0: op.kind = HK_H; break;
         case 1: op.kind = HK_X; break;
@@ -327,13 +358,13 @@ void flush(PendingDiag &pd, PassPlan &pp, const int (&kidx)[64])
     auto reg = [&](int bit) { return kidx[bit]; };   // -1 if not a register bit
     int tab[64] = {0};
     const int N = 1 << pp.R;
-    bool odd = false;
+    bool odd = false;      // some weight is not a multiple of 4 (the phase is not a sign)
     // lin
     std::vector<std::pair<int, int>> lin_b;
     for (auto &kv : pd.lin) {
         const int w = kv.second & 7;
         if (!w) continue;
-        if (w & 1) odd = true;
+        if (w & 3) odd = true;
         const int k = reg(kv.first);
         if (k >= 0) {
             for (int j = 0; j < N; ++j) if ((j >> k) & 1) tab[j] += w;
@@ -464,7 +495,7 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
     int carry = 0;
     for (int l = 0; l < level; ++l) {
         int nn = 0;
-        for (const HalfOp &op : hp.segments[l]) if (!is_diag(op.kind)) ++nn;
+        for (const HalfOp &op : hp.segments[l]) if (has_gain(op.kind)) ++nn;
         carry = (carry + nn) % 2;
     }
     int taken = 0;
@@ -482,7 +513,7 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
             int nd = 0;
             for (const HalfOp &op : rem) {
                 const uint64_t qm = (uint64_t(1) << op.q0) | (op.kind == HK_CZ ? uint64_t(1) << op.q1 : 0);
-                bool take = !(qm & blocked) && op.kind != HK_PROJ && op.kind != HK_ZCTL;
+                bool take = !(qm & blocked) && !is_branch(op.kind);
                 std::vector<int> nq = Q;
                 if (take) {
                     const int qq[2] = {op.q0, op.kind == HK_CZ ? (int)op.q1 : -1};
@@ -566,13 +597,21 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
                 const uint64_t qm = uint64_t(1) << op.q0;
                 if (pd.touched & qm) flush(pd, pp, kidx);
                 PassOp po;
-                po.kind = op.kind == HK_H ? GK_H : (op.kind == HK_X ? GK_X : GK_Y);
+                const bool lane = op.q0 < n_lane_q;
+                po.target = lane ? (uint8_t)(p + op.q0) : (uint8_t)kidx[p + op.q0];
                 po.pad = 0;
-                po.group = 0;
-                if (op.q0 < n_lane_q) { po.type = PO_LANE; po.target = (uint8_t)(p + op.q0); }
-                else { po.type = PO_REG; po.target = (uint8_t)kidx[p + op.q0]; }
+                if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) {
+                    po.type = lane ? PO_PFLIP_LANE : PO_PFLIP_REG;
+                    po.kind = op.kind == HK_PFLIPI ? 1 : 0;
+                    po.group = op.bit;
+                    pp.needs_slot_path = true;
+                } else {
+                    po.type = lane ? PO_LANE : PO_REG;
+                    po.kind = op.kind == HK_H ? GK_H : (op.kind == HK_X ? GK_X : GK_Y);
+                    po.group = 0;
+                    ++pp.n_nondiag;
+                }
                 pp.ops.push_back(po);
-                ++pp.n_nondiag;
                 continue;
             }
             switch (op.kind) {

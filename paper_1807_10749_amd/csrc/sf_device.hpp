@@ -14,7 +14,8 @@
 // applied in registers, gates on the (up to 6) qubits that sit in lane bits
 // with cross-lane shuffles, and diagonal gates (CZ, T, and the per-path
 // projector / Z of crossing CZs, Section 2 Eq. (CZ)) as bitmask phase
-// evaluations (the paper's bitmask + mod-8 arithmetic of Section 2).
+// evaluations (the paper's bitmask + mod-8 arithmetic of Section 2).  The
+// per-path flips of crossing iSWAPs are register swaps or lane shuffles.
 #pragma once
 #include <stdint.h>
 
@@ -28,14 +29,16 @@ namespace sf {
 // folds exact powers of two back in ("rescaling").
 enum GateKind : uint8_t { GK_H = 0, GK_X = 1, GK_Y = 2 };
 
-enum PassOpType : uint8_t { PO_REG = 0, PO_LANE = 1, PO_DIAG = 2 };
+// PO_PFLIP_*: the non-diagonal branch operator of a crossing iSWAP (Eq. (4way)): flip the target
+// qubit in the slots whose path bits u and u+1 differ, and (kind 1) multiply those slots by i.
+enum PassOpType : uint8_t { PO_REG = 0, PO_LANE = 1, PO_DIAG = 2, PO_PFLIP_REG = 3, PO_PFLIP_LANE = 4 };
 
 struct PassOp {
     uint8_t type;    // PassOpType
-    uint8_t kind;    // GateKind for PO_REG / PO_LANE
-    uint8_t target;  // register index k (PO_REG) or lane bit b (PO_LANE)
+    uint8_t kind;    // GateKind for PO_REG / PO_LANE; 1 = with the factor i for PO_PFLIP_*
+    uint8_t target;  // register index k (PO_REG, PO_PFLIP_REG) or lane bit b (PO_LANE, PO_PFLIP_LANE)
     uint8_t pad;
-    uint32_t group;  // diagonal group index (PO_DIAG)
+    uint32_t group;  // diagonal group index (PO_DIAG); path bit u (PO_PFLIP_*)
 };
 
 // A merged set of commuting diagonal operators, evaluated per amplitude as
@@ -47,7 +50,7 @@ struct PassOp {
 // given by register index k) or base bits ("b", extended bit position).
 struct DiagGroup {
     uint16_t n_lin_b, n_quad_bb, n_quad_br, n_zs_b, n_zs_r, n_proj_b, n_proj_r;
-    uint16_t flags;            // bit 0: some odd phase weight; bit 1: has projectors
+    uint16_t flags;            // bit 0: some weight not a multiple of 4; bit 1: has projectors
     uint32_t term_off;         // offset (in byte pairs) into the term array
     uint32_t pad;
     uint64_t tab[4];           // m contribution of register-only terms, 4 bits per j < 64

@@ -17,15 +17,21 @@ enum HalfKind : uint8_t {
     HK_H = 0, HK_X = 1, HK_Y = 2, HK_T = 3, HK_CZ = 4,
     HK_PROJ = 5,   // keep amplitudes whose bit q0 equals path bit `bit` (crossing CZ, block A side)
     HK_ZCTL = 6,   // negate amplitudes whose bit q0 is 1 when path bit `bit` is 1 (block B side)
+    HK_PFLIP = 7,  // flip bit q0 when path bits bit and bit+1 differ (crossing iSWAP, X^{i xor j})
+    HK_PFLIPI = 8, // as HK_PFLIP, and multiply by i when it flips
 };
 
 struct HalfOp {
     uint8_t kind;
     uint8_t q0, q1;
-    uint8_t bit;   // path bit index u (bit u of the path id), HK_PROJ / HK_ZCTL only
+    uint8_t bit;   // path bit index u (bit u of the path id): HK_PROJ / HK_ZCTL, lower bit of HK_PFLIP(I)
 };
 
 inline bool is_diag(uint8_t k) { return k == HK_T || k == HK_CZ || k == HK_PROJ || k == HK_ZCTL; }
+// operators that depend on the path id (branch operators of crossing gates)
+inline bool is_branch(uint8_t k) { return k == HK_PROJ || k == HK_ZCTL || k == HK_PFLIP || k == HK_PFLIPI; }
+// the unnormalised one-qubit forms, whose norm gain sqrt2 the host tracks and rescales
+inline bool has_gain(uint8_t k) { return k == HK_H || k == HK_X || k == HK_Y; }
 
 // One pass of a segment: kernel ops plus the register-bit choice.
 struct PassPlan {
@@ -80,9 +86,9 @@ struct HalfProgram {
 };
 
 struct Level {
-    int cycle;          // clock cycle of this level's crossing CZs
-    int first_cut;      // crossing-CZ indices [first_cut, first_cut + n_cut)
-    int n_cut;
+    int cycle;          // clock cycle of this level's crossing gates
+    int first_cut;      // index (in cut_gate) of its first crossing gate
+    int n_cut;          // path bits its crossing gates decide (1 per CZ, 2 per iSWAP)
     int bits_after;     // path bits decided once this level's branch operators are applied
 };
 
@@ -94,8 +100,8 @@ struct Circuit {
     bool has_cut = false;
     uint64_t mask_a = 0, mask_b = 0;
     int k = 0;
-    std::vector<int> cut_gate;        // gate index of crossing CZ j (path-bit order)
-    std::vector<Level> levels;        // levels[0] is the root (no crossing CZ)
+    std::vector<int> cut_gate;        // gate index of crossing gate j (path-bit order)
+    std::vector<Level> levels;        // levels[0] is the root (no crossing gate)
     HalfProgram half[2];              // 0 = A, 1 = B
 
     // tuning

@@ -67,7 +67,8 @@ int count_crossing(const Circuit &c, uint64_t mask_a)
 {
     int k = 0;
     for (const sf_gate_t &g : c.gates)
-        if (g.kind == 4 && (((mask_a >> g.q0) & 1) != ((mask_a >> g.q1) & 1))) ++k;
+        if ((g.kind == 4 || g.kind == 5) && (((mask_a >> g.q0) & 1) != ((mask_a >> g.q1) & 1)))
+            k += g.kind == 5 ? 2 : 1;   // path bits: two terms for a CZ, four for an iSWAP
     return k;
 }
 
@@ -90,17 +91,19 @@ int create_circuit(int rows, int cols, const sf_gate_t *gates, size_t n_gates, s
         std::vector<int> seen(n, -1);
         for (size_t i = 0; i < n_gates; ++i) {
             const sf_gate_t &g = gates[i];
-            if (g.kind > 4) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": unknown kind");
+            if (g.kind > 5) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": unknown kind");
             if (g.q0 >= n) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": qubit outside the grid");
             if (g.cycle < last_cycle) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": cycle decreases");
             last_cycle = g.cycle;
-            if (g.kind == 4) {
-                if (g.q1 >= n || g.q1 == g.q0) return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": bad CZ qubits");
+            const bool two = g.kind == 4 || g.kind == 5;
+            if (two) {
+                if (g.q1 >= n || g.q1 == g.q0)
+                    return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": bad two-qubit gate qubits");
                 const int r0 = g.q0 / cols, c0 = g.q0 % cols, r1 = g.q1 / cols, c1 = g.q1 % cols;
                 if (std::abs(r0 - r1) + std::abs(c0 - c1) != 1)
-                    return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": CZ on non-adjacent qubits");
+                    return fail(SF_ERR_INVALID, "gate " + std::to_string(i) + ": two-qubit gate on non-adjacent qubits");
             }
-            const int qs[2] = {g.q0, g.kind == 4 ? (int)g.q1 : -1};
+            const int qs[2] = {g.q0, two ? (int)g.q1 : -1};
             for (int q : qs) {
                 if (q < 0) continue;
                 if (seen[q] == g.cycle)

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workload import CONFIGS, CZ, GATE_DTYPE, H, grid_circuit, make_workload
+from workload import CONFIGS, CZ, GATE_DTYPE, H, ISWAP, grid_circuit, make_workload
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "sfpath.h")
@@ -60,6 +60,28 @@ def test_set_cut_counts_match_oracle(sf):
         k = sf.set_cut(c, cfg.cut_mask())
         assert k == oracle.num_cut(cfg.n_qubits, g, cfg.cut_mask()), name
         sf.destroy_circuit(c)
+
+
+def test_iswap_path_bits(sf):
+    """A crossing iSWAP takes two path bits (four terms, Eq. (4way)); 80 bits are refused."""
+    for name, cfg in CONFIGS.items():
+        g = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed, two_qubit=ISWAP)
+        kcz = oracle.num_cut(cfg.n_qubits, grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed),
+                             cfg.cut_mask())
+        assert oracle.num_cut(cfg.n_qubits, g, cfg.cut_mask()) == 2 * kcz
+        c = sf.create_circuit(cfg.rows, cfg.cols, g)
+        if 2 * kcz <= 62:
+            assert sf.set_cut(c, cfg.cut_mask()) == 2 * kcz, name
+            assert "folded" not in sf.describe_plan(c)      # per-path flips are not diagonal
+        else:
+            with pytest.raises(sf.SFError) as e:
+                sf.set_cut(c, cfg.cut_mask())
+            assert e.value.code == sf.SF_ERR_UNSUPPORTED
+        sf.destroy_circuit(c)
+    bad = np.array([(ISWAP, 0, 0, 0, 5)], dtype=GATE_DTYPE)          # not neighbours on 2 x 4
+    with pytest.raises(sf.SFError) as e:
+        sf.create_circuit(2, 4, bad)
+    assert e.value.code == sf.SF_ERR_INVALID
 
 
 def test_set_cut_validation(sf):

@@ -1,10 +1,7 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerance (floating point): for amplitudes a (GPU) and o (oracle) over a set
-of m of the 2^k paths of an n-qubit circuit,
-    e_x = | |a_x|^2 - |o_x|^2 | / max(|o_x|^2, (m / 2^k) 2^-n),
-the floor being the mean |amp|^2 of such a partial sum; max_x e_x <= 1e-5
-for complex64 sweeps and <= 1e-10 for complex128 sweeps.  Path and
+Tolerance (floating point): the relative error in |amp|^2 of parity_tol,
+at most 1e-5 for complex64 sweeps and 1e-10 for complex128 sweeps.  Path and
 bitstring indexing is exact: single-path runs expose any permutation as an
 O(1) error.
 """
@@ -12,17 +9,10 @@ import numpy as np
 import pytest
 
 import oracle
+from parity_tol import TOL_C128, TOL_C64, c11_error
 from workload import CONFIGS, grid_circuit, make_workload, path_block, random_bitstrings
 
 pytestmark = pytest.mark.gpu
-
-TOL_C64 = 1e-5
-TOL_C128 = 1e-10
-
-
-def c11_error(a, o, m, k, n):
-    floor = (m / 2.0 ** k) * 2.0 ** (-n)
-    return float(np.max(np.abs(np.abs(a) ** 2 - np.abs(o) ** 2) / np.maximum(np.abs(o) ** 2, floor)))
 
 
 def say(msg):
@@ -394,3 +384,23 @@ def test_repeated_request_reuses_plan(sf):
     c.tune(fold_levels=1)
     sf.run_paths(c.handle, ids2, 0, ids2.size, dbits, 200, acc, flags, stream, ws, ws.numel())
     assert c11_error(acc.cpu().numpy().view(np.complex128)[:200], o2[:200], ids2.size, c.k, 30) <= TOL_C64
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_diagonal_group_quarter_turn_phases(sf, fp64):
+    """Two T gates on a qubit with only diagonal gates between them give the phase i (weight 2
+    of 8), which a merged diagonal group must not take for a sign."""
+    from workload import GATE_DTYPE, H, T, CZ
+    g = [(H, 0, 0, q, 0) for q in range(16)]
+    for cyc in (1, 2):
+        g += [(T, 0, cyc, q, 0) for q in range(0, 16, 3)]        # S = T^2 on every third qubit
+    g += [(CZ, 0, 3, 1, 2), (CZ, 0, 3, 5, 6), (CZ, 0, 3, 8, 12)]
+    g += [(H, 0, 4, q, 0) for q in range(16)]
+    g = np.array(g, dtype=GATE_DTYPE)
+    mask = CONFIGS["grid4x4_d16"].cut_mask()
+    c = sf.Circuit(4, 4, g, mask)
+    bits = np.arange(1 << 16, dtype=np.uint64)[::13]
+    say(f"T^2 / T^3 phases fp64={fp64} k={c.k}")
+    a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS if fp64 else 0)
+    o = oracle.full_state(16, g)[bits.astype(np.int64)]
+    assert c11_error(a, o, 1, 0, 16) <= (TOL_C128 if fp64 else TOL_C64)
