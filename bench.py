@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving mix (0 = skip)")
     ap.add_argument("--no-sampling", action="store_true", help="skip the rejection-sampling measurement")
+    ap.add_argument("--no-iswap", action="store_true", help="skip the iSWAP-variant measurement")
     ap.add_argument("--tuning", default="",
                     help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels]]] "
                          "(skips autotune)")
@@ -169,6 +170,10 @@ def main():
         torch.cuda.synchronize()
         validation = validation_bench(c, bits, d_amps, cfg.bits_seed, ws, ws_bytes, stream)
 
+    iswap = None
+    if not args.no_iswap and args.workload != "grid5x6_d24_iswap":
+        iswap = iswap_bench(stream)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, gates, bits, c.k, ids, begin, npaths, args.cpu_seconds)
@@ -207,6 +212,7 @@ def main():
         "serving": serving,
         "sampling": sampling,
         "validation": validation,
+        "iswap": iswap,
     }
     print(json.dumps(out), flush=True)
     c.close()
@@ -281,6 +287,51 @@ def validation_bench(c, bits, d_amps, index_seed, ws, ws_bytes, stream, f1=0.25,
             best = (dt, fe, ok)
     return {"indices": int(bits.size), "f1": f1, "delta": delta, "f_e": best[1], "passed": best[2],
             "ms": best[0] * 1e3}
+
+
+def iswap_bench(stream, steps=3, warmup=1):
+    """The harder variant (every CZ of the default circuit an iSWAP, Eq. (4way): four terms and
+    two path bits per crossing gate, k = 30): one seeded aligned block of 2^18 paths, 1e5
+    bitstrings, autotuned, timed like the headline step."""
+    import torch
+    from paper_1807_10749_amd import binding as sf
+    from workload import make_workload, path_block
+    w = make_workload("grid5x6_d24_iswap")
+    cfg, bits = w["cfg"], w["bitstrings"]
+    c = sf.Circuit(cfg.rows, cfg.cols, w["gates"], cfg.cut_mask())
+    begin, npaths = path_block(c.k, cfg.block_bits, cfg.path_seed)
+    d_bits = torch.from_numpy(bits.view(np.int64)).cuda()
+    d_amps = torch.zeros(2 * bits.size, dtype=torch.float64, device="cuda")
+    # the bound assumes every leaf resident at once; the library batches leaves within what it gets
+    free_b, _ = torch.cuda.mem_get_info()
+    ws_bytes = min(sf.workspace_size(c.handle, npaths, bits.size, 0), 64 << 30, int(free_b * 0.5))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    flags = sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
+    tuning = sf.autotune(c.handle, None, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,
+                         n_measure=4)
+    for _ in range(warmup):
+        sf.run_paths(c.handle, None, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes)
+    torch.cuda.synchronize()
+    tot = {"ms_sweep": 0.0, "ms_gather": 0.0, "ms_other": 0.0, "sweep_bytes": 0, "n_sweep_launches": 0}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sf.run_paths(c.handle, None, begin, npaths, d_bits, bits.size, d_amps, flags | sf.SF_TIMING, stream, ws,
+                     ws_bytes)
+        st = c.stats()
+        for key in tot:
+            tot[key] += st[key]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    sweep_gbs = tot["sweep_bytes"] / (tot["ms_sweep"] * 1e-3) / 1e9 if tot["ms_sweep"] else 0.0
+    out = {"workload": cfg.name, "k": c.k, "paths": npaths, "bitstrings": int(bits.size),
+           "paths_per_s": npaths / dt, "ms_per_step": dt * 1e3,
+           "kernel_ms_per_step": {"sweep": tot["ms_sweep"] / steps, "gather": tot["ms_gather"] / steps,
+                                  "other": tot["ms_other"] / steps},
+           "sweep_launches_per_step": tot["n_sweep_launches"] / steps,
+           "sweep_GB_per_s": sweep_gbs, "sweep_frac_of_hbm_peak": sweep_gbs / HBM_PEAK_GBS,
+           "tuning": tuning}
+    c.close()
+    return out
 
 
 def serving_bench(n_jobs, workers=4, chunk_paths=16384, seed=5005):

@@ -90,6 +90,7 @@ struct Launch {
     size_t mask_off = 0;          // FOLD: element offset of the batch's child masks
     int half = 0;
     int R = 0;
+    bool flip = false;            // PASS: the program holds per-path flips
     PassArgs pa{};
     GatherArgs ga{};
     size_t plan_off = 0;      // device offset of the pass program inside the plan blob
@@ -500,6 +501,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 ln.kind = Launch::PASS;
                 ln.half = h;
                 ln.R = pp.R;
+                ln.flip = pp.has_flip;
                 ln.level = level;
                 PassArgs &a = ln.pa;
                 std::memset(&a, 0, sizeof(a));
@@ -831,7 +833,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 a.groups_word = ln.groups_word;
                 a.terms_word = ln.terms_word;
                 timed(0);
-                if ((he = launch_pass(fp64, ln.R, a, ln.grid, stream)) != hipSuccess) return dev_err("pass", he);
+                if ((he = launch_pass(fp64, ln.R, ln.flip, a, ln.grid, stream)) != hipSuccess) return dev_err("pass", he);
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;
             } else if (ln.kind == Launch::FOLD) {

@@ -125,7 +125,9 @@ __device__ __forceinline__ void lane_gate(int b, int kind, int lane, C (&v)[1 <<
 
 // ---------------------------------------------------------------- per-path flips
 
-// Swap the pairs of register qubit K where f (this lane's slot) is set.
+// Swap the pairs of register qubit K where f (this lane's slot) is set.  Each pair passes through
+// an empty asm statement first: without it the compiler merges the cases of reg_flip_dispatch
+// into one access of v with a computed index, which moves v out of registers into scratch memory.
 template <int K, int R, typename C>
 __device__ __forceinline__ void reg_flip(bool f, C (&v)[1 << R])
 {
@@ -134,7 +136,8 @@ __device__ __forceinline__ void reg_flip(bool f, C (&v)[1 << R])
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         if (j & B) continue;
-        const C a = v[j], b = v[j | B];
+        C a = v[j], b = v[j | B];
+        asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(b.x), "+v"(b.y));
         v[j].x = f ? b.x : a.x; v[j].y = f ? b.y : a.y;
         v[j | B].x = f ? a.x : b.x; v[j | B].y = f ? a.y : b.y;
     }
@@ -257,7 +260,9 @@ __device__ __forceinline__ uint64_t reg_offset(const int32_t (&pos)[6], int j, i
     return o;
 }
 
-template <typename T, int R>
+// FLIP: the program may hold per-path flips (crossing iSWAPs); passes without them run the
+// variant that has no code for them, whose register allocation they do not affect.
+template <typename T, int R, bool FLIP>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
     using C = typename Cplx<T>::type;
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                 reg_dispatch<R>(op.target, op.kind, v);
             } else if (op.type == PO_LANE) {
                 lane_gate<R>(op.target, op.kind, (int)lane, v);
-            } else if (op.type == PO_DIAG) {
+            } else if (!FLIP || op.type == PO_DIAG) {
                 apply_diag<R, T>(groups + op.group, terms, eB, sp, v);
             } else {
                 const bool f = (((sp >> op.group) ^ (sp >> (op.group + 1))) & 1u) != 0;
@@ -381,25 +386,27 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     }
 }
 
-template <typename T>
+template <typename T, bool FLIP>
 static hipError_t launch_pass_t(int R, const PassArgs &a, unsigned grid, hipStream_t s)
 {
     switch (R) {
-    case 0: pass_kernel<T, 0><<<grid, 256, 0, s>>>(a); break;
-    case 1: pass_kernel<T, 1><<<grid, 256, 0, s>>>(a); break;
-    case 2: pass_kernel<T, 2><<<grid, 256, 0, s>>>(a); break;
-    case 3: pass_kernel<T, 3><<<grid, 256, 0, s>>>(a); break;
-    case 4: pass_kernel<T, 4><<<grid, 256, 0, s>>>(a); break;
-    case 5: if constexpr (sizeof(T) == 4) { pass_kernel<T, 5><<<grid, 256, 0, s>>>(a); break; }
+    case 0: pass_kernel<T, 0, FLIP><<<grid, 256, 0, s>>>(a); break;
+    case 1: pass_kernel<T, 1, FLIP><<<grid, 256, 0, s>>>(a); break;
+    case 2: pass_kernel<T, 2, FLIP><<<grid, 256, 0, s>>>(a); break;
+    case 3: pass_kernel<T, 3, FLIP><<<grid, 256, 0, s>>>(a); break;
+    case 4: pass_kernel<T, 4, FLIP><<<grid, 256, 0, s>>>(a); break;
+    case 5: if constexpr (sizeof(T) == 4) { pass_kernel<T, 5, FLIP><<<grid, 256, 0, s>>>(a); break; }
             return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_pass(bool fp64, int R, const PassArgs &a, unsigned grid, hipStream_t s)
+hipError_t launch_pass(bool fp64, int R, bool flips, const PassArgs &a, unsigned grid, hipStream_t s)
 {
-    return fp64 ? launch_pass_t<double>(R, a, grid, s) : launch_pass_t<float>(R, a, grid, s);
+    if (flips)
+        return fp64 ? launch_pass_t<double, true>(R, a, grid, s) : launch_pass_t<float, true>(R, a, grid, s);
+    return fp64 ? launch_pass_t<double, false>(R, a, grid, s) : launch_pass_t<float, false>(R, a, grid, s);
 }
 
 // ---------------------------------------------------------------- dense block on matrix cores

@@ -14,7 +14,8 @@ constexpr int kMaxRegBitsF64 = 4;
 
 // Stream one pass over a block state (see PassArgs).  R = register bits
 // (0..kMaxRegBits), fp64 selects complex128 states.
-hipError_t launch_pass(bool fp64, int R, const PassArgs &a, unsigned grid, hipStream_t s);
+// flips: the program holds PO_PFLIP_* ops (selects the kernel variant that has code for them)
+hipError_t launch_pass(bool fp64, int R, bool flips, const PassArgs &a, unsigned grid, hipStream_t s);
 
 // Dense 4-qubit block on matrix cores (complex64 states only).
 hipError_t launch_dense(const DenseArgs &a, unsigned grid, hipStream_t s);

@@ -605,6 +605,7 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
                     po.kind = op.kind == HK_PFLIPI ? 1 : 0;
                     po.group = op.bit;
                     pp.needs_slot_path = true;
+                    pp.has_flip = true;
                 } else {
                     po.type = lane ? PO_LANE : PO_REG;
                     po.kind = op.kind == HK_H ? GK_H : (op.kind == HK_X ? GK_X : GK_Y);

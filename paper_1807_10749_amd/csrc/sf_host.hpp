@@ -43,6 +43,7 @@ struct PassPlan {
     int n_nondiag = 0;
     int rescale_exp = 0;            // divide by 2^rescale_exp at the end of the pass
     bool needs_slot_path = false;   // has path-dependent terms
+    bool has_flip = false;          // has per-path flips (PO_PFLIP_*)
     // dense pass (matrix cores): a 16 x 16 block on four qubits instead of the op list
     bool dense = false;
     int bpos[4] = {0, 0, 0, 0};     // extended bit positions, ascending

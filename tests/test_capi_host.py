@@ -55,7 +55,7 @@ def test_create_circuit_validation(sf):
 
 def test_set_cut_counts_match_oracle(sf):
     for name, cfg in CONFIGS.items():
-        g = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed)
+        g = make_workload(name, n_bits=1)["gates"]
         c = sf.create_circuit(cfg.rows, cfg.cols, g)
         k = sf.set_cut(c, cfg.cut_mask())
         assert k == oracle.num_cut(cfg.n_qubits, g, cfg.cut_mask()), name

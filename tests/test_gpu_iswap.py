@@ -144,3 +144,28 @@ def test_iswap_grid6x7_sampled_paths(sf):
     a = c.amplitudes(bits, path_ids=ids)
     o = oracle.path_sum(42, g, cfg.cut_mask(), ids, bits)
     assert c11_error(a, o, ids.size, c.k, 42) <= TOL_C64
+
+
+@pytest.mark.slow
+def test_iswap_full_workload_block(sf):
+    """The iSWAP variant at its measured size (aligned block of 2^18 paths, 1e5 bitstrings,
+    default launch configuration): the block equals the sum of its quarters, and an aligned
+    1024-path sub-block matches the oracle on every bitstring."""
+    from workload import make_workload
+    w = make_workload("grid5x6_d24_iswap")
+    cfg, g, bits = w["cfg"], w["gates"], w["bitstrings"]
+    c = sf.Circuit(cfg.rows, cfg.cols, g, cfg.cut_mask())
+    begin, count = path_block(c.k, cfg.block_bits, cfg.path_seed)
+    assert (c.k, count) == (30, 1 << 18)
+    say(f"iswap 5x6 d24 full block {begin}+{count}, 1e5 bitstrings")
+    a = c.amplitudes(bits, path_begin=begin, n_paths=count)
+    q = np.zeros_like(a)
+    for i in range(4):
+        say(f"iswap 5x6 d24 quarter {i}")
+        q += c.amplitudes(bits, path_begin=begin + i * (count // 4), n_paths=count // 4)
+    assert np.abs(a - q).max() <= 1e-5 * np.abs(a).max()
+    sub = begin + 173 * 1024
+    say(f"iswap 5x6 d24 sub-block {sub}+1024 against the oracle")
+    a = c.amplitudes(bits, path_begin=sub, n_paths=1024)
+    o = oracle.path_sum(30, g, cfg.cut_mask(), np.arange(sub, sub + 1024, dtype=np.uint64), bits)
+    assert c11_error(a, o, 1024, c.k, 30) <= TOL_C64

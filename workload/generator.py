@@ -5,7 +5,7 @@ Conventions (fixed here because the paper leaves them open):
 * Qubit id on an R x C grid is ``r*C + c`` (row-major, as in the qubit-grid
   printouts of the paper's simulation logs, Appendix D).
 * Gate kinds: 0 = H, 1 = X^1/2, 2 = Y^1/2, 3 = T, 4 = CZ (Section 1 names
-  this gate set).  Records are 8 bytes: kind u8, pad u8, cycle u16, q0 u16,
+  this gate set), 5 = iSWAP (the harder variant of Section 7).  Records are 8 bytes: kind u8, pad u8, cycle u16, q0 u16,
   q1 u16 (q1 unused for one-qubit gates).
 * Cycle 0 is a layer of H on every qubit.  Cycles 1..D each apply one of
   eight CZ layouts; layout (c mod 8) is chosen so that every nearest-
@@ -200,6 +200,7 @@ class WorkloadConfig:
     circuit_seed: int = 0
     bits_seed: int = 0
     path_seed: int = 0
+    two_qubit: int = CZ     # CZ, or ISWAP for the harder variant (every CZ replaced)
 
     @property
     def n_qubits(self) -> int:
@@ -229,13 +230,18 @@ CONFIGS = {
     # 7x8, 1+40+1, 28+28 cut, one seeded aligned block of 1024 paths, 1e6 bitstrings
     "grid7x8_d40": _cfg(4, name="grid7x8_d40", rows=7, cols=8, depth=40, cut=("col", 4),
                         n_bits=1_000_000, paths="block", block_bits=10),
+    # the 5x6, 1+24+1 circuit above with every CZ an iSWAP (2 path bits per crossing gate,
+    # k = 30): one seeded aligned block of 2^18 paths, 1e5 bitstrings
+    "grid5x6_d24_iswap": WorkloadConfig(name="grid5x6_d24_iswap", rows=5, cols=6, depth=24, cut=("col", 3),
+                                        n_bits=100_000, paths="block", block_bits=18, circuit_seed=1002,
+                                        bits_seed=2002, path_seed=3005, two_qubit=ISWAP),
 }
 
 
 def make_workload(name: str, n_bits: Optional[int] = None) -> dict:
     """Gate list, cut mask and bitstrings of a named configuration."""
     cfg = CONFIGS[name]
-    gates = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed)
+    gates = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed, two_qubit=cfg.two_qubit)
     nb = cfg.n_bits if n_bits is None else n_bits
     bits = random_bitstrings(cfg.n_qubits, nb, cfg.bits_seed)
     return {"cfg": cfg, "gates": gates, "mask_a": cfg.cut_mask(), "bitstrings": bits}
