@@ -87,6 +87,7 @@ struct Launch {
     enum Kind { PASS, GATHER, DENSE, FOLD } kind;
     DenseArgs da{};
     FoldArgs fa{};
+    FoldIswapArgs fia{};          // FOLD of crossing iSWAPs
     size_t mask_off = 0;          // FOLD: element offset of the batch's child masks
     int half = 0;
     int R = 0;
@@ -148,7 +149,7 @@ int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32
     const int FD = fold_depth(c);
     // upper bound: every level resident with min(2^bits, n_paths) nodes
     size_t total = 0;
-    if (FD) total += align_up(n_paths * 4 + 64 * 4);   // descendant masks instead of folded levels
+    if (FD) total += align_up(n_paths * 8 + 64 * 8);   // descendant masks instead of folded levels
     for (int l = 0; l <= L; ++l) {
         if (l > L - FD) continue;
         const int b = c.levels[l].bits_after;
@@ -280,7 +281,8 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         if (fold) {
             // bitstrings that share their block-A bits outside the fold's S qubits read the same
             // rows of block A: visit them together
-            const uint32_t kmask = (qh[0] >= 32 ? ~0u : ((1u << qh[0]) - 1)) & ~fh[0]->smask;
+            const uint32_t kmask = (qh[0] >= 32 ? ~0u : ((1u << qh[0]) - 1)) &
+                                   ~(fh[0]->iswap ? fh[0]->qmask : fh[0]->smask);
             if ((he = launch_key(d_xa, n_bits, kmask, (uint32_t *)(wsp + off_fkey), stream)) != hipSuccess) return dev_err("key", he);
             keys = (const uint32_t *)(wsp + off_fkey);
             key_bits = __builtin_popcount(kmask);
@@ -343,7 +345,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             table_bound += 2 * tree.node[l].size() + lb[l].cap + min_slots * (l ? tree.node[l - 1].size() : 1);
         }
         table_bound = align_up(table_bound * 8) + align_up(table_bound * 4);
-        if (fold) table_bound += align_up(tree.node[fold_at].size() * 4);   // descendant masks
+        if (fold) table_bound += align_up(tree.node[fold_at].size() * 8 + 8);   // descendant masks
         size_t budget;
         if (workspace) {
             if (workspace_bytes < fixed + table_bound) { err = "workspace too small"; return SF_ERR_OOM; }
@@ -400,7 +402,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         fscale *= s;
     }
     std::vector<uint32_t> &tmaskv = PL.tmaskv;
-    std::vector<uint32_t> node_mask;     // per node of the level the fold reads (filled below)
+    std::vector<uint64_t> node_mask;     // per node of the level the fold reads (filled below)
     size_t (&fold_tab_off)[2] = PL.fold_tab_off;
     size_t &plain_mask_idx = PL.plain_mask_idx;
 
@@ -444,9 +446,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         c.stats.a_groups = a_groups;
         for (const Launch &ln : ls) {
             if (ln.kind != Launch::GATHER && ln.kind != Launch::FOLD) continue;
-            const uint64_t slots = ln.kind == Launch::FOLD ? ln.fa.n_slots : ln.ga.n_slots;
-            const uint64_t ra = ln.kind == Launch::FOLD ? uint64_t(1) << fh[0]->n_s : 1;
-            const uint64_t rb = ln.kind == Launch::FOLD ? uint64_t(1) << fh[1]->n_s : 1;
+            const bool fi = ln.kind == Launch::FOLD && fh[0]->iswap;
+            const uint64_t slots = ln.kind == Launch::FOLD ? (fi ? ln.fia.n_slots : ln.fa.n_slots) : ln.ga.n_slots;
+            // parent rows per bitstring: 2^|S| (CZ form) or 2^G (iSWAP form) per block
+            const uint64_t ra = ln.kind == Launch::FOLD ? uint64_t(1) << (fi ? fh[0]->ng : fh[0]->n_s) : 1;
+            const uint64_t rb = ln.kind == Launch::FOLD ? uint64_t(1) << (fi ? fh[1]->ng : fh[1]->n_s) : 1;
             const uint64_t per = slots * elem * (a_groups * ra + (uint64_t)n_bits * rb) + (uint64_t)n_bits * 44 +
                                  (ln.kind == Launch::FOLD ? slots * 4 : 0);
             c.stats.n_gather_launches += rounds;
@@ -562,44 +566,74 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             Launch ln;
             ln.kind = Launch::FOLD;
             ln.level = l;
-            FoldArgs &f = ln.fa;
-            std::memset(&f, 0, sizeof(f));
-            for (int h = 0; h < 2; ++h) {
-                const LeafFold &lf = *fh[h];
-                FoldHalf &d = f.h[h];
-                d.smask = lf.smask;
-                d.tmask = lf.tmask;
-                d.n_s = lf.n_s;
-                d.dsel = 0;
-                for (int u = 0; u < lf.nb; ++u) {
-                    d.bq[u] = (uint8_t)lf.bq[u];
-                    if (lf.ypos[u] >= 0) {
-                        d.sstride[u] = 1u << lf.bq[u];
-                        d.ypos[u] = (uint8_t)lf.ypos[u];
-                    } else {
-                        d.dsel |= 1u << u;
+            const int nd = 1 << fh[0]->nb;                       // descendants per node (one mask bit each)
+            const uint64_t full = nd >= 64 ? ~uint64_t(0) : (uint64_t(1) << nd) - 1;
+            bool all = true;
+            for (size_t i = 0; i < nodes.size(); ++i) all = all && node_mask[nodes[i]] == full;
+            if (fh[0]->iswap) {
+                FoldIswapArgs &f = ln.fia;
+                std::memset(&f, 0, sizeof(f));
+                for (int h = 0; h < 2; ++h) {
+                    const LeafFold &lf = *fh[h];
+                    FoldIswapHalf &d = f.h[h];
+                    d.qmask = lf.qmask;
+                    d.tmask = lf.tmask;
+                    d.n_s = lf.n_s;
+                    for (int g = 0; g < lf.ng; ++g) {
+                        d.q[g] = (uint8_t)lf.gq[g];
+                        d.ypos[g] = (int8_t)lf.gy[g];
                     }
                 }
+                for (int g = 0; g < fh[0]->ng; ++g) f.u[g] = (uint8_t)fh[0]->gu[g];
+                f.n_bits = n_bits;
+                f.n_slots = (uint32_t)nodes.size();
+                f.p = log2u(nslots);
+                f.scale_re = fscale.real();
+                f.scale_im = fscale.imag();
+                f.all_children = all && !plain ? 1 : 0;
+                // 64-bit masks, two words each (the first one 8-byte aligned)
+                if (tmaskv.size() & 1) tmaskv.push_back(0);
+                ln.mask_off = tmaskv.size();
+                if (plain) plain_mask_idx = tmaskv.size();
+                for (size_t i = 0; i < nodes.size(); ++i) {
+                    tmaskv.push_back((uint32_t)node_mask[nodes[i]]);
+                    tmaskv.push_back((uint32_t)(node_mask[nodes[i]] >> 32));
+                }
+                ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem * (uint64_t(2) << fh[0]->ng);
+            } else {
+                FoldArgs &f = ln.fa;
+                std::memset(&f, 0, sizeof(f));
+                for (int h = 0; h < 2; ++h) {
+                    const LeafFold &lf = *fh[h];
+                    FoldHalf &d = f.h[h];
+                    d.smask = lf.smask;
+                    d.tmask = lf.tmask;
+                    d.n_s = lf.n_s;
+                    d.dsel = 0;
+                    for (int u = 0; u < lf.nb; ++u) {
+                        d.bq[u] = (uint8_t)lf.bq[u];
+                        if (lf.ypos[u] >= 0) {
+                            d.sstride[u] = 1u << lf.bq[u];
+                            d.ypos[u] = (uint8_t)lf.ypos[u];
+                        } else {
+                            d.dsel |= 1u << u;
+                        }
+                    }
+                }
+                f.n_bits = n_bits;
+                f.n_slots = (uint32_t)nodes.size();
+                f.p = log2u(nslots);
+                f.scale_re = fscale.real();
+                f.scale_im = fscale.imag();
+                ln.mask_off = tmaskv.size();
+                if (plain) plain_mask_idx = tmaskv.size();
+                for (size_t i = 0; i < nodes.size(); ++i) tmaskv.push_back((uint32_t)node_mask[nodes[i]]);
+                f.all_children = all && !plain ? 1 : 0;
+                ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem *
+                           ((uint64_t(1) << fh[0]->n_s) + (uint64_t(1) << fh[1]->n_s));
             }
-            f.n_bits = n_bits;
-            f.n_slots = (uint32_t)nodes.size();
-            f.p = log2u(nslots);
-            f.scale_re = fscale.real();
-            f.scale_im = fscale.imag();
-            const int nd = 1 << fh[0]->nb;                       // descendants per node (one mask bit each)
-            const uint32_t full = nd >= 32 ? ~0u : (1u << nd) - 1;
-            bool all = true;
-            ln.mask_off = tmaskv.size();
-            if (plain) plain_mask_idx = tmaskv.size();
-            for (size_t i = 0; i < nodes.size(); ++i) {
-                tmaskv.push_back(node_mask[nodes[i]]);
-                all = all && node_mask[nodes[i]] == full;
-            }
-            f.all_children = all && !plain ? 1 : 0;
             ln.dst_off = lb[own].off[0];
             ln.src_off = lb[own].off[1];
-            ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem *
-                       ((uint64_t(1) << fh[0]->n_s) + (uint64_t(1) << fh[1]->n_s));
             launches.push_back(ln);
             ++n_leaf_batches;
             return;
@@ -681,7 +715,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         for (size_t i = 0; i < tree.node[L].size(); ++i) {
             size_t a = i;
             for (int l = L; l > fold_at; --l) a = tree.parent[l][a];
-            node_mask[a] |= 1u << (tree.node[L][i] & low);
+            node_mask[a] |= uint64_t(1) << (tree.node[L][i] & low);
         }
     }
     if (n_paths && fold && !hit) {
@@ -716,7 +750,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             }
         }
         // planning only: every bitstring its own block-A group unless there are fewer rows
-        const int kb = fold ? qh[0] - fh[0]->n_s : qh[0];
+        const int kb = fold ? qh[0] - (fh[0]->iswap ? __builtin_popcount(fh[0]->qmask) : fh[0]->n_s) : qh[0];
         account_gather(launches, rounds, std::min<uint64_t>(n_bits, kb >= 32 ? n_bits : (uint64_t(1) << kb)));
         c.stats.n_batches = n_leaf_batches * rounds;
         return SF_OK;
@@ -797,7 +831,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 const uint64_t v = drop >= 64 ? 0 : ((pid >> drop) << drop);
                 for (uint64_t i = 0; i < b.slots; ++i) tpath[b.table_off + i] = v;
             }
-            if (plain_mask_idx != SIZE_MAX) tmaskv[plain_mask_idx] = 1u << (pid & ((uint64_t(1) << fh[0]->nb) - 1));
+            if (plain_mask_idx != SIZE_MAX) {
+                const uint64_t m = uint64_t(1) << (pid & ((uint64_t(1) << fh[0]->nb) - 1));
+                tmaskv[plain_mask_idx] = (uint32_t)m;
+                if (fh[0]->iswap) tmaskv[plain_mask_idx + 1] = (uint32_t)(m >> 32);
+            }
             // the previous path's launches must be done with the old tables
             if ((he = hipStreamSynchronize(stream)) != hipSuccess) return dev_err("sync", he);
             if ((he = hipMemcpy(ws + off_tpath, tpath.data(), tpath.size() * 8, hipMemcpyHostToDevice)) != hipSuccess) return dev_err("copy tables", he);
@@ -836,6 +874,18 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 if ((he = launch_pass(fp64, ln.R, ln.flip, a, ln.grid, stream)) != hipSuccess) return dev_err("pass", he);
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;
+            } else if (ln.kind == Launch::FOLD && fh[0]->iswap) {
+                FoldIswapArgs f = ln.fia;
+                f.h[0].par = buf + ln.dst_off;
+                f.h[1].par = buf + ln.src_off;
+                for (int h = 0; h < 2; ++h) f.h[h].tab = (const double *)(ws + off_blob + fold_tab_off[h]);
+                f.xa = d_xa;
+                f.xb = d_xb;
+                f.order = d_order;
+                f.acc = d_acc;
+                f.child_mask = (const uint64_t *)((const uint32_t *)(ws + off_tmask) + ln.mask_off);
+                timed(1);
+                if ((he = launch_fold_iswap(fp64, fh[0]->ng, f, stream)) != hipSuccess) return dev_err("fold", he);
             } else if (ln.kind == Launch::FOLD) {
                 FoldArgs f = ln.fa;
                 f.h[0].par = buf + ln.dst_off;

@@ -778,6 +778,154 @@ hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
+// amp[j] += scale * sum_{slot < n_slots} sum_{descendants (i, j') requested}
+//            V_A(i) row_A(j') V_B(j') row_B(i) i^{popcount(i ^ j')}
+// with the terms of FoldIswapArgs.  Per slot, a[i] = V_A(i) row_B(i) and b[j'] = row_A(j') V_B(j')
+// are formed (2^G values each, from 2 x 2^G rows); with every descendant requested the double
+// sum is a^T (M x ... x M) b with M = [[1, i], [i, 1]] per gate, one butterfly stage per gate.
+// Lane layout (WIDE or not) as in fold_kernel; the products and sums are in FP64.
+template <typename T, int G, bool WIDE, bool MASKED>
+__global__ __launch_bounds__(256) void fold_iswap_kernel(FoldIswapArgs g)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int NI = 1 << G;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t P = 1u << g.p;
+    const uint32_t L = WIDE ? 64u : P;
+    const uint32_t GB = 64u / L;
+    const uint64_t wave = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 4u + wid;
+    const uint64_t jj = wave * GB + (uint32_t)lane / L;
+    const uint32_t sl = (uint32_t)lane % L;
+    uint64_t j = jj < g.n_bits ? (uint64_t)g.order[jj] : g.n_bits;
+    if (WIDE) {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)j);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(j >> 32));
+        j = ((uint64_t)hi << 32) | lo;
+    }
+    double re = 0.0, im = 0.0;
+    if (j < g.n_bits) {
+        const C *base[2];
+        C vv[2][NI];                  // V_h(t)
+        uint32_t off[2][NI];          // row offsets (in rows) of pattern t
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const FoldIswapHalf &f = g.h[h];
+            const uint32_t x = h ? g.xb[j] : g.xa[j];
+            base[h] = (const C *)f.par + ((uint64_t)(x & ~f.qmask) << g.p);
+            const double *tr = f.tab + 2 * ((uint64_t)pext32(x, f.tmask) << f.n_s);
+#pragma unroll
+            for (int t = 0; t < NI; ++t) {
+                bool ok = true;
+                uint32_t y = 0, o = 0;
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) {
+                    const uint32_t b = (uint32_t)(t >> gg) & 1u;
+                    if (f.ypos[gg] >= 0) y |= b << f.ypos[gg];
+                    else ok = ok && ((x >> f.q[gg]) & 1u) == b;
+                    o |= b << f.q[gg];
+                }
+                vv[h][t].x = ok ? (T)tr[2 * y] : T(0);
+                vv[h][t].y = ok ? (T)tr[2 * y + 1] : T(0);
+                off[h][t] = o;
+            }
+        }
+        uint32_t vi[NI], vj[NI];      // descendant index bits of an i pattern / a j pattern
+#pragma unroll
+        for (int t = 0; t < NI; ++t) {
+            vi[t] = vj[t] = 0;
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) {
+                vi[t] |= (uint32_t)((t >> gg) & 1) << (g.u[gg] + 1);
+                vj[t] |= (uint32_t)((t >> gg) & 1) << g.u[gg];
+            }
+        }
+        for (uint32_t s = sl; s < g.n_slots; s += L) {
+            double ar[NI], ai[NI], br[NI], bi[NI];
+#pragma unroll
+            for (int t = 0; t < NI; ++t) {
+                const C rb = base[1][((uint64_t)off[1][t] << g.p) + s];    // row_B(i = t)
+                const C ra = base[0][((uint64_t)off[0][t] << g.p) + s];    // row_A(j = t)
+                const C va = vv[0][t], vb = vv[1][t];
+                ar[t] = (double)(va.x * rb.x - va.y * rb.y);
+                ai[t] = (double)(va.x * rb.y + va.y * rb.x);
+                br[t] = (double)(vb.x * ra.x - vb.y * ra.y);
+                bi[t] = (double)(vb.x * ra.y + vb.y * ra.x);
+            }
+            if (!MASKED) {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+                    for (int t = 0; t < NI; ++t)
+                        if (!(t & (1 << gg))) {
+                            const int t1 = t | (1 << gg);
+                            const double r0 = br[t], i0 = bi[t], r1 = br[t1], i1 = bi[t1];
+                            br[t] = r0 - i1;  bi[t] = i0 + r1;      // b0 + i b1
+                            br[t1] = r1 - i0; bi[t1] = i1 + r0;     // i b0 + b1
+                        }
+#pragma unroll
+                for (int t = 0; t < NI; ++t) {
+                    re += ar[t] * br[t] - ai[t] * bi[t];
+                    im += ar[t] * bi[t] + ai[t] * br[t];
+                }
+            } else {
+                const uint64_t m = g.child_mask[s];
+#pragma unroll
+                for (int ti = 0; ti < NI; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < NI; ++tj) {
+                        double pr = ar[ti] * br[tj] - ai[ti] * bi[tj];
+                        double pi = ar[ti] * bi[tj] + ai[ti] * br[tj];
+                        const int e = __popc((uint32_t)(ti ^ tj)) & 3;     // times i^e
+                        if (e & 1) { const double tmp = pr; pr = -pi; pi = tmp; }
+                        if (e & 2) { pr = -pr; pi = -pi; }
+                        const bool use = (m >> (vi[ti] | vj[tj])) & 1u;
+                        re += use ? pr : 0.0;
+                        im += use ? pi : 0.0;
+                    }
+            }
+        }
+    }
+    for (uint32_t mm = 1; mm < L; mm <<= 1) {
+        re += __shfl_xor(re, (int)mm);
+        im += __shfl_xor(im, (int)mm);
+    }
+    if (j < g.n_bits && sl == 0) {
+        double *o = g.acc + 2 * j;
+        o[0] += g.scale_re * re - g.scale_im * im;
+        o[1] += g.scale_re * im + g.scale_im * re;
+    }
+}
+
+template <typename T, int G>
+static void fold_iswap_launch(const FoldIswapArgs &g, unsigned blocks, bool wide, hipStream_t s)
+{
+    if (g.all_children) {
+        if (wide) fold_iswap_kernel<T, G, true, false><<<blocks, 256, 0, s>>>(g);
+        else fold_iswap_kernel<T, G, false, false><<<blocks, 256, 0, s>>>(g);
+    } else {
+        if (wide) fold_iswap_kernel<T, G, true, true><<<blocks, 256, 0, s>>>(g);
+        else fold_iswap_kernel<T, G, false, true><<<blocks, 256, 0, s>>>(g);
+    }
+}
+
+hipError_t launch_fold_iswap(bool fp64, int G, const FoldIswapArgs &g, hipStream_t s)
+{
+    if (g.n_bits == 0) return hipSuccess;
+    if (G < 1 || G > 3 || g.p < 0 || g.p > 31 || !g.order || !g.child_mask) return hipErrorInvalidValue;
+    const uint64_t P = (uint64_t)1 << g.p;
+    const bool wide = P >= 64;
+    const uint64_t per_wave = wide ? 1 : 64 / P;
+    const uint64_t waves = (g.n_bits + per_wave - 1) / per_wave;
+    const unsigned blocks = (unsigned)(((waves + 3) / 4 + 7) / 8 * 8);   // a multiple of 8 (xcd_block)
+    switch (G) {
+    case 1: fp64 ? fold_iswap_launch<double, 1>(g, blocks, wide, s) : fold_iswap_launch<float, 1>(g, blocks, wide, s); break;
+    case 2: fp64 ? fold_iswap_launch<double, 2>(g, blocks, wide, s) : fold_iswap_launch<float, 2>(g, blocks, wide, s); break;
+    default: fp64 ? fold_iswap_launch<double, 3>(g, blocks, wide, s) : fold_iswap_launch<float, 3>(g, blocks, wide, s); break;
+    }
+    return hipGetLastError();
+}
+
 // key[i] = pext(x[i], mask): visiting key of the leaf fold (bitstrings that share their block-A
 // bits outside the fold's S qubits read the same parent rows)
 __global__ void key_kernel(const uint32_t *x, uint64_t n, uint32_t mask, uint32_t *key)

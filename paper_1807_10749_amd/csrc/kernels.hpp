@@ -27,6 +27,8 @@ hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s);
 // FoldArgs); nb = path bits decided by the folded levels (1..5).  g.order and g.child_mask must
 // be given.
 hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s);
+// Fold of G (1..3) trailing crossing iSWAPs into the gather (FoldIswapArgs).
+hipError_t launch_fold_iswap(bool fp64, int G, const FoldIswapArgs &g, hipStream_t s);
 
 // key[i] = pext(x[i], mask) (32-bit).
 hipError_t launch_key(const uint32_t *x, uint64_t n, uint32_t mask, uint32_t *key, hipStream_t s);

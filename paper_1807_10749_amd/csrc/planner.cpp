@@ -31,59 +31,20 @@ namespace {
 void gate2x2(uint8_t kind, std::complex<double> g[4]);
 }  // namespace
 
-// The last F tree levels of block h as V * D(b) (see LeafFold).  Their segments, in order, are
-// applied to the state of the level above; the branch operators are diagonal, so each one can
-// be moved to the right of every earlier gate of these segments that is diagonal or acts on
-// other qubits.  The form holds when no non-diagonal gate precedes a branch operator on its
-// qubit, and it is used when every non-diagonal gate of the segments acts on a branch qubit
-// (then a descendant reads no more rows of the level above than it has branch values).  V is
-// multiplied out exactly with the normalised gates.
-static LeafFold make_fold(const Circuit &c, int h, int F)
+// <x_T| V |x_T with the S bits replaced by y> for the ops `rest` (V, in order) on the qubits of
+// tmask, as a [2^|T|][2^|S|] table; V is multiplied out exactly with the normalised gates.
+static std::vector<std::complex<double>> fold_table(const std::vector<HalfOp> &rest, uint32_t tmask, uint32_t smask)
 {
-    LeafFold f;
-    const int L = (int)c.levels.size() - 1;
-    if (F < 1 || F > L) return f;
-    const int nb = c.k - c.levels[L - F].bits_after;     // path bits decided by the F levels
-    if (nb < 1 || nb > kMaxFoldBits) return f;
-    int bq[kMaxFoldBits];
-    for (int u = 0; u < kMaxFoldBits; ++u) bq[u] = -1;  // local qubit of the branch operator of path bit u
-    uint32_t nondiag_seen = 0, smask = 0, tmask = 0;
-    std::vector<HalfOp> rest;
-    for (int l = L - F + 1; l <= L; ++l)
-        for (const HalfOp &op : c.half[h].segments[l]) {
-            if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) return f;   // a branch operator that is not diagonal
-            if (op.kind == HK_PROJ || op.kind == HK_ZCTL) {
-                if (op.bit >= nb || bq[op.bit] >= 0 || op.q0 >= 32 || ((nondiag_seen >> op.q0) & 1)) return f;
-                bq[op.bit] = op.q0;
-                continue;
-            }
-            if (op.q0 >= 32 || (op.kind == HK_CZ && op.q1 >= 32)) return f;
-            if (!is_diag(op.kind)) {
-                nondiag_seen |= 1u << op.q0;
-                smask |= 1u << op.q0;
-            }
-            tmask |= 1u << op.q0;
-            if (op.kind == HK_CZ) tmask |= 1u << op.q1;
-            rest.push_back(op);
-        }
-    uint32_t bmask = 0;
-    for (int u = 0; u < nb; ++u) {
-        if (bq[u] < 0) return f;
-        bmask |= 1u << bq[u];
-    }
-    if ((smask & ~bmask) != 0) return f;            // a non-diagonal gate off the branch qubits
-    const int n_t = __builtin_popcount(tmask), n_s = __builtin_popcount(smask);
-    if (n_t > 8) return f;
-    // T-local index of each local qubit in T, S-local index of each qubit in S
+    const int n_s = __builtin_popcount(smask);
     int tpos[32], spos[32];
     for (int t = 0, a = 0, b = 0; t < 32; ++t) {
         tpos[t] = ((tmask >> t) & 1) ? a++ : -1;
         spos[t] = ((smask >> t) & 1) ? b++ : -1;
     }
     // V as a 2^n_t x 2^n_t matrix, column by column
-    const int D = 1 << n_t;
+    const int D = 1 << __builtin_popcount(tmask);
     std::vector<std::complex<double>> M((size_t)D * D);
-    const std::complex<double> I(0, 1), omega(std::cos(M_PI / 4), std::sin(M_PI / 4));
+    const std::complex<double> omega(std::cos(M_PI / 4), std::sin(M_PI / 4));
     const std::complex<double> s_h(1.0 / std::sqrt(2.0), 0.0), s_xy(0.5, 0.5);
     for (int col = 0; col < D; ++col) {
         std::vector<std::complex<double>> v(D, 0.0);
@@ -111,7 +72,7 @@ static LeafFold make_fold(const Circuit &c, int h, int F)
         for (int r = 0; r < D; ++r) M[(size_t)r * D + col] = v[r];
     }
     // table row x_T, entry y: column = x_T with its S bits replaced by y
-    f.tab.assign((size_t)D << n_s, 0.0);
+    std::vector<std::complex<double>> tab((size_t)D << n_s, 0.0);
     for (int xt = 0; xt < D; ++xt)
         for (int y = 0; y < (1 << n_s); ++y) {
             int col = xt;
@@ -120,8 +81,61 @@ static LeafFold make_fold(const Circuit &c, int h, int F)
                     const int bit = (y >> spos[t]) & 1;
                     col = (col & ~(1 << tpos[t])) | (bit << tpos[t]);
                 }
-            f.tab[((size_t)xt << n_s) + y] = M[(size_t)xt * D + col];
+            tab[((size_t)xt << n_s) + y] = M[(size_t)xt * D + col];
         }
+    return tab;
+}
+
+static LeafFold make_fold_iswap(const Circuit &c, int h, int F);
+
+// The last F tree levels of block h as V * D(b) (see LeafFold).  Their segments, in order, are
+// applied to the state of the level above; the branch operators are diagonal, so each one can
+// be moved to the right of every earlier gate of these segments that is diagonal or acts on
+// other qubits.  The form holds when no non-diagonal gate precedes a branch operator on its
+// qubit, and it is used when every non-diagonal gate of the segments acts on a branch qubit
+// (then a descendant reads no more rows of the level above than it has branch values).  V is
+// multiplied out exactly with the normalised gates.
+static LeafFold make_fold(const Circuit &c, int h, int F)
+{
+    LeafFold f;
+    const int L = (int)c.levels.size() - 1;
+    if (F < 1 || F > L) return f;
+    for (int l = L - F + 1; l <= L; ++l)
+        for (const HalfOp &op : c.half[h].segments[l])
+            if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) return make_fold_iswap(c, h, F);
+    const int nb = c.k - c.levels[L - F].bits_after;     // path bits decided by the F levels
+    if (nb < 1 || nb > kMaxFoldBits) return f;
+    int bq[kMaxFoldBits];
+    for (int u = 0; u < kMaxFoldBits; ++u) bq[u] = -1;  // local qubit of the branch operator of path bit u
+    uint32_t nondiag_seen = 0, smask = 0, tmask = 0;
+    std::vector<HalfOp> rest;
+    for (int l = L - F + 1; l <= L; ++l)
+        for (const HalfOp &op : c.half[h].segments[l]) {
+            if (op.kind == HK_PROJ || op.kind == HK_ZCTL) {
+                if (op.bit >= nb || bq[op.bit] >= 0 || op.q0 >= 32 || ((nondiag_seen >> op.q0) & 1)) return f;
+                bq[op.bit] = op.q0;
+                continue;
+            }
+            if (op.q0 >= 32 || (op.kind == HK_CZ && op.q1 >= 32)) return f;
+            if (!is_diag(op.kind)) {
+                nondiag_seen |= 1u << op.q0;
+                smask |= 1u << op.q0;
+            }
+            tmask |= 1u << op.q0;
+            if (op.kind == HK_CZ) tmask |= 1u << op.q1;
+            rest.push_back(op);
+        }
+    uint32_t bmask = 0;
+    for (int u = 0; u < nb; ++u) {
+        if (bq[u] < 0) return f;
+        bmask |= 1u << bq[u];
+    }
+    if ((smask & ~bmask) != 0) return f;            // a non-diagonal gate off the branch qubits
+    const int n_t = __builtin_popcount(tmask), n_s = __builtin_popcount(smask);
+    if (n_t > 8) return f;
+    f.tab = fold_table(rest, tmask, smask);
+    int spos[32];
+    for (int t = 0, b = 0; t < 32; ++t) spos[t] = ((smask >> t) & 1) ? b++ : -1;
     for (int u = 0; u < nb; ++u) {
         f.bq[u] = bq[u];
         f.ypos[u] = spos[bq[u]];
@@ -137,6 +151,81 @@ static LeafFold make_fold(const Circuit &c, int h, int F)
     return f;
 }
 
+// The last F tree levels of block h when all their crossing gates are iSWAPs.  Gate g's branch
+// operators on this block are a projector and a per-path flip on one qubit (X^{i xor j} P_j on
+// block A, i^{i xor j} X^{i xor j} P_i on block B; the factor i^{i xor j} is left to the kernel).
+// The form holds when they are the first operations on their qubit within these levels; every
+// other operation is part of V, and every non-diagonal one must act on a gate qubit.
+static LeafFold make_fold_iswap(const Circuit &c, int h, int F)
+{
+    LeafFold f;
+    const int L = (int)c.levels.size() - 1;
+    const int nb = c.k - c.levels[L - F].bits_after;
+    if (nb < 2 || nb > 2 * kMaxFoldGates || (nb & 1)) return f;
+    int proj_bit[32];
+    for (int q = 0; q < 32; ++q) proj_bit[q] = -1;        // PROJ seen, its flip not yet
+    uint32_t seen = 0, covered = 0, qmask = 0, smask = 0, tmask = 0;
+    int ng = 0, gq[kMaxFoldGates], gu[kMaxFoldGates];
+    std::vector<HalfOp> rest;
+    for (int l = L - F + 1; l <= L; ++l)
+        for (const HalfOp &op : c.half[h].segments[l]) {
+            if (op.q0 >= 32 || (op.kind == HK_CZ && op.q1 >= 32)) return f;
+            const uint32_t m0 = 1u << op.q0;
+            if (op.kind == HK_ZCTL) return f;
+            if (op.kind == HK_PROJ) {
+                if (seen & m0) return f;
+                proj_bit[op.q0] = op.bit;
+                seen |= m0;
+                continue;
+            }
+            if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) {
+                const int u = op.bit;
+                const bool want_b = h == 1;
+                if ((op.kind == HK_PFLIPI) != want_b || u + 1 >= nb) return f;
+                if (proj_bit[op.q0] != (want_b ? u + 1 : u)) return f;
+                if ((covered >> u) & 3u) return f;
+                if (ng == kMaxFoldGates) return f;
+                covered |= 3u << u;
+                qmask |= m0;
+                gq[ng] = op.q0;
+                gu[ng] = u;
+                ++ng;
+                proj_bit[op.q0] = -2;
+                continue;
+            }
+            const uint32_t m = m0 | (op.kind == HK_CZ ? 1u << op.q1 : 0u);
+            for (int q = 0; q < 32; ++q)
+                if (((m >> q) & 1) && proj_bit[q] >= 0) return f;   // between a projector and its flip
+            if (!is_diag(op.kind)) smask |= m0;
+            tmask |= m;
+            seen |= m;
+            rest.push_back(op);
+        }
+    if (covered != (nb >= 32 ? ~0u : (1u << nb) - 1)) return f;
+    if ((smask & ~qmask) != 0) return f;            // a non-diagonal gate off the gate qubits
+    const int n_t = __builtin_popcount(tmask);
+    if (n_t > 8) return f;
+    f.tab = fold_table(rest, tmask, smask);
+    int spos[32];
+    for (int t = 0, b = 0; t < 32; ++t) spos[t] = ((smask >> t) & 1) ? b++ : -1;
+    f.iswap = true;
+    f.ng = ng;
+    for (int g = 0; g < ng; ++g) {
+        f.gq[g] = gq[g];
+        f.gu[g] = gu[g];
+        f.gy[g] = spos[gq[g]];
+    }
+    f.qmask = qmask;
+    f.levels = F;
+    f.nb = nb;
+    f.n_s = __builtin_popcount(smask);
+    f.n_t = n_t;
+    f.smask = smask;
+    f.tmask = tmask;
+    f.ok = true;
+    return f;
+}
+
 int fold_depth(const Circuit &c)
 {
     if (c.tuning.no_leaf_fold) return 0;
@@ -144,7 +233,8 @@ int fold_depth(const Circuit &c)
     const int n = (int)std::min(c.half[0].folds.size(), c.half[1].folds.size());
     for (int F = 1; F <= n; ++F) {
         if (c.tuning.fold_levels && F > (int)c.tuning.fold_levels) break;
-        if (c.half[0].folds[F - 1].ok && c.half[1].folds[F - 1].ok) best = F;
+        const LeafFold &a = c.half[0].folds[F - 1], &b = c.half[1].folds[F - 1];
+        if (a.ok && b.ok && a.iswap == b.iswap) best = F;
     }
     return best;
 }

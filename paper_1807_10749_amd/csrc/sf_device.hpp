@@ -152,4 +152,36 @@ struct FoldArgs {
     double scale_re, scale_im;
 };
 
+// Fold of trailing levels whose crossing gates are all iSWAPs (G of them, Eq. (4way)).  Gate g
+// decides path bits u[g] (j) and u[g]+1 (i) of the descendant; block A takes |i><j| = X^{i^j} P_j
+// and block B G_ij = i^{i^j} X^{i^j} P_i on qubit q[g].  For a block, a pattern t of G bits (bit g
+// = the branch value feeding V's column: i on A, j on B; the parent row takes the other value,
+// written r below) gives
+//   V_h(t) = [ x at q[g] equals t_g for every g outside S ] * tab[pext(x, tmask) * 2^n_s + y(t)],
+//   row_h(r) = parent_h[(x & ~qmask) | sum_g r_g << q[g]][slot],
+// and the descendant (i, j) adds V_A(i) row_A(j) * V_B(j) row_B(i) * i^{popcount(i ^ j)}.
+struct FoldIswapHalf {
+    const void *par;              // states of the block at level L-F, 2^(p+q) complex
+    const double *tab;            // complex (re, im) table of V, [2^|T|][2^n_s]
+    uint32_t qmask, tmask;        // local qubits of the gates, of T (all of V)
+    int32_t n_s;
+    uint8_t q[4];                 // local qubit of gate g
+    int8_t ypos[4];               // S index of q[g], -1 if q[g] is outside S
+    uint32_t pad;
+};
+
+struct FoldIswapArgs {
+    FoldIswapHalf h[2];
+    const uint32_t *xa, *xb;      // per bitstring: x_A, x_B
+    const uint32_t *order;        // visiting order of the bitstrings
+    const uint64_t *child_mask;   // per parent slot: bit v set if descendant v is requested
+    double *acc;                  // 2 * n_bits doubles, accumulated
+    uint64_t n_bits;
+    uint32_t n_slots;             // real parent slots (<= 2^p)
+    int32_t p;                    // parent slot bits
+    int32_t all_children;         // 1: every parent slot has all descendants (masks not read)
+    uint8_t u[4];                 // lower path bit of gate g among the folded bits
+    double scale_re, scale_im;
+};
+
 }  // namespace sf

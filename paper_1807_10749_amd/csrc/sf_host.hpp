@@ -58,6 +58,8 @@ struct SegmentPlan {
 
 // Most path bits the folded levels may decide (virtual slots per parent slot = 2^bits).
 constexpr int kMaxFoldBits = 5;
+// Most crossing iSWAPs the folded levels may hold (two path bits each).
+constexpr int kMaxFoldGates = 3;
 
 // The last F tree levels of one block written as V * D(b): D(b) = their branch operators for
 // descendant branch value b (diagonal), V = the block's remaining gates of those levels
@@ -74,6 +76,14 @@ struct LeafFold {
     int bq[kMaxFoldBits] = {0};                 // local qubit of the branch operator of path bit u
     int ypos[kMaxFoldBits] = {0};               // its index in S (-1 if outside S)
     std::vector<std::complex<double>> tab;      // [2^n_t][2^n_s]: <x_T| V |x_T with S bits := y>
+    // iSWAP form (every branch operator a crossing iSWAP's projector + per-path flip): gate g
+    // decides path bits gu[g] (j) and gu[g]+1 (i); its branch operators act on local qubit gq[g],
+    // which feeds V's column with the branch value after the flip (index gy[g] in S, -1 if outside
+    // S) and is read from the parent row with the value before it.  bq / ypos / dmask are unused.
+    bool iswap = false;
+    int ng = 0;
+    int gq[kMaxFoldGates] = {0}, gu[kMaxFoldGates] = {0}, gy[kMaxFoldGates] = {0};
+    uint32_t qmask = 0;                         // the gates' qubits (bits the parent row takes from the branch)
 };
 
 struct HalfProgram {

@@ -396,7 +396,8 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
                 s += " A " + std::to_string(c->half[0].segments[l].size()) + " ops, B " +
                      std::to_string(c->half[1].segments[l].size()) + " ops folded into the gather";
                 if (l == L)
-                    s += " (" + std::to_string(FD) + " levels, branch bits " + std::to_string(f0.nb) + "; A: S " +
+                    s += " (" + std::to_string(FD) + " levels, branch bits " + std::to_string(f0.nb) +
+                         (f0.iswap ? ", " + std::to_string(f0.ng) + " iSWAP gates" : std::string()) + "; A: S " +
                          std::to_string(f0.n_s) + " qubits, T " + std::to_string(f0.n_t) + "; B: S " +
                          std::to_string(f1.n_s) + " qubits, T " + std::to_string(f1.n_t) + ")";
                 s += "\n";

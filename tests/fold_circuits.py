@@ -63,3 +63,17 @@ def two_level_tail_circuit(depth=8, seed=5):
     for r in range(rows):
         mask_a |= (1 << q(r, 0)) | (1 << q(r, 1))
     return rows, cols, np.array(gates, dtype=GATE_DTYPE), mask_a
+
+
+def iswap_tail_circuit(drop_final_h=()):
+    """2 x 4 grid, cut between columns 1 and 2, whose last two cycles each hold one crossing
+    iSWAP (rows 0 and 1) after in-block iSWAPs and one-qubit gates: both trailing tree levels
+    can be folded (two iSWAP gates).  Qubits in drop_final_h get no closing H, so their
+    branch operators are not followed by a non-diagonal gate."""
+    from workload import GATE_DTYPE, H, XH, YH, T, ISWAP, column_cut_mask
+    g = [(H, 0, 0, q, 0) for q in range(8)]
+    g += [(ISWAP, 0, 1, 0, 4), (ISWAP, 0, 1, 3, 7)] + [(T, 0, 1, q, 0) for q in (1, 2, 5, 6)]
+    g += [(ISWAP, 0, 2, 1, 2), (XH, 0, 2, 0, 0), (YH, 0, 2, 4, 0), (T, 0, 2, 3, 0)]
+    g += [(ISWAP, 0, 3, 5, 6), (T, 0, 3, 0, 0), (XH, 0, 3, 7, 0)]
+    g += [(H, 0, 4, q, 0) for q in range(8) if q not in drop_final_h]
+    return 2, 4, np.array(g, dtype=GATE_DTYPE), column_cut_mask(2, 4, 2)

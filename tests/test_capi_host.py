@@ -72,7 +72,11 @@ def test_iswap_path_bits(sf):
         c = sf.create_circuit(cfg.rows, cfg.cols, g)
         if 2 * kcz <= 62:
             assert sf.set_cut(c, cfg.cut_mask()) == 2 * kcz, name
-            assert "folded" not in sf.describe_plan(c)      # per-path flips are not diagonal
+            plan = sf.describe_plan(c)
+            if cfg.rows * cfg.cols == 30:       # three crossing iSWAPs in the last cycle: folded
+                assert "1 levels, branch bits 6, 3 iSWAP gates; A: S 3 qubits, T 3; B: S 3 qubits, T 3" in plan
+            else:                               # four or more: not folded
+                assert "folded" not in plan, name
         else:
             with pytest.raises(sf.SFError) as e:
                 sf.set_cut(c, cfg.cut_mask())
@@ -205,6 +209,15 @@ def test_leaf_fold_eligibility(sf):
              (crossing_tail_circuit(rows=4), "1 levels, branch bits 4; A: S 3 qubits, T 4; B: S 2 qubits, T 3"),
              (two_level_tail_circuit(), "2 levels, branch bits 4; A: S 3 qubits, T 4; B: S 2 qubits, T 3")]
     for (r, cc, g, m), want in cases:
+        c = sf.create_circuit(r, cc, g)
+        sf.set_cut(c, m)
+        assert want in sf.describe_plan(c)
+        sf.destroy_circuit(c)
+    # crossing iSWAPs: projector + per-path flip; a qubit without a later gate stays outside S
+    from fold_circuits import iswap_tail_circuit
+    for drop, want in [((), "2 levels, branch bits 4, 2 iSWAP gates; A: S 2 qubits, T 2; B: S 2 qubits, T 2"),
+                       ((5, 2), "2 levels, branch bits 4, 2 iSWAP gates; A: S 1 qubits, T 1; B: S 1 qubits, T 1")]:
+        r, cc, g, m = iswap_tail_circuit(drop)
         c = sf.create_circuit(r, cc, g)
         sf.set_cut(c, m)
         assert want in sf.describe_plan(c)

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from parity_tol import TOL_C128, TOL_C64, c11_error
+from fold_circuits import iswap_tail_circuit
 from workload import CONFIGS, CZ, ISWAP, column_cut_mask, grid_circuit, path_block, random_bitstrings
 
 pytestmark = pytest.mark.gpu
@@ -169,3 +170,48 @@ def test_iswap_full_workload_block(sf):
     a = c.amplitudes(bits, path_begin=sub, n_paths=1024)
     o = oracle.path_sum(30, g, cfg.cut_mask(), np.arange(sub, sub + 1024, dtype=np.uint64), bits)
     assert c11_error(a, o, 1024, c.k, 30) <= TOL_C64
+
+
+# ---------------------------------------------------------------- trailing iSWAP levels folded into the gather
+
+@pytest.mark.parametrize("shape", [(3, 4, 6, 1), (3, 5, 10, 2), (2, 6, 16, 1), (3, 6, 16, 2)])
+@pytest.mark.parametrize("fp64", [True, False])
+def test_iswap_fold_small_grids(sf, shape, fp64):
+    r, cc, d, seed = shape
+    g = grid_circuit(r, cc, d, seed, two_qubit=ISWAP)
+    m = column_cut_mask(r, cc, cc // 2)
+    c = sf.Circuit(r, cc, g, m)
+    assert "iSWAP gates" in sf.describe_plan(c.handle)
+    n = r * cc
+    bits = np.arange(1 << n, dtype=np.uint64)[:: max(1, (1 << n) // 4096)]
+    flags = sf.SF_FP64_SWEEPS if fp64 else 0
+    say(f"iswap fold {shape} fp64={fp64} k={c.k}")
+    a = c.amplitudes(bits, flags=flags)
+    o = oracle.path_sum(n, g, m, np.arange(1 << c.k, dtype=np.uint64), bits)
+    assert c11_error(a, o, 1 << c.k, c.k, n) <= (TOL_C128 if fp64 else TOL_C64)
+    c.tune(no_leaf_fold=1)
+    b = c.amplitudes(bits, flags=flags)
+    assert c11_error(b, o, 1 << c.k, c.k, n) <= (TOL_C128 if fp64 else TOL_C64)
+
+
+@pytest.mark.parametrize("drop", [(), (5, 2), (1, 6)])
+def test_iswap_fold_two_levels(sf, drop):
+    """Two folded levels, gate qubits inside and outside S; all paths, every single path (the
+    masked form), scattered subsets and the one-path-at-a-time form."""
+    r, cc, g, m = iswap_tail_circuit(drop)
+    c = sf.Circuit(r, cc, g, m)
+    assert "2 levels" in sf.describe_plan(c.handle)
+    bits = np.arange(256, dtype=np.uint64)
+    say(f"iswap two-level fold drop={drop} all paths")
+    a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS)
+    assert c11_error(a, oracle.full_state(8, g), 1, 0, 8) <= TOL_C128
+    for p in range(1 << c.k):
+        a = c.amplitudes(bits, path_begin=p, n_paths=1, flags=sf.SF_FP64_SWEEPS)
+        o = oracle.path_sum(8, g, m, [p], bits)
+        assert c11_error(a, o, 1, c.k, 8) <= TOL_C128, p
+    ids = np.array([1, 2, 7, 8, 13, 14], dtype=np.uint64)
+    say(f"iswap two-level fold drop={drop} subsets, plain")
+    o = oracle.path_sum(8, g, m, ids, bits)
+    for flags in (0, sf.SF_FP64_SWEEPS, sf.SF_PLAIN):
+        a = c.amplitudes(bits, path_ids=ids, flags=flags)
+        assert c11_error(a, o, ids.size, c.k, 8) <= (TOL_C128 if flags == sf.SF_FP64_SWEEPS else TOL_C64), flags
