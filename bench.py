@@ -136,9 +136,13 @@ def main():
     amps_per_s = bits.size * args.steps / elapsed
 
     # dominant kernel category by measured time
-    folded = "folded" in sf.describe_plan(c.handle)
+    plan_text = sf.describe_plan(c.handle)
+    folded = "folded" in plan_text
     if sweep_ms >= gather_ms:
         dom, dom_ms, dom_n, dom_bytes = "pass_kernel (gate sweep)", sweep_ms, sweep_launches, sweep_bytes
+    elif folded and "iSWAP gates" in plan_text:
+        dom, dom_ms, dom_n, dom_bytes = ("fold_iswap_kernel (last levels + path sum)", gather_ms, gather_launches,
+                                         gather_bytes)
     elif folded:
         dom, dom_ms, dom_n, dom_bytes = "fold_kernel (last level + path sum)", gather_ms, gather_launches, gather_bytes
     else:
