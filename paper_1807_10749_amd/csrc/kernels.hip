@@ -125,9 +125,10 @@ __device__ __forceinline__ void lane_gate(int b, int kind, int lane, C (&v)[1 <<
 
 // ---------------------------------------------------------------- per-path flips
 
-// Swap the pairs of register qubit K where f (this lane's slot) is set.  Each pair passes through
-// an empty asm statement first: without it the compiler merges the cases of reg_flip_dispatch
-// into one access of v with a computed index, which moves v out of registers into scratch memory.
+// Swap the pairs of register qubit K where f (this lane's slot) is set.  The empty asm statement
+// with K as an operand ends every case of reg_flip_dispatch with an instruction the compiler
+// cannot merge across cases; otherwise it sinks the cases' identical selects into one access of
+// v with a computed index, which moves v out of registers into scratch memory.
 template <int K, int R, typename C>
 __device__ __forceinline__ void reg_flip(bool f, C (&v)[1 << R])
 {
@@ -136,11 +137,11 @@ __device__ __forceinline__ void reg_flip(bool f, C (&v)[1 << R])
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         if (j & B) continue;
-        C a = v[j], b = v[j | B];
-        asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(b.x), "+v"(b.y));
+        const C a = v[j], b = v[j | B];
         v[j].x = f ? b.x : a.x; v[j].y = f ? b.y : a.y;
         v[j | B].x = f ? a.x : b.x; v[j | B].y = f ? a.y : b.y;
     }
+    asm volatile("; reg_flip %0" :: "n"(K));
 }
 
 template <int R, typename C>
@@ -362,13 +363,13 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                 const bool f = (((sp >> op.group) ^ (sp >> (op.group + 1))) & 1u) != 0;
                 if (op.type == PO_PFLIP_REG) reg_flip_dispatch<R>(op.target, f, v);
                 else lane_flip<R>(op.target, f, v);
-                if (op.kind && f) {
+                // times i where the slot flips (selects: a branch here costs registers everywhere)
+                const bool fi = op.kind && f;
 #pragma unroll
-                    for (int j = 0; j < N; ++j) {       // times i
-                        const T x = v[j].x;
-                        v[j].x = -v[j].y;
-                        v[j].y = x;
-                    }
+                for (int j = 0; j < N; ++j) {
+                    const T x = v[j].x, y = v[j].y;
+                    v[j].x = fi ? -y : x;
+                    v[j].y = fi ? x : y;
                 }
             }
         }
