@@ -185,13 +185,32 @@ int get_tuning(const sf_circuit_t *c, sf_tuning_t *t);
  * with real run_paths
  * calls on this request (same argument rules as run_paths; amps is
  * overwritten) and the fastest is kept on the circuit and written to *best.
- * Results are cached for the process per (block sizes, k, number of paths,
- * number of bitstrings, flags).
+ * Results are cached for the process per (device kind, block sizes, k, tree
+ * levels, number of paths, number of bitstrings, flags); see
+ * save_tuning_cache / load_tuning_cache to keep them across processes.
  */
 int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
              const uint64_t *bitstrings, size_t n_bits, double *amps, uint32_t flags,
              void *hip_stream, void *workspace, size_t workspace_bytes, uint32_t n_measure,
              sf_tuning_t *best);
+
+/*
+ * save_tuning_cache: write every tuning autotune has chosen in this process
+ * (or loaded) to the text file at path, one entry per line:
+ *   <device arch>:<compute units>/<qA>/<qB>/<k>/<levels>/<paths>/<bitstrings>/<flags>
+ *   reg_qubits leaf_batch max_slots waves_per_cu dense_qubits no_leaf_fold fold_levels
+ * (lines starting with '#' are comments).  The file is overwritten.
+ * SF_ERR_INVALID if path is NULL or cannot be written.
+ *
+ * load_tuning_cache: add the entries of such a file to the process cache
+ * (an entry with the same key replaces the cached one); a later autotune of a
+ * request with that key on that kind of device takes the stored tuning
+ * without measuring.  Writes the number of entries read to *n_loaded (may be
+ * NULL).  SF_ERR_INVALID if the file cannot be read or a line is malformed or
+ * out of range (then nothing is added).  Both are thread-safe.
+ */
+int save_tuning_cache(const char *path);
+int load_tuning_cache(const char *path, uint32_t *n_loaded);
 
 /* Statistics of the last run_paths call on this circuit. Times are only
  * filled when the run used SF_TIMING. */

@@ -24,7 +24,7 @@ EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_pa
            "describe_plan", "last_error", "server_create", "server_submit", "server_poll", "server_release",
            "server_drain", "server_stats", "server_destroy", "server_last_error", "rejection_m",
            "sample_bitstrings", "rejection_workspace_size", "rejection_accept", "frugal_sample",
-           "fidelity_estimate", "xeb_fidelity", "verify_claim"]
+           "fidelity_estimate", "xeb_fidelity", "verify_claim", "save_tuning_cache", "load_tuning_cache"]
 SF_PENDING = 1
 
 
@@ -89,6 +89,8 @@ def _load():
     lib.workspace_size.argtypes = [vp, u64, sz, u32, ctypes.POINTER(sz)]
     lib.set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.save_tuning_cache.argtypes = [ctypes.c_char_p]
+    lib.load_tuning_cache.argtypes = [ctypes.c_char_p, ctypes.POINTER(u32)]
     lib.get_run_stats.argtypes = [vp, ctypes.POINTER(RunStats)]
     lib.describe_plan.argtypes = [vp, ctypes.c_char_p, sz]
     lib.autotune.argtypes = [vp, vp, u64, u64, vp, sz, vp, u32, vp, vp, sz, u32, ctypes.POINTER(Tuning)]
@@ -299,6 +301,16 @@ def autotune(c: int, path_ids, path_begin: int, n_paths: int, bitstrings, n_bits
     _check(lib.autotune(c, _ptr(ids), path_begin, n_paths, _ptr(bitstrings), n_bits, _ptr(amps), flags,
                         _stream_handle(stream), _ptr(workspace), workspace_bytes, n_measure, ctypes.byref(t)))
     return {name: getattr(t, name) for name, _ in Tuning._fields_}
+
+
+def save_tuning_cache(path: str) -> None:
+    _check(lib.save_tuning_cache(str(path).encode()))
+
+
+def load_tuning_cache(path: str) -> int:
+    n = ctypes.c_uint32(0)
+    _check(lib.load_tuning_cache(str(path).encode(), ctypes.byref(n)))
+    return n.value
 
 
 def get_run_stats(c: int) -> dict:

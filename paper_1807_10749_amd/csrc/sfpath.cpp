@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <set>
@@ -266,6 +267,18 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::string, sf_tuning_t> g_tune_cache;
 
+// "<arch>:<compute units>" of the current device: tunings are kept per device kind.
+std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + ":" + std::to_string(prop.multiProcessorCount);
+}
+
 // Effective rates of the cost model (bytes/s, s per launch) on one MI355X, from
 // measured pass and gather kernels; only the ranking of candidates depends on them.
 constexpr double kSweepRate = 5.0e12, kGatherRate = 6.0e12, kLaunchCost = 4e-6;
@@ -280,7 +293,7 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
         if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
         if (flags & ~uint32_t(63)) return fail(SF_ERR_INVALID, "unknown flag");
         const bool fp64 = (flags & SF_FP64_SWEEPS) != 0;
-        const std::string key = std::to_string(c->half[0].q) + "/" + std::to_string(c->half[1].q) + "/" +
+        const std::string key = device_tag() + "/" + std::to_string(c->half[0].q) + "/" + std::to_string(c->half[1].q) + "/" +
                                 std::to_string(c->k) + "/" + std::to_string(c->levels.size()) + "/" +
                                 std::to_string(n_paths) + "/" + std::to_string(n_bits) + "/" +
                                 std::to_string(flags & (SF_FP64_SWEEPS | SF_PLAIN));
@@ -363,6 +376,58 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
         *best = best_t_cfg;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = best_t_cfg;
+        return ok();
+    });
+}
+
+int save_tuning_cache(const char *path)
+{
+    return guarded([&]() -> int {
+        if (!path) return fail(SF_ERR_INVALID, "path is NULL");
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        FILE *f = std::fopen(path, "w");
+        if (!f) return fail(SF_ERR_INVALID, std::string("cannot write ") + path);
+        std::fprintf(f, "# sfpath tuning cache: key reg_qubits leaf_batch max_slots waves_per_cu dense_qubits "
+                        "no_leaf_fold fold_levels\n");
+        for (const auto &kv : g_tune_cache) {
+            const sf_tuning_t &t = kv.second;
+            std::fprintf(f, "%s %u %u %u %u %u %u %u\n", kv.first.c_str(), t.reg_qubits, t.leaf_batch, t.max_slots,
+                         t.waves_per_cu, t.dense_qubits, t.no_leaf_fold, t.fold_levels);
+        }
+        const bool bad = std::ferror(f) != 0;
+        if (std::fclose(f) != 0 || bad) return fail(SF_ERR_INVALID, std::string("cannot write ") + path);
+        return ok();
+    });
+}
+
+int load_tuning_cache(const char *path, uint32_t *n_loaded)
+{
+    return guarded([&]() -> int {
+        if (!path) return fail(SF_ERR_INVALID, "path is NULL");
+        FILE *f = std::fopen(path, "r");
+        if (!f) return fail(SF_ERR_INVALID, std::string("cannot read ") + path);
+        std::map<std::string, sf_tuning_t> got;
+        char line[1024];
+        int lineno = 0;
+        while (std::fgets(line, sizeof(line), f)) {
+            ++lineno;
+            if (line[0] == '#' || line[0] == '\n') continue;
+            char key[512];
+            sf_tuning_t t{};
+            char extra;
+            if (std::sscanf(line, "%511s %u %u %u %u %u %u %u %c", key, &t.reg_qubits, &t.leaf_batch, &t.max_slots,
+                            &t.waves_per_cu, &t.dense_qubits, &t.no_leaf_fold, &t.fold_levels, &extra) != 8 ||
+                t.reg_qubits > 5 || t.dense_qubits == 1 || t.dense_qubits > 4 || t.no_leaf_fold > 1 ||
+                t.fold_levels > 62) {
+                std::fclose(f);
+                return fail(SF_ERR_INVALID, std::string(path) + ":" + std::to_string(lineno) + ": malformed entry");
+            }
+            got[key] = t;
+        }
+        std::fclose(f);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : got) g_tune_cache[kv.first] = kv.second;
+        if (n_loaded) *n_loaded = (uint32_t)got.size();
         return ok();
     });
 }

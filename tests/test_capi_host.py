@@ -263,3 +263,27 @@ def test_rejection_host_entries_match_oracle(sf):
         assert e.value.code == sf.SF_ERR_INVALID
     with pytest.raises(sf.SFError):
         sf.sample_bitstrings(4, 17, 1)
+
+
+def test_tuning_cache_file_roundtrip(sf, tmp_path):
+    """Autotuner results kept across processes: a text file of keyed tunings, validated on load."""
+    src = tmp_path / "in.txt"
+    src.write_text("# comment\n"
+                   "gfx950:256/15/15/15/7/32768/100000/0 5 0 0 32 4 0 2\n"
+                   "gfx950:256/15/15/30/7/262144/100000/0 4 4096 0 16 0 1 0\n")
+    assert sf.load_tuning_cache(str(src)) == 2
+    out = tmp_path / "out.txt"
+    sf.save_tuning_cache(str(out))
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert "gfx950:256/15/15/15/7/32768/100000/0 5 0 0 32 4 0 2" in lines
+    assert "gfx950:256/15/15/30/7/262144/100000/0 4 4096 0 16 0 1 0" in lines
+    for bad in ["k 1 2 3\n", "k 9 0 0 32 0 0 0\n", "k 5 0 0 32 1 0 0\n", "k 5 0 0 32 0 0 0 7\n"]:
+        f = tmp_path / "bad.txt"
+        f.write_text(bad)
+        with pytest.raises(sf.SFError) as e:
+            sf.load_tuning_cache(str(f))
+        assert e.value.code == sf.SF_ERR_INVALID
+    with pytest.raises(sf.SFError):
+        sf.load_tuning_cache(str(tmp_path / "missing.txt"))
+    with pytest.raises(sf.SFError):
+        sf.save_tuning_cache(str(tmp_path / "no_such_dir" / "x.txt"))

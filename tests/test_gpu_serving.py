@@ -131,3 +131,39 @@ def test_autotune_keeps_parity(sf):
     err = np.max(np.abs(np.abs(a) ** 2 - np.abs(o) ** 2) / np.maximum(np.abs(o) ** 2, floor))
     assert err <= 1e-5, err
     c.close()
+
+
+def test_autotune_cache_file(sf, tmp_path):
+    """A tuning saved to a file and loaded again is taken by autotune without measuring."""
+    import time
+    from workload import CONFIGS
+    cfg = CONFIGS["grid4x4_d16"]
+    g = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed)
+    c = sf.Circuit(cfg.rows, cfg.cols, g, cfg.cut_mask())
+    bits = random_bitstrings(16, 333, 5)
+    amps = np.zeros(2 * bits.size)
+    say("autotune grid4x4_d16, 200 paths, then save / load the cache")
+    t = sf.autotune(c.handle, None, 0, 200, bits, bits.size, amps, n_measure=2)
+    path = tmp_path / "tune.txt"
+    sf.save_tuning_cache(str(path))
+    want = " ".join(str(t[k]) for k in ("reg_qubits", "leaf_batch", "max_slots", "waves_per_cu", "dense_qubits",
+                                         "no_leaf_fold", "fold_levels"))
+    lines = [l for l in path.read_text().splitlines() if l.endswith("/200/333/0 " + want)]
+    assert len(lines) == 1 and lines[0].startswith("gfx950:"), path.read_text()
+    # a stored tuning for this key replaces the cached one and is returned as is
+    key = lines[0].split()[0]
+    forced = "4 0 0 16 0 1 0"
+    (tmp_path / "forced.txt").write_text(f"{key} {forced}\n")
+    assert sf.load_tuning_cache(str(tmp_path / "forced.txt")) == 1
+    c.tune()
+    t0 = time.perf_counter()
+    t2 = sf.autotune(c.handle, None, 0, 200, bits, bits.size, amps, n_measure=2)
+    assert time.perf_counter() - t0 < 0.5
+    assert " ".join(str(t2[k]) for k in ("reg_qubits", "leaf_batch", "max_slots", "waves_per_cu", "dense_qubits",
+                                         "no_leaf_fold", "fold_levels")) == forced
+    assert sf.get_tuning(c.handle) == t2
+    a = c.amplitudes(bits, n_paths=200)
+    o = oracle.path_sum(16, g, cfg.cut_mask(), np.arange(200, dtype=np.uint64), bits)
+    floor = (200 / 2.0 ** c.k) * 2.0 ** (-16)
+    assert np.max(np.abs(np.abs(a) ** 2 - np.abs(o) ** 2) / np.maximum(np.abs(o) ** 2, floor)) <= 1e-5
+    c.close()
