@@ -37,12 +37,20 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving mix (0 = skip)")
     ap.add_argument("--no-sampling", action="store_true", help="skip the rejection-sampling measurement")
     ap.add_argument("--no-iswap", action="store_true", help="skip the iSWAP-variant measurement")
+    ap.add_argument("--chunk-paths", type=int, default=0,
+                    help="split a step into run_paths calls of at most this many paths (accumulated; one progress "
+                         "line each), for workloads whose step takes minutes")
     ap.add_argument("--tuning", default="",
                     help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels]]] "
                          "(skips autotune)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (known HBM traffic for counter scaling)")
     return ap.parse_args()
+
+
+def progress(msg):
+    """One line on stderr per phase, so a long run shows it is moving."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -93,8 +101,25 @@ def main():
     flags = flags_base | sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
 
     def step(extra=0):
-        sf.run_paths(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags | extra, stream, ws, ws_bytes)
+        """One pass over the whole request; returns the summed run statistics of its calls."""
+        chunk = args.chunk_paths if 0 < args.chunk_paths < npaths else npaths
+        tot = None
+        for off in range(0, max(npaths, 1), max(chunk, 1)):
+            n = min(chunk, npaths - off)
+            acc = sf.SF_ACCUMULATE if off else 0
+            if ids is not None:
+                sf.run_paths(c.handle, ids[off:off + n], 0, n, d_bits, bits.size, d_amps, flags | extra | acc, stream,
+                             ws, ws_bytes)
+            else:
+                sf.run_paths(c.handle, None, begin + off, n, d_bits, bits.size, d_amps, flags | extra | acc, stream,
+                             ws, ws_bytes)
+            st = c.stats()
+            tot = st if tot is None else {k: tot[k] + st[k] if k != "a_groups" else st[k] for k in st}
+            if chunk < npaths:
+                progress(f"  paths {off + n}/{npaths}")
+        return tot
 
+    progress(f"{args.workload}: k={c.k}, {npaths} paths, {bits.size} bitstrings, workspace {ws_bytes / 2**30:.1f} GiB")
     tuning = None
     if args.tuning:
         vals = [int(v) for v in args.tuning.split(",")]
@@ -106,19 +131,21 @@ def main():
                       no_leaf_fold=nofold, fold_levels=flev)
         tuning = sf.get_tuning(c.handle)
     elif not args.no_autotune:
+        progress("autotune")
         tuning = sf.autotune(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,
                              n_measure=6)
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
+        progress(f"warm-up step {i + 1}/{args.warmup}")
         step()
     torch.cuda.synchronize()
     sweep_ms = gather_ms = other_ms = host_ms = plan_ms = 0.0
     sweep_launches = gather_launches = 0
     sweep_bytes = gather_bytes = gather_row_bytes = 0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(sf.SF_TIMING)
-        st = c.stats()
+    for i in range(args.steps):
+        progress(f"timed step {i + 1}/{args.steps}")
+        st = step(sf.SF_TIMING)
         sweep_ms += st["ms_sweep"]
         gather_ms += st["ms_gather"]
         other_ms += st["ms_other"]
@@ -166,6 +193,7 @@ def main():
         plain_paths_per_s = plain_n / (time.perf_counter() - tp)
         plain = {"paths_per_s": plain_paths_per_s, "paths": plain_n, "speedup_of_batched": paths_per_s / plain_paths_per_s}
 
+    progress("timed steps done")
     serving = serving_bench(args.serve_jobs) if args.serve_jobs > 0 else None
     sampling = None if args.no_sampling else sampling_bench(c, ids, begin, npaths, bits.size, ws, ws_bytes, stream)
     validation = None
@@ -176,9 +204,11 @@ def main():
 
     iswap = None
     if not args.no_iswap and args.workload != "grid5x6_d24_iswap":
+        progress("iSWAP variant")
         iswap = iswap_bench(stream)
 
     cpu = None
+    progress("CPU oracle sample")
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, gates, bits, c.k, ids, begin, npaths, args.cpu_seconds)
 
@@ -212,6 +242,11 @@ def main():
                      "row_bytes_per_launch": (gather_row_bytes / max(gather_launches, 1)
                                               if not dom.startswith("pass") else None),
                      "a_groups": st["a_groups"]},
+        "sweep_roofline": {"kernels": "pass_kernel + dense_kernel (gate sweeps, all levels written)", "bound": "hbm",
+                           "achieved": (sweep_bytes / max(sweep_ms, 1e-9)) / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": (sweep_bytes / max(sweep_ms, 1e-9)) / 1e6 / HBM_PEAK_GBS,
+                           "bytes_per_step": sweep_bytes / args.steps, "launches_per_step": sweep_launches / args.steps,
+                           "note": "time of one event pair around each run of sweep launches, gaps included"},
         "cpu_baseline": cpu,
         "serving": serving,
         "sampling": sampling,
