@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving mix (0 = skip)")
     ap.add_argument("--no-sampling", action="store_true", help="skip the rejection-sampling measurement")
     ap.add_argument("--no-iswap", action="store_true", help="skip the iSWAP-variant measurement")
+    ap.add_argument("--bitstrings", type=int, default=0,
+                    help="number of requested bitstrings instead of the workload's (amplitude-count scaling)")
     ap.add_argument("--chunk-paths", type=int, default=0,
                     help="split a step into run_paths calls of at most this many paths (accumulated; one progress "
                          "line each), for workloads whose step takes minutes")
@@ -73,7 +75,7 @@ def main():
     from workload import CONFIGS, make_workload, path_block
 
     cfg = CONFIGS[args.workload]
-    w = make_workload(args.workload)
+    w = make_workload(args.workload, n_bits=args.bitstrings or None)
     gates, bits = w["gates"], w["bitstrings"]
     n = cfg.n_qubits
     torch.cuda.set_device(0)

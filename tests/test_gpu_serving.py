@@ -94,6 +94,34 @@ def test_server_results_match_oracle(sf):
     sf.server_destroy(srv)
 
 
+def test_server_iswap_jobs_match_oracle(sf):
+    """iSWAP circuits (four terms per crossing gate) served next to a CZ job."""
+    from workload import ISWAP
+    srv = sf.server_create(2 << 30, None, 3, 64)
+    specs = [(3, 4, 10, 21, 400, 1.0, 0, ISWAP), (4, 4, 12, 22, 600, 0.05, 7, ISWAP), (4, 4, 16, 11, 500, 1.0, 0, 4)]
+    subs = []
+    for rows, cols, depth, cseed, nb, f, pseed, two in specs:
+        g = grid_circuit(rows, cols, depth, cseed, two_qubit=two)
+        bits = random_bitstrings(rows * cols, nb, cseed + 1000)
+        subs.append((sf.server_submit(srv, rows, cols, g, bits, f=f, path_seed=pseed), g, bits, rows, cols, f, pseed))
+    say("server iSWAP + CZ mix")
+    sf.server_drain(srv)
+    for jid, g, bits, rows, cols, f, pseed in subs:
+        done, a, info = sf.server_poll(srv, jid, bits.size)
+        assert done and info["status"] == 0
+        n = rows * cols
+        c = sf.Circuit(rows, cols, g)
+        k = c.k
+        ids = np.arange(1 << k, dtype=np.uint64) if f >= 1 else oracle.sample_paths(k, f, pseed)
+        o = oracle.path_sum(n, g, c.mask_a, ids, bits)
+        c.close()
+        assert info["n_paths"] == ids.size
+        floor = (ids.size / 2.0 ** k) * 2.0 ** (-n)
+        err = np.max(np.abs(np.abs(a) ** 2 - np.abs(o) ** 2) / np.maximum(np.abs(o) ** 2, floor))
+        assert err <= 1e-5, (rows, cols, f, err)
+    sf.server_destroy(srv)
+
+
 def test_server_admission_respects_arena(sf):
     """Each job needs at least a 256 MiB workspace: a 1 GiB arena holds three at a time."""
     say("server admission, 1 GiB arena, 8 jobs")
