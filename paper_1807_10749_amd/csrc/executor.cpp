@@ -92,6 +92,7 @@ struct Launch {
     int half = 0;
     int R = 0;
     bool flip = false;            // PASS: the program holds per-path flips
+    bool pair_next = false;       // PASS: launched together with the next launch (the other block's pass)
     PassArgs pa{};
     GatherArgs ga{};
     size_t plan_off = 0;      // device offset of the pass program inside the plan blob
@@ -477,6 +478,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                            uint64_t src_slots, size_t table_off, int n_low = 0, int low_first = 0) {
         const int p = log2u(nslots);
         const int ps = log2u(src_slots);
+        std::vector<Launch> hl[2];      // each block's launches of this segment, in order
         for (int h = 0; h < 2; ++h) {
             const SegmentPlan &sp = get_segment_plan(c, h, level, p, R, fp64 ? 0 : (int)c.tuning.dense_qubits);
             if (!sp.ok) { plan_error = true; return; }
@@ -498,7 +500,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                     ln.plan_off = be[i].off;
                     ln.grid = (unsigned)std::min<uint64_t>((ln.da.n_groups + 3) / 4, max_grid);
                     ln.bytes = (uint64_t(1) << n_ext) * elem * 2;
-                    launches.push_back(ln);
+                    hl[h].push_back(ln);
                     continue;
                 }
                 Launch ln;
@@ -551,8 +553,22 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 ln.bytes = (uint64_t(1) << n_ext) * elem * (a.src_mode == SRC_INIT ? 1 : 2);
                 if (a.src_mode == SRC_FANOUT)
                     ln.bytes = (uint64_t(1) << n_ext) * elem + (uint64_t(1) << (ps + qh[h])) * elem;
+                hl[h].push_back(ln);
+            }
+        }
+        // The two blocks' passes are independent: interleave them, and launch the i-th pass of
+        // block A together with the i-th pass of block B (one kernel, the blocks of the grid split
+        // between them) when both run the same kernel variant.  Small levels are bound by launch
+        // and wave latency, which the pair then pays once.
+        for (size_t i = 0; i < std::max(hl[0].size(), hl[1].size()); ++i) {
+            const bool both = i < hl[0].size() && i < hl[1].size();
+            if (i < hl[0].size()) {
+                Launch ln = hl[0][i];
+                ln.pair_next = both && ln.kind == Launch::PASS && hl[1][i].kind == Launch::PASS &&
+                               ln.R == hl[1][i].R && ln.flip == hl[1][i].flip;
                 launches.push_back(ln);
             }
+            if (i < hl[1].size()) launches.push_back(hl[1][i]);
         }
     };
 
@@ -742,9 +758,10 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     const size_t tables_bytes = align_up(tpath.size() * 8) + align_up(tparent.size() * 4) + align_up(tmaskv.size() * 4);
     if (dry_run) {
         const uint64_t rounds = n_paths ? (plain ? n_paths : 1) : 0;
-        for (const Launch &ln : launches) {
+        for (size_t li = 0; li < launches.size(); ++li) {
+            const Launch &ln = launches[li];
             if (ln.kind != Launch::GATHER && ln.kind != Launch::FOLD) {
-                c.stats.n_sweep_launches += rounds;
+                if (!(li > 0 && launches[li - 1].pair_next)) c.stats.n_sweep_launches += rounds;   // a pair is one launch
                 c.stats.sweep_bytes += rounds * ln.bytes;
                 (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
             }
@@ -849,7 +866,32 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             cur_id = ev_begin(cat);
             cur_cat = cat;
         };
-        for (Launch &ln : launches) {
+        auto pass_args = [&](const Launch &ln) {
+            PassArgs a = ln.pa;
+            a.dst = buf + ln.dst_off;
+            a.src = buf + ln.src_off;
+            a.slot_path = (const uint64_t *)(ws + off_tpath) + ln.table_off;
+            a.slot_parent = (const uint32_t *)(ws + off_tparent) + ln.table_off;
+            a.slot_parent_base = 0;
+            a.prog = (const uint32_t *)(ws + off_blob + ln.plan_off);
+            a.prog_words = ln.prog_words;
+            a.groups_word = ln.groups_word;
+            a.terms_word = ln.terms_word;
+            return a;
+        };
+        for (size_t li = 0; li < launches.size(); ++li) {
+            const Launch &ln = launches[li];
+            if (ln.kind == Launch::PASS && ln.pair_next) {
+                const Launch &l2 = launches[li + 1];
+                timed(0);
+                if ((he = launch_pass_pair(fp64, ln.R, ln.flip, pass_args(ln), ln.grid, pass_args(l2), l2.grid, stream)) !=
+                    hipSuccess)
+                    return dev_err("pass", he);
+                c.stats.n_sweep_launches++;
+                c.stats.sweep_bytes += ln.bytes + l2.bytes;
+                ++li;
+                continue;
+            }
             if (ln.kind == Launch::DENSE) {
                 DenseArgs d = ln.da;
                 d.dst = buf + ln.dst_off;
@@ -860,18 +902,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;
             } else if (ln.kind == Launch::PASS) {
-                PassArgs a = ln.pa;
-                a.dst = buf + ln.dst_off;
-                a.src = buf + ln.src_off;
-                a.slot_path = (const uint64_t *)(ws + off_tpath) + ln.table_off;
-                a.slot_parent = (const uint32_t *)(ws + off_tparent) + ln.table_off;
-                a.slot_parent_base = 0;
-                a.prog = (const uint32_t *)(ws + off_blob + ln.plan_off);
-                a.prog_words = ln.prog_words;
-                a.groups_word = ln.groups_word;
-                a.terms_word = ln.terms_word;
                 timed(0);
-                if ((he = launch_pass(fp64, ln.R, ln.flip, a, ln.grid, stream)) != hipSuccess) return dev_err("pass", he);
+                if ((he = launch_pass(fp64, ln.R, ln.flip, pass_args(ln), ln.grid, stream)) != hipSuccess)
+                    return dev_err("pass", he);
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;
             } else if (ln.kind == Launch::FOLD && fh[0]->iswap) {

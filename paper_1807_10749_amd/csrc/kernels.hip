@@ -261,15 +261,16 @@ __device__ __forceinline__ uint64_t reg_offset(const int32_t (&pos)[6], int j, i
     return o;
 }
 
-// FLIP: the program may hold per-path flips (crossing iSWAPs); passes without them run the
-// variant that has no code for them, whose register allocation they do not affect.
+// One pass for workgroup `block` of `nblocks` (see PassArgs).  FLIP: the program may hold
+// per-path flips (crossing iSWAPs); passes without them run the variant that has no code for
+// them, whose register allocation they do not affect.
 template <typename T, int R, bool FLIP>
-__global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
+__device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t nblocks)
 {
     using C = typename Cplx<T>::type;
     constexpr int N = 1 << R;
     const unsigned lane = threadIdx.x & 63u;
-    const uint64_t nwaves = (uint64_t)gridDim.x * 4u;
+    const uint64_t nwaves = (uint64_t)nblocks * 4u;
     int32_t pos[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) pos[k] = a.reg_pos[k];
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     };
     // per-lane slot tables of a tile are fetched one tile ahead, so the data loads of a
     // fan-out pass do not wait behind a dependent table load
-    uint64_t tile = (uint64_t)blockIdx.x * 4u + wid;
+    uint64_t tile = (uint64_t)block * 4u + wid;
     uint64_t nx_sp = 0;
     uint32_t nx_par = 0;
     if (tile < a.n_tiles) {
@@ -385,6 +386,51 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
             row[lane] = v[j];
         }
     }
+}
+
+template <typename T, int R, bool FLIP>
+__global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
+{
+    pass_body<T, R, FLIP>(a, blockIdx.x, gridDim.x);
+}
+
+// Two independent passes in one launch (block A's and block B's pass of a tree level): the
+// first grid0 workgroups run a0, the rest a1.  The choice is per workgroup, so every wave
+// takes one branch.
+template <typename T, int R, bool FLIP>
+__global__ __launch_bounds__(256) void pass_kernel_pair(PassArgs a0, PassArgs a1, uint32_t grid0)
+{
+    if (blockIdx.x < grid0) pass_body<T, R, FLIP>(a0, blockIdx.x, grid0);
+    else pass_body<T, R, FLIP>(a1, blockIdx.x - grid0, gridDim.x - grid0);
+}
+
+template <typename T, bool FLIP>
+static hipError_t launch_pass_pair_t(int R, const PassArgs &a0, unsigned g0, const PassArgs &a1, unsigned g1,
+                                     hipStream_t s)
+{
+    const unsigned grid = g0 + g1;
+    switch (R) {
+    case 0: pass_kernel_pair<T, 0, FLIP><<<grid, 256, 0, s>>>(a0, a1, g0); break;
+    case 1: pass_kernel_pair<T, 1, FLIP><<<grid, 256, 0, s>>>(a0, a1, g0); break;
+    case 2: pass_kernel_pair<T, 2, FLIP><<<grid, 256, 0, s>>>(a0, a1, g0); break;
+    case 3: pass_kernel_pair<T, 3, FLIP><<<grid, 256, 0, s>>>(a0, a1, g0); break;
+    case 4: pass_kernel_pair<T, 4, FLIP><<<grid, 256, 0, s>>>(a0, a1, g0); break;
+    case 5: if constexpr (sizeof(T) == 4) { pass_kernel_pair<T, 5, FLIP><<<grid, 256, 0, s>>>(a0, a1, g0); break; }
+            return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_pair(bool fp64, int R, bool flips, const PassArgs &a0, unsigned grid0, const PassArgs &a1,
+                            unsigned grid1, hipStream_t s)
+{
+    if (grid0 == 0 || grid1 == 0) return hipErrorInvalidValue;
+    if (flips)
+        return fp64 ? launch_pass_pair_t<double, true>(R, a0, grid0, a1, grid1, s)
+                    : launch_pass_pair_t<float, true>(R, a0, grid0, a1, grid1, s);
+    return fp64 ? launch_pass_pair_t<double, false>(R, a0, grid0, a1, grid1, s)
+                : launch_pass_pair_t<float, false>(R, a0, grid0, a1, grid1, s);
 }
 
 template <typename T, bool FLIP>

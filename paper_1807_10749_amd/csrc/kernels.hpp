@@ -16,6 +16,9 @@ constexpr int kMaxRegBitsF64 = 4;
 // (0..kMaxRegBits), fp64 selects complex128 states.
 // flips: the program holds PO_PFLIP_* ops (selects the kernel variant that has code for them)
 hipError_t launch_pass(bool fp64, int R, bool flips, const PassArgs &a, unsigned grid, hipStream_t s);
+// Two independent passes of the same kernel variant in one launch (grid0 + grid1 workgroups).
+hipError_t launch_pass_pair(bool fp64, int R, bool flips, const PassArgs &a0, unsigned grid0, const PassArgs &a1,
+                            unsigned grid1, hipStream_t s);
 
 // Dense 4-qubit block on matrix cores (complex64 states only).
 hipError_t launch_dense(const DenseArgs &a, unsigned grid, hipStream_t s);

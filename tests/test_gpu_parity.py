@@ -404,3 +404,18 @@ def test_diagonal_group_quarter_turn_phases(sf, fp64):
     a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS if fp64 else 0)
     o = oracle.full_state(16, g)[bits.astype(np.int64)]
     assert c11_error(a, o, 1, 0, 16) <= (TOL_C128 if fp64 else TOL_C64)
+
+
+@pytest.mark.parametrize("two_qubit,fp64", [(4, True), (4, False), (5, True), (5, False)])
+def test_full_output_norm(sf, two_qubit, fp64):
+    """All 2^16 amplitudes over all paths form the unit-norm output state (a property that holds
+    at any size; here with FP64 sums over 256 or 4096 paths)."""
+    from workload import ISWAP
+    depth = 16 if two_qubit == 4 else 12
+    g = grid_circuit(4, 4, depth, 5, two_qubit=two_qubit)
+    c = sf.Circuit(4, 4, g, CONFIGS["grid4x4_d16"].cut_mask())
+    bits = np.arange(1 << 16, dtype=np.uint64)
+    say(f"full output norm, {'iSWAP' if two_qubit == ISWAP else 'CZ'} 4x4, k={c.k}, fp64={fp64}")
+    a = c.amplitudes(bits, flags=sf.SF_FP64_SWEEPS if fp64 else 0)
+    norm = float(np.sum(np.abs(a) ** 2))
+    assert abs(norm - 1.0) <= (1e-12 if fp64 else 1e-5), norm
