@@ -34,9 +34,10 @@
  *     Y^1/2 = [[1+i,-1-i],[1+i,1+i]]/2, T = diag(1, e^{i pi/4});
  *   - bitstring bit q is the value of qubit q; local index of a qubit inside
  *     its block is its rank among the block's qubits;
- *   - crossing CZs are ordered by (cycle, smaller qubit id); crossing CZ j
- *     is decided by bit (k-1-j) of the path id; the projector goes on the
- *     block-A endpoint and Z on the block-B endpoint.
+ *   - crossing gates are ordered by (cycle, smaller qubit id); the first
+ *     takes the highest path bits (one for a CZ, two for an iSWAP), so in a
+ *     CZ-only circuit crossing CZ j is decided by bit (k-1-j); the projector
+ *     goes on the block-A endpoint and Z on the block-B endpoint.
  *
  * Everything is plain loops in double precision.  OpenMP is used only to
  * spread independent loop iterations over host cores.

@@ -5,7 +5,7 @@
 // The paper keeps one checkpoint per process after the x_p-bit prefix and
 // replays 2^x_b branches from it (Section 2); its logs show a second
 // checkpoint level ("p + r + b").  Here every clock cycle that holds
-// crossing CZs is a tree level: the nodes of a level are the distinct
+// crossing gates is a tree level: the nodes of a level are the distinct
 // prefixes of the requested path ids, a node's block states are evolved
 // once and shared by all paths below it, and the states of many nodes of
 // one level sit side by side as the slots of one batch array.

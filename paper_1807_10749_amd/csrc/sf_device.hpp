@@ -13,7 +13,7 @@
 // the remaining bits come from the tile index.  Gates on register qubits are
 // applied in registers, gates on the (up to 6) qubits that sit in lane bits
 // with cross-lane shuffles, and diagonal gates (CZ, T, and the per-path
-// projector / Z of crossing CZs, Section 2 Eq. (CZ)) as bitmask phase
+// projector / Z of crossing gates, Section 2 Eq. (CZ)) as bitmask phase
 // evaluations (the paper's bitmask + mod-8 arithmetic of Section 2).  The
 // per-path flips of crossing iSWAPs are register swaps or lane shuffles.
 #pragma once

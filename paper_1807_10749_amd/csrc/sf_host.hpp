@@ -15,7 +15,7 @@ namespace sf {
 // Operations of one block's program, in local qubit indices.
 enum HalfKind : uint8_t {
     HK_H = 0, HK_X = 1, HK_Y = 2, HK_T = 3, HK_CZ = 4,
-    HK_PROJ = 5,   // keep amplitudes whose bit q0 equals path bit `bit` (crossing CZ, block A side)
+    HK_PROJ = 5,   // keep amplitudes whose bit q0 equals path bit `bit` (crossing CZ block A side; both sides of an iSWAP)
     HK_ZCTL = 6,   // negate amplitudes whose bit q0 is 1 when path bit `bit` is 1 (block B side)
     HK_PFLIP = 7,  // flip bit q0 when path bits bit and bit+1 differ (crossing iSWAP, X^{i xor j})
     HK_PFLIPI = 8, // as HK_PFLIP, and multiply by i when it flips

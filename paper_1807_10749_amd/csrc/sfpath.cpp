@@ -159,7 +159,7 @@ int choose_cut(const sf_circuit_t *c, uint64_t *block_a_mask)
 {
     return guarded([&]() -> int {
         if (!c || !block_a_mask) return fail(SF_ERR_INVALID, "NULL argument");
-        // candidates: (larger block, crossing CZs, horizontal?, index, mask)
+        // candidates: (larger block, path bits of the crossing gates, horizontal?, index, mask)
         bool found = false;
         std::tuple<int, int, int, int> best{};
         uint64_t best_mask = 0;
