@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--chunk-paths", type=int, default=0,
                     help="split a step into run_paths calls of at most this many paths (accumulated; one progress "
                          "line each), for workloads whose step takes minutes")
+    ap.add_argument("--max-paths", type=int, default=0,
+                    help="time only the first N paths of the request (a bounded sample, for profiling)")
     ap.add_argument("--tuning", default="",
                     help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels]]] "
                          "(skips autotune)")
@@ -89,6 +91,11 @@ def main():
     else:
         ids = sf.sample_paths(c.k, cfg.f, cfg.path_seed)
         begin, npaths = 0, ids.size
+    full_paths = npaths
+    if 0 < args.max_paths < npaths:
+        npaths = args.max_paths
+        if ids is not None:
+            ids = ids[:npaths]
     flags_base = sf.SF_FP64_SWEEPS if cfg.fp64_sweeps else 0
 
     d_bits = torch.from_numpy(bits.view(np.int64)).cuda()
@@ -230,7 +237,8 @@ def main():
         "config": {"workload": args.workload, "grid": f"{cfg.rows}x{cfg.cols}", "depth": f"1+{cfg.depth}+1",
                    "cut": f"{bin(cfg.cut_mask()).count('1')}+{n - bin(cfg.cut_mask()).count('1')}",
                    "k": c.k, "paths": npaths, "f": cfg.f if cfg.paths == "sample" else npaths / 2.0 ** c.k,
-                   "bitstrings": int(bits.size), "tuning": tuning or sf.get_tuning(c.handle)},
+                   "bitstrings": int(bits.size), "tuning": tuning or sf.get_tuning(c.handle),
+                   **({"paths_sample": f"first {npaths} of {full_paths} paths"} if npaths < full_paths else {})},
         "amps_per_s": amps_per_s,
         "plain_form": plain,
         "kernel_ms_per_step": {"sweep": sweep_ms / args.steps, "gather": gather_ms / args.steps,
