@@ -474,8 +474,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         return off;
     };
 
+    // src_read: parent slots a fan-out actually reads (distinct parents of its children), for
+    // the byte count; 0 = all src_slots
     auto add_segment = [&](int level, uint64_t nslots, const size_t dst[2], int mode, const size_t src[2],
-                           uint64_t src_slots, size_t table_off, int n_low = 0, int low_first = 0) {
+                           uint64_t src_slots, size_t table_off, int n_low = 0, int low_first = 0,
+                           uint64_t src_read = 0) {
         const int p = log2u(nslots);
         const int ps = log2u(src_slots);
         std::vector<Launch> hl[2];      // each block's launches of this segment, in order
@@ -552,7 +555,8 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 ln.grid = (unsigned)std::min<uint64_t>((a.n_tiles + 3) / 4, max_grid);
                 ln.bytes = (uint64_t(1) << n_ext) * elem * (a.src_mode == SRC_INIT ? 1 : 2);
                 if (a.src_mode == SRC_FANOUT)
-                    ln.bytes = (uint64_t(1) << n_ext) * elem + (uint64_t(1) << (ps + qh[h])) * elem;
+                    ln.bytes = (uint64_t(1) << n_ext) * elem +
+                               (src_read ? src_read : uint64_t(1) << ps) * (uint64_t(1) << qh[h]) * elem;
                 hl[h].push_back(ln);
             }
         }
@@ -722,10 +726,18 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             std::vector<uint32_t> ch(a1 - a0), par(a1 - a0);
             std::vector<uint64_t> pv(a1 - a0);
             for (size_t i = a0; i < a1; ++i) { ch[i - a0] = chs[i].node; par[i - a0] = chs[i].slot; pv[i - a0] = cnode[chs[i].node]; }
+            // distinct parents read by this chunk (each parent's children are adjacent in
+            // parent-major order; in branch-major order a chunk spans whole runs of parents)
+            uint64_t n_read = 0;
+            {
+                std::vector<uint32_t> u(par);
+                std::sort(u.begin(), u.end());
+                n_read = (uint64_t)(std::unique(u.begin(), u.end()) - u.begin());
+            }
             const size_t toff = put_tables(pv, par, ns);
             batches.push_back(BatchRec{l + 1, toff, ns});
             const size_t dst[2] = {cb.off[0], cb.off[1]};
-            add_segment(l + 1, ns, dst, SRC_FANOUT, src, nslots, toff, n_low, log2u(nslots));
+            add_segment(l + 1, ns, dst, SRC_FANOUT, src, nslots, toff, n_low, log2u(nslots), n_read);
             visit(l + 1, ch, ns);
             if (plan_error) return;
         }
