@@ -93,6 +93,7 @@ struct Launch {
     int R = 0;
     bool flip = false;            // PASS: the program holds per-path flips
     bool pair_next = false;       // PASS: launched together with the next launch (the other block's pass)
+    bool zskip = false;           // PASS: leaves the source's zero subspace unread (pa.n_zero entries)
     PassArgs pa{};
     GatherArgs ga{};
     size_t plan_off = 0;      // device offset of the pass program inside the plan blob
@@ -547,6 +548,32 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                     a.p_src = ps;
                     ln.src_off = src[h];
                 }
+                // zero subspace of the source (the initial state has none): its amplitudes are
+                // left unread, and the algorithmic bytes count the reads of the rest (at most
+                // 2^-|qubits| of the state; two entries on one qubit can zero whole slots)
+                int z_qubits = 0;
+                a.n_zero = 0;
+                if (a.src_mode != SRC_INIT) {
+                    uint64_t zq = 0;
+                    for (const auto &e : pp.zero_in) {
+                        if (a.n_zero == kMaxZeroEntries) break;
+                        const int pos_e = p + e.first;
+                        int r = -1;
+                        for (int kk = 0; kk < pp.R; ++kk)
+                            if (pp.reg_pos[kk] == pos_e) r = kk;
+                        a.zero_reg[a.n_zero] = (int8_t)r;
+                        a.zero_pos[a.n_zero] = (uint8_t)pos_e;
+                        a.zero_bit[a.n_zero] = e.second;
+                        ++a.n_zero;
+                        zq |= uint64_t(1) << e.first;
+                    }
+                    z_qubits = __builtin_popcountll(zq);
+                }
+                ln.zskip = a.n_zero > 0 && !fp64 && !pp.has_flip && (pp.R == 4 || pp.R == 5);
+                if (!ln.zskip) {
+                    a.n_zero = 0;
+                    z_qubits = 0;
+                }
                 ln.table_off = table_off;
                 ln.plan_off = be[i].off;
                 ln.prog_words = be[i].words;
@@ -554,9 +581,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 ln.terms_word = be[i].terms_word;
                 ln.grid = (unsigned)std::min<uint64_t>((a.n_tiles + 3) / 4, max_grid);
                 ln.bytes = (uint64_t(1) << n_ext) * elem * (a.src_mode == SRC_INIT ? 1 : 2);
+                if (a.src_mode == SRC_SAME)
+                    ln.bytes = (uint64_t(1) << n_ext) * elem + ((uint64_t(1) << n_ext) * elem >> z_qubits);
                 if (a.src_mode == SRC_FANOUT)
                     ln.bytes = (uint64_t(1) << n_ext) * elem +
-                               (src_read ? src_read : uint64_t(1) << ps) * (uint64_t(1) << qh[h]) * elem;
+                               ((src_read ? src_read : uint64_t(1) << ps) * (uint64_t(1) << qh[h]) * elem >> z_qubits);
                 hl[h].push_back(ln);
             }
         }
@@ -904,8 +933,8 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             if (ln.kind == Launch::PASS && ln.pair_next) {
                 const Launch &l2 = launches[li + 1];
                 timed(0);
-                if ((he = launch_pass_pair(fp64, ln.R, ln.flip, pass_args(ln), ln.grid, pass_args(l2), l2.grid, stream)) !=
-                    hipSuccess)
+                if ((he = launch_pass_pair(fp64, ln.R, ln.flip, ln.zskip || l2.zskip, pass_args(ln), ln.grid,
+                                           pass_args(l2), l2.grid, stream)) != hipSuccess)
                     return dev_err("pass", he);
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes + l2.bytes;
@@ -923,7 +952,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 c.stats.sweep_bytes += ln.bytes;
             } else if (ln.kind == Launch::PASS) {
                 timed(0);
-                if ((he = launch_pass(fp64, ln.R, ln.flip, pass_args(ln), ln.grid, stream)) != hipSuccess)
+                if ((he = launch_pass(fp64, ln.R, ln.flip, ln.zskip, pass_args(ln), ln.grid, stream)) != hipSuccess)
                     return dev_err("pass", he);
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;

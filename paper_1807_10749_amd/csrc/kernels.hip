@@ -263,8 +263,10 @@ __device__ __forceinline__ uint64_t reg_offset(const int32_t (&pos)[6], int j, i
 
 // One pass for workgroup `block` of `nblocks` (see PassArgs).  FLIP: the program may hold
 // per-path flips (crossing iSWAPs); passes without them run the variant that has no code for
-// them, whose register allocation they do not affect.
-template <typename T, int R, bool FLIP>
+// them, whose register allocation they do not affect.  ZSKIP: registers (and lanes) that the
+// source's zero subspace (PassArgs::n_zero) says are zero are set to zero instead of loaded;
+// where a whole cache line is zero its bytes are never fetched.
+template <typename T, int R, bool FLIP, bool ZSKIP = false>
 __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t nblocks)
 {
     using C = typename Cplx<T>::type;
@@ -315,6 +317,25 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
         const uint64_t sp = nx_sp;
         const uint32_t par = nx_par;
 
+        // zero subspace of the source: register j of this lane can be non-zero only if
+        // (j & z_m) == z_v, and none of them if a lane or tile bit disagrees with its path bit
+        bool z_lane = true;
+        uint32_t z_m = 0, z_v = 0;
+        if (ZSKIP) {
+            for (int k = 0; k < a.n_zero; ++k) {
+                const uint32_t sb = (uint32_t)(sp >> a.zero_bit[k]) & 1u;
+                const int r = a.zero_reg[k];
+                if (r >= 0) {
+                    if (((z_m >> r) & 1u) && (((z_v >> r) & 1u) != sb)) z_lane = false;
+                    z_m |= 1u << r;
+                    z_v |= sb << r;
+                } else if (((uint32_t)(eB >> a.zero_pos[k]) & 1u) != sb) {
+                    z_lane = false;
+                }
+            }
+        }
+        auto live = [&](int j) { return !ZSKIP || (z_lane && (((uint32_t)j & z_m) == z_v)); };
+
         C v[N];
         if (a.src_mode == SRC_INIT) {
 #pragma unroll
@@ -334,13 +355,23 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 const C *row = (const C *)a.src + (su + reg_offset<R>(pos, j, a.p_dst, a.p_src));   // uniform
-                v[j] = row[sl];
+                if (live(j)) {
+                    v[j] = row[sl];
+                } else {
+                    v[j].x = T(0);
+                    v[j].y = T(0);
+                }
             }
         } else {
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 const C *row = (const C *)a.src + (et + reg_offset<R>(pos, j, 0, 0));   // uniform
-                v[j] = row[lane];
+                if (live(j)) {
+                    v[j] = row[lane];
+                } else {
+                    v[j].x = T(0);
+                    v[j].y = T(0);
+                }
             }
         }
         {
@@ -388,20 +419,20 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
     }
 }
 
-template <typename T, int R, bool FLIP>
+template <typename T, int R, bool FLIP, bool ZSKIP = false>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
-    pass_body<T, R, FLIP>(a, blockIdx.x, gridDim.x);
+    pass_body<T, R, FLIP, ZSKIP>(a, blockIdx.x, gridDim.x);
 }
 
 // Two independent passes in one launch (block A's and block B's pass of a tree level): the
 // first grid0 workgroups run a0, the rest a1.  The choice is per workgroup, so every wave
 // takes one branch.
-template <typename T, int R, bool FLIP>
+template <typename T, int R, bool FLIP, bool ZSKIP = false>
 __global__ __launch_bounds__(256) void pass_kernel_pair(PassArgs a0, PassArgs a1, uint32_t grid0)
 {
-    if (blockIdx.x < grid0) pass_body<T, R, FLIP>(a0, blockIdx.x, grid0);
-    else pass_body<T, R, FLIP>(a1, blockIdx.x - grid0, gridDim.x - grid0);
+    if (blockIdx.x < grid0) pass_body<T, R, FLIP, ZSKIP>(a0, blockIdx.x, grid0);
+    else pass_body<T, R, FLIP, ZSKIP>(a1, blockIdx.x - grid0, gridDim.x - grid0);
 }
 
 template <typename T, bool FLIP>
@@ -422,10 +453,22 @@ static hipError_t launch_pass_pair_t(int R, const PassArgs &a0, unsigned g0, con
     return hipGetLastError();
 }
 
-hipError_t launch_pass_pair(bool fp64, int R, bool flips, const PassArgs &a0, unsigned grid0, const PassArgs &a1,
-                            unsigned grid1, hipStream_t s)
+// The zero-skipping variants exist for the complex64 passes without flips at R = 4 and 5 (the
+// widths the tuner uses); other passes ignore the zero list, which only ever saves reads.
+static bool zskip_variant(bool zskip, bool fp64, int R, bool flips)
+{
+    return zskip && !fp64 && !flips && (R == 4 || R == 5);
+}
+
+hipError_t launch_pass_pair(bool fp64, int R, bool flips, bool zskip, const PassArgs &a0, unsigned grid0,
+                            const PassArgs &a1, unsigned grid1, hipStream_t s)
 {
     if (grid0 == 0 || grid1 == 0) return hipErrorInvalidValue;
+    if (zskip_variant(zskip, fp64, R, flips)) {
+        if (R == 5) pass_kernel_pair<float, 5, false, true><<<grid0 + grid1, 256, 0, s>>>(a0, a1, grid0);
+        else pass_kernel_pair<float, 4, false, true><<<grid0 + grid1, 256, 0, s>>>(a0, a1, grid0);
+        return hipGetLastError();
+    }
     if (flips)
         return fp64 ? launch_pass_pair_t<double, true>(R, a0, grid0, a1, grid1, s)
                     : launch_pass_pair_t<float, true>(R, a0, grid0, a1, grid1, s);
@@ -449,8 +492,13 @@ static hipError_t launch_pass_t(int R, const PassArgs &a, unsigned grid, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_pass(bool fp64, int R, bool flips, const PassArgs &a, unsigned grid, hipStream_t s)
+hipError_t launch_pass(bool fp64, int R, bool flips, bool zskip, const PassArgs &a, unsigned grid, hipStream_t s)
 {
+    if (zskip_variant(zskip, fp64, R, flips)) {
+        if (R == 5) pass_kernel<float, 5, false, true><<<grid, 256, 0, s>>>(a);
+        else pass_kernel<float, 4, false, true><<<grid, 256, 0, s>>>(a);
+        return hipGetLastError();
+    }
     if (flips)
         return fp64 ? launch_pass_t<double, true>(R, a, grid, s) : launch_pass_t<float, true>(R, a, grid, s);
     return fp64 ? launch_pass_t<double, false>(R, a, grid, s) : launch_pass_t<float, false>(R, a, grid, s);

@@ -15,10 +15,12 @@ constexpr int kMaxRegBitsF64 = 4;
 // Stream one pass over a block state (see PassArgs).  R = register bits
 // (0..kMaxRegBits), fp64 selects complex128 states.
 // flips: the program holds PO_PFLIP_* ops (selects the kernel variant that has code for them)
-hipError_t launch_pass(bool fp64, int R, bool flips, const PassArgs &a, unsigned grid, hipStream_t s);
+// zskip: leave the amplitudes in the source's zero subspace (PassArgs::n_zero) unread, where a
+// variant for (fp64, R, flips) exists; otherwise the list is ignored
+hipError_t launch_pass(bool fp64, int R, bool flips, bool zskip, const PassArgs &a, unsigned grid, hipStream_t s);
 // Two independent passes of the same kernel variant in one launch (grid0 + grid1 workgroups).
-hipError_t launch_pass_pair(bool fp64, int R, bool flips, const PassArgs &a0, unsigned grid0, const PassArgs &a1,
-                            unsigned grid1, hipStream_t s);
+hipError_t launch_pass_pair(bool fp64, int R, bool flips, bool zskip, const PassArgs &a0, unsigned grid0,
+                            const PassArgs &a1, unsigned grid1, hipStream_t s);
 
 // Dense 4-qubit block on matrix cores (complex64 states only).
 hipError_t launch_dense(const DenseArgs &a, unsigned grid, hipStream_t s);

@@ -591,6 +591,25 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
     int taken = 0;
     const int seg_exp = hp.seg_rescale_exp[level];
 
+    // Zero subspace (the paper's zero-block skipping): after the projector P_s of a crossing
+    // gate on qubit t, and until the next non-diagonal gate on t, every amplitude whose bit t
+    // differs from the path bit s is zero.  Pass plans keep the program order of the operations
+    // on each qubit, so the set at the start of a pass follows from the program order of what
+    // ran before it.
+    std::vector<std::pair<uint8_t, uint8_t>> zs;
+    auto zupdate = [&zs](const HalfOp &op) {
+        if (op.kind == HK_PROJ) {
+            const std::pair<uint8_t, uint8_t> e{op.q0, op.bit};
+            if (std::find(zs.begin(), zs.end(), e) == zs.end()) zs.push_back(e);
+        } else if (!is_diag(op.kind)) {
+            zs.erase(std::remove_if(zs.begin(), zs.end(),
+                                    [&op](const std::pair<uint8_t, uint8_t> &e) { return e.first == op.q0; }),
+                     zs.end());
+        }
+    };
+    for (int l = 0; l < level; ++l)
+        for (const HalfOp &op : hp.segments[l]) zupdate(op);
+
     bool first = true;
     const bool dense_ok = dense_m >= 2 && n_ext >= 9 && q >= 4;
     while (first || !rem.empty()) {
@@ -640,6 +659,8 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
                     taken += e;
                     carry -= 2 * e;
                 }
+                pp.zero_in = zs;
+                for (const HalfOp &op : blk) zupdate(op);
                 sp.passes.push_back(std::move(pp));
                 rem.swap(dfr);
                 continue;
@@ -740,6 +761,8 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
             taken += e;
             carry -= 2 * e;
         }
+        pp.zero_in = zs;
+        for (const HalfOp &op : sched) zupdate(op);
         sp.passes.push_back(std::move(pp));
         rem.swap(defer);
     }

@@ -66,6 +66,8 @@ enum SrcMode : int32_t { SRC_SAME = 0, SRC_INIT = 1, SRC_FANOUT = 2 };
 // it in LDS once per workgroup so the per-tile interpreter never touches
 // global memory for it.
 constexpr int kMaxProgWords = 2048;
+// Most known-zero entries a pass carries (a subset of the true zeros is always valid).
+constexpr int kMaxZeroEntries = 4;
 
 struct PassArgs {
     void *dst;
@@ -91,6 +93,15 @@ struct PassArgs {
     int32_t n_low, n_skip;
     int32_t low_pos[4];
     int32_t skip_pos[10];
+    // Known zeros of the source state (zero-subspace skipping): the amplitude at extended
+    // index e is zero unless, for every entry k < n_zero, the bit of e that holds qubit
+    // zero_pos[k] (destination layout) equals bit zero_bit[k] of the slot's path id.  Entries
+    // with zero_reg[k] >= 0 sit on register bit zero_reg[k]; the others on lane or tile bits.
+    // A kernel built for it leaves such amplitudes unread; any other kernel ignores the list.
+    int32_t n_zero;
+    int8_t zero_reg[kMaxZeroEntries];
+    uint8_t zero_pos[kMaxZeroEntries];
+    uint8_t zero_bit[kMaxZeroEntries];
 };
 
 // Dense fused block: a 2^4 x 2^4 complex matrix U applied to four qubits (extended bit

@@ -44,6 +44,10 @@ struct PassPlan {
     int rescale_exp = 0;            // divide by 2^rescale_exp at the end of the pass
     bool needs_slot_path = false;   // has path-dependent terms
     bool has_flip = false;          // has per-path flips (PO_PFLIP_*)
+    // Zero subspace of the pass's input: (local qubit t, path bit u) pairs such that every
+    // amplitude whose bit t differs from path bit u is zero (a projector on t applied, and no
+    // non-diagonal gate on t since)
+    std::vector<std::pair<uint8_t, uint8_t>> zero_in;
     // dense pass (matrix cores): a 16 x 16 block on four qubits instead of the op list
     bool dense = false;
     int bpos[4] = {0, 0, 0, 0};     // extended bit positions, ascending
