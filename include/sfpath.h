@@ -240,8 +240,11 @@ int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);
  * describe_plan: human-readable summary of the block programs: per tree level
  * and block the number of operations and of fused passes, planned for the
  * slot count an all-paths run uses at that level (2^bits, capped by the
- * tuning).  Host only, no device work.  Writes a NUL-terminated string of
- * at most cap bytes.
+ * tuning).  Each pass reads "<non-diagonal gates>g/<diagonal groups>d" (or
+ * "dense"), with "/z<N>" when its source state has a known zero subspace on N
+ * projected qubits (Section 2 zero blocks: a crossing gate's projector not yet
+ * followed by a non-diagonal gate on its qubit).  Host only, no device work.
+ * Writes a NUL-terminated string of at most cap bytes.
  */
 int describe_plan(sf_circuit_t *c, char *out, size_t cap);
 

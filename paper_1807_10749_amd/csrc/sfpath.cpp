@@ -474,9 +474,14 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
                 for (const sf::HalfOp &op : c->half[h].segments[l]) nd += sf::is_diag(op.kind) ? 0 : 1;
                 s += std::string(h ? "  B " : " A ") + std::to_string(c->half[h].segments[l].size()) + " ops (" +
                      std::to_string(nd) + " non-diag) " + std::to_string(sp.passes.size()) + " passes [";
-                for (size_t i = 0; i < sp.passes.size(); ++i)
+                for (size_t i = 0; i < sp.passes.size(); ++i) {
+                    // zN: the pass reads a source whose zero subspace spans N projected qubits
+                    uint64_t zq = 0;
+                    for (const auto &e : sp.passes[i].zero_in) zq |= uint64_t(1) << e.first;
                     s += (i ? "," : "") + std::to_string(sp.passes[i].n_nondiag) + "g/" +
-                         (sp.passes[i].dense ? std::string("dense") : std::to_string(sp.passes[i].groups.size()) + "d");
+                         (sp.passes[i].dense ? std::string("dense") : std::to_string(sp.passes[i].groups.size()) + "d") +
+                         (zq ? "/z" + std::to_string(__builtin_popcountll(zq)) : std::string());
+                }
                 s += "]";
             }
             s += "\n";

@@ -287,3 +287,52 @@ def test_tuning_cache_file_roundtrip(sf, tmp_path):
         sf.load_tuning_cache(str(tmp_path / "missing.txt"))
     with pytest.raises(sf.SFError):
         sf.save_tuning_cache(str(tmp_path / "no_such_dir" / "x.txt"))
+
+
+def _plan_parts(plan):
+    """(level, block A part, block B part) of each describe_plan level line."""
+    out = []
+    for line in plan.splitlines():
+        m = re.match(r"level (\d+) .*?: A (.*?)  B (.*)$", line)
+        if m:
+            out.append((int(m.group(1)), m.group(2), m.group(3)))
+    return out
+
+
+def test_zero_subspace_marked_in_plan(sf):
+    """Section 2 zero blocks: after a crossing CZ's projector on a block-A qubit, and until the
+    next non-diagonal gate on that qubit, half of block A's amplitudes are zero; block B gets no
+    projector (its branch operator is Z), so it never has such zeros (the paper's zero counts
+    are on A only).  The planner marks passes whose source has them with /z<qubits>."""
+    from workload.generator import T
+    # 2x2 grid, qubits 0 1 / 2 3, A = column 0 = {0, 2}; the second crossing CZ is on qubit 0
+    # again, so the final H on qubit 0 cannot move up to level 1
+    def circ(mix_between):
+        g = [(H, 0, 0, q, 0) for q in range(4)]
+        g.append((CZ, 0, 1, 0, 1))                       # crossing: level 1, projector on qubit 0
+        g.append((T, 0, 2, 0, 0))                        # diagonal: keeps the zeros
+        g.append((H, 0, 2, 2, 0))                        # other qubit: keeps the zeros
+        if mix_between:
+            g.append((H, 0, 3, 0, 0))                    # non-diagonal on qubit 0: mixes them
+        g.append((CZ, 0, 4, 0, 1))                       # crossing: level 2
+        g.append((H, 0, 5, 0, 0))
+        g.append((H, 0, 5, 2, 0))
+        return np.array(g, dtype=GATE_DTYPE)
+    for mix, want in ((False, True), (True, False)):
+        c = sf.create_circuit(2, 2, circ(mix))
+        sf.set_cut(c, 0b0101)
+        sf.set_tuning(c, no_leaf_fold=1)
+        parts = _plan_parts(sf.describe_plan(c))
+        lvl2 = [p for p in parts if p[0] == 2]
+        assert lvl2, parts
+        assert ("/z1" in lvl2[0][1]) == want, (mix, parts)
+        assert all("/z" not in b for _, _, b in parts), parts
+        sf.destroy_circuit(c)
+    # the benchmark circuit: block A's fan-outs into levels 3 and 4 read a half-zero state
+    cfg = CONFIGS["grid5x6_d24"]
+    c = sf.create_circuit(cfg.rows, cfg.cols, grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed))
+    sf.set_cut(c, cfg.cut_mask())
+    parts = _plan_parts(sf.describe_plan(c))
+    assert all("/z" not in b for _, _, b in parts), parts
+    assert any("/z" in a for _, a, _ in parts), parts
+    sf.destroy_circuit(c)
