@@ -475,12 +475,15 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         return off;
     };
 
-    // src_read: parent slots a fan-out actually reads (distinct parents of its children), for
-    // the byte count; 0 = all src_slots
-    auto add_segment = [&](int level, uint64_t nslots, const size_t dst[2], int mode, const size_t src[2],
-                           uint64_t src_slots, size_t table_off, int n_low = 0, int low_first = 0,
-                           uint64_t src_read = 0) {
+    // n_real: slots in use (the rest of the nslots pad the batch to a power of two); src_read:
+    // parent slots a fan-out actually reads (distinct parents of its children), for the byte
+    // count, 0 = all src_slots
+    auto add_segment = [&](int level, uint64_t nslots, uint64_t n_real, const size_t dst[2], int mode,
+                           const size_t src[2], uint64_t src_slots, size_t table_off, int n_low = 0,
+                           int low_first = 0, uint64_t src_read = 0) {
         const int p = log2u(nslots);
+        const uint64_t slots_real = n_real && n_real < nslots ? n_real : 0;
+        const uint64_t used = slots_real ? slots_real : nslots;
         const int ps = log2u(src_slots);
         std::vector<Launch> hl[2];      // each block's launches of this segment, in order
         for (int h = 0; h < 2; ++h) {
@@ -498,12 +501,14 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                     std::memset(&ln.da, 0, sizeof(ln.da));
                     ln.da.n_groups = uint64_t(1) << (n_ext - 9);
                     ln.da.rescale = std::ldexp(1.0, -pp.rescale_exp);
+                    ln.da.p = p;
+                    ln.da.slots_real = slots_real;
                     for (int t = 0; t < 4; ++t) ln.da.bpos[t] = pp.bpos[t];
                     ln.dst_off = dst[h];
                     ln.src_off = dst[h];
                     ln.plan_off = be[i].off;
                     ln.grid = (unsigned)std::min<uint64_t>((ln.da.n_groups + 3) / 4, max_grid);
-                    ln.bytes = (uint64_t(1) << n_ext) * elem * 2;
+                    ln.bytes = used * (uint64_t(1) << qh[h]) * elem * 2;
                     hl[h].push_back(ln);
                     continue;
                 }
@@ -521,6 +526,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 a.p_src = p;
                 a.src_mode = SRC_SAME;
                 a.rescale = std::ldexp(1.0, -pp.rescale_exp);
+                a.slots_real = slots_real;
                 for (int kk = 0; kk < 6; ++kk) a.reg_pos[kk] = pp.reg_pos[kk];
                 {
                     // sibling bits as the lowest tile bits (first pass of a regular fan-out only)
@@ -580,12 +586,13 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 ln.groups_word = be[i].groups_word;
                 ln.terms_word = be[i].terms_word;
                 ln.grid = (unsigned)std::min<uint64_t>((a.n_tiles + 3) / 4, max_grid);
-                ln.bytes = (uint64_t(1) << n_ext) * elem * (a.src_mode == SRC_INIT ? 1 : 2);
-                if (a.src_mode == SRC_SAME)
-                    ln.bytes = (uint64_t(1) << n_ext) * elem + ((uint64_t(1) << n_ext) * elem >> z_qubits);
+                // algorithmic bytes over the slots in use: the state written once, the source read
+                // once (its non-zero part)
+                const uint64_t state_bytes = used * (uint64_t(1) << qh[h]) * elem;
+                ln.bytes = state_bytes;
+                if (a.src_mode == SRC_SAME) ln.bytes += state_bytes >> z_qubits;
                 if (a.src_mode == SRC_FANOUT)
-                    ln.bytes = (uint64_t(1) << n_ext) * elem +
-                               ((src_read ? src_read : uint64_t(1) << ps) * (uint64_t(1) << qh[h]) * elem >> z_qubits);
+                    ln.bytes += (src_read ? src_read : uint64_t(1) << ps) * (uint64_t(1) << qh[h]) * elem >> z_qubits;
                 hl[h].push_back(ln);
             }
         }
@@ -716,7 +723,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             const size_t toff = put_tables(pv, pz, nslots);
             batches.push_back(BatchRec{l + 1, toff, nslots});
             const size_t base[2] = {lb[own].off[0], lb[own].off[1]};
-            add_segment(l + 1, nslots, base, SRC_SAME, base, nslots, toff);
+            add_segment(l + 1, nslots, nodes.size(), base, SRC_SAME, base, nslots, toff);
             visit(l + 1, ch, nslots);
             return;
         }
@@ -766,7 +773,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             const size_t toff = put_tables(pv, par, ns);
             batches.push_back(BatchRec{l + 1, toff, ns});
             const size_t dst[2] = {cb.off[0], cb.off[1]};
-            add_segment(l + 1, ns, dst, SRC_FANOUT, src, nslots, toff, n_low, log2u(nslots), n_read);
+            add_segment(l + 1, ns, a1 - a0, dst, SRC_FANOUT, src, nslots, toff, n_low, log2u(nslots), n_read);
             visit(l + 1, ch, ns);
             if (plan_error) return;
         }
@@ -799,7 +806,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         const size_t toff = put_tables(std::vector<uint64_t>{0}, std::vector<uint32_t>{0}, ns0);
         batches.push_back(BatchRec{0, toff, ns0});
         const size_t base0[2] = {lb[0].off[0], lb[0].off[1]};
-        add_segment(0, ns0, base0, SRC_INIT, base0, ns0, toff);
+        add_segment(0, ns0, 1, base0, SRC_INIT, base0, ns0, toff);
         visit(0, std::vector<uint32_t>{0}, ns0);
     }
     if (plan_error) { err = "internal: a segment could not be scheduled into passes"; return SF_ERR_UNSUPPORTED; }

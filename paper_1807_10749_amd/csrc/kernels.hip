@@ -313,6 +313,17 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
     }
     for (; tile < a.n_tiles; tile += nwaves) {
         const uint64_t et = tile_base(tile);
+        if (a.slots_real && (et & pmask_dst) >= a.slots_real) {
+            // every slot of the tile is padding (the lane bits are the 6 lowest slot bits):
+            // only fetch the next tile's tables
+            const uint64_t nt = tile + nwaves;
+            if (nt < a.n_tiles) {
+                const uint64_t slot = (tile_base(nt) | lane) & pmask_dst;
+                nx_sp = a.slot_path[slot];
+                if (fan) nx_par = a.slot_parent[slot];
+            }
+            continue;
+        }
         const uint64_t eB = et | (uint64_t)lane;     // this lane's amplitude with register bits 0
         const uint64_t sp = nx_sp;
         const uint32_t par = nx_par;
@@ -539,6 +550,8 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a)
             const int p = a.bpos[t];
             et = ((et >> p) << (p + 1)) | (et & (((uint64_t)1 << p) - 1u));
         }
+        // 32 columns of padding slots (the 5 lowest extended bits are slot bits when p >= 5)
+        if (a.slots_real && (et & ((((uint64_t)1) << a.p) - 1u)) >= a.slots_real) continue;
         const float2 *src = (const float2 *)a.src + et + col;
         float2 v[8];
 #pragma unroll

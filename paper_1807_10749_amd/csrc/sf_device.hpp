@@ -98,6 +98,10 @@ struct PassArgs {
     // zero_pos[k] (destination layout) equals bit zero_bit[k] of the slot's path id.  Entries
     // with zero_reg[k] >= 0 sit on register bit zero_reg[k]; the others on lane or tile bits.
     // A kernel built for it leaves such amplitudes unread; any other kernel ignores the list.
+    // Slots in use (the rest pad the batch to a power of two; 0 = all): a tile whose 64 slots
+    // all lie beyond them is neither read nor written.  Lanes and registers never mix slots, so
+    // padding never reaches a slot in use.
+    uint64_t slots_real;
     int32_t n_zero;
     int8_t zero_reg[kMaxZeroEntries];
     uint8_t zero_pos[kMaxZeroEntries];
@@ -115,6 +119,8 @@ struct DenseArgs {
     uint64_t n_groups;            // 2^(n_ext - 9): groups of 32 columns
     double rescale;
     int32_t bpos[4];
+    int32_t p;                    // slot bits
+    uint64_t slots_real;          // slots in use (0 = all): groups of padding slots are skipped
 };
 
 struct GatherArgs {
