@@ -221,7 +221,10 @@ typedef struct {
     double ms_other;         /* init, pext, zero fill */
     uint64_t n_sweep_launches;
     uint64_t n_gather_launches;
-    uint64_t sweep_bytes;    /* algorithmic bytes: read + written by sweep passes */
+    uint64_t sweep_bytes;    /* algorithmic bytes of the sweep passes: each writes the slots in
+                                use of its state once and reads its source once (a fan-out: the
+                                parent slots of its children; amplitudes in a known zero
+                                subspace excluded) */
     uint64_t gather_bytes;   /* algorithmic bytes of gather launches in their visiting order:
                                 block-A rows once per group of bitstrings that read the same
                                 block-A rows, block-B rows once per bitstring, plus indices
