@@ -290,10 +290,15 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool fan = a.src_mode == SRC_FANOUT;
     const uint32_t pmax = (1u << a.p_src) - 1u;
+    // this lane's part of the extended index: the lane number, or its 5 low bits plus bit 5 at
+    // lane_qpos
+    const bool lq = a.lane_qpos > 0;
+    const uint64_t lx = lq ? ((uint64_t)(lane & 31u) | ((uint64_t)(lane >> 5) << a.lane_qpos)) : (uint64_t)lane;
+    const int lane_bits = lq ? 5 : 6;
     auto tile_base = [&](uint64_t tile) {
         // wave-uniform part of the extended index: the low tile bits go to low_pos, the rest
         // is spread around the register and low positions
-        uint64_t et = (tile >> a.n_low) << 6;
+        uint64_t et = (tile >> a.n_low) << lane_bits;
         for (int k = 0; k < a.n_skip; ++k) {
             const int p = a.skip_pos[k];
             et = ((et >> p) << (p + 1)) | (et & (((uint64_t)1 << p) - 1u));
@@ -307,24 +312,24 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
     uint64_t nx_sp = 0;
     uint32_t nx_par = 0;
     if (tile < a.n_tiles) {
-        const uint64_t slot = (tile_base(tile) | lane) & pmask_dst;
+        const uint64_t slot = (tile_base(tile) | lx) & pmask_dst;
         nx_sp = a.slot_path[slot];
         if (fan) nx_par = a.slot_parent[slot];
     }
     for (; tile < a.n_tiles; tile += nwaves) {
         const uint64_t et = tile_base(tile);
         if (a.slots_real && (et & pmask_dst) >= a.slots_real) {
-            // every slot of the tile is padding (the lane bits are the 6 lowest slot bits):
+            // every slot of the tile is padding (the lane bits hold the 5 or 6 lowest slot bits):
             // only fetch the next tile's tables
             const uint64_t nt = tile + nwaves;
             if (nt < a.n_tiles) {
-                const uint64_t slot = (tile_base(nt) | lane) & pmask_dst;
+                const uint64_t slot = (tile_base(nt) | lx) & pmask_dst;
                 nx_sp = a.slot_path[slot];
                 if (fan) nx_par = a.slot_parent[slot];
             }
             continue;
         }
-        const uint64_t eB = et | (uint64_t)lane;     // this lane's amplitude with register bits 0
+        const uint64_t eB = et | lx;                 // this lane's amplitude with register bits 0
         const uint64_t sp = nx_sp;
         const uint32_t par = nx_par;
 
@@ -359,10 +364,10 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
             // parent slot inside the source batch; clamped so padded slots stay in bounds
             uint32_t ps = par - a.slot_parent_base;
             ps = ps > pmax ? pmax : ps;
-            // source index = ((et >> p_dst) << p_src) + ((lane >> p_dst) << p_src) + ps: the first
-            // term is wave-uniform (et has zeros in bits 0..5), the rest a small per-lane offset
+            // source index = ((et >> p_dst) << p_src) + ((lx >> p_dst) << p_src) + ps: the first
+            // term is wave-uniform (et has zeros at the lane bits), the rest a per-lane offset
             const uint64_t su = (et >> a.p_dst) << a.p_src;
-            const uint32_t sl = ((lane >> a.p_dst) << a.p_src) + ps;
+            const uint64_t sl = ((lx >> a.p_dst) << a.p_src) + ps;
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 const C *row = (const C *)a.src + (su + reg_offset<R>(pos, j, a.p_dst, a.p_src));   // uniform
@@ -378,7 +383,7 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
             for (int j = 0; j < N; ++j) {
                 const C *row = (const C *)a.src + (et + reg_offset<R>(pos, j, 0, 0));   // uniform
                 if (live(j)) {
-                    v[j] = row[lane];
+                    v[j] = row[lx];
                 } else {
                     v[j].x = T(0);
                     v[j].y = T(0);
@@ -388,7 +393,7 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
         {
             const uint64_t nt = tile + nwaves;
             if (nt < a.n_tiles) {
-                const uint64_t slot = (tile_base(nt) | lane) & pmask_dst;
+                const uint64_t slot = (tile_base(nt) | lx) & pmask_dst;
                 nx_sp = a.slot_path[slot];
                 if (fan) nx_par = a.slot_parent[slot];
             }
@@ -425,7 +430,7 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             C *row = (C *)a.dst + (et + reg_offset<R>(pos, j, 0, 0));   // uniform
-            row[lane] = v[j];
+            row[lx] = v[j];
         }
     }
 }

@@ -102,6 +102,11 @@ struct PassArgs {
     // all lie beyond them is neither read nor written.  Lanes and registers never mix slots, so
     // padding never reaches a slot in use.
     uint64_t slots_real;
+    // Lane bits: with lane_qpos = 0 the 6 lowest extended bits; otherwise (every lane bit would be
+    // a slot bit, p_dst >= 6) the 5 lowest, and lane bit 5 holds extended bit lane_qpos (a qubit),
+    // so a pass applies gates to one more qubit; each load and store then covers two runs of 32
+    // consecutive amplitudes.  Bit 5 then comes from the tile index, and lane_qpos is in skip_pos.
+    int32_t lane_qpos;
     int32_t n_zero;
     int8_t zero_reg[kMaxZeroEntries];
     uint8_t zero_pos[kMaxZeroEntries];
