@@ -49,7 +49,7 @@ def _case(i):
     return rows, cols, g, mask, kind, tuning, fp64, rng
 
 
-@pytest.mark.parametrize("i", range(120))
+@pytest.mark.parametrize("i", range(600))
 def test_random_circuit(sf, i):
     rows, cols, g, mask, kind, tuning, fp64, rng = _case(i)
     n = rows * cols
