@@ -76,3 +76,35 @@ def test_random_circuit(sf, i):
     err = c11_error(a, o, ids.size, k, n)
     assert err <= (TOL_C128 if fp64 else TOL_C64), (i, err)
     c.close()
+
+
+def _large_case(i):
+    """Larger blocks (up to 15 qubits) and sparse path subsets, so levels hold 64 or more slots:
+    passes with a qubit in lane bit 5, zero-subspace loads and tiles of padding slots occur."""
+    rng = np.random.default_rng(19000 + i)
+    rows, cols = int(rng.integers(4, 6)), int(rng.integers(4, 7))
+    depth = int(rng.integers(16, 33))
+    kind = ("cz", "cz", "iswap")[int(rng.integers(0, 3))]
+    g = grid_circuit(rows, cols, depth, 1500 + i, two_qubit=ISWAP if kind == "iswap" else CZ)
+    mask = column_cut_mask(rows, cols, cols // 2)
+    tuning = dict(reg_qubits=int(rng.integers(4, 6)), dense_qubits=int(rng.choice([0, 4])),
+                  no_leaf_fold=int(rng.integers(0, 2)))
+    return rows, cols, g, mask, kind, tuning, rng
+
+
+@pytest.mark.parametrize("i", range(24))
+def test_random_large_blocks(sf, i):
+    rows, cols, g, mask, kind, tuning, rng = _large_case(i)
+    n = rows * cols
+    c = sf.Circuit(rows, cols, g, mask)
+    c.tune(**tuning)
+    k = c.k
+    m = int(rng.integers(150, 401))
+    ids = np.unique(rng.integers(0, 1 << k, m).astype(np.uint64)) if k > 8 else np.arange(1 << k, dtype=np.uint64)
+    bits = random_bitstrings(n, 96, 17000 + i)
+    say(f"large case {i}: {rows}x{cols} {kind} k={k} paths={ids.size} {tuning}")
+    a = c.amplitudes(bits, path_ids=ids)
+    o = oracle.path_sum(n, g, mask, ids, bits)
+    err = c11_error(a, o, ids.size, k, n)
+    assert err <= TOL_C64, (i, err)
+    c.close()
