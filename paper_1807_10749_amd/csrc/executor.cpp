@@ -529,10 +529,12 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 a.slots_real = slots_real;
                 for (int kk = 0; kk < 6; ++kk) a.reg_pos[kk] = pp.reg_pos[kk];
                 a.lane_qpos = pp.lane_q >= 0 ? p + pp.lane_q : 0;
+                a.lane_qpos4 = pp.lane_q >= 0 && pp.lane_q4 >= 0 ? p + pp.lane_q4 : 0;
                 {
                     // sibling bits as the lowest tile bits (first pass of a regular fan-out only)
                     std::vector<int> skip(pp.reg_pos, pp.reg_pos + pp.R);
                     if (pp.lane_q >= 0) skip.push_back(p + pp.lane_q);
+                    if (pp.lane_q >= 0 && pp.lane_q4 >= 0) skip.push_back(p + pp.lane_q4);
                     a.n_low = 0;
                     if (i == 0 && mode == SRC_FANOUT && n_low > 0)
                         for (int t = 0; t < n_low; ++t) {

@@ -290,11 +290,13 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool fan = a.src_mode == SRC_FANOUT;
     const uint32_t pmax = (1u << a.p_src) - 1u;
-    // this lane's part of the extended index: the lane number, or its 5 low bits plus bit 5 at
-    // lane_qpos
-    const bool lq = a.lane_qpos > 0;
-    const uint64_t lx = lq ? ((uint64_t)(lane & 31u) | ((uint64_t)(lane >> 5) << a.lane_qpos)) : (uint64_t)lane;
-    const int lane_bits = lq ? 5 : 6;
+    // this lane's part of the extended index: the lane number, or its low bits plus bit 5 at
+    // lane_qpos (and bit 4 at lane_qpos4)
+    const bool lq = a.lane_qpos > 0, lq4 = lq && a.lane_qpos4 > 0;
+    const int lane_bits = lq4 ? 4 : lq ? 5 : 6;
+    const uint64_t lx = !lq ? (uint64_t)lane
+                            : ((uint64_t)(lane & ((1u << lane_bits) - 1u)) | ((uint64_t)(lane >> 5) << a.lane_qpos) |
+                               (lq4 ? (uint64_t)((lane >> 4) & 1u) << a.lane_qpos4 : 0));
     auto tile_base = [&](uint64_t tile) {
         // wave-uniform part of the extended index: the low tile bits go to low_pos, the rest
         // is spread around the register and low positions
@@ -319,7 +321,7 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
     for (; tile < a.n_tiles; tile += nwaves) {
         const uint64_t et = tile_base(tile);
         if (a.slots_real && (et & pmask_dst) >= a.slots_real) {
-            // every slot of the tile is padding (the lane bits hold the 5 or 6 lowest slot bits):
+            // every slot of the tile is padding (the lane bits hold the 4 to 6 lowest slot bits):
             // only fetch the next tile's tables
             const uint64_t nt = tile + nwaves;
             if (nt < a.n_tiles) {

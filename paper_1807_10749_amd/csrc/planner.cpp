@@ -566,9 +566,9 @@ std::vector<float> dense_matrix(const std::vector<HalfOp> &ops, const int qs[4])
 
 }  // namespace
 
-// The passes of one block over one tree level.  allow_lq: a pass may keep one qubit in lane bit 5
-// when the slots fill all six lane bits (PassArgs::lane_qpos).
-static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, int R, int dense_m, bool allow_lq)
+// The passes of one block over one tree level.  max_lq: a pass may keep up to this many qubits
+// (0..2) in lane bits 5 and 4 when the slots fill all six lane bits (PassArgs::lane_qpos).
+static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, int R, int dense_m, int max_lq)
 {
     const HalfProgram &hp = c.half[half];
     const int q = hp.q;
@@ -670,18 +670,20 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
         std::vector<HalfOp> sched, defer;
         uint64_t blocked = 0;
         // when the slots fill all six lane bits, lane bit 5 may hold one qubit (PassArgs::lane_qpos)
-        int lq = -1;
-        const bool lq_ok = allow_lq && n_lane_q == 0 && p >= 6 && q > R_eff;
+        int lq = -1, lq4 = -1;
+        const bool lq_ok = max_lq >= 1 && n_lane_q == 0 && p >= 6 && q > R_eff;
+        const bool lq4_ok = lq_ok && max_lq >= 2 && q > R_eff + 1;
         for (const HalfOp &op : rem) {
             const uint64_t qm = (uint64_t(1) << op.q0) | (op.kind == HK_CZ ? uint64_t(1) << op.q1 : 0);
             if (qm & blocked) { defer.push_back(op); blocked |= qm; continue; }
             if (!is_diag(op.kind)) {
                 const int t = op.q0;
-                const bool lane = t < n_lane_q || t == lq;
+                const bool lane = t < n_lane_q || t == lq || t == lq4;
                 const bool have = std::find(regq.begin(), regq.end(), t) != regq.end();
                 if (lane || have) { sched.push_back(op); continue; }
                 if ((int)regq.size() < R_eff) { regq.push_back(t); sched.push_back(op); continue; }
                 if (lq_ok && lq < 0) { lq = t; sched.push_back(op); continue; }
+                if (lq4_ok && lq4 < 0) { lq4 = t; sched.push_back(op); continue; }
                 defer.push_back(op);
                 blocked |= qm;
                 continue;
@@ -695,10 +697,11 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
         }
         // pad the register bits with untouched qubits so every tile holds 64 * 2^R_eff amplitudes
         for (int t = q - 1; t >= n_lane_q && (int)regq.size() < R_eff; --t)
-            if (t != lq && std::find(regq.begin(), regq.end(), t) == regq.end()) regq.push_back(t);
+            if (t != lq && t != lq4 && std::find(regq.begin(), regq.end(), t) == regq.end()) regq.push_back(t);
         std::sort(regq.begin(), regq.end());
         pp.R = (int)regq.size();
         pp.lane_q = lq;
+        pp.lane_q4 = lq4;
         int kidx[64];
         for (int i = 0; i < 64; ++i) kidx[i] = -1;
         for (int k = 0; k < pp.R; ++k) {
@@ -711,8 +714,9 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
                 const uint64_t qm = uint64_t(1) << op.q0;
                 if (pd.touched & qm) flush(pd, pp, kidx);
                 PassOp po;
-                const bool lane = op.q0 < n_lane_q || op.q0 == lq;
-                po.target = op.q0 == lq ? (uint8_t)5 : lane ? (uint8_t)(p + op.q0) : (uint8_t)kidx[p + op.q0];
+                const bool lane = op.q0 < n_lane_q || op.q0 == lq || op.q0 == lq4;
+                po.target = op.q0 == lq ? (uint8_t)5 : op.q0 == lq4 ? (uint8_t)4
+                                                      : lane ? (uint8_t)(p + op.q0) : (uint8_t)kidx[p + op.q0];
                 po.pad = 0;
                 if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) {
                     po.type = lane ? PO_PFLIP_LANE : PO_PFLIP_REG;
@@ -778,13 +782,14 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
     const auto key = std::make_tuple(half, level, p, R, dense_m);
     auto it = c.plan_cache.find(key);
     if (it != c.plan_cache.end()) return it->second;
-    // a qubit in lane bit 5 halves the contiguous runs of a load (two of 32 amplitudes): use it
-    // only where it saves a pass
-    SegmentPlan sp = plan_segment(c, half, level, p, R, dense_m, false);
-    if (p >= 6) {
-        SegmentPlan lq = plan_segment(c, half, level, p, R, dense_m, true);
-        if (lq.ok && (!sp.ok || lq.passes.size() < sp.passes.size())) sp = std::move(lq);
-    }
+    // a qubit in a lane bit splits the contiguous runs of a load (two of 32 amplitudes, or four
+    // of 16 = one cache line each with two): use one or two only where that saves a pass
+    SegmentPlan sp = plan_segment(c, half, level, p, R, dense_m, 0);
+    if (p >= 6)
+        for (int m = 1; m <= 2; ++m) {
+            SegmentPlan lq = plan_segment(c, half, level, p, R, dense_m, m);
+            if (lq.ok && (!sp.ok || lq.passes.size() < sp.passes.size())) sp = std::move(lq);
+        }
     auto res = c.plan_cache.emplace(key, std::move(sp));
     return res.first->second;
 }

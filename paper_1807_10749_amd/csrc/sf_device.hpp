@@ -103,10 +103,12 @@ struct PassArgs {
     // padding never reaches a slot in use.
     uint64_t slots_real;
     // Lane bits: with lane_qpos = 0 the 6 lowest extended bits; otherwise (every lane bit would be
-    // a slot bit, p_dst >= 6) the 5 lowest, and lane bit 5 holds extended bit lane_qpos (a qubit),
-    // so a pass applies gates to one more qubit; each load and store then covers two runs of 32
-    // consecutive amplitudes.  Bit 5 then comes from the tile index, and lane_qpos is in skip_pos.
+    // a slot bit, p_dst >= 6) lane bit 5 holds extended bit lane_qpos (a qubit), and with
+    // lane_qpos4 > 0 lane bit 4 holds extended bit lane_qpos4 too, so a pass applies gates to one
+    // or two more qubits; each load and store then covers two runs of 32 (four of 16) consecutive
+    // amplitudes.  The displaced slot bits come from the tile index; the positions are in skip_pos.
     int32_t lane_qpos;
+    int32_t lane_qpos4;
     int32_t n_zero;
     int8_t zero_reg[kMaxZeroEntries];
     uint8_t zero_pos[kMaxZeroEntries];

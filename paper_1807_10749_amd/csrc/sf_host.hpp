@@ -49,6 +49,7 @@ struct PassPlan {
     // non-diagonal gate on t since)
     std::vector<std::pair<uint8_t, uint8_t>> zero_in;
     int lane_q = -1;                // local qubit held by lane bit 5 (when the slots fill all lane bits)
+    int lane_q4 = -1;               // local qubit held by lane bit 4 (only with lane_q)
     // dense pass (matrix cores): a 16 x 16 block on four qubits instead of the op list
     bool dense = false;
     int bpos[4] = {0, 0, 0, 0};     // extended bit positions, ascending
