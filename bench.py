@@ -389,8 +389,11 @@ def serving_bench(n_jobs, workers=4, chunk_paths=16384, seed=5005):
     Jobs (grid 4x5..6x6, depth 1+16+1..1+32+1, 1e3..1e5 bitstrings, f in
     {0.01, 0.1, 1}) are served by the library's server (continuous batching over
     `workers` streams).  References on the same jobs: the batched form run one
-    job at a time, and the plain one-path-per-launch form run one job at a time
-    (timed on up to 8 paths per job and scaled to the job's path count).
+    job at a time (its throughput, and the latencies a FIFO queue of those
+    measured run times gives under the same arrivals), and the plain
+    one-path-per-launch form run one job at a time (timed on up to 8 paths per
+    job and scaled to the job's path count).  A second served run submits every
+    job at once, for the throughput of a saturated server.
     """
     import math
     from paper_1807_10749_amd import binding as sf
@@ -444,30 +447,54 @@ def serving_bench(n_jobs, workers=4, chunk_paths=16384, seed=5005):
         u = ((rng.next() >> 11) + 1) * (1.0 / (1 << 53))
         t += -math.log(u) / rate
         arrivals.append(t)
-    srv = sf.server_create(arena, None, workers, chunk_paths)
-    t0 = time.perf_counter()
-    jids = []
+    def served(arr):
+        """Submit job i at arr[i] seconds (all at once when arr is all zeros), drain, and return
+        the latencies, the first submit and last completion times, the largest relative
+        difference from the one-at-a-time results, and the server's counters."""
+        srv = sf.server_create(arena, None, workers, chunk_paths)
+        t0 = time.perf_counter()
+        jids = []
+        for i in range(n_jobs):
+            dt = arr[i] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            jids.append(submit(srv, i))
+        sf.server_drain(srv)
+        lat, first, last, dev = [], 1e300, 0.0, 0.0
+        for i, jid in enumerate(jids):
+            done, a, info = sf.server_poll(srv, jid, specs[i]["n_bits"])
+            lat.append(info["t_done"] - info["t_submit"])
+            first, last = min(first, info["t_submit"]), max(last, info["t_done"])
+            ref = seq_res[i]
+            dev = max(dev, float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)))
+        st = sf.server_stats(srv)
+        sf.server_destroy(srv)
+        return sorted(lat), first, last, dev, st
+
+    def pct(lat, q):
+        return lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+
+    lat, first, last, dev, st = served(arrivals)
+    # the one-at-a-time form under the same arrivals: a FIFO queue whose service times are the
+    # measured one-at-a-time run times of the same jobs
+    fifo, free = [], 0.0
     for i in range(n_jobs):
-        dt = arrivals[i] - (time.perf_counter() - t0)
-        if dt > 0:
-            time.sleep(dt)
-        jids.append(submit(srv, i))
-    sf.server_drain(srv)
-    lat, first, last, dev = [], 1e300, 0.0, 0.0
-    for i, jid in enumerate(jids):
-        done, a, info = sf.server_poll(srv, jid, specs[i]["n_bits"])
-        lat.append(info["t_done"] - info["t_submit"])
-        first, last = min(first, info["t_submit"]), max(last, info["t_done"])
-        ref = seq_res[i]
-        dev = max(dev, float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)))
-    st = sf.server_stats(srv)
-    sf.server_destroy(srv)
-    lat.sort()
-    pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+        start = max(arrivals[i], free)
+        free = start + seq_t[i]
+        fifo.append(free - arrivals[i])
+    fifo.sort()
+    # saturated: every job submitted at once, so the device always has admitted work queued
+    sat_lat, sat_first, sat_last, sat_dev, sat_st = served([0.0] * n_jobs)
     return {"jobs": n_jobs, "workers": workers, "arrival_rate_jobs_per_s": rate, "total_paths": total_paths,
-            "p50_latency_ms": 1e3 * pct(0.50), "p99_latency_ms": 1e3 * pct(0.99),
+            "p50_latency_ms": 1e3 * pct(lat, 0.50), "p99_latency_ms": 1e3 * pct(lat, 0.99),
             "served_paths_per_s": total_paths / (last - first), "makespan_s": last - first,
             "sequential_paths_per_s": total_paths / sum(seq_t),
+            "sequential_fifo_p50_latency_ms": 1e3 * pct(fifo, 0.50),
+            "sequential_fifo_p99_latency_ms": 1e3 * pct(fifo, 0.99),
+            "saturated": {"paths_per_s": total_paths / (sat_last - sat_first), "makespan_s": sat_last - sat_first,
+                          "p50_latency_ms": 1e3 * pct(sat_lat, 0.50), "p99_latency_ms": 1e3 * pct(sat_lat, 0.99),
+                          "max_concurrent_chunks": sat_st["max_concurrent_chunks"],
+                          "alone_vs_mix_max_rel_diff": sat_dev},
             "plain_sequential_paths_per_s": total_paths / plain_total, "plain_extrapolated": True,
             "max_concurrent_chunks": st["max_concurrent_chunks"], "peak_arena_bytes": st["peak_bytes"],
             "alone_vs_mix_max_rel_diff": dev}
