@@ -731,13 +731,14 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             visit(l + 1, ch, nslots);
             return;
         }
-        // Slot order of the children.  Dense fan-outs go branch-major, (new path bits of the
-        // child, parent slot), so that consecutive slots of one branch value read consecutive
-        // parent slots.  With m children per parent out of 2^n_cut branch values, one branch
-        // value holds only a fraction m / 2^n_cut of the parents, and a wave's 64 parent reads
-        // spread over 2^n_cut / m times as many parent slots; parent-major order (the order the
-        // children are collected in) makes the reads contiguous instead, with m lanes on each
-        // parent value.  Branch-major is kept where that spread is the smaller cost: m^2 >= 2^n_cut.
+        // Slot order of the children.  Full fan-outs (every parent has all 2^n_cut children) go
+        // branch-major, (new path bits of the child, parent slot), so that consecutive slots of
+        // one branch value read consecutive parent slots.  Otherwise, with m children per parent,
+        // one branch value holds only a fraction m / 2^n_cut of the parents: a wave's parent
+        // reads would skip the parents without that child, and every parent would be fetched
+        // once per child.  Parent-major order (the order the children are collected in) makes
+        // the reads contiguous instead, with m lanes on each parent value, so each parent is
+        // fetched about once.
         const int shift = k - c.levels[l + 1].bits_after;
         const uint64_t bmask = (uint64_t(1) << c.levels[l + 1].n_cut) - 1;
         struct Ch { uint64_t b; uint32_t slot; uint32_t node; };
@@ -745,8 +746,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         for (size_t i = 0; i < nodes.size(); ++i)
             for (uint64_t cc = fc[nodes[i]]; cc < fc[nodes[i] + 1]; ++cc)
                 chs.push_back(Ch{shift >= 64 ? 0 : ((cnode[cc] >> shift) & bmask), (uint32_t)i, (uint32_t)cc});
-        const double m_avg = nodes.empty() ? 0.0 : (double)chs.size() / (double)nodes.size();
-        if (m_avg * m_avg >= std::ldexp(1.0, c.levels[l + 1].n_cut))
+        if (chs.size() == nodes.size() << c.levels[l + 1].n_cut)
             std::stable_sort(chs.begin(), chs.end(),
                              [](const Ch &x, const Ch &y) { return x.b != y.b ? x.b < y.b : x.slot < y.slot; });
         const LevelBuf &cb = lb[l + 1];
