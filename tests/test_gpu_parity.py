@@ -148,6 +148,23 @@ def test_grid5x6_path_subsets(sf, no_fold):
     assert c11_error(a, o, 512, c.k, 30) <= TOL_C64
 
 
+@pytest.mark.parametrize("no_fold", [0, 1])
+def test_grid5x6_partial_fanouts(sf, no_fold):
+    """A dense random subset (about 60% of an aligned block of 2048 paths): the deepest fan-outs
+    keep about 60% of their children, so they are neither full (branch-major slots) nor sparse,
+    and take parent-major child slots; with no_leaf_fold the last level is such a fan-out too."""
+    cfg, g, c = _circuit(sf, "grid5x6_d24")
+    c.tune(no_leaf_fold=no_fold)
+    rng = np.random.default_rng(23)
+    block = np.arange(13 * 2048, 14 * 2048, dtype=np.uint64)
+    ids = np.sort(block[rng.random(block.size) < 0.6])
+    bits = random_bitstrings(30, 600, cfg.bits_seed + 9)
+    say(f"grid5x6_d24 no_leaf_fold={no_fold}: {ids.size} paths of an aligned block of 2048")
+    a = c.amplitudes(bits, path_ids=ids)
+    o = oracle.path_sum(30, g, cfg.cut_mask(), ids, bits)
+    assert c11_error(a, o, ids.size, c.k, 30) <= TOL_C64
+
+
 @pytest.mark.slow
 def test_grid5x6_full_benchmark_size(sf):
     """All 2^15 paths, 1e5 bitstrings, default launch configuration (the benchmark's)."""
