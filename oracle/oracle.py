@@ -11,18 +11,21 @@ _LIB = None
 
 
 def lib_path() -> str:
-    return os.path.join(_HERE, "liboracle.so")
+    """This host's build of the oracle (the file name carries a hash of the CPU it is built for)."""
+    from .build import out_path
+    return out_path()
 
 
 def load():
-    """Load liboracle.so, building it first if it is missing."""
+    """Load this host's oracle library, building it first if it is missing."""
     global _LIB
     if _LIB is not None:
         return _LIB
-    if not os.path.exists(lib_path()):
+    path = lib_path()
+    if not os.path.exists(path):
         from .build import build
         build()
-    lib = ctypes.CDLL(lib_path())
+    lib = ctypes.CDLL(path)
     c_u64p = ctypes.POINTER(ctypes.c_uint64)
     c_dp = ctypes.POINTER(ctypes.c_double)
     c_i64p = ctypes.POINTER(ctypes.c_int64)
