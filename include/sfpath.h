@@ -125,7 +125,8 @@ int sample_paths(uint32_t k, double f, uint64_t seed, uint64_t *out, uint64_t ca
  *   path_ids   host array of n_paths distinct ids < 2^k, or NULL for the
  *              range [path_begin, path_begin + n_paths);
  *   bitstrings n_bits uint64 values < 2^n (host, or device with
- *              SF_BITS_ON_DEVICE);
+ *              SF_BITS_ON_DEVICE); n_bits <= 2^31 - 1, else
+ *              SF_ERR_UNSUPPORTED;
  *   amps       2*n_bits doubles (re, im), host or device (SF_OUT_ON_DEVICE);
  *   hip_stream hipStream_t to enqueue on (NULL = default stream);
  *   workspace  caller-owned device memory of workspace_bytes, or NULL to let
@@ -183,8 +184,9 @@ int get_tuning(const sf_circuit_t *c, sf_tuning_t *t);
  * every kind (folded levels or written leaves, dense blocks or not), more
  * candidates by rank up to n_measure, and the current tuning are then timed
  * with real run_paths
- * calls on this request (same argument rules as run_paths; amps is
- * overwritten) and the fastest is kept on the circuit and written to *best.
+ * calls on this request (same argument rules as run_paths, checked before
+ * any device work; amps is overwritten, so SF_ACCUMULATE is rejected with
+ * SF_ERR_INVALID) and the fastest is kept on the circuit and written to *best.
  * Results are cached for the process per (device kind, block sizes, k, tree
  * levels, number of paths, number of bitstrings, flags); see
  * save_tuning_cache / load_tuning_cache to keep them across processes.
@@ -373,7 +375,8 @@ typedef struct {
 } sf_job_t;
 
 typedef struct {
-    double t_submit, t_admit, t_done;   /* seconds since server_create */
+    double t_submit, t_admit, t_done;   /* seconds since server_create; t_submit is taken on entry
+                                           to server_submit */
     uint64_t n_paths;
     uint32_t k;
     uint32_t chunks;                    /* path chunks run so far */
@@ -391,18 +394,35 @@ typedef struct {
  * server_create: a serving runtime over one device-memory arena of
  * arena_bytes (caller memory `arena`, or NULL to let the server allocate it)
  * with n_workers workers (1..16), each owning a HIP stream of default
- * priority.  A job is admitted when its memory (bitstrings, FP64 partial
- * sums and a run_paths workspace, in the form of Section 9's M_proc) fits
- * in the arena; jobs that do not fit wait (later, smaller ones may pass).
- * Admitted jobs are worked on in chunks of chunk_paths paths (0 = 4096),
- * round-robin over all admitted jobs, one chunk per job at a time, so jobs
- * admitted while others run start at once and their kernels overlap on the
- * device.  Partial sums stay on the device until the job's last chunk.
+ * priority, and one thread that prepares submitted jobs (cut, path sample,
+ * memory estimate).  A job is admitted when its memory (bitstrings, FP64
+ * partial sums and a run_paths workspace, in the form of Section 9's M_proc)
+ * fits in the arena; jobs that do not fit wait (later, smaller ones may
+ * pass).  Admitted jobs are worked on in chunks of chunk_paths paths (0 =
+ * 4096), one chunk per job at a time; a free worker takes the next chunk of
+ * the admitted job the policy names (server_set_policy), so jobs admitted
+ * while others run start on the next free worker and their kernels overlap
+ * on the device.  Partial sums stay on the device until the job's last chunk.
  */
 int server_create(size_t arena_bytes, void *arena, uint32_t n_workers, uint64_t chunk_paths,
                   sf_server_t **out);
-/* server_submit: enqueue a job (host-side setup: cut, path sample); returns at once. */
+/* server_submit: validate and copy a job (gate list, bitstrings) and enqueue it; returns at
+ * once.  The cut, path sample and memory estimate are made on the server's preparation
+ * thread; a job whose preparation fails (e.g. a bitstring outside the grid) finishes with that
+ * error, which server_poll returns.  SF_ERR_OOM at once if even the smallest slice such a job
+ * can have (bitstrings, FP64 sums, a 256 MiB workspace) exceeds the arena. */
 int server_submit(sf_server_t *s, const sf_job_t *job, uint64_t *job_id);
+
+/* Which admitted job a free worker serves next (server_set_policy):
+ *   SF_SERVE_OLDEST_FIRST  the earliest admitted job with paths left (default): each job keeps
+ *                          one worker from admission to completion, later jobs use the rest;
+ *   SF_SERVE_ROUND_ROBIN   the admitted jobs in turn;
+ *   SF_SERVE_LEAST_WORK    the job with the least remaining planned work (sweep and gather
+ *                          bytes of its chunks, planned without device work). */
+#define SF_SERVE_OLDEST_FIRST 0u
+#define SF_SERVE_ROUND_ROBIN  1u
+#define SF_SERVE_LEAST_WORK   2u
+int server_set_policy(sf_server_t *s, uint32_t policy);
 /* server_poll: SF_PENDING while running; SF_OK when done (copies 2*n_bits doubles
  * into amps if not NULL), or the job's error code. */
 int server_poll(sf_server_t *s, uint64_t job_id, double *amps, sf_job_info_t *info);

@@ -24,8 +24,10 @@ EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_pa
            "describe_plan", "last_error", "server_create", "server_submit", "server_poll", "server_release",
            "server_drain", "server_stats", "server_destroy", "server_last_error", "rejection_m",
            "sample_bitstrings", "rejection_workspace_size", "rejection_accept", "frugal_sample",
-           "fidelity_estimate", "xeb_fidelity", "verify_claim", "save_tuning_cache", "load_tuning_cache"]
+           "fidelity_estimate", "xeb_fidelity", "verify_claim", "save_tuning_cache", "load_tuning_cache",
+           "server_set_policy"]
 SF_PENDING = 1
+SF_SERVE_OLDEST_FIRST, SF_SERVE_ROUND_ROBIN, SF_SERVE_LEAST_WORK = 0, 1, 2
 
 
 class SFError(RuntimeError):
@@ -101,6 +103,7 @@ def _load():
     lib.server_drain.argtypes = [vp]
     lib.server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.server_destroy.argtypes = [vp]
+    lib.server_set_policy.argtypes = [vp, u32]
     lib.rejection_m.argtypes = [u32, ctypes.c_double, u32, ctypes.POINTER(ctypes.c_double)]
     lib.sample_bitstrings.argtypes = [u32, u64, u64, vp]
     lib.rejection_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
@@ -379,6 +382,10 @@ def server_stats(s: int) -> dict:
 
 def server_destroy(s: int):
     _scheck(lib.server_destroy(s))
+
+
+def server_set_policy(s: int, policy: int):
+    _scheck(lib.server_set_policy(s, policy))
 
 
 # ---------------------------------------------------------------- convenience wrapper

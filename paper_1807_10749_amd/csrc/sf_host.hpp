@@ -153,3 +153,6 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
 int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32_t flags, size_t *bytes);
 
 }  // namespace sf
+
+// The C ABI's opaque circuit handle is the planner's circuit.
+struct sf_circuit : sf::Circuit {};

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -20,7 +21,6 @@
 
 using sf::Circuit;
 
-struct sf_circuit : Circuit {};
 
 namespace {
 
@@ -224,17 +224,29 @@ int workspace_size(const sf_circuit_t *c, uint64_t n_paths, size_t n_bits, uint3
     });
 }
 
+namespace {
+// Argument rules shared by run_paths and autotune (both end in sf::execute); 0 or an error code
+// with the thread's message set.  The device sort, select and reduce of the bitstrings count in
+// int, hence the INT_MAX limit.
+int check_run_args(const sf_circuit_t *c, const uint64_t *bitstrings, size_t n_bits, const double *amps,
+                   uint32_t flags, const void *workspace, size_t workspace_bytes)
+{
+    if (!c) return fail(SF_ERR_INVALID, "circuit is NULL");
+    if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
+    if (n_bits && (!bitstrings || !amps)) return fail(SF_ERR_INVALID, "bitstrings or amps is NULL");
+    if (flags & ~uint32_t(63)) return fail(SF_ERR_INVALID, "unknown flag");
+    if (workspace && workspace_bytes < (size_t(1) << 28)) return fail(SF_ERR_OOM, "workspace smaller than 256 MiB");
+    if (n_bits > (size_t)INT_MAX) return fail(SF_ERR_UNSUPPORTED, "more than 2^31 - 1 bitstrings");
+    return SF_OK;
+}
+}  // namespace
+
 int run_paths(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
               const uint64_t *bitstrings, size_t n_bits, double *amps, uint32_t flags, void *hip_stream,
               void *workspace, size_t workspace_bytes)
 {
     return guarded([&]() -> int {
-        if (!c) return fail(SF_ERR_INVALID, "circuit is NULL");
-        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
-        if (n_bits && (!bitstrings || !amps)) return fail(SF_ERR_INVALID, "bitstrings or amps is NULL");
-        if (flags & ~uint32_t(63)) return fail(SF_ERR_INVALID, "unknown flag");
-        if (workspace && workspace_bytes < (size_t(1) << 28)) return fail(SF_ERR_OOM, "workspace smaller than 256 MiB");
-        if (n_bits > (size_t(1) << 32)) return fail(SF_ERR_UNSUPPORTED, "more than 2^32 bitstrings");
+        if (const int rc = check_run_args(c, bitstrings, n_bits, amps, flags, workspace, workspace_bytes)) return rc;
         std::string err;
         const int rc = sf::execute(*c, path_ids, path_begin, n_paths, bitstrings, n_bits, amps, flags, hip_stream,
                                    workspace, workspace_bytes, err);
@@ -289,9 +301,9 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
              void *workspace, size_t workspace_bytes, uint32_t n_measure, sf_tuning_t *best)
 {
     return guarded([&]() -> int {
-        if (!c || !best) return fail(SF_ERR_INVALID, "NULL argument");
-        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
-        if (flags & ~uint32_t(63)) return fail(SF_ERR_INVALID, "unknown flag");
+        if (!best) return fail(SF_ERR_INVALID, "best is NULL");
+        if (const int rc = check_run_args(c, bitstrings, n_bits, amps, flags, workspace, workspace_bytes)) return rc;
+        if (flags & SF_ACCUMULATE) return fail(SF_ERR_INVALID, "autotune overwrites amps: SF_ACCUMULATE is not accepted");
         const bool fp64 = (flags & SF_FP64_SWEEPS) != 0;
         const std::string key = device_tag() + "/" + std::to_string(c->half[0].q) + "/" + std::to_string(c->half[1].q) + "/" +
                                 std::to_string(c->k) + "/" + std::to_string(c->levels.size()) + "/" +
@@ -562,6 +574,7 @@ int rejection_accept(const double *amps, uint64_t n, uint32_t n_qubits, double m
         if (n && (!amps || !accepted || !workspace)) return fail(SF_ERR_INVALID, "NULL device buffer");
         if (n_qubits < 1 || n_qubits > 64 || !(m > 0.0)) return fail(SF_ERR_INVALID, "bad n_qubits or m");
         if (flags & ~uint32_t(SF_SAMPLE_BASIC)) return fail(SF_ERR_INVALID, "unknown flag");
+        if (n > (uint64_t)INT_MAX) return fail(SF_ERR_UNSUPPORTED, "more than 2^31 - 1 candidates");
         size_t need = 0;
         int rc = rejection_workspace_size(n, &need);
         if (rc) return rc;
@@ -605,7 +618,7 @@ int frugal_sample(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin
         if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
         const uint32_t run_flags = flags & (SF_FP64_SWEEPS | SF_PLAIN);
         if (flags & ~uint32_t(SF_FP64_SWEEPS | SF_PLAIN | SF_SAMPLE_BASIC)) return fail(SF_ERR_INVALID, "unknown flag");
-        if (n_candidates > (uint64_t(1) << 31)) return fail(SF_ERR_UNSUPPORTED, "more than 2^31 candidates");
+        if (n_candidates > (uint64_t)INT_MAX) return fail(SF_ERR_UNSUPPORTED, "more than 2^31 - 1 candidates");
         *n_out = 0;
         *err_est = 0.0;
         // Step 2: candidates

@@ -168,6 +168,43 @@ def test_workspace_size_and_run_validation(sf):
     sf.destroy_circuit(c)
 
 
+def test_autotune_and_run_paths_reject_bad_arguments_before_device_work(sf):
+    """autotune takes run_paths' argument rules (it ends in the same executor): NULL bitstrings
+    or amplitudes, a workspace under 256 MiB and more than 2^31 - 1 bitstrings are refused, and
+    so is SF_ACCUMULATE (autotune overwrites amps once per timed candidate).  Every case returns
+    before any device call."""
+    w = make_workload("grid4x4_d16", n_bits=16)
+    c = sf.create_circuit(4, 4, w["gates"])
+    sf.set_cut(c, w["mask_a"])
+    bits, amps = w["bitstrings"], np.zeros(32)
+    cases = [
+        (dict(bitstrings=None, amps=amps), sf.SF_ERR_INVALID),
+        (dict(bitstrings=bits, amps=None), sf.SF_ERR_INVALID),
+        (dict(bitstrings=bits, amps=amps, flags=sf.SF_ACCUMULATE), sf.SF_ERR_INVALID),
+        (dict(bitstrings=bits, amps=amps, flags=1 << 10), sf.SF_ERR_INVALID),
+        (dict(bitstrings=bits, amps=amps, workspace=12345, workspace_bytes=1 << 20), sf.SF_ERR_OOM),
+        (dict(bitstrings=bits, amps=amps, n_bits=2 ** 31), sf.SF_ERR_UNSUPPORTED),
+    ]
+    for kw, code in cases:
+        kw = dict(kw)
+        nb = kw.pop("n_bits", 16)
+        with pytest.raises(sf.SFError) as e:
+            sf.autotune(c, None, 0, 4, kw.pop("bitstrings"), nb, kw.pop("amps"), **kw)
+        assert e.value.code == code, kw
+    with pytest.raises(sf.SFError) as e:
+        sf.run_paths(c, None, 0, 4, bits, 2 ** 31, amps)
+    assert e.value.code == sf.SF_ERR_UNSUPPORTED
+    assert sf.lib.autotune(c, None, 0, 4, bits.ctypes.data, 16, amps.ctypes.data, 0, None, None, 0, 2,
+                           None) == sf.SF_ERR_INVALID      # best is NULL
+    sf.destroy_circuit(c)
+    # rejection_accept: more candidates than the device sort and select count in an int
+    acc = np.zeros(4, dtype=np.uint32)
+    ws = np.zeros(16, dtype=np.uint8)
+    with pytest.raises(sf.SFError) as e:
+        sf.rejection_accept(np.zeros(8), 2 ** 31, 20, 10.0, 1, acc, workspace=ws, workspace_bytes=ws.size)
+    assert e.value.code == sf.SF_ERR_UNSUPPORTED
+
+
 def test_dense_plan_uses_matrix_core_blocks(sf):
     """With dense_qubits set, the planner packs four-qubit windows into dense blocks."""
     w = make_workload("grid5x6_d24", n_bits=4)
