@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--plain-paths", type=int, default=64)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=500, help="jobs in the serving mix (0 = skip)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving mix and print its JSON")
     ap.add_argument("--serve-policies", default="oldest",
                     help="comma-separated scheduling policies of the served runs (oldest, round_robin, least_work)")
     ap.add_argument("--no-sampling", action="store_true", help="skip the rejection-sampling measurement")
@@ -71,7 +72,7 @@ def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure
     device, and the tuning (fixed, autotuned on this request, or the library default)."""
     import torch
     from paper_1807_10749_amd import binding as sf
-    from workload import CONFIGS, make_workload, path_block
+    from workload import CONFIGS, make_workload, workload_block
 
     cfg = CONFIGS[workload]
     w = make_workload(workload, n_bits=n_bits or None)
@@ -82,7 +83,7 @@ def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure
     if cfg.paths == "all":
         ids, begin, npaths = None, 0, 1 << c.k
     elif cfg.paths == "block":
-        begin, npaths = path_block(c.k, cfg.block_bits, cfg.path_seed)
+        begin, npaths = workload_block(workload)
         ids = None
     else:
         ids = sf.sample_paths(c.k, cfg.f, cfg.path_seed)
@@ -223,6 +224,10 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": x.numel(), "calibrate_copy_bytes_written": y.numel()}))
         return
     from paper_1807_10749_amd import binding as sf
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(args.serve_jobs, policies=tuple(args.serve_policies.split(",")))}),
+              flush=True)
+        return
 
     progress(f"{args.workload}: set-up" + ("" if args.tuning or args.no_autotune else " and autotune"))
     req = prepare(args.workload, n_bits=args.bitstrings, max_paths=args.max_paths, tuning=args.tuning,
@@ -497,11 +502,11 @@ def iswap_bench(stream, steps=3, warmup=1):
     bitstrings, autotuned, timed like the headline step."""
     import torch
     from paper_1807_10749_amd import binding as sf
-    from workload import make_workload, path_block
+    from workload import make_workload, workload_block
     w = make_workload("grid5x6_d24_iswap")
     cfg, bits = w["cfg"], w["bitstrings"]
     c = sf.Circuit(cfg.rows, cfg.cols, w["gates"], cfg.cut_mask())
-    begin, npaths = path_block(c.k, cfg.block_bits, cfg.path_seed)
+    begin, npaths = workload_block(cfg.name)
     d_bits = torch.from_numpy(bits.view(np.int64)).cuda()
     d_amps = torch.zeros(2 * bits.size, dtype=torch.float64, device="cuda")
     # the bound assumes every leaf resident at once; the library batches leaves within what it gets

@@ -136,6 +136,11 @@ int sample_paths(uint32_t k, double f, uint64_t seed, uint64_t *out, uint64_t ca
  * Returns after the work has finished (the stream is synchronised).
  * Blocks evolve in complex64 (complex128 with SF_FP64_SWEEPS); the
  * cross-path sum is formed in FP64.
+ * Paths whose term is exactly zero are skipped: a qubit that receives two
+ * cut-gate projectors with only diagonal gates on it in between keeps a
+ * nonzero amplitude only if both path bits agree (Section 2: the projectors
+ * of Eq. (CZ) leave zero blocks, which the simulator skips; here whole zero
+ * states).  get_run_stats reports how many requested paths remained.
  */
 int run_paths(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin,
               uint64_t n_paths, const uint64_t *bitstrings, size_t n_bits,
@@ -237,6 +242,7 @@ typedef struct {
     uint64_t a_groups;       /* groups of bitstrings that share their block-A rows (estimated
                                 from the bitstring count in a planning-only run) */
     double ms_plan;          /* host time from entry to the first enqueued device operation */
+    uint64_t n_paths_live;   /* requested paths whose term is not known to be zero (see run_paths) */
 } sf_run_stats_t;
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);

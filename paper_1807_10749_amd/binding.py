@@ -50,7 +50,8 @@ class RunStats(ctypes.Structure):
                 ("sweep_bytes", ctypes.c_uint64), ("gather_bytes", ctypes.c_uint64),
                 ("n_batches", ctypes.c_uint64), ("n_passes_a", ctypes.c_uint64),
                 ("n_passes_b", ctypes.c_uint64), ("gather_row_bytes", ctypes.c_uint64),
-                ("a_groups", ctypes.c_uint64), ("ms_plan", ctypes.c_double)]
+                ("a_groups", ctypes.c_uint64), ("ms_plan", ctypes.c_double),
+                ("n_paths_live", ctypes.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

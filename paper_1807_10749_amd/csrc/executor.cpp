@@ -88,6 +88,7 @@ struct Launch {
     DenseArgs da{};
     FoldArgs fa{};
     FoldIswapArgs fia{};          // FOLD of crossing iSWAPs
+    GFoldArgs gfa{};              // FOLD in the general form
     size_t mask_off = 0;          // FOLD: element offset of the batch's child masks
     int half = 0;
     int R = 0;
@@ -121,6 +122,7 @@ struct Planned {
     std::vector<uint32_t> tmaskv;         // descendant masks of the batches the fold reads
     std::vector<char> blob;               // pass programs, dense matrices, fold tables
     size_t fold_tab_off[2] = {0, 0};
+    size_t fold_off_off[2] = {0, 0};      // general fold: column offsets
     size_t plain_mask_idx = SIZE_MAX;
     uint64_t n_leaf_batches = 0;
 };
@@ -182,10 +184,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     const int qh[2] = {c.half[0].q, c.half[1].q};
     int R = c.tuning.reg_qubits ? (int)c.tuning.reg_qubits : kMaxRegBits;
     R = std::max(1, std::min(R, fp64 ? kMaxRegBitsF64 : kMaxRegBits));
-    const int FD = fold_depth(c);          // trailing levels folded into the gather
-    const bool fold = FD > 0;
-    const int fold_at = L - FD;            // the level the gather reads
-    const LeafFold *fh[2] = {fold ? &c.half[0].folds[FD - 1] : nullptr, fold ? &c.half[1].folds[FD - 1] : nullptr};
+    int FD = fold_depth(c);                // trailing levels folded into the gather
     c.stats = sf_run_stats_t{};
 
     if (!path_ids && n_paths && k < 64 && ((path_begin + n_paths - 1) >> k) != 0) {
@@ -195,6 +194,54 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     if (path_ids)
         for (uint64_t i = 0; i < n_paths; ++i)
             if (k < 64 && (path_ids[i] >> k)) { err = "path id >= 2^k"; return SF_ERR_INVALID; }
+    // paths whose term is zero (two projectors on one qubit decided by different path bits,
+    // equal_bit_pairs) are dropped from the request; the rest run as an explicit list
+    std::vector<uint64_t> live_ids;
+    if (!c.equal_bits.empty() && n_paths) {
+        bool all_live = true;
+        for (uint64_t i = 0; i < n_paths && all_live; ++i)
+            all_live = path_is_live(c, path_ids ? path_ids[i] : path_begin + i);
+        if (!all_live) {
+            live_ids.reserve(n_paths);
+            for (uint64_t i = 0; i < n_paths; ++i) {
+                const uint64_t id = path_ids ? path_ids[i] : path_begin + i;
+                if (path_is_live(c, id)) live_ids.push_back(id);
+            }
+            path_ids = live_ids.data();
+            path_begin = 0;
+            n_paths = live_ids.size();
+        }
+    }
+    c.stats.n_paths_live = n_paths;
+
+    // The general fold reads 2^|S'| rows of the level above per bitstring and parent instead of
+    // one row of each descendant: with the library choosing the depth (fold_levels 0) it is
+    // used only when those reads are fewer bytes than writing the folded levels' states once
+    // and gathering from them (a lower bound of that work), which holds when parents have many
+    // requested descendants and fails for sparse path subsets.
+    bool gfold = FD > 0 && fold_general(c, FD);
+    if (gfold && !c.tuning.fold_levels && n_paths) {
+        const LeafFold &a = c.half[0].folds[FD - 1], &b = c.half[1].folds[FD - 1];
+        const int nbf = a.nb;
+        uint64_t parents = n_paths;         // plain form: every path is its own tree
+        if (plain) {
+        } else if (!path_ids) {
+            parents = ((path_begin + n_paths - 1) >> nbf) - (path_begin >> nbf) + 1;
+        } else if (std::is_sorted(path_ids, path_ids + n_paths)) {
+            parents = 1;
+            for (uint64_t i = 1; i < n_paths; ++i) parents += (path_ids[i] >> nbf) != (path_ids[i - 1] >> nbf);
+        }
+        const double fold_b = (double)n_bits * (double)parents * (double)elem *
+                              (std::ldexp(1.0, a.g_ns) + std::ldexp(1.0, b.g_ns));
+        const double mat_b = (double)n_paths * (double)elem *
+                                 (2.0 * FD * (std::ldexp(1.0, qh[0]) + std::ldexp(1.0, qh[1]))) +
+                             (double)n_bits * (double)n_paths * 2.0 * (double)elem;
+        if (fold_b >= mat_b) FD = 0;
+    }
+    const bool fold = FD > 0;
+    gfold = gfold && fold;
+    const int fold_at = L - FD;            // the level the gather reads
+    const LeafFold *fh[2] = {fold ? &c.half[0].folds[FD - 1] : nullptr, fold ? &c.half[1].folds[FD - 1] : nullptr};
     const uint64_t all = c.n == 64 ? ~uint64_t(0) : ((uint64_t(1) << c.n) - 1);
     if (!bits_dev && !dry_run)
         for (size_t j = 0; j < n_bits; ++j)
@@ -284,7 +331,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             // bitstrings that share their block-A bits outside the fold's S qubits read the same
             // rows of block A: visit them together
             const uint32_t kmask = (qh[0] >= 32 ? ~0u : ((1u << qh[0]) - 1)) &
-                                   ~(fh[0]->iswap ? fh[0]->qmask : fh[0]->smask);
+                                   ~(gfold ? fh[0]->g_smask : fh[0]->iswap ? fh[0]->qmask : fh[0]->smask);
             if ((he = launch_key(d_xa, n_bits, kmask, (uint32_t *)(wsp + off_fkey), stream)) != hipSuccess) return dev_err("key", he);
             keys = (const uint32_t *)(wsp + off_fkey);
             key_bits = __builtin_popcount(kmask);
@@ -449,10 +496,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         for (const Launch &ln : ls) {
             if (ln.kind != Launch::GATHER && ln.kind != Launch::FOLD) continue;
             const bool fi = ln.kind == Launch::FOLD && fh[0]->iswap;
-            const uint64_t slots = ln.kind == Launch::FOLD ? (fi ? ln.fia.n_slots : ln.fa.n_slots) : ln.ga.n_slots;
+            const uint64_t slots = ln.kind == Launch::FOLD ? (fi ? ln.fia.n_slots : gfold ? ln.gfa.n_slots : ln.fa.n_slots)
+                                                           : ln.ga.n_slots;
             // parent rows per bitstring: 2^|S| (CZ form) or 2^G (iSWAP form) per block
-            const uint64_t ra = ln.kind == Launch::FOLD ? uint64_t(1) << (fi ? fh[0]->ng : fh[0]->n_s) : 1;
-            const uint64_t rb = ln.kind == Launch::FOLD ? uint64_t(1) << (fi ? fh[1]->ng : fh[1]->n_s) : 1;
+            const uint64_t ra = ln.kind == Launch::FOLD ? uint64_t(1) << (fi ? fh[0]->ng : gfold ? fh[0]->g_ns : fh[0]->n_s) : 1;
+            const uint64_t rb = ln.kind == Launch::FOLD ? uint64_t(1) << (fi ? fh[1]->ng : gfold ? fh[1]->g_ns : fh[1]->n_s) : 1;
             const uint64_t per = slots * elem * (a_groups * ra + (uint64_t)n_bits * rb) + (uint64_t)n_bits * 44 +
                                  (ln.kind == Launch::FOLD ? slots * 4 : 0);
             c.stats.n_gather_launches += rounds;
@@ -660,6 +708,27 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                     tmaskv.push_back((uint32_t)(node_mask[nodes[i]] >> 32));
                 }
                 ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem * (uint64_t(2) << fh[0]->ng);
+            } else if (gfold) {
+                GFoldArgs &f = ln.gfa;
+                std::memset(&f, 0, sizeof(f));
+                for (int h = 0; h < 2; ++h) {
+                    const LeafFold &lf = *fh[h];
+                    f.h[h].smask = lf.g_smask;
+                    f.h[h].tmask = lf.g_tmask;
+                    f.h[h].n_s = lf.g_ns;
+                    f.h[h].n_rest = lf.g_ns - lf.nb;
+                }
+                f.n_bits = n_bits;
+                f.n_slots = (uint32_t)nodes.size();
+                f.p = log2u(nslots);
+                f.scale_re = fscale.real();
+                f.scale_im = fscale.imag();
+                ln.mask_off = tmaskv.size();
+                if (plain) plain_mask_idx = tmaskv.size();
+                for (size_t i = 0; i < nodes.size(); ++i) tmaskv.push_back((uint32_t)node_mask[nodes[i]]);
+                f.all_children = all && !plain ? 1 : 0;
+                ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem *
+                           ((uint64_t(1) << fh[0]->g_ns) + (uint64_t(1) << fh[1]->g_ns));
             } else {
                 FoldArgs &f = ln.fa;
                 std::memset(&f, 0, sizeof(f));
@@ -794,7 +863,27 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             node_mask[a] |= uint64_t(1) << (tree.node[L][i] & low);
         }
     }
-    if (n_paths && fold && !hit) {
+    if (n_paths && gfold && !hit) {
+        // general fold: the table in the state precision and the column offsets
+        for (int h = 0; h < 2; ++h) {
+            const std::vector<std::complex<double>> &tab = fh[h]->gtab;
+            fold_tab_off[h] = align_up(blob.size());
+            blob.resize(fold_tab_off[h] + tab.size() * elem);
+            for (size_t i = 0; i < tab.size(); ++i) {
+                if (fp64) {
+                    const double v[2] = {tab[i].real(), tab[i].imag()};
+                    std::memcpy(blob.data() + fold_tab_off[h] + 16 * i, v, 16);
+                } else {
+                    const float v[2] = {(float)tab[i].real(), (float)tab[i].imag()};
+                    std::memcpy(blob.data() + fold_tab_off[h] + 8 * i, v, 8);
+                }
+            }
+            const std::vector<uint32_t> &off = fh[h]->goff;
+            PL.fold_off_off[h] = align_up(blob.size());
+            blob.resize(PL.fold_off_off[h] + off.size() * 4);
+            std::memcpy(blob.data() + PL.fold_off_off[h], off.data(), off.size() * 4);
+        }
+    } else if (n_paths && fold && !hit) {
         for (int h = 0; h < 2; ++h) {
             const std::vector<std::complex<double>> &tab = fh[h]->tab;
             fold_tab_off[h] = align_up(blob.size());
@@ -827,7 +916,8 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             }
         }
         // planning only: every bitstring its own block-A group unless there are fewer rows
-        const int kb = fold ? qh[0] - (fh[0]->iswap ? __builtin_popcount(fh[0]->qmask) : fh[0]->n_s) : qh[0];
+        const int kb = fold ? qh[0] - (gfold ? fh[0]->g_ns : fh[0]->iswap ? __builtin_popcount(fh[0]->qmask) : fh[0]->n_s)
+                            : qh[0];
         account_gather(launches, rounds, std::min<uint64_t>(n_bits, kb >= 32 ? n_bits : (uint64_t(1) << kb)));
         c.stats.n_batches = n_leaf_batches * rounds;
         return SF_OK;
@@ -979,6 +1069,21 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 f.child_mask = (const uint64_t *)((const uint32_t *)(ws + off_tmask) + ln.mask_off);
                 timed(1);
                 if ((he = launch_fold_iswap(fp64, fh[0]->ng, f, stream)) != hipSuccess) return dev_err("fold", he);
+            } else if (ln.kind == Launch::FOLD && gfold) {
+                GFoldArgs f = ln.gfa;
+                f.h[0].par = buf + ln.dst_off;
+                f.h[1].par = buf + ln.src_off;
+                for (int h = 0; h < 2; ++h) {
+                    f.h[h].tab = ws + off_blob + fold_tab_off[h];
+                    f.h[h].off = (const uint32_t *)(ws + off_blob + PL.fold_off_off[h]);
+                }
+                f.xa = d_xa;
+                f.xb = d_xb;
+                f.order = d_order;
+                f.acc = d_acc;
+                f.child_mask = (const uint32_t *)(ws + off_tmask) + ln.mask_off;
+                timed(1);
+                if ((he = launch_gfold(fp64, fh[0]->nb, f, stream)) != hipSuccess) return dev_err("fold", he);
             } else if (ln.kind == Launch::FOLD) {
                 FoldArgs f = ln.fa;
                 f.h[0].par = buf + ln.dst_off;

@@ -893,6 +893,139 @@ hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- general fold + FP64 path sum
+
+// amp[j] += scale * sum_{slot < n_slots} sum_{b in child_mask[slot]} w_A[b] * WHT(w_B)[b] with w_h
+// formed from 2^|S'| rows of the level the gather reads (GFoldArgs).  WIDE: one bitstring per
+// wave, lanes over slots (P >= 64); else P lanes per bitstring, 64 / P bitstrings per wave.  Per
+// slot the 2^NB accumulators of block B are formed and transformed, then those of block A; each
+// round r loads 2^NB rows, all in flight before their first use.  The column patterns are
+// ordered branch bits first, so every accumulator index is a compile-time constant.  Products
+// with V and the sums over column patterns run in the state precision (the work of the gates the
+// fold replaces), the products c_A c_B and all sums over slots in FP64.
+template <typename T, int NB, bool WIDE, bool MASKED>
+__global__ __launch_bounds__(256) void gfold_kernel(GFoldArgs g)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int V = 1 << NB;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t P = 1u << g.p;
+    const uint32_t L = WIDE ? 64u : P;
+    const uint32_t G = 64u / L;
+    const uint64_t wave = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 4u + wid;
+    const uint64_t jj = wave * G + (uint32_t)lane / L;
+    const uint32_t sl = (uint32_t)lane % L;
+    uint64_t j = jj < g.n_bits ? (uint64_t)g.order[jj] : g.n_bits;
+    if (WIDE) {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)j);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(j >> 32));
+        j = ((uint64_t)hi << 32) | lo;
+    }
+    double re = 0.0, im = 0.0;
+    if (j < g.n_bits) {
+        const C *base[2];             // row (x & ~smask) of each block
+        const C *trow[2];             // table row of x_T'
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const GFoldHalf &f = g.h[h];
+            const uint32_t x = h ? g.xb[j] : g.xa[j];
+            trow[h] = (const C *)f.tab + ((uint64_t)pext32(x, f.tmask) << f.n_s);
+            base[h] = (const C *)f.par + ((uint64_t)(x & ~f.smask) << g.p);
+        }
+        // w[b] = sum_r V[x_T', b | r << NB] * row(b | r << NB)[slot] for one block
+        auto accumulate = [&](const GFoldHalf &f, const C *bs, const C *tr, uint32_t s, C (&w)[V]) {
+#pragma unroll
+            for (int b = 0; b < V; ++b) { w[b].x = T(0); w[b].y = T(0); }
+            const uint32_t nr = 1u << f.n_rest;
+            for (uint32_t r = 0; r < nr; ++r) {
+                C t[V];
+#pragma unroll
+                for (int b = 0; b < V; ++b) t[b] = bs[((uint64_t)f.off[b | (r << NB)] << g.p) + s];
+#pragma unroll
+                for (int b = 0; b < V; ++b) {
+                    const C v = tr[b | (r << NB)];
+                    w[b].x += v.x * t[b].x - v.y * t[b].y;
+                    w[b].y += v.x * t[b].y + v.y * t[b].x;
+                }
+            }
+        };
+        for (uint32_t s = sl; s < g.n_slots; s += L) {
+            C wb[V], wa[V];
+            accumulate(g.h[1], base[1], trow[1], s, wb);
+            accumulate(g.h[0], base[0], trow[0], s, wa);
+            // block B: the descendant's Z^b signs summed over the column patterns' branch bits
+#pragma unroll
+            for (int stp = 1; stp < V; stp <<= 1)
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+                    if (!(i & stp)) {
+                        const C u = wb[i], w = wb[i | stp];
+                        wb[i].x = u.x + w.x;
+                        wb[i].y = u.y + w.y;
+                        wb[i | stp].x = u.x - w.x;
+                        wb[i | stp].y = u.y - w.y;
+                    }
+            const uint32_t m = MASKED ? g.child_mask[s] : 0xffffffffu;
+#pragma unroll
+            for (int b = 0; b < V; ++b) {
+                const double ar = wa[b].x, ai = wa[b].y, br = wb[b].x, bi = wb[b].y;
+                const double pr = ar * br - ai * bi, pi = ar * bi + ai * br;
+                if (MASKED) {
+                    const bool use = (m >> b) & 1u;    // a select, not a branch
+                    re += use ? pr : 0.0;
+                    im += use ? pi : 0.0;
+                } else {
+                    re += pr;
+                    im += pi;
+                }
+            }
+        }
+    }
+    for (uint32_t mm = 1; mm < L; mm <<= 1) {
+        re += __shfl_xor(re, (int)mm);
+        im += __shfl_xor(im, (int)mm);
+    }
+    if (j < g.n_bits && sl == 0) {
+        double *o = g.acc + 2 * j;
+        o[0] += g.scale_re * re - g.scale_im * im;
+        o[1] += g.scale_re * im + g.scale_im * re;
+    }
+}
+
+template <typename T, int NB>
+static void gfold_launch(const GFoldArgs &g, unsigned blocks, bool wide, hipStream_t s)
+{
+    if (g.all_children) {
+        if (wide) gfold_kernel<T, NB, true, false><<<blocks, 256, 0, s>>>(g);
+        else gfold_kernel<T, NB, false, false><<<blocks, 256, 0, s>>>(g);
+    } else {
+        if (wide) gfold_kernel<T, NB, true, true><<<blocks, 256, 0, s>>>(g);
+        else gfold_kernel<T, NB, false, true><<<blocks, 256, 0, s>>>(g);
+    }
+}
+
+hipError_t launch_gfold(bool fp64, int nb, const GFoldArgs &g, hipStream_t s)
+{
+    if (g.n_bits == 0) return hipSuccess;
+    if (nb < 1 || nb > kMaxGFoldBits || g.p < 0 || g.p > 31 || !g.order || !g.child_mask) return hipErrorInvalidValue;
+    for (int h = 0; h < 2; ++h)
+        if (!g.h[h].par || !g.h[h].tab || !g.h[h].off || g.h[h].n_rest < 0 || g.h[h].n_s != nb + g.h[h].n_rest)
+            return hipErrorInvalidValue;
+    const uint64_t P = (uint64_t)1 << g.p;
+    const bool wide = P >= 64;
+    const uint64_t per_wave = wide ? 1 : 64 / P;
+    const uint64_t waves = (g.n_bits + per_wave - 1) / per_wave;
+    const unsigned blocks = (unsigned)(((waves + 3) / 4 + 7) / 8 * 8);   // a multiple of 8 (xcd_block)
+    switch (nb) {
+    case 1: fp64 ? gfold_launch<double, 1>(g, blocks, wide, s) : gfold_launch<float, 1>(g, blocks, wide, s); break;
+    case 2: fp64 ? gfold_launch<double, 2>(g, blocks, wide, s) : gfold_launch<float, 2>(g, blocks, wide, s); break;
+    case 3: fp64 ? gfold_launch<double, 3>(g, blocks, wide, s) : gfold_launch<float, 3>(g, blocks, wide, s); break;
+    default: fp64 ? gfold_launch<double, 4>(g, blocks, wide, s) : gfold_launch<float, 4>(g, blocks, wide, s); break;
+    }
+    return hipGetLastError();
+}
+
 // amp[j] += scale * sum_{slot < n_slots} sum_{descendants (i, j') requested}
 //            V_A(i) row_A(j') V_B(j') row_B(i) i^{popcount(i ^ j')}
 // with the terms of FoldIswapArgs.  Per slot, a[i] = V_A(i) row_B(i) and b[j'] = row_A(j') V_B(j')

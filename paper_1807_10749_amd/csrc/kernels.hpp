@@ -32,6 +32,10 @@ hipError_t launch_gather(bool fp64, const GatherArgs &g, hipStream_t s);
 // FoldArgs); nb = path bits decided by the folded levels (1..5).  g.order and g.child_mask must
 // be given.
 hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s);
+// General fold (GFoldArgs) + FP64 path sum for one batch of the level it reads; nb = path bits
+// decided by the folded levels (1..kMaxGFoldBits).  g.order and g.child_mask must be given.
+constexpr int kMaxGFoldBits = 4;
+hipError_t launch_gfold(bool fp64, int nb, const GFoldArgs &g, hipStream_t s);
 // Fold of G (1..3) trailing crossing iSWAPs into the gather (FoldIswapArgs).
 hipError_t launch_fold_iswap(bool fp64, int G, const FoldIswapArgs &g, hipStream_t s);
 

@@ -130,6 +130,40 @@ static LeafFold make_fold(const Circuit &c, int h, int F)
         if (bq[u] < 0) return f;
         bmask |= 1u << bq[u];
     }
+    f.levels = F;
+    f.nb = nb;
+    for (int u = 0; u < nb; ++u) f.bq[u] = bq[u];
+    // general form: every branch qubit joins S (an identity there), so each column pattern's
+    // branch bits are the descendant's branch values
+    const uint32_t gs = smask | bmask, gt = tmask | bmask;
+    const int gns = __builtin_popcount(gs), gnt = __builtin_popcount(gt);
+    if (nb <= kMaxGeneralFoldBits && __builtin_popcount(bmask) == nb && gns <= kMaxGeneralFoldS &&
+        gns + gnt <= kMaxGeneralFoldTableBits) {
+        const std::vector<std::complex<double>> std_tab = fold_table(rest, gt, gs);
+        int gpos[32];                                    // index of each S' qubit in ascending order
+        for (int t = 0, b = 0; t < 32; ++t) gpos[t] = ((gs >> t) & 1) ? b++ : -1;
+        int col_q[32];                                   // qubit of column bit i
+        for (int u = 0; u < nb; ++u) col_q[u] = bq[u];
+        for (int t = 0, i = nb; t < 32; ++t)
+            if (((gs & ~bmask) >> t) & 1) col_q[i++] = t;
+        const int D = 1 << gns;
+        f.goff.assign(D, 0);
+        std::vector<int> ystd(D, 0);
+        for (int y = 0; y < D; ++y)
+            for (int i = 0; i < gns; ++i)
+                if ((y >> i) & 1) {
+                    f.goff[y] |= 1u << col_q[i];
+                    ystd[y] |= 1 << gpos[col_q[i]];
+                }
+        f.gtab.assign((size_t)1 << (gnt + gns), 0.0);
+        for (int xt = 0; xt < (1 << gnt); ++xt)
+            for (int y = 0; y < D; ++y) f.gtab[((size_t)xt << gns) + y] = std_tab[((size_t)xt << gns) + ystd[y]];
+        f.g_ns = gns;
+        f.g_nt = gnt;
+        f.g_smask = gs;
+        f.g_tmask = gt;
+        f.gen_ok = true;
+    }
     if ((smask & ~bmask) != 0) return f;            // a non-diagonal gate off the branch qubits
     const int n_t = __builtin_popcount(tmask), n_s = __builtin_popcount(smask);
     if (n_t > 8) return f;
@@ -226,17 +260,27 @@ static LeafFold make_fold_iswap(const Circuit &c, int h, int F)
     return f;
 }
 
+// The deepest fold whose non-diagonal gates act on branch qubits only, else the deepest general
+// one (which reads more rows of the level above per bitstring).
 int fold_depth(const Circuit &c)
 {
     if (c.tuning.no_leaf_fold) return 0;
-    int best = 0;
+    int best = 0, best_gen = 0;
     const int n = (int)std::min(c.half[0].folds.size(), c.half[1].folds.size());
     for (int F = 1; F <= n; ++F) {
         if (c.tuning.fold_levels && F > (int)c.tuning.fold_levels) break;
         const LeafFold &a = c.half[0].folds[F - 1], &b = c.half[1].folds[F - 1];
         if (a.ok && b.ok && a.iswap == b.iswap) best = F;
+        if (a.gen_ok && b.gen_ok) best_gen = F;
     }
-    return best;
+    return best ? best : best_gen;
+}
+
+bool fold_general(const Circuit &c, int FD)
+{
+    if (FD < 1) return false;
+    const LeafFold &a = c.half[0].folds[FD - 1], &b = c.half[1].folds[FD - 1];
+    return !(a.ok && b.ok && a.iswap == b.iswap);
 }
 
 int build_programs(Circuit &c, std::string &err)
@@ -411,8 +455,46 @@ int build_programs(Circuit &c, std::string &err)
         c.half[h].folds.clear();
         for (int F = 1; F <= L; ++F) c.half[h].folds.push_back(make_fold(c, h, F));
     }
+    c.equal_bits = equal_bit_pairs(c);
     c.plan_cache.clear();
     return SF_OK;
+}
+
+// Pairs of path bits that a path with a nonzero term sets equal (Section 2: the projectors of
+// the cut gates leave zero blocks in the block states; here the whole state).  Each block's
+// program is walked in order, tracking per qubit the path bit whose value the qubit is known to
+// hold: a projector onto path bit u sets it (and, if the qubit already holds path bit v, the
+// product of the two projectors is zero unless bits u and v are equal); diagonal gates keep it;
+// the per-path flip of a crossing iSWAP on bits (u, u+1) swaps u and u+1 (it flips exactly
+// when they differ) and otherwise forgets; every other non-diagonal gate forgets it.  Within a
+// segment the planner keeps the order of the operations on each qubit.
+std::vector<std::pair<int, int>> equal_bit_pairs(const Circuit &c)
+{
+    std::vector<std::pair<int, int>> pairs;
+    for (int h = 0; h < 2; ++h) {
+        int held[64];
+        for (int q = 0; q < 64; ++q) held[q] = -1;
+        for (const std::vector<HalfOp> &seg : c.half[h].segments)
+            for (const HalfOp &op : seg) {
+                const int t = op.q0;
+                if (op.kind == HK_PROJ) {
+                    if (held[t] >= 0 && held[t] != op.bit) pairs.push_back({held[t], op.bit});
+                    held[t] = op.bit;
+                } else if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) {
+                    held[t] = held[t] == op.bit ? op.bit + 1 : held[t] == op.bit + 1 ? op.bit : -1;
+                } else if (!is_diag(op.kind)) {
+                    held[t] = -1;
+                }
+            }
+    }
+    return pairs;
+}
+
+bool path_is_live(const Circuit &c, uint64_t id)
+{
+    for (const auto &pr : c.equal_bits)
+        if (((id >> pr.first) ^ (id >> pr.second)) & 1u) return false;
+    return true;
 }
 
 // ----------------------------------------------------------------------------

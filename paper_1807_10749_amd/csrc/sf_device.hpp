@@ -176,6 +176,40 @@ struct FoldArgs {
     double scale_re, scale_im;
 };
 
+// General fold of the last F tree levels (CZ branch operators only), for levels whose
+// non-diagonal gates also act on qubits other than their branch qubits.  S' = the qubits of the
+// non-diagonal gates plus the nb branch qubits, T' = S' plus the qubits the levels' diagonal
+// gates touch.  A column index y' of S' patterns holds the branch values in its nb low bits (bit
+// u = the qubit of path bit u) and the other S' qubits above them in ascending order.  For block
+// h, output bits x (local) and descendant branch value b:
+//   w_h[b] = sum_{r < 2^(|S'|-nb)} tab[pext(x, tmask) * 2^|S'| + (b | r << nb)]
+//                                  * parent_h[(x & ~smask) | off[b | r << nb]][slot]
+// Block A's projectors keep exactly the column patterns whose branch bits equal b, so
+// c_A[b] = w_A[b]; block B's Z^b signs give c_B = WHT(w_B) over b.  Then
+// amp[x] += scale * sum_slot sum_{b in child_mask[slot]} c_A[b] c_B[b].
+struct GFoldHalf {
+    const void *par;              // states of the block at level L-F, 2^(p+q) complex
+    const void *tab;              // table of V in the state precision (complex), [2^|T'|][2^|S'|]
+    const uint32_t *off;          // per column pattern y': its S' bits placed at their local qubits
+    uint32_t smask, tmask;        // local qubits of S', of T'
+    int32_t n_s;                  // |S'|
+    int32_t n_rest;               // |S'| - nb
+};
+
+struct GFoldArgs {
+    GFoldHalf h[2];
+    const uint32_t *xa, *xb;      // per bitstring: x_A, x_B
+    const uint32_t *order;        // visiting order of the bitstrings
+    const uint32_t *child_mask;   // per parent slot: bit b set if descendant b is requested
+    double *acc;                  // 2 * n_bits doubles, accumulated
+    uint64_t n_bits;
+    uint32_t n_slots;             // real parent slots (<= 2^p)
+    int32_t p;                    // parent slot bits
+    int32_t all_children;         // 1: every parent slot has all 2^nb descendants (masks not read)
+    int32_t pad;
+    double scale_re, scale_im;
+};
+
 // Fold of trailing levels whose crossing gates are all iSWAPs (G of them, Eq. (4way)).  Gate g
 // decides path bits u[g] (j) and u[g]+1 (i) of the descendant; block A takes |i><j| = X^{i^j} P_j
 // and block B G_ij = i^{i^j} X^{i^j} P_i on qubit q[g].  For a block, a pattern t of G bits (bit g

@@ -66,6 +66,11 @@ struct SegmentPlan {
 constexpr int kMaxFoldBits = 5;
 // Most crossing iSWAPs the folded levels may hold (two path bits each).
 constexpr int kMaxFoldGates = 3;
+// General fold: most path bits (the kernel keeps 2 x 2^nb accumulators per lane), most S'
+// qubits and most table bits |S'| + |T'| (the table goes to the plan blob in the state precision).
+constexpr int kMaxGeneralFoldBits = 4;
+constexpr int kMaxGeneralFoldS = 10;
+constexpr int kMaxGeneralFoldTableBits = 16;
 
 // The last F tree levels of one block written as V * D(b): D(b) = their branch operators for
 // descendant branch value b (diagonal), V = the block's remaining gates of those levels
@@ -90,6 +95,16 @@ struct LeafFold {
     int ng = 0;
     int gq[kMaxFoldGates] = {0}, gu[kMaxFoldGates] = {0}, gy[kMaxFoldGates] = {0};
     uint32_t qmask = 0;                         // the gates' qubits (bits the parent row takes from the branch)
+    // General form (GFoldArgs, CZ branch operators): S' = S plus the branch qubits, T' = T plus
+    // the branch qubits, for levels whose non-diagonal gates also act on other qubits.  Available
+    // when nb <= kMaxGFoldBits, the branch qubits are distinct and the table is small enough.
+    // Columns y' hold the branch values in their nb low bits (bit u = path bit u) and the other
+    // S' qubits above them in ascending order.
+    bool gen_ok = false;
+    int g_ns = 0, g_nt = 0;                     // |S'|, |T'|
+    uint32_t g_smask = 0, g_tmask = 0;
+    std::vector<std::complex<double>> gtab;     // [2^|T'|][2^|S'|]: <x_T'| V |x_T' with S' bits := y'>
+    std::vector<uint32_t> goff;                 // per y': its S' bits at their local qubits
 };
 
 struct HalfProgram {
@@ -120,6 +135,9 @@ struct Circuit {
     std::vector<int> cut_gate;        // gate index of crossing gate j (path-bit order)
     std::vector<Level> levels;        // levels[0] is the root (no crossing gate)
     HalfProgram half[2];              // 0 = A, 1 = B
+    // pairs of path bits a path with a nonzero term sets equal (equal_bit_pairs); the others
+    // are skipped
+    std::vector<std::pair<int, int>> equal_bits;
 
     // tuning
     sf_tuning_t tuning{};
@@ -140,6 +158,13 @@ int build_programs(Circuit &c, std::string &err);
 // Number of trailing tree levels folded into the gather with the current tuning (0 = none):
 // the largest F for which both blocks' folds[F-1] qualify, capped by tuning.fold_levels.
 int fold_depth(const Circuit &c);
+// Pairs (u, v) of path bits with bit u == bit v in every path whose term is nonzero, and the
+// test of one path id against them.
+std::vector<std::pair<int, int>> equal_bit_pairs(const Circuit &c);
+bool path_is_live(const Circuit &c, uint64_t id);
+// Whether those FD levels use the general form (LeafFold::gen_ok) rather than the one whose
+// non-diagonal gates act on branch qubits only.
+bool fold_general(const Circuit &c, int FD);
 // dense_m: 0 = register/lane passes only; 2..4 = also fuse windows of up to dense_m qubits
 // into dense 4-qubit blocks applied on matrix cores.
 const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m = 0);

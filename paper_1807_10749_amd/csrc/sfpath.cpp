@@ -461,6 +461,10 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
         const int L = (int)c->levels.size() - 1;
         s += "k=" + std::to_string(c->k) + " qA=" + std::to_string(c->half[0].q) +
              " qB=" + std::to_string(c->half[1].q) + " levels=" + std::to_string(L) + "\n";
+        // pairs of path bits that must agree for a nonzero term (other paths are skipped)
+        s += "equal path bits:";
+        for (const auto &pr : c->equal_bits) s += " " + std::to_string(pr.first) + "=" + std::to_string(pr.second);
+        s += "\n";
         for (int l = 0; l <= L; ++l) {
             int p = std::min(c->levels[l].bits_after, 20);
             const int qmin = std::min(c->half[0].q, c->half[1].q);
@@ -472,7 +476,12 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
                 const sf::LeafFold &f0 = c->half[0].folds[FD - 1], &f1 = c->half[1].folds[FD - 1];
                 s += " A " + std::to_string(c->half[0].segments[l].size()) + " ops, B " +
                      std::to_string(c->half[1].segments[l].size()) + " ops folded into the gather";
-                if (l == L)
+                if (l == L && sf::fold_general(*c, FD))
+                    s += " (" + std::to_string(FD) + " levels, branch bits " + std::to_string(f0.nb) +
+                         ", general form; A: S' " + std::to_string(f0.g_ns) + " qubits, T' " +
+                         std::to_string(f0.g_nt) + "; B: S' " + std::to_string(f1.g_ns) + " qubits, T' " +
+                         std::to_string(f1.g_nt) + "; used when cheaper than writing the levels)";
+                else if (l == L)
                     s += " (" + std::to_string(FD) + " levels, branch bits " + std::to_string(f0.nb) +
                          (f0.iswap ? ", " + std::to_string(f0.ng) + " iSWAP gates" : std::string()) + "; A: S " +
                          std::to_string(f0.n_s) + " qubits, T " + std::to_string(f0.n_t) + "; B: S " +

@@ -1,9 +1,9 @@
 """Write FP64 oracle amplitudes of the 7x8 block workload to tests/golden/grid7x8_d40_paths.npz.
 
 Workload: the 7x8 grid (56 qubits), depth 1+40+1, vertical cut into two
-28-qubit blocks (35 crossing CZs), the seeded aligned block of 1024 path ids
-the benchmark runs (Section 5 and Appendix H: the 56-qubit run with a 28+28
-cut).  The oracle's O2 path sum evolves both 28-qubit blocks in FP64 (4 GiB
+28-qubit blocks (35 crossing CZs), the seeded live aligned block of 1024 path
+ids the benchmark runs (workload.workload_block; Section 5 and Appendix H: the
+56-qubit run with a 28+28 cut).  The oracle's O2 path sum evolves both 28-qubit blocks in FP64 (4 GiB
 each) for every listed path, so only a few paths are stored:
 
 * an aligned sub-block of 8 paths inside the block, at a seeded offset (it
@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from workload import CONFIGS, SplitMix64, grid_circuit, path_block, random_bitstrings  # noqa: E402
+from workload import CONFIGS, SplitMix64, grid_circuit, random_bitstrings, workload_block  # noqa: E402
 
 OUT = os.path.join(HERE, "grid7x8_d40_paths.npz")
 N_BITS = 4096
@@ -41,7 +41,7 @@ def main():
     gates = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed)
     mask = cfg.cut_mask()
     k = oracle.num_cut(cfg.n_qubits, gates, mask)
-    begin, count = path_block(k, cfg.block_bits, cfg.path_seed)
+    begin, count = workload_block(cfg.name)
     sub = (SplitMix64(SUB_SEED).next() >> 57) * 8          # 0, 8, ..., 1016
     ids = [begin + sub + i for i in range(8)] + [begin + count - 1]
     bits = random_bitstrings(cfg.n_qubits, N_BITS, cfg.bits_seed)
@@ -53,6 +53,8 @@ def main():
     sub_sum = np.zeros(N_BITS, dtype=np.complex128)
     for i in range(8):
         sub_sum += amps[i]
+    for i in range(len(ids)):
+        assert np.abs(amps[i]).max() > 0, f"path {int(ids[i])} has a zero term"
     np.savez(OUT, k=np.int64(k), block_begin=np.uint64(begin), block_count=np.int64(count),
              ids=np.array(ids, dtype=np.uint64), bitstrings=bits, amps=amps, sub_block_sum=sub_sum,
              n_qubits=np.int64(cfg.n_qubits), mask_a=np.uint64(mask))

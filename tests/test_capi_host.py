@@ -219,19 +219,25 @@ def test_dense_plan_uses_matrix_core_blocks(sf):
 
 def test_leaf_fold_eligibility(sf):
     """Trailing tree levels are folded into the gather when every non-diagonal gate among them
-    acts on one of their branch qubits (at most 5 path bits); fold_levels caps how many."""
+    acts on one of their branch qubits (at most 5 path bits); otherwise, with at most 4 path
+    bits, in the general form whose S' adds the branch qubits (used when it reads fewer bytes
+    than writing the levels); fold_levels caps how many."""
     import sys
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from fold_circuits import crossing_tail_circuit, two_level_tail_circuit
-    expect = {"grid4x4_d16": None, "grid6x7_d32": None, "grid7x8_d40": None,
-              "grid5x6_d24": "2 levels, branch bits 5; A: S 5 qubits, T 5; B: S 5 qubits, T 5"}
+    general = {"grid4x4_d16": "2 levels, branch bits 4, general form; A: S' 7 qubits, T' 7; B: S' 7 qubits, T' 7",
+               "grid6x7_d32": "1 levels, branch bits 3, general form; A: S' 6 qubits, T' 6; B: S' 3 qubits, T' 3",
+               "grid7x8_d40": "1 levels, branch bits 4, general form; A: S' 8 qubits, T' 8; B: S' 5 qubits, T' 5"}
+    expect = {**general, "grid5x6_d24": "2 levels, branch bits 5; A: S 5 qubits, T 5; B: S 5 qubits, T 5"}
     for name, fold in expect.items():
         cfg = CONFIGS[name]
         c = sf.create_circuit(cfg.rows, cfg.cols, grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed))
         sf.set_cut(c, cfg.cut_mask())
         plan = sf.describe_plan(c)
-        if fold is None:
-            assert "folded" not in plan, name
+        assert fold in plan, plan
+        if name in general:
+            sf.set_tuning(c, no_leaf_fold=1)
+            assert "folded" not in sf.describe_plan(c)
         else:
             assert fold in plan, plan
             sf.set_tuning(c, fold_levels=1)
@@ -259,12 +265,13 @@ def test_leaf_fold_eligibility(sf):
         sf.set_cut(c, m)
         assert want in sf.describe_plan(c)
         sf.destroy_circuit(c)
-    # a non-diagonal gate on a non-branch qubit in the last level: not folded
+    # a non-diagonal gate on a non-branch qubit in the last level: only the general form
     r, cc, g, m = crossing_tail_circuit(rows=3)
     extra = np.array([(H, 0, int(g["cycle"].max()) + 1, 0, 0)], dtype=GATE_DTYPE)   # H on (0,0) after its CZ
     c = sf.create_circuit(r, cc, np.concatenate([g, extra]))
     sf.set_cut(c, m)
-    assert "folded" not in sf.describe_plan(c)
+    plan = sf.describe_plan(c)
+    assert "general form" in plan and "A: S' 4 qubits" in plan, plan
     sf.destroy_circuit(c)
 
 

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from parity_tol import TOL_C128, TOL_C64, c11_error
 from fold_circuits import iswap_tail_circuit
-from workload import CONFIGS, CZ, ISWAP, column_cut_mask, grid_circuit, path_block, random_bitstrings
+from workload import CONFIGS, CZ, ISWAP, column_cut_mask, grid_circuit, path_block, random_bitstrings, workload_block
 
 pytestmark = pytest.mark.gpu
 
@@ -156,7 +156,7 @@ def test_iswap_full_workload_block(sf):
     w = make_workload("grid5x6_d24_iswap")
     cfg, g, bits = w["cfg"], w["gates"], w["bitstrings"]
     c = sf.Circuit(cfg.rows, cfg.cols, g, cfg.cut_mask())
-    begin, count = path_block(c.k, cfg.block_bits, cfg.path_seed)
+    begin, count = workload_block(cfg.name)
     assert (c.k, count) == (30, 1 << 18)
     say(f"iswap 5x6 d24 full block {begin}+{count}, 1e5 bitstrings")
     a = c.amplitudes(bits, path_begin=begin, n_paths=count)

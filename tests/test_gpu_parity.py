@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from parity_tol import TOL_C128, TOL_C64, c11_error
-from workload import CONFIGS, grid_circuit, make_workload, path_block, random_bitstrings
+from workload import CONFIGS, grid_circuit, make_workload, random_bitstrings, workload_block
 
 pytestmark = pytest.mark.gpu
 
@@ -182,7 +182,17 @@ def test_grid6x7_sampled_paths(sf):
     cfg, g, c = _circuit(sf, "grid6x7_d32")
     ids_all = sf.sample_paths(c.k, cfg.f, cfg.path_seed)
     assert ids_all.size == 2684355
-    ids = ids_all[:: ids_all.size // 4][:4]
+    # four ids spread over the sample, each the first live one at or after its position (the
+    # others have zero terms, which the library skips)
+    from workload import equal_bit_pairs, is_live
+    pairs = equal_bit_pairs(g, cfg.cut_mask())
+    ids = []
+    for start in range(0, ids_all.size, ids_all.size // 4):
+        i = start
+        while not is_live(int(ids_all[i]), pairs):
+            i += 1
+        ids.append(ids_all[i])
+    ids = np.array(ids[:4], dtype=np.uint64)
     bits = random_bitstrings(42, 20000, cfg.bits_seed)
     say(f"grid6x7_d32 sampled paths {ids.tolist()}")
     a = c.amplitudes(bits, path_ids=ids)
@@ -199,7 +209,7 @@ def test_grid7x8_block_properties(sf):
     """Full 28+28 shape: a path block equals the sum of its parts, the plain form, and each
     single-path term is rank one in (x_A, x_B)."""
     cfg, g, c = _circuit(sf, "grid7x8_d40")
-    begin, count = path_block(c.k, cfg.block_bits, cfg.path_seed)
+    begin, count = workload_block("grid7x8_d40")
     bits = random_bitstrings(56, 4096, cfg.bits_seed)
     say("grid7x8_d40 16-path sub-block, tree")
     a = c.amplitudes(bits, path_begin=begin, n_paths=16)

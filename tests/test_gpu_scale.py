@@ -7,8 +7,9 @@
   the tuning the benchmark's autotuner picks for the full request and all 1e6 bitstrings;
   and the full block at that tuning equal to the sum of its two halves (linearity in the path
   set, Section 3).
-* 6x7 grid, depth 1+32+1, f = 0.01: 64 ids spread over the seeded sample of 2,684,355, on
-  1e5 of the workload's bitstrings, against the oracle's path sum over the same ids.
+* 6x7 grid, depth 1+32+1, f = 0.01: 64 live ids spread over the seeded sample of 2,684,355
+  (most sampled ids have zero terms, which the library skips), on 1e5 of the workload's
+  bitstrings, against the oracle's path sum over the same ids.
 * 5x6 grid, all 2^15 paths, 1e5 bitstrings, at the tuning the benchmark's autotuner picks.
 
 Tolerance: max relative |amp|^2 error (parity_tol.c11_error) 1e-5 for complex64 sweeps.
@@ -20,7 +21,7 @@ import pytest
 
 import oracle
 from parity_tol import TOL_C64, c11_error
-from workload import CONFIGS, grid_circuit, make_workload, random_bitstrings
+from workload import CONFIGS, equal_bit_pairs, grid_circuit, is_live, make_workload, random_bitstrings
 
 pytestmark = pytest.mark.gpu
 
@@ -47,16 +48,27 @@ def _release(req):
     torch.cuda.empty_cache()
 
 
+@pytest.fixture(scope="module")
+def req7x8(bench):
+    """The benchmark's 7x8 request (1024-path block, 1e6 bitstrings, device buffers, workspace),
+    autotuned once for both tests."""
+    say("grid7x8_d40: set-up and autotune of the full benchmark request")
+    req = bench.prepare("grid7x8_d40", n_measure=3)
+    say(f"grid7x8_d40 tuning {req['tuning']}")
+    yield req
+    _release(req)
+
+
 @pytest.mark.slow
-def test_grid7x8_golden_at_benchmark_tuning(bench):
+@pytest.mark.timeout(900)
+def test_grid7x8_golden_at_benchmark_tuning(req7x8):
     """The sub-block, its paths one at a time and the block's last path against the oracle's
     stored FP64 amplitudes, in the benchmark's launch configuration."""
     from paper_1807_10749_amd import binding as sf
     if not os.path.exists(GOLDEN_7X8):
         pytest.skip("golden file not generated (tests/golden/make_grid7x8_golden.py)")
     gold = np.load(GOLDEN_7X8, allow_pickle=False)
-    say("grid7x8_d40: set-up and autotune of the full benchmark request")
-    req = bench.prepare("grid7x8_d40", n_measure=3)
+    req = req7x8
     c = req["c"]
     begin, count = req["begin"], req["npaths"]
     assert c.k == int(gold["k"]) and begin == int(gold["block_begin"]) and count == int(gold["block_count"])
@@ -64,7 +76,6 @@ def test_grid7x8_golden_at_benchmark_tuning(bench):
     nb = gb.size
     assert np.array_equal(req["bits"][:nb], gb)
     ids = gold["ids"]
-    say(f"grid7x8_d40 tuning {req['tuning']}")
 
     def run(path_ids):
         sf.run_paths(c.handle, np.ascontiguousarray(path_ids, dtype=np.uint64), 0, len(path_ids), req["d_bits"],
@@ -78,16 +89,15 @@ def test_grid7x8_golden_at_benchmark_tuning(bench):
         say(f"grid7x8_d40 single path {int(ids[i])}")
         a = run(ids[i:i + 1])
         assert c11_error(a, gold["amps"][i], 1, c.k, 56) <= TOL_C64, int(ids[i])
-    _release(req)
 
 
 @pytest.mark.slow
-def test_grid7x8_full_block_is_sum_of_halves(bench):
+@pytest.mark.timeout(900)
+def test_grid7x8_full_block_is_sum_of_halves(req7x8):
     """All 1024 paths of the block over 1e6 bitstrings, benchmark tuning, equal the sum of the
     two aligned 512-path halves run as separate requests."""
     from paper_1807_10749_amd import binding as sf
-    say("grid7x8_d40: set-up and autotune of the full benchmark request")
-    req = bench.prepare("grid7x8_d40", n_measure=3)
+    req = req7x8
     c, begin, count = req["c"], req["begin"], req["npaths"]
 
     def run(b, n):
@@ -106,10 +116,10 @@ def test_grid7x8_full_block_is_sum_of_halves(bench):
     # a nonzero result at the expected scale: the mean |amp|^2 of 1024 of 2^35 paths
     mean = float(np.mean(np.abs(full) ** 2))
     assert 0.25 < mean / (count / 2.0 ** c.k * 2.0 ** -56) < 4.0, mean
-    _release(req)
 
 
 @pytest.mark.slow
+@pytest.mark.timeout(900)
 def test_grid6x7_64_sampled_paths(bench):
     """64 of the seeded f = 0.01 ids on 1e5 bitstrings, library default tuning and dense
     four-qubit blocks, against the oracle."""
@@ -118,10 +128,17 @@ def test_grid6x7_64_sampled_paths(bench):
     g = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed)
     c = sf.Circuit(cfg.rows, cfg.cols, g, cfg.cut_mask())
     ids_all = sf.sample_paths(c.k, cfg.f, cfg.path_seed)
-    ids = ids_all[:: ids_all.size // 64][:64]
+    pairs = equal_bit_pairs(g, cfg.cut_mask())
+    live = np.array([is_live(int(p), pairs) for p in ids_all[:200_000]])
+    ids = ids_all[:200_000][live][:: int(live.sum()) // 64][:64]      # 64 live ids spread over the sample
+    dead = ids_all[:200_000][~live][:4]
     bits = random_bitstrings(42, 100_000, cfg.bits_seed)
-    say(f"grid6x7_d32 oracle over 64 sampled paths x {bits.size} bitstrings")
-    o = oracle.path_sum(42, g, cfg.cut_mask(), ids, bits)
+    say(f"grid6x7_d32 oracle over 64 sampled live paths x {bits.size} bitstrings")
+    o, na, _ = oracle.path_sum(42, g, cfg.cut_mask(), ids, bits, norms=True)
+    assert np.all(na > 1e-12)
+    say("grid6x7_d32 oracle norms of 4 zero-term paths of the sample")
+    _, nd, _ = oracle.path_sum(42, g, cfg.cut_mask(), dead, bits[:10], norms=True)
+    assert np.all(nd == 0.0)
     for tune in ({}, {"dense_qubits": 4}):
         c.tune(**tune)
         say(f"grid6x7_d32 64 sampled paths {tune}")
@@ -131,6 +148,7 @@ def test_grid6x7_64_sampled_paths(bench):
 
 
 @pytest.mark.slow
+@pytest.mark.timeout(900)
 def test_grid5x6_full_size_at_benchmark_tuning(bench):
     """All 2^15 paths over the 1e5 bitstrings in the launch configuration the benchmark's
     autotuner picks for that request."""

@@ -8,6 +8,6 @@ other's computation through it.
 from .generator import (  # noqa: F401
     GATE_DTYPE, H, XH, YH, T, CZ, ISWAP, GATE_NAMES,
     SplitMix64, splitmix64_array,
-    cz_pattern_edges, grid_circuit, random_bitstrings, path_block,
-    column_cut_mask, row_cut_mask, CONFIGS, WorkloadConfig, make_workload, serving_mix,
+    cz_pattern_edges, grid_circuit, random_bitstrings, path_block, equal_bit_pairs, is_live, live_path_block,
+    column_cut_mask, row_cut_mask, CONFIGS, WorkloadConfig, make_workload, serving_mix, workload_block,
 )

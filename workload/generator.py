@@ -171,6 +171,59 @@ def path_block(k: int, block_bits: int, seed: int):
     return b << block_bits, 1 << block_bits
 
 
+def equal_bit_pairs(gates: np.ndarray, mask_a: int):
+    """Pairs (u, v) of path bits that every path with a nonzero term sets equal, for circuits whose
+    crossing two-qubit gates are all CZs (an empty list otherwise).
+
+    Path bits follow the crossing CZs in (cycle, smaller qubit) order, the first CZ taking the
+    highest bit (k-1).  A crossing CZ's path bit s puts the projector onto |s> on its block-A
+    endpoint (Section 2, Eq. (CZ)).  When a block-A qubit meets two crossing CZs with only
+    diagonal gates (T, CZ) on it in between, the two projectors multiply, and the path's term is
+    zero unless both bits are equal: such paths are skipped (the paper's zero blocks, Section 2),
+    and a benchmark path block must avoid them.  This only scans the gate list."""
+    in_a = lambda q: (mask_a >> int(q)) & 1
+    crossing = [i for i, g in enumerate(gates) if int(g["kind"]) in (CZ, ISWAP) and in_a(g["q0"]) != in_a(g["q1"])]
+    if any(int(gates[i]["kind"]) != CZ for i in crossing):
+        return []
+    order = sorted(crossing, key=lambda i: (int(gates[i]["cycle"]), min(int(gates[i]["q0"]), int(gates[i]["q1"]))))
+    k = len(order)
+    bit_of = {gi: k - 1 - j for j, gi in enumerate(order)}
+    held = {}          # block-A qubit -> path bit of its projector, while only diagonal gates follow
+    pairs = []
+    for i, g in enumerate(gates):
+        kind, q0, q1 = int(g["kind"]), int(g["q0"]), int(g["q1"])
+        if i in bit_of:
+            a = q0 if in_a(q0) else q1
+            if a in held:
+                pairs.append((held[a], bit_of[i]))
+            held[a] = bit_of[i]
+        elif kind in (H, XH, YH):
+            held.pop(q0, None)
+    return pairs
+
+
+def is_live(path_id: int, pairs) -> bool:
+    """Whether a path id sets every pair of equal_bit_pairs equal."""
+    return all(((path_id >> u) & 1) == ((path_id >> v) & 1) for u, v in pairs)
+
+
+def live_path_block(k: int, block_bits: int, seed: int, pairs):
+    """A seeded aligned block of 2^block_bits path ids whose shared prefix is live: the first
+    output of SplitMix64(seed) (top k - block_bits bits as the block index) whose block has no
+    pair of equal_bit_pairs decided differently within the prefix; returns (begin, count).
+    Pairs that involve the low block_bits bits are left to the paths of the block."""
+    if block_bits > k:
+        raise ValueError("block larger than the path space")
+    hi_bits = k - block_bits
+    pre = [(u, v) for u, v in pairs if u >= block_bits and v >= block_bits]
+    rng = SplitMix64(seed)
+    for _ in range(1 << 16):
+        b = 0 if hi_bits == 0 else rng.next() >> (64 - hi_bits)
+        if is_live(b << block_bits, pre):
+            return b << block_bits, 1 << block_bits
+    raise ValueError("no live block found")
+
+
 def column_cut_mask(rows: int, cols: int, ncols_a: int) -> int:
     """Block A = columns 0..ncols_a-1 (a vertical cut)."""
     m = 0
@@ -245,6 +298,20 @@ def make_workload(name: str, n_bits: Optional[int] = None) -> dict:
     nb = cfg.n_bits if n_bits is None else n_bits
     bits = random_bitstrings(cfg.n_qubits, nb, cfg.bits_seed)
     return {"cfg": cfg, "gates": gates, "mask_a": cfg.cut_mask(), "bitstrings": bits}
+
+
+def workload_block(name: str):
+    """(begin, count) of a block workload's path ids: the live aligned block (live_path_block)
+    of its seeded draws, so that the block's paths carry nonzero terms."""
+    cfg = CONFIGS[name]
+    if cfg.paths != "block":
+        raise ValueError(f"{name} is not a path-block workload")
+    gates = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed, two_qubit=cfg.two_qubit)
+    mask = cfg.cut_mask()
+    in_a = lambda q: (mask >> int(q)) & 1
+    k = sum(1 if int(g["kind"]) == CZ else 2 for g in gates
+            if int(g["kind"]) in (CZ, ISWAP) and in_a(g["q0"]) != in_a(g["q1"]))
+    return live_path_block(k, cfg.block_bits, cfg.path_seed, equal_bit_pairs(gates, mask))
 
 
 def serving_mix(n_jobs: int, seed: int):
