@@ -148,6 +148,21 @@ int run_paths(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin,
               void *workspace, size_t workspace_bytes);
 
 /*
+ * run_paths_noalloc: run_paths for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * results as run_paths with SF_BITS_ON_DEVICE | SF_OUT_ON_DEVICE (both required; SF_TIMING is
+ * refused), but the workspace is a fixed 64 MiB device array of the library, one per GPU, held
+ * until the process ends; the call makes no device allocation.  A request whose workspace does
+ * not fit in 64 MiB (bitstring indices and visiting order, slot tables, pass programs, one
+ * block-state slot per tree level) returns SF_ERR_OOM with that reason.  Every call on a GPU
+ * uses that GPU's one array: calls that overlap on one GPU (other threads or streams) race and
+ * must be serialised by the caller; each call initialises what it reads.
+ */
+int run_paths_noalloc(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin,
+                      uint64_t n_paths, const uint64_t *bitstrings, size_t n_bits,
+                      double *amps, uint32_t flags, void *hip_stream);
+
+/*
  * workspace_size: device bytes run_paths would use for a request of
  * n_paths paths and n_bits bitstrings with the current tuning when it
  * may keep every tree level of the request resident (the library then
@@ -186,7 +201,8 @@ int get_tuning(const sf_circuit_t *c, sf_tuning_t *t);
  * gather bytes over measured bandwidths plus a per-launch cost (the paper's
  * C1 2^x_p (q1 2^q1 + q2 2^q2)(d_p + C2 2^x_b d_b) + C3 2^(x_p+x_b) n_a
  * with the constants taken from the device).  The best-ranked candidate of
- * every kind (folded levels or written leaves, dense blocks or not), more
+ * every kind (folded levels or written leaves; no dense blocks, or dense
+ * windows of up to 2, 3 or 4 qubits), more
  * candidates by rank up to n_measure, and the current tuning are then timed
  * with real run_paths
  * calls on this request (same argument rules as run_paths, checked before

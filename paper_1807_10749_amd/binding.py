@@ -25,7 +25,7 @@ EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_pa
            "server_drain", "server_stats", "server_destroy", "server_last_error", "rejection_m",
            "sample_bitstrings", "rejection_workspace_size", "rejection_accept", "frugal_sample",
            "fidelity_estimate", "xeb_fidelity", "verify_claim", "save_tuning_cache", "load_tuning_cache",
-           "server_set_policy"]
+           "server_set_policy", "run_paths_noalloc"]
 SF_PENDING = 1
 SF_SERVE_OLDEST_FIRST, SF_SERVE_ROUND_ROBIN, SF_SERVE_LEAST_WORK = 0, 1, 2
 
@@ -89,6 +89,7 @@ def _load():
     lib.num_paths.argtypes = [u32, ctypes.c_double, pu64]
     lib.sample_paths.argtypes = [u32, ctypes.c_double, u64, vp, u64, pu64]
     lib.run_paths.argtypes = [vp, vp, u64, u64, vp, sz, vp, u32, vp, vp, sz]
+    lib.run_paths_noalloc.argtypes = [vp, vp, u64, u64, vp, sz, vp, u32, vp]
     lib.workspace_size.argtypes = [vp, u64, sz, u32, ctypes.POINTER(sz)]
     lib.set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -275,6 +276,17 @@ def run_paths(c: int, path_ids, path_begin: int, n_paths: int, bitstrings, n_bit
         n_paths = ids.size
     _check(lib.run_paths(c, _ptr(ids), path_begin, n_paths, _ptr(bitstrings), n_bits, _ptr(amps), flags,
                          _stream_handle(stream), _ptr(workspace), workspace_bytes))
+
+
+def run_paths_noalloc(c: int, path_ids, path_begin: int, n_paths: int, bitstrings, n_bits: int, amps,
+                      flags: int = 0, stream=None):
+    """Raw call of the entry point without device allocations (device bitstrings and amps)."""
+    ids = None
+    if path_ids is not None:
+        ids = np.ascontiguousarray(path_ids, dtype=np.uint64)
+        n_paths = ids.size
+    _check(lib.run_paths_noalloc(c, _ptr(ids), path_begin, n_paths, _ptr(bitstrings), n_bits, _ptr(amps), flags,
+                                 _stream_handle(stream)))
 
 
 def workspace_size(c: int, n_paths: int, n_bits: int, flags: int = 0) -> int:

@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsfpath.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "planner.cpp", "executor.cpp", "sfpath.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "planner.cpp", "executor.cpp", "sfpath.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -8,7 +8,10 @@
 // register index by the 64 lanes are 64 consecutive complex values (512 B
 // in complex64), i.e. whole cache lines.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_reduce.hpp>
+#include <rocprim/device/device_select.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "kernels.hpp"
 
@@ -653,8 +656,8 @@ __global__ void iota_kernel(uint32_t *p, uint64_t n)
 hipError_t sort_by_key_temp_bytes(uint64_t n, size_t *bytes)
 {
     *bytes = 0;
-    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                              (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 32);
+    return rocprim::radix_sort_pairs(nullptr, *bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                     (const uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n, 0u, 32u);
 }
 
 hipError_t launch_order_by_key(const uint32_t *keys, uint32_t *keys_sorted, uint32_t *idx, uint32_t *order,
@@ -664,8 +667,8 @@ hipError_t launch_order_by_key(const uint32_t *keys, uint32_t *keys_sorted, uint
     iota_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(idx, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, idx, order, (int)n, 0,
-                                              key_bits < 1 ? 1 : key_bits, s);
+    return rocprim::radix_sort_pairs(temp, temp_bytes, keys, keys_sorted, idx, order, (size_t)n, 0u,
+                                     (unsigned)(key_bits < 1 ? 1 : key_bits), s);
 }
 
 // ---------------------------------------------------------------- small helpers
@@ -1236,11 +1239,10 @@ __global__ void accept_kernel(const double *amps, uint64_t n, double scale, uint
 hipError_t reject_temp_bytes(uint64_t n, size_t *bytes)
 {
     size_t a = 0, b = 0;
-    hipError_t e = hipcub::DeviceSelect::Flagged(nullptr, a, hipcub::CountingInputIterator<uint32_t>(0),
-                                                 (const uint8_t *)nullptr, (uint32_t *)nullptr,
-                                                 (uint64_t *)nullptr, (int)n);
+    hipError_t e = rocprim::select(nullptr, a, rocprim::counting_iterator<uint32_t>(0), (const uint8_t *)nullptr,
+                                   (uint32_t *)nullptr, (uint64_t *)nullptr, (size_t)n);
     if (e != hipSuccess) return e;
-    e = hipcub::DeviceReduce::Sum(nullptr, b, (const double *)nullptr, (double *)nullptr, (int)n);
+    e = rocprim::reduce(nullptr, b, (const double *)nullptr, (double *)nullptr, (size_t)n, rocprim::plus<double>());
     *bytes = a > b ? a : b;
     return e;
 }
@@ -1254,11 +1256,11 @@ hipError_t launch_accept(const double *amps, uint64_t n, double scale, uint64_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t tb = temp_bytes;
-    e = hipcub::DeviceSelect::Flagged(temp, tb, hipcub::CountingInputIterator<uint32_t>(0), flag, accepted,
-                                      n_accepted, (int)n, s);
+    e = rocprim::select(temp, tb, rocprim::counting_iterator<uint32_t>(0), (const uint8_t *)flag, accepted, n_accepted,
+                        (size_t)n, s);
     if (e != hipSuccess) return e;
     tb = temp_bytes;
-    return hipcub::DeviceReduce::Sum(temp, tb, excess, excess_sum, (int)n, s);
+    return rocprim::reduce(temp, tb, (const double *)excess, excess_sum, (size_t)n, rocprim::plus<double>(), s);
 }
 
 // ---------------------------------------------------------------- validation: overlaps

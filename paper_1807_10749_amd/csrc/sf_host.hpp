@@ -169,6 +169,13 @@ bool fold_general(const Circuit &c, int FD);
 // into dense 4-qubit blocks applied on matrix cores.
 const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m = 0);
 
+// sfpath.cpp: run_paths' argument checks and execution on a given workspace of any size (the
+// entry point without allocations), and the thread's last_error() message.
+int run_paths_in(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
+                 const uint64_t *bitstrings, size_t n_bits, double *amps, uint32_t flags, void *hip_stream,
+                 void *workspace, size_t workspace_bytes);
+int set_error(int code, const std::string &msg);
+
 // executor.cpp
 // dry_run: plan the request (tree, batches, passes) and fill the launch and byte counts of
 // c.stats without touching device memory.

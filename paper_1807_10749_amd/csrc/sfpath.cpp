@@ -241,6 +241,29 @@ int check_run_args(const sf_circuit_t *c, const uint64_t *bitstrings, size_t n_b
 }
 }  // namespace
 
+}  // extern "C"
+
+namespace sf {
+// run_paths on a workspace of the caller's choosing that may be smaller than run_paths'
+// 256 MiB minimum (the executor still refuses one that cannot hold a single slot per level).
+int run_paths_in(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
+                 const uint64_t *bitstrings, size_t n_bits, double *amps, uint32_t flags, void *hip_stream,
+                 void *workspace, size_t workspace_bytes)
+{
+    return guarded([&]() -> int {
+        if (const int rc = check_run_args(c, bitstrings, n_bits, amps, flags, nullptr, 0)) return rc;
+        std::string err;
+        const int rc = sf::execute(*c, path_ids, path_begin, n_paths, bitstrings, n_bits, amps, flags, hip_stream,
+                                   workspace, workspace_bytes, err);
+        return rc ? fail(rc, err) : ok();
+    });
+}
+
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+}  // namespace sf
+
+extern "C" {
+
 int run_paths(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
               const uint64_t *bitstrings, size_t n_bits, double *amps, uint32_t flags, void *hip_stream,
               void *workspace, size_t workspace_bytes)
@@ -331,7 +354,7 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
         std::swap(probe, c->tuning);
         for (uint32_t r : regs)
             for (uint32_t w : wpcs)
-                for (uint32_t dq : {0u, 4u}) {
+                for (uint32_t dq : {0u, 2u, 3u, 4u}) {
                     if (dq && fp64) continue;                 // dense blocks on matrix cores: complex64 only
                     for (int F = 1; F <= max_fold; ++F) {     // F trailing levels folded into the gather
                         const int Fp = max_fold > 1 ? max_fold - 1 : 1;

@@ -60,8 +60,10 @@ def test_general_fold_matches_oracle(sf, rows, cols, depth, seed, ncols_a):
         a = c.amplitudes(bits, path_ids=sub)
         o = oracle.path_sum(n, g, mask, sub, bits)
         assert c11_error(a, o, sub.size, c.k, n) <= TOL_C64, F
-        pairs = equal_bit_pairs(g, mask)
-        live = [int(p) for p in sub if is_live(int(p), pairs)][:3]
+        # three paths of the subset whose terms are nonzero (by the oracle's block-A norms)
+        _, na, _ = oracle.path_sum(n, g, mask, sub[:64], bits[:2], norms=True)
+        live = [int(p) for p, v in zip(sub[:64], na) if v > 0][:3]
+        assert len(live) == 3
         say(f"{rows}x{cols} d{depth}: general fold F={F}, plain form and single paths {live}")
         a = c.amplitudes(bits, path_ids=live, flags=sf.SF_PLAIN)
         o = oracle.path_sum(n, g, mask, live, bits)

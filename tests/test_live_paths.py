@@ -5,8 +5,11 @@ between multiply to zero unless their path bits agree, so such paths carry no am
 paper's zero blocks, Section 2).  The seeded input generator (workload.equal_bit_pairs, which
 picks live benchmark blocks) and the library (equal_bit_pairs in the planner, which skips dead
 paths; printed by describe_plan) each derive the pairs of path bits that must agree from the
-gate list.  Both are pinned here against the FP64 oracle's arithmetic: a path's block-A norm is
-zero exactly when one of the pairs disagrees.
+gate list.  Both are pinned here against the FP64 oracle's arithmetic: every path that
+disagrees on a pair has block-A norm zero (the rule is sound: it never drops a nonzero term),
+and on these circuits, the benchmark's 5x6 and 6x7 among them, the converse holds too.  Terms
+can also vanish through longer chains of gates on several qubits (the last case below), which
+the rule does not see; such paths are computed and contribute zero.
 """
 import re
 
@@ -50,6 +53,22 @@ def test_zero_terms_are_exactly_the_unequal_pairs(sf, rows, cols, depth, seed, n
     assert np.all(na[~live] == 0.0)
     assert np.all(na[live] > 1e-12)
     assert 0 < live.sum() < ids.size or not pairs
+
+
+def test_rule_is_sound_where_other_zeros_exist(sf):
+    """A 5x4 circuit with zero terms beyond the pairs: no path the rule rejects has a nonzero
+    term, and the library finds the same pairs."""
+    from workload import column_cut_mask
+    g = grid_circuit(5, 4, 24, 3)
+    mask = column_cut_mask(5, 4, 2)
+    pairs = equal_bit_pairs(g, mask)
+    assert sorted(pairs) == library_pairs(sf, 5, 4, g, mask)
+    k = oracle.num_cut(20, g, mask)
+    ids = np.sort(np.random.default_rng(2).choice(1 << k, 600, replace=False)).astype(np.uint64)
+    _, na, _ = oracle.path_sum(20, g, mask, ids, random_bitstrings(20, 2, 1), norms=True)
+    live = np.array([is_live(int(p), pairs) for p in ids])
+    assert np.all(na[~live] == 0.0)
+    assert np.any(na[live] == 0.0)
 
 
 def test_hand_built_pairs():
