@@ -178,6 +178,109 @@ __device__ __forceinline__ void lane_flip(int b, bool f, C (&v)[1 << R])
     }
 }
 
+// ---------------------------------------------------------------- iSWAP inside a block
+
+// iSWAP (Section 7) on two qubits of the tile: the amplitudes with the qubits' bits (0, 1) and
+// (1, 0) trade places, each multiplied by i; (0, 0) and (1, 1) are kept.  Selects, shuffles and
+// sign flips only.
+
+// Both qubits in registers KA < KB.  The empty asm statement keeps the cases of the dispatch
+// apart (see reg_flip).
+template <int KA, int KB, int R, typename C>
+__device__ __forceinline__ void reg_iswap(C (&v)[1 << R])
+{
+    constexpr int N = 1 << R;
+    constexpr int A = 1 << KA, B = 1 << KB;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if ((j & A) || !(j & B)) continue;          // j holds (a, b) = (0, 1)
+        constexpr int X = A | B;
+        const C x = v[j], y = v[j ^ X];
+        v[j].x = -y.y; v[j].y = y.x;                // (0, 1) <- i (1, 0)
+        v[j ^ X].x = -x.y; v[j ^ X].y = x.x;        // (1, 0) <- i (0, 1)
+    }
+    asm volatile("; reg_iswap %0 %1" :: "n"(KA), "n"(KB));
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void reg_iswap_dispatch(int ka, int kb, C (&v)[1 << R])
+{
+    if (ka > kb) { const int t = ka; ka = kb; kb = t; }
+    switch (ka * 8 + kb) {
+    case 0 * 8 + 1: if constexpr (R > 1) reg_iswap<0, 1, R>(v); break;
+    case 0 * 8 + 2: if constexpr (R > 2) reg_iswap<0, 2, R>(v); break;
+    case 0 * 8 + 3: if constexpr (R > 3) reg_iswap<0, 3, R>(v); break;
+    case 0 * 8 + 4: if constexpr (R > 4) reg_iswap<0, 4, R>(v); break;
+    case 1 * 8 + 2: if constexpr (R > 2) reg_iswap<1, 2, R>(v); break;
+    case 1 * 8 + 3: if constexpr (R > 3) reg_iswap<1, 3, R>(v); break;
+    case 1 * 8 + 4: if constexpr (R > 4) reg_iswap<1, 4, R>(v); break;
+    case 2 * 8 + 3: if constexpr (R > 3) reg_iswap<2, 3, R>(v); break;
+    case 2 * 8 + 4: if constexpr (R > 4) reg_iswap<2, 4, R>(v); break;
+    case 3 * 8 + 4: if constexpr (R > 4) reg_iswap<3, 4, R>(v); break;
+    default: break;
+    }
+}
+
+// One qubit in register K, the other in lane bit b: each lane trades with its partner across
+// lane bit b.  A lane with the lane qubit 1 takes i times its partner's register j|A into its
+// register j (bits (0, 1) <- (1, 0)); a lane with it 0 takes i times the partner's register j
+// into its register j|A ((1, 0) <- (0, 1)).
+template <int K, int R, typename C>
+__device__ __forceinline__ void reg_lane_iswap(int b, int lane, C (&v)[1 << R])
+{
+    constexpr int N = 1 << R;
+    constexpr int A = 1 << K;
+    const int m = 1 << b;
+    const bool hi = (lane & m) != 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j & A) continue;
+        const C x0 = v[j], x1 = v[j | A];
+        C t0, t1;
+        t0.x = __shfl_xor(x0.x, m);
+        t0.y = __shfl_xor(x0.y, m);
+        t1.x = __shfl_xor(x1.x, m);
+        t1.y = __shfl_xor(x1.y, m);
+        v[j].x = hi ? -t1.y : x0.x;
+        v[j].y = hi ? t1.x : x0.y;
+        v[j | A].x = hi ? x1.x : -t0.y;
+        v[j | A].y = hi ? x1.y : t0.x;
+    }
+    asm volatile("; reg_lane_iswap %0" :: "n"(K));
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void reg_lane_iswap_dispatch(int k, int b, int lane, C (&v)[1 << R])
+{
+    switch (k) {
+    case 0: if constexpr (R > 0) reg_lane_iswap<0, R>(b, lane, v); break;
+    case 1: if constexpr (R > 1) reg_lane_iswap<1, R>(b, lane, v); break;
+    case 2: if constexpr (R > 2) reg_lane_iswap<2, R>(b, lane, v); break;
+    case 3: if constexpr (R > 3) reg_lane_iswap<3, R>(b, lane, v); break;
+    case 4: if constexpr (R > 4) reg_lane_iswap<4, R>(b, lane, v); break;
+    default: break;
+    }
+}
+
+// Both qubits in lane bits ba, bb: a lane whose two bits differ takes i times the value of the
+// lane with both bits flipped; the others keep theirs.
+template <int R, typename C>
+__device__ __forceinline__ void lane_iswap(int ba, int bb, int lane, C (&v)[1 << R])
+{
+    constexpr int N = 1 << R;
+    const int m = (1 << ba) | (1 << bb);
+    const bool sel = (((lane >> ba) ^ (lane >> bb)) & 1) != 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const C o = v[j];
+        C t;
+        t.x = __shfl_xor(o.x, m);
+        t.y = __shfl_xor(o.y, m);
+        v[j].x = sel ? -t.y : o.x;
+        v[j].y = sel ? t.x : o.y;
+    }
+}
+
 // ---------------------------------------------------------------- diagonal groups
 
 __device__ __forceinline__ int tab_entry(const uint64_t (&tab)[4], int j)
@@ -412,6 +515,12 @@ __device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t n
                 lane_gate<R>(op.target, op.kind, (int)lane, v);
             } else if (!FLIP || op.type == PO_DIAG) {
                 apply_diag<R, T>(groups + op.group, terms, eB, sp, v);
+            } else if (op.type == PO_ISWAP) {
+                const int t0 = op.target, t1 = (int)(op.group & 0xffu);
+                if (op.kind == 0) reg_iswap_dispatch<R>(t0, t1, v);
+                else if (op.kind == 3) lane_iswap<R>(t0, t1, (int)lane, v);
+                else if (op.kind == 1) reg_lane_iswap_dispatch<R>(t1, t0, (int)lane, v);
+                else reg_lane_iswap_dispatch<R>(t0, t1, (int)lane, v);
             } else {
                 const bool f = (((sp >> op.group) ^ (sp >> (op.group + 1))) & 1u) != 0;
                 if (op.type == PO_PFLIP_REG) reg_flip_dispatch<R>(op.target, f, v);

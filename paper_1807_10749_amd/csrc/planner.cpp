@@ -56,6 +56,16 @@ static std::vector<std::complex<double>> fold_table(const std::vector<HalfOp> &r
             } else if (op.kind == HK_CZ) {
                 const int b = tpos[op.q1];
                 for (int r = 0; r < D; ++r) if (((r >> a) & 1) && ((r >> b) & 1)) v[r] = -v[r];
+            } else if (op.kind == HK_ISWAP) {
+                const int b = tpos[op.q1];
+                const std::complex<double> I(0.0, 1.0);
+                for (int r = 0; r < D; ++r)
+                    if (!((r >> a) & 1) && ((r >> b) & 1)) {
+                        const int r2 = r ^ (1 << a) ^ (1 << b);
+                        const std::complex<double> x = v[r], y = v[r2];
+                        v[r] = I * y;
+                        v[r2] = I * x;
+                    }
             } else {
                 std::complex<double> g[4];
                 gate2x2(op.kind, g);
@@ -116,13 +126,13 @@ static LeafFold make_fold(const Circuit &c, int h, int F)
                 bq[op.bit] = op.q0;
                 continue;
             }
-            if (op.q0 >= 32 || (op.kind == HK_CZ && op.q1 >= 32)) return f;
+            if (op.q0 >= 32 || (is_two_qubit(op.kind) && op.q1 >= 32)) return f;
+            const uint32_t om = (1u << op.q0) | (is_two_qubit(op.kind) ? 1u << op.q1 : 0u);
             if (!is_diag(op.kind)) {
-                nondiag_seen |= 1u << op.q0;
-                smask |= 1u << op.q0;
+                nondiag_seen |= om;
+                smask |= om;
             }
-            tmask |= 1u << op.q0;
-            if (op.kind == HK_CZ) tmask |= 1u << op.q1;
+            tmask |= om;
             rest.push_back(op);
         }
     uint32_t bmask = 0;
@@ -203,7 +213,7 @@ static LeafFold make_fold_iswap(const Circuit &c, int h, int F)
     std::vector<HalfOp> rest;
     for (int l = L - F + 1; l <= L; ++l)
         for (const HalfOp &op : c.half[h].segments[l]) {
-            if (op.q0 >= 32 || (op.kind == HK_CZ && op.q1 >= 32)) return f;
+            if (op.q0 >= 32 || (is_two_qubit(op.kind) && op.q1 >= 32)) return f;
             const uint32_t m0 = 1u << op.q0;
             if (op.kind == HK_ZCTL) return f;
             if (op.kind == HK_PROJ) {
@@ -227,10 +237,10 @@ static LeafFold make_fold_iswap(const Circuit &c, int h, int F)
                 proj_bit[op.q0] = -2;
                 continue;
             }
-            const uint32_t m = m0 | (op.kind == HK_CZ ? 1u << op.q1 : 0u);
+            const uint32_t m = m0 | (is_two_qubit(op.kind) ? 1u << op.q1 : 0u);
             for (int q = 0; q < 32; ++q)
                 if (((m >> q) & 1) && proj_bit[q] >= 0) return f;   // between a projector and its flip
-            if (!is_diag(op.kind)) smask |= m0;
+            if (!is_diag(op.kind)) smask |= m;
             tmask |= m;
             seen |= m;
             rest.push_back(op);
@@ -369,13 +379,10 @@ int build_programs(Circuit &c, std::string &err)
         const int h = in_a(g.q0) ? 0 : 1;
         const uint8_t a = (uint8_t)local[g.q0];
         if (g.kind == 5) {
-            // iSWAP inside a block, exactly: H_b H_a CZ H_a H_b CZ H_b H_a, then S = T^2 on both
-            const uint8_t b = (uint8_t)local[g.q1];
-            const HalfOp seq[] = {{HK_H, b, 0, 0}, {HK_H, a, 0, 0}, {HK_CZ, a, b, 0}, {HK_H, a, 0, 0},
-                                  {HK_H, b, 0, 0}, {HK_CZ, a, b, 0}, {HK_H, b, 0, 0}, {HK_H, a, 0, 0},
-                                  {HK_T, a, 0, 0}, {HK_T, a, 0, 0}, {HK_T, b, 0, 0}, {HK_T, b, 0, 0}};
-            for (const HalfOp &op : seq) ops[h].push_back(op);
-            own[h].resize(ops[h].size(), 0);
+            // iSWAP inside a block: one operation on both qubits (a swap of the |01> and |10>
+            // amplitudes, each times i)
+            ops[h].push_back(HalfOp{HK_ISWAP, a, (uint8_t)local[g.q1], 0});
+            own[h].push_back(0);
             continue;
         }
         HalfOp op{0, a, 0, 0};
@@ -406,8 +413,10 @@ int build_programs(Circuit &c, std::string &err)
                 if (op.kind == HK_CZ) D[op.q1] = std::max(D[op.q1], lvl);
             } else {
                 lvl = std::max(lvl, std::max(N[op.q0], D[op.q0]));
+                if (op.kind == HK_ISWAP) lvl = std::max(lvl, std::max(N[op.q1], D[op.q1]));
                 N[op.q0] = lvl;
                 D[op.q0] = lvl;
+                if (op.kind == HK_ISWAP) N[op.q1] = D[op.q1] = lvl;
             }
             c.half[h].segments[lvl].push_back(op);
         }
@@ -422,7 +431,7 @@ int build_programs(Circuit &c, std::string &err)
         std::vector<HalfOp> kept;
         int folded = 0;
         for (const HalfOp &op : hp.segments[0]) {
-            const uint64_t m = (uint64_t(1) << op.q0) | (op.kind == HK_CZ ? uint64_t(1) << op.q1 : 0);
+            const uint64_t m = (uint64_t(1) << op.q0) | (is_two_qubit(op.kind) ? uint64_t(1) << op.q1 : 0);
             if (op.kind == HK_H && !(touched & m)) {
                 hp.init_h_mask |= m;
                 ++folded;
@@ -482,6 +491,8 @@ std::vector<std::pair<int, int>> equal_bit_pairs(const Circuit &c)
                     held[t] = op.bit;
                 } else if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) {
                     held[t] = held[t] == op.bit ? op.bit + 1 : held[t] == op.bit + 1 ? op.bit : -1;
+                } else if (op.kind == HK_ISWAP) {
+                    std::swap(held[t], held[op.q1]);       // |ab> -> (phase) |ba>
                 } else if (!is_diag(op.kind)) {
                     held[t] = -1;
                 }
@@ -620,6 +631,18 @@ std::vector<float> dense_matrix(const std::vector<HalfOp> &ops, const int qs[4])
         } else if (op.kind == HK_CZ) {
             const int t1 = idx(op.q0), t2 = idx(op.q1);
             for (int r = 0; r < 16; ++r) if (((r >> t1) & 1) && ((r >> t2) & 1)) for (int c2 = 0; c2 < 16; ++c2) M[r][c2] = -M[r][c2];
+        } else if (op.kind == HK_ISWAP) {
+            const int t1 = idx(op.q0), t2 = idx(op.q1);
+            const std::complex<double> I(0.0, 1.0);
+            for (int r = 0; r < 16; ++r) {
+                if (((r >> t1) & 1) || !((r >> t2) & 1)) continue;
+                const int r2 = r ^ (1 << t1) ^ (1 << t2);
+                for (int c2 = 0; c2 < 16; ++c2) {
+                    const std::complex<double> x = M[r][c2], y = M[r2][c2];
+                    M[r][c2] = I * y;
+                    M[r2][c2] = I * x;
+                }
+            }
         } else {
             std::complex<double> g[4];
             gate2x2(op.kind, g);
@@ -669,7 +692,30 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
         carry = (carry + nn) % 2;
     }
     int taken = 0;
-    const int seg_exp = hp.seg_rescale_exp[level];
+    int seg_exp = hp.seg_rescale_exp[level];
+    // An iSWAP whose two qubits cannot both sit in one pass (fewer free registers and lane-qubit
+    // slots than it needs) is applied as H_b H_a CZ H_a H_b CZ H_b H_a followed by S = T^2 on both
+    // qubits, which is the iSWAP exactly; its six unnormalised H gates gain a factor 8, divided
+    // out with the segment's rescaling.
+    {
+        const bool lq_seg = max_lq >= 1 && n_lane_q == 0 && p >= 6 && q > R_eff;
+        const bool lq4_seg = lq_seg && max_lq >= 2 && q > R_eff + 1;
+        const int cap = R_eff + (lq_seg ? 1 : 0) + (lq4_seg ? 1 : 0);
+        std::vector<HalfOp> out;
+        for (const HalfOp &op : rem) {
+            if (op.kind == HK_ISWAP && (op.q0 >= n_lane_q) + (op.q1 >= n_lane_q) > cap) {
+                const uint8_t a = op.q0, b = op.q1;
+                const HalfOp seq[] = {{HK_H, b, 0, 0}, {HK_H, a, 0, 0}, {HK_CZ, a, b, 0}, {HK_H, a, 0, 0},
+                                      {HK_H, b, 0, 0}, {HK_CZ, a, b, 0}, {HK_H, b, 0, 0}, {HK_H, a, 0, 0},
+                                      {HK_T, a, 0, 0}, {HK_T, a, 0, 0}, {HK_T, b, 0, 0}, {HK_T, b, 0, 0}};
+                for (const HalfOp &x : seq) out.push_back(x);
+                seg_exp += 3;
+                continue;
+            }
+            out.push_back(op);
+        }
+        rem.swap(out);
+    }
 
     // Zero subspace (the paper's zero-block skipping): after the projector P_s of a crossing
     // gate on qubit t, and until the next non-diagonal gate on t, every amplitude whose bit t
@@ -682,8 +728,11 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
             const std::pair<uint8_t, uint8_t> e{op.q0, op.bit};
             if (std::find(zs.begin(), zs.end(), e) == zs.end()) zs.push_back(e);
         } else if (!is_diag(op.kind)) {
+            const bool two = op.kind == HK_ISWAP;
             zs.erase(std::remove_if(zs.begin(), zs.end(),
-                                    [&op](const std::pair<uint8_t, uint8_t> &e) { return e.first == op.q0; }),
+                                    [&op, two](const std::pair<uint8_t, uint8_t> &e) {
+                                        return e.first == op.q0 || (two && e.first == op.q1);
+                                    }),
                      zs.end());
         }
     };
@@ -701,11 +750,11 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
             uint64_t blocked = 0;
             int nd = 0;
             for (const HalfOp &op : rem) {
-                const uint64_t qm = (uint64_t(1) << op.q0) | (op.kind == HK_CZ ? uint64_t(1) << op.q1 : 0);
+                const uint64_t qm = (uint64_t(1) << op.q0) | (is_two_qubit(op.kind) ? uint64_t(1) << op.q1 : 0);
                 bool take = !(qm & blocked) && !is_branch(op.kind);
                 std::vector<int> nq = Q;
                 if (take) {
-                    const int qq[2] = {op.q0, op.kind == HK_CZ ? (int)op.q1 : -1};
+                    const int qq[2] = {op.q0, is_two_qubit(op.kind) ? (int)op.q1 : -1};
                     for (int x : qq) {
                         if (x < 0) continue;
                         if (p + x < 5) take = false;
@@ -732,7 +781,7 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
                 for (int t = 0; t < 4; ++t) { qs[t] = Q[t]; pp.bpos[t] = p + Q[t]; }
                 pp.mat = dense_matrix(blk, qs);
                 pp.n_nondiag = nd;
-                carry += pp.n_nondiag;
+                for (const HalfOp &op : blk) carry += has_gain(op.kind) ? 1 : 0;   // norm gain sqrt2 each
                 if (carry >= 32) {
                     const int e = std::min(carry / 2, seg_exp - taken);
                     pp.rescale_exp = e;
@@ -756,16 +805,31 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
         const bool lq_ok = max_lq >= 1 && n_lane_q == 0 && p >= 6 && q > R_eff;
         const bool lq4_ok = lq_ok && max_lq >= 2 && q > R_eff + 1;
         for (const HalfOp &op : rem) {
-            const uint64_t qm = (uint64_t(1) << op.q0) | (op.kind == HK_CZ ? uint64_t(1) << op.q1 : 0);
+            const uint64_t qm = (uint64_t(1) << op.q0) | (is_two_qubit(op.kind) ? uint64_t(1) << op.q1 : 0);
             if (qm & blocked) { defer.push_back(op); blocked |= qm; continue; }
             if (!is_diag(op.kind)) {
-                const int t = op.q0;
-                const bool lane = t < n_lane_q || t == lq || t == lq4;
-                const bool have = std::find(regq.begin(), regq.end(), t) != regq.end();
-                if (lane || have) { sched.push_back(op); continue; }
-                if ((int)regq.size() < R_eff) { regq.push_back(t); sched.push_back(op); continue; }
-                if (lq_ok && lq < 0) { lq = t; sched.push_back(op); continue; }
-                if (lq4_ok && lq4 < 0) { lq4 = t; sched.push_back(op); continue; }
+                // every qubit of a non-diagonal op must sit in a lane bit or a register of this pass;
+                // a qubit not yet placed takes a free register, else lane bit 5, else lane bit 4
+                const int qs[2] = {op.q0, op.kind == HK_ISWAP ? (int)op.q1 : -1};
+                std::vector<int> r2 = regq;
+                int lq2 = lq, lq42 = lq4;
+                bool fits = true;
+                for (int t : qs) {
+                    if (t < 0) continue;
+                    const bool lane = t < n_lane_q || t == lq2 || t == lq42;
+                    if (lane || std::find(r2.begin(), r2.end(), t) != r2.end()) continue;
+                    if ((int)r2.size() < R_eff) r2.push_back(t);
+                    else if (lq_ok && lq2 < 0) lq2 = t;
+                    else if (lq4_ok && lq42 < 0) lq42 = t;
+                    else fits = false;
+                }
+                if (fits) {
+                    regq = r2;
+                    lq = lq2;
+                    lq4 = lq42;
+                    sched.push_back(op);
+                    continue;
+                }
                 defer.push_back(op);
                 blocked |= qm;
                 continue;
@@ -791,15 +855,29 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
             kidx[p + regq[k]] = k;
         }
         PendingDiag pd;
+        // position of a placed qubit: its lane bit, or its register index
+        auto qpos = [&](int t, bool &lane) -> uint8_t {
+            lane = t < n_lane_q || t == lq || t == lq4;
+            return t == lq ? (uint8_t)5 : t == lq4 ? (uint8_t)4 : lane ? (uint8_t)(p + t) : (uint8_t)kidx[p + t];
+        };
         for (const HalfOp &op : sched) {
             if (!is_diag(op.kind)) {
-                const uint64_t qm = uint64_t(1) << op.q0;
+                const uint64_t qm = (uint64_t(1) << op.q0) | (op.kind == HK_ISWAP ? uint64_t(1) << op.q1 : 0);
                 if (pd.touched & qm) flush(pd, pp, kidx);
                 PassOp po;
-                const bool lane = op.q0 < n_lane_q || op.q0 == lq || op.q0 == lq4;
-                po.target = op.q0 == lq ? (uint8_t)5 : op.q0 == lq4 ? (uint8_t)4
-                                                      : lane ? (uint8_t)(p + op.q0) : (uint8_t)kidx[p + op.q0];
+                bool lane = false;
+                po.target = qpos(op.q0, lane);
                 po.pad = 0;
+                if (op.kind == HK_ISWAP) {
+                    bool lane1 = false;
+                    po.type = PO_ISWAP;
+                    po.group = qpos(op.q1, lane1);
+                    po.kind = (uint8_t)((lane ? 1 : 0) | (lane1 ? 2 : 0));
+                    pp.has_flip = true;          // the kernel variant that carries the two-qubit ops
+                    ++pp.n_nondiag;
+                    pp.ops.push_back(po);
+                    continue;
+                }
                 if (op.kind == HK_PFLIP || op.kind == HK_PFLIPI) {
                     po.type = lane ? PO_PFLIP_LANE : PO_PFLIP_REG;
                     po.kind = op.kind == HK_PFLIPI ? 1 : 0;
@@ -843,7 +921,7 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
         }
         flush(pd, pp, kidx);
         // rescale: intermediate passes only when the gain got large, the last pass settles the segment
-        carry += pp.n_nondiag;
+        for (const HalfOp &op : sched) carry += has_gain(op.kind) ? 1 : 0;
         if (carry >= 32) {
             const int e = std::min(carry / 2, seg_exp - taken);
             pp.rescale_exp = e;

@@ -31,7 +31,10 @@ enum GateKind : uint8_t { GK_H = 0, GK_X = 1, GK_Y = 2 };
 
 // PO_PFLIP_*: the non-diagonal branch operator of a crossing iSWAP (Eq. (4way)): flip the target
 // qubit in the slots whose path bits u and u+1 differ, and (kind 1) multiply those slots by i.
-enum PassOpType : uint8_t { PO_REG = 0, PO_LANE = 1, PO_DIAG = 2, PO_PFLIP_REG = 3, PO_PFLIP_LANE = 4 };
+// PO_ISWAP: an iSWAP between two qubits of the block held in the pass's registers or lanes;
+// target and group (low byte) give the two positions (register index or lane bit) and kind bit 0
+// (bit 1) says that the target (group) position is a lane bit.
+enum PassOpType : uint8_t { PO_REG = 0, PO_LANE = 1, PO_DIAG = 2, PO_PFLIP_REG = 3, PO_PFLIP_LANE = 4, PO_ISWAP = 5 };
 
 struct PassOp {
     uint8_t type;    // PassOpType

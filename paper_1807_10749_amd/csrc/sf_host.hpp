@@ -19,6 +19,7 @@ enum HalfKind : uint8_t {
     HK_ZCTL = 6,   // negate amplitudes whose bit q0 is 1 when path bit `bit` is 1 (block B side)
     HK_PFLIP = 7,  // flip bit q0 when path bits bit and bit+1 differ (crossing iSWAP, X^{i xor j})
     HK_PFLIPI = 8, // as HK_PFLIP, and multiply by i when it flips
+    HK_ISWAP = 9,  // iSWAP on q0, q1 inside the block: |01> -> i|10>, |10> -> i|01> (Section 7)
 };
 
 struct HalfOp {
@@ -28,6 +29,8 @@ struct HalfOp {
 };
 
 inline bool is_diag(uint8_t k) { return k == HK_T || k == HK_CZ || k == HK_PROJ || k == HK_ZCTL; }
+// operations on two local qubits (q0 and q1)
+inline bool is_two_qubit(uint8_t k) { return k == HK_CZ || k == HK_ISWAP; }
 // operators that depend on the path id (branch operators of crossing gates)
 inline bool is_branch(uint8_t k) { return k == HK_PROJ || k == HK_ZCTL || k == HK_PFLIP || k == HK_PFLIPI; }
 // the unnormalised one-qubit forms, whose norm gain sqrt2 the host tracks and rescales
