@@ -101,7 +101,7 @@ def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure
     ws_bytes = sf.workspace_size(c.handle, npaths, bits.size, flags_base)
     sf.set_tuning(c.handle)
     free_b, _ = torch.cuda.mem_get_info()
-    ws_bytes = min(ws_bytes, int(free_b * ws_frac))
+    ws_bytes = max(min(ws_bytes, int(free_b * ws_frac)), 1 << 28)     # run_paths takes at least 256 MiB
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     flags = flags_base | sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
     tuned = None
@@ -237,6 +237,7 @@ def main():
     progress(f"{args.workload}: k={c.k}, {npaths} paths, {bits.size} bitstrings, "
              f"workspace {req['ws_bytes'] / 2**30:.1f} GiB, tuning {req['tuning']}")
     tot = time_steps(req, args.steps, args.warmup, args.chunk_paths)
+    live_paths = c.stats()["n_paths_live"] if not args.chunk_paths else None
     elapsed = tot["elapsed_s"]
     ms_per_step = 1e3 * elapsed / args.steps
     paths_per_s = npaths * args.steps / elapsed
@@ -247,8 +248,12 @@ def main():
     if plain:
         plain["speedup_of_batched"] = paths_per_s / plain["paths_per_s"]
     progress("timed steps done")
-    sampling = None if args.no_sampling else sampling_bench(c, req["ids"], req["begin"], npaths, bits.size, req["ws"],
-                                                            req["ws_bytes"], req["stream"])
+    # rejection sampling and the validation protocol need the full output distribution: they run
+    # on an all-paths request (this one, or the 5x6 line's)
+    sampling = None
+    if not args.no_sampling and cfg.paths == "all":
+        sampling = sampling_bench(c, req["ids"], req["begin"], npaths, bits.size, req["ws"], req["ws_bytes"],
+                                  req["stream"])
     validation = None
     if not args.no_sampling and cfg.paths == "all":
         run_step(req)                # exact amplitudes again (the plain-form runs overwrote them)
@@ -272,7 +277,9 @@ def main():
             if name == args.workload:
                 continue
             progress(f"extra configuration {name}")
-            extra[name] = config_line(name, extra["ceilings"], max_paths=131072 if name == "grid6x7_d32" else 0)
+            extra[name] = config_line(name, extra["ceilings"], max_paths=131072 if name == "grid6x7_d32" else 0,
+                                      with_sampling=name == "grid5x6_d24" and not args.no_sampling
+                                      and sampling is None)
             torch.cuda.empty_cache()
     iswap = None
     if not args.no_iswap and args.workload != "grid5x6_d24_iswap":
@@ -310,6 +317,7 @@ def main():
                    **({"path_block": [int(begin), int(begin + npaths)]} if cfg.paths == "block" else {}),
                    **({"paths_sample": f"first {npaths} of {full_paths} paths"} if npaths < full_paths else {})},
         "amps_per_s": amps_per_s,
+        "live_paths": live_paths,
         "path_amp_contributions_per_s": npaths * bits.size * args.steps / elapsed,
         "plain_form": plain,
         "kernel_ms_per_step": {"sweep": run_stats["ms_sweep"] / args.steps,
@@ -359,15 +367,17 @@ PAPER_CONTEXT = {
 }
 
 
-def config_line(name, ceilings, max_paths=0, steps=3, warmup=1):
+def config_line(name, ceilings, max_paths=0, steps=3, warmup=1, with_sampling=False):
     """A short line for another configuration: paths/s, amps/s and kernel times, autotuned, on
-    the whole request or on its first max_paths paths."""
+    the whole request or on its first max_paths paths (with_sampling: also rejection sampling and
+    the validation protocol on it)."""
     import torch
     req = prepare(name, max_paths=max_paths, n_measure=3)
     tot = time_steps(req, steps, warmup, label=f"{name}: ")
+    live = req["c"].stats()["n_paths_live"]
     el = tot["elapsed_s"]
     dom, avg_ms, lps, bpl, ach = dominant(req, tot, steps)
-    out = {"paths": req["npaths"], "bitstrings": int(req["bits"].size), "k": req["c"].k,
+    out = {"paths": req["npaths"], "live_paths": live, "bitstrings": int(req["bits"].size), "k": req["c"].k,
            "paths_per_s": req["npaths"] * steps / el, "amps_per_s": req["bits"].size * steps / el,
            "ms_per_step": 1e3 * el / steps,
            "kernel_ms_per_step": {"sweep": tot["ms_sweep"] / steps, "gather": tot["ms_gather"] / steps,
@@ -387,8 +397,14 @@ def config_line(name, ceilings, max_paths=0, steps=3, warmup=1):
         out["gather"] = {"contributions_per_s": req["npaths"] * req["bits"].size / (tot["ms_gather"] / steps * 1e-3),
                          "row_bytes_per_step": rows, "ms_per_step": tot["ms_gather"] / steps,
                          "row_GB_per_s": rows / (tot["ms_gather"] / steps * 1e-3) / 1e9}
-        if ceilings and ceilings.get("mall_read_GB_per_s"):
-            out["gather"]["frac_of_mall_read_ceiling"] = out["gather"]["row_GB_per_s"] / ceilings["mall_read_GB_per_s"]
+    if with_sampling:
+        c, bits = req["c"], req["bits"]
+        out["sampling"] = sampling_bench(c, req["ids"], req["begin"], req["npaths"], bits.size, req["ws"],
+                                         req["ws_bytes"], req["stream"])
+        run_step(req)               # exact amplitudes again
+        torch.cuda.synchronize()
+        out["validation"] = validation_bench(c, bits, req["d_amps"], req["cfg"].bits_seed, req["ws"],
+                                             req["ws_bytes"], req["stream"])
     req["c"].close()
     del req
     torch.cuda.empty_cache()
@@ -417,11 +433,13 @@ def measure_ceilings():
     xf = x.view(torch.float32)
     out["hbm_read_GB_per_s"] = bw(lambda: xf.sum(), x.numel(), 10)
     del x, y, xf
-    small = torch.ones(1 << 25, dtype=torch.float32, device="cuda")       # 128 MiB
-    out["mall_read_GB_per_s"] = bw(lambda: small.sum(), small.numel() * 4, 50)
-    del small
+    a = torch.ones(1 << 26, dtype=torch.uint8, device="cuda")             # 2 x 64 MiB, Infinity-Cache resident
+    b = torch.empty_like(a)
+    out["mall_copy_GB_per_s"] = bw(lambda: b.copy_(a), 2 * a.numel(), 200)
+    del a, b
     torch.cuda.empty_cache()
-    out["note"] = "torch copy_ and sum kernels, timed with events; read ceilings count the bytes read once"
+    out["note"] = ("torch copy_ and sum kernels, timed with events; copies count read + write bytes, the read "
+                   "counts the bytes read once")
     return out
 
 
@@ -711,10 +729,10 @@ def cpu_baseline(cfg, gates, bits, k, ids, begin, npaths, budget_s):
 
     Blocks of up to 24 qubits: whole paths (the first ones of the request) over all bitstrings,
     until the budget is spent.  Larger blocks (a single 28-qubit path takes minutes): one path
-    of the request run on two prefixes of the gate list (every gate up to a cycle; the path id
-    keeps its bits of the crossing gates in the prefix), each over all bitstrings; a line
-    through the two (time = fixed part + rate x gates) extrapolated to the whole gate list gives
-    the time of one path."""
+    of the request run on two prefixes of the gate list (every gate up to cycle 9, and up to
+    cycle 17; the path id keeps its bits of the crossing gates in the prefix), each over all
+    bitstrings; the first prefix's time plus the remaining gates at the rate between the two
+    gives the time of one path."""
     import oracle
     from oracle.build import build
     if not os.path.exists(oracle.lib_path()):
@@ -737,7 +755,7 @@ def cpu_baseline(cfg, gates, bits, k, ids, begin, npaths, budget_s):
                 "sample": f"first {done} of {npaths} paths x all {bits.size} bitstrings, {el:.1f} s"}
     first = int(ids[0]) if ids is not None else int(begin)
     pts = []
-    for last_cycle in (1, 3):
+    for last_cycle in (9, 17):
         pre = gates[gates["cycle"] <= last_cycle]
         kp = oracle.num_cut(cfg.n_qubits, pre, cfg.cut_mask())
         pid = np.array([first >> (k - kp)], dtype=np.uint64)
@@ -745,13 +763,14 @@ def cpu_baseline(cfg, gates, bits, k, ids, begin, npaths, budget_s):
         oracle.path_sum(cfg.n_qubits, pre, cfg.cut_mask(), pid, bits)
         pts.append((pre.size, time.perf_counter() - t0))
     (g1, t1), (g2, t2) = pts
+    # the time of the first prefix (opening H layer, allocation, the final gather) plus the rest of
+    # the gates at the rate of cycles 10-17 (a steady mix of one-qubit gates, CZs and projectors)
     rate = (t2 - t1) / max(g2 - g1, 1)
-    fixed = max(t1 - rate * g1, 0.0)
-    per_path = fixed + rate * gates.size
+    per_path = t1 + rate * (gates.size - g1)
     return {"value": 1.0 / per_path, **info, "extrapolated": True, "s_per_path": per_path,
-            "sample": (f"path {first}: gates of cycles 0-1 ({g1} gates, {t1:.1f} s) and 0-3 ({g2} gates, "
-                       f"{t2:.1f} s), all {bits.size} bitstrings; line through both extrapolated to "
-                       f"{gates.size} gates")}
+            "sample": (f"path {first}: gates of cycles 0-9 ({g1} gates, {t1:.1f} s) and 0-17 ({g2} gates, "
+                       f"{t2:.1f} s), all {bits.size} bitstrings; the remaining {gates.size - g1} gates at the "
+                       f"rate of cycles 10-17")}
 
 
 if __name__ == "__main__":
