@@ -443,16 +443,26 @@ def measure_ceilings():
     return out
 
 
+def library_source_sha256():
+    """SHA-256 over the library's sources (kernels, planner, executor): the counters of a
+    profile hold only while the kernels and the launch plan they were taken on are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1807_10749_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        h.update(name.encode())
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of
-    this workload, or None if there is none or the kernel source changed since."""
-    import hashlib
+    this workload, or None if there is none or the library's sources changed since."""
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1807_10749_amd", "csrc", "kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+    if library_source_sha256() != rec.get("library_source_sha256"):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["traffic_bytes_per_launch"]

@@ -678,8 +678,12 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
     const HalfProgram &hp = c.half[half];
     const int q = hp.q;
     const int n_ext = p + q;
-    const int n_lane_q = std::max(0, std::min(q, 6 - p));  // qubits 0..n_lane_q-1 sit in lane bits
-    const int n_free = q - n_lane_q;
+    // With fewer than six slot bits the lowest qubits fill the other lane bits; with max_lq = m
+    // the top m lane bits are freed for chosen qubits instead (lq, lq4 below), so qubits
+    // 0..n_lane_q-1 sit in the fixed lane bits and qubit n_lane_q.. in registers or tile bits.
+    const bool lq_small = p < 6 && max_lq >= 1;
+    const int n_lane_q = std::max(0, std::min(q, 6 - p - (lq_small ? max_lq : 0)));
+    const int n_free = q - std::max(0, std::min(q, 6 - p));
     const int R_eff = std::max(0, std::min({R, n_ext - 6, n_free}));
 
     SegmentPlan sp;
@@ -698,7 +702,7 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
     // qubits, which is the iSWAP exactly; its six unnormalised H gates gain a factor 8, divided
     // out with the segment's rescaling.
     {
-        const bool lq_seg = max_lq >= 1 && n_lane_q == 0 && p >= 6 && q > R_eff;
+        const bool lq_seg = max_lq >= 1 && n_lane_q == 0 && p >= 6 && q > R_eff;   // p < 6: not counted
         const bool lq4_seg = lq_seg && max_lq >= 2 && q > R_eff + 1;
         const int cap = R_eff + (lq_seg ? 1 : 0) + (lq4_seg ? 1 : 0);
         std::vector<HalfOp> out;
@@ -800,9 +804,11 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
         std::vector<int> regq;
         std::vector<HalfOp> sched, defer;
         uint64_t blocked = 0;
-        // when the slots fill all six lane bits, lane bit 5 may hold one qubit (PassArgs::lane_qpos)
+        // lane bit 5 (and 4) may hold a chosen qubit (PassArgs::lane_qpos): when the slots fill all
+        // six lane bits, where a qubit needs it; with fewer slot bits, always (a qubit without
+        // gates in the pass fills it otherwise)
         int lq = -1, lq4 = -1;
-        const bool lq_ok = max_lq >= 1 && n_lane_q == 0 && p >= 6 && q > R_eff;
+        const bool lq_ok = max_lq >= 1 && (lq_small || (n_lane_q == 0 && p >= 6)) && q > R_eff;
         const bool lq4_ok = lq_ok && max_lq >= 2 && q > R_eff + 1;
         for (const HalfOp &op : rem) {
             const uint64_t qm = (uint64_t(1) << op.q0) | (is_two_qubit(op.kind) ? uint64_t(1) << op.q1 : 0);
@@ -844,6 +850,17 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
         // pad the register bits with untouched qubits so every tile holds 64 * 2^R_eff amplitudes
         for (int t = q - 1; t >= n_lane_q && (int)regq.size() < R_eff; --t)
             if (t != lq && t != lq4 && std::find(regq.begin(), regq.end(), t) == regq.end()) regq.push_back(t);
+        if (lq_small) {
+            // the freed lane bits must hold some qubit: the lowest one not placed yet
+            auto free_q = [&]() {
+                for (int t = n_lane_q; t < q; ++t)
+                    if (t != lq && t != lq4 && std::find(regq.begin(), regq.end(), t) == regq.end()) return t;
+                return -1;
+            };
+            if (lq < 0) lq = free_q();
+            if (max_lq >= 2 && lq4 < 0) lq4 = free_q();
+            if (lq < 0 || (max_lq >= 2 && lq4 < 0)) { sp.ok = false; break; }
+        }
         std::sort(regq.begin(), regq.end());
         pp.R = (int)regq.size();
         pp.lane_q = lq;
@@ -945,8 +962,9 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
     // a qubit in a lane bit splits the contiguous runs of a load (two of 32 amplitudes, or four
     // of 16 = one cache line each with two): use one or two only where that saves a pass
     SegmentPlan sp = plan_segment(c, half, level, p, R, dense_m, 0);
-    if (p >= 6)
-        for (int m = 1; m <= 2; ++m) {
+    const int q = c.half[half].q;
+    if (p >= 6 || q > 6 - p)
+        for (int m = 1; m <= 2 && (p >= 6 || 6 - p - m >= 0); ++m) {
             SegmentPlan lq = plan_segment(c, half, level, p, R, dense_m, m);
             if (lq.ok && (!sp.ok || lq.passes.size() < sp.passes.size())) sp = std::move(lq);
         }
