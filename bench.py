@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--max-paths", type=int, default=0,
                     help="time only the first N paths of the request (a bounded sample, for profiling)")
     ap.add_argument("--tuning", default="",
-                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels]]] "
+                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes]]]] "
                          "(skips autotune)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (known HBM traffic for counter scaling)")
@@ -111,8 +111,9 @@ def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure
         dense = vals[3] if len(vals) > 3 else 0
         nofold = vals[4] if len(vals) > 4 else 0
         flev = vals[5] if len(vals) > 5 else 0
+        chain = vals[6] if len(vals) > 6 else 0
         sf.set_tuning(c.handle, reg_qubits=r, leaf_batch=lb, waves_per_cu=wpc, dense_qubits=dense,
-                      no_leaf_fold=nofold, fold_levels=flev)
+                      no_leaf_fold=nofold, fold_levels=flev, chain_passes=chain)
         tuned = sf.get_tuning(c.handle)
     elif autotune:
         tuned = sf.autotune(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,
@@ -152,7 +153,7 @@ def time_steps(req, steps, warmup, chunk_paths=0, label=""):
         run_step(req, chunk_paths=chunk_paths)
     torch.cuda.synchronize()
     keys = ("ms_sweep", "ms_gather", "ms_other", "ms_total", "ms_plan", "n_sweep_launches", "n_gather_launches",
-            "sweep_bytes", "gather_bytes", "gather_row_bytes")
+            "sweep_bytes", "gather_bytes", "gather_row_bytes", "n_chained_passes")
     tot = {k: 0 for k in keys}
     st = None
     t0 = time.perf_counter()
@@ -384,6 +385,8 @@ def config_line(name, ceilings, max_paths=0, steps=3, warmup=1, with_sampling=Fa
                                   "other": tot["ms_other"] / steps},
            "dominant": {"kernel": dom, "avg_launch_ms": avg_ms, "launches_per_step": lps,
                         "bytes_per_launch": bpl, "GB_per_s": ach},
+           "sweep_launches_per_step": tot["n_sweep_launches"] / steps,
+           "chained_passes_per_step": tot["n_chained_passes"] / steps,
            "sweep_GB_per_s": tot["sweep_bytes"] / max(tot["ms_sweep"], 1e-9) / 1e6,
            "sweep_frac_of_hbm_peak": tot["sweep_bytes"] / max(tot["ms_sweep"], 1e-9) / 1e6 / HBM_PEAK_GBS,
            "tuning": req["tuning"], "dtype": "c128" if req["cfg"].fp64_sweeps else "c64 sweeps, f64 path sum"}
@@ -397,6 +400,17 @@ def config_line(name, ceilings, max_paths=0, steps=3, warmup=1, with_sampling=Fa
         out["gather"] = {"contributions_per_s": req["npaths"] * req["bits"].size / (tot["ms_gather"] / steps * 1e-3),
                          "row_bytes_per_step": rows, "ms_per_step": tot["ms_gather"] / steps,
                          "row_GB_per_s": rows / (tot["ms_gather"] / steps * 1e-3) / 1e9}
+    if req["tuning"] is not None and tot["n_sweep_launches"] > steps:
+        # the same request and tuning with the passes of small tree levels chained into
+        # persistent cooperative launches (grid barriers instead of kernel boundaries)
+        from paper_1807_10749_amd import binding as sf
+        sf.set_tuning(req["c"].handle, **dict(req["tuning"], chain_passes=1))
+        ch = time_steps(req, steps, warmup, label=f"{name} chained: ")
+        sf.set_tuning(req["c"].handle, **req["tuning"])
+        out["chained_passes"] = {"ms_sweep_per_step": ch["ms_sweep"] / steps,
+                                 "sweep_launches_per_step": ch["n_sweep_launches"] / steps,
+                                 "chained_passes_per_step": ch["n_chained_passes"] / steps,
+                                 "ms_per_step": 1e3 * ch["elapsed_s"] / steps}
     if with_sampling:
         c, bits = req["c"], req["bits"]
         out["sampling"] = sampling_bench(c, req["ids"], req["begin"], req["npaths"], bits.size, req["ws"],

@@ -188,6 +188,11 @@ typedef struct {
     uint32_t fold_levels;    /* most trailing tree levels folded into the gather (0: as many as
                                 qualify, up to 5 path bits; a group of levels qualifies when all
                                 its non-diagonal gates act on its branch qubits) */
+    uint32_t chain_passes;   /* 0: one launch per pass; 1: consecutive small passes of one kernel
+                                variant (each at most one workgroup per compute unit) run as one
+                                persistent cooperative launch with a grid barrier between them.
+                                The barrier costs more than a kernel boundary between back-to-back
+                                launches on one stream, so 0 is the default */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);
@@ -259,6 +264,8 @@ typedef struct {
                                 from the bitstring count in a planning-only run) */
     double ms_plan;          /* host time from entry to the first enqueued device operation */
     uint64_t n_paths_live;   /* requested paths whose term is not known to be zero (see run_paths) */
+    uint64_t n_chained_passes;  /* sweep passes run inside chained launches (see chain_passes); a chain
+                                   counts once in n_sweep_launches */
 } sf_run_stats_t;
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);

@@ -18,6 +18,8 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 
 #include "kernels.hpp"
 #include "sf_host.hpp"
@@ -107,6 +109,36 @@ struct Launch {
 };
 
 struct BatchRec { int level; size_t table_off; uint64_t slots; };
+
+// A run of PASS launches [begin, end) that executes as one chained launch (pass_chain_kernel).
+struct ChainRec {
+    size_t begin = 0, end = 0;
+    uint32_t n_phases = 0;
+    unsigned grid = 0;
+    int R = 0;
+    bool flip = false, zskip = false;
+    size_t args_first = 0, phases_first = 0;   // entries in the call's chain argument arrays
+};
+
+// Grid of a chained launch of one kernel variant: at most one workgroup per compute unit, and at
+// most half of what can be resident at once, so that chains launched on two streams fit side by
+// side.  Cached per device.
+unsigned chain_grid_limit(bool fp64, int R, bool flip, int cus)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, bool, int, bool>, unsigned> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    const auto key = std::make_tuple(dev, fp64, R, flip);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    unsigned resident = 0;
+    if (chain_max_grid(fp64, R, flip, chain_zskip(fp64, R, flip), &resident) != hipSuccess) resident = 0;
+    const unsigned g = std::min<unsigned>((unsigned)std::max(cus, 0), resident / 2);
+    cache[key] = g;
+    return g;
+}
 
 struct BlobEntry { size_t off; uint32_t words, groups_word, terms_word; };
 
@@ -282,6 +314,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     const size_t off_sort_tmp = fixed; fixed += align_up(sort_temp);
     const size_t blob_budget = size_t(1) << 22;
     const size_t off_blob = fixed; fixed += blob_budget;
+    // pass arguments and phase lists of the chained launches (runs that do not fit stay unchained)
+    const size_t chain_budget = size_t(1) << 20;
+    const size_t off_chain = fixed; fixed += chain_budget;
 
     auto dev_err = [&](const char *what, hipError_t e) {
         err = std::string(what) + ": " + hipGetErrorString(e);
@@ -323,7 +358,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         const int id = ev_begin(2);
         if (!bits_dev && n_bits)
             if ((he = hipMemcpyAsync((void *)d_bits, bits, n_bits * 8, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy bitstrings", he);
-        if ((he = launch_fill_zero_i32(d_flag, 2, stream)) != hipSuccess) return dev_err("fill", he);
+        // flags: [0] bad bitstring, [1] visiting groups, [2] barrier fault of a chained launch,
+        // [4..5] the chained launches' 64-bit barrier counter
+        if ((he = launch_fill_zero_i32(d_flag, 6, stream)) != hipSuccess) return dev_err("fill", he);
         if ((he = launch_pext(d_bits, n_bits, c.mask_a, c.mask_b, all, d_xa, d_xb, d_flag, stream)) != hipSuccess) return dev_err("pext", he);
         const uint32_t *keys = d_xa;
         int key_bits = qh[0];
@@ -905,12 +942,73 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     if (plan_error) { err = "internal: a segment could not be scheduled into passes"; return SF_ERR_UNSUPPORTED; }
     if (blob.size() > blob_budget) { err = "internal: pass programs exceed their reservation"; return SF_ERR_UNSUPPORTED; }
     const size_t tables_bytes = align_up(tpath.size() * 8) + align_up(tparent.size() * 4) + align_up(tmaskv.size() * 4);
+
+    // Chains (tuning chain_passes): maximal runs of consecutive PASS launches (a pair is one
+    // phase) of one kernel variant whose grids are at most chain_grid_limit run as one cooperative
+    // launch with a grid barrier between phases: one launch per run of small tree levels instead
+    // of one per pass.  On MI355X a grid barrier of 256 workgroups (one device-scope atomic each,
+    // L2 write-back and invalidate around it) takes about 16-25 us while back-to-back launches on
+    // one stream are about 2.5 us apart, so chaining is off unless asked for.
+    std::vector<ChainRec> chains;
+    std::vector<char> in_chain(launches.size(), 0);
+    const size_t chain_args_cap = chain_budget / 2 / sizeof(PassArgs);
+    const size_t chain_phases_cap = chain_budget / 2 / sizeof(ChainPhase);
+    if (c.tuning.chain_passes && n_paths) {
+        size_t n_args = 0, n_ph = 0;
+        // the phase that starts at launch j: its grid and the launch after it
+        auto phase_at = [&](size_t j, unsigned &g, size_t &next) {
+            const Launch &ln = launches[j];
+            if (ln.kind != Launch::PASS) return false;
+            g = ln.pair_next ? ln.grid + launches[j + 1].grid : ln.grid;
+            next = ln.pair_next ? j + 2 : j + 1;
+            return true;
+        };
+        for (size_t li = 0; li < launches.size();) {
+            unsigned g = 0;
+            size_t nx = li + 1;
+            if (!phase_at(li, g, nx)) { ++li; continue; }
+            const Launch &l0 = launches[li];
+            const unsigned lim = chain_grid_limit(fp64, l0.R, l0.flip, c.device_cus);
+            size_t j = li, na = 0;
+            uint32_t np = 0;
+            unsigned gmax = 0;
+            while (j < launches.size()) {
+                unsigned gj = 0;
+                size_t nj = j + 1;
+                if (!phase_at(j, gj, nj)) break;
+                if (launches[j].R != l0.R || launches[j].flip != l0.flip || gj > lim) break;
+                if (n_args + na + (nj - j) > chain_args_cap || n_ph + np + 1 > chain_phases_cap) break;
+                na += nj - j;
+                ++np;
+                gmax = std::max(gmax, gj);
+                j = nj;
+            }
+            if (np < 2) { li = nx; continue; }
+            ChainRec ch;
+            ch.begin = li;
+            ch.end = j;
+            ch.n_phases = np;
+            ch.grid = gmax;
+            ch.R = l0.R;
+            ch.flip = l0.flip;
+            ch.zskip = chain_zskip(fp64, l0.R, l0.flip);
+            ch.args_first = n_args;
+            ch.phases_first = n_ph;
+            n_args += na;
+            n_ph += np;
+            for (size_t t = li; t < j; ++t) in_chain[t] = 1;
+            chains.push_back(ch);
+            li = j;
+        }
+    }
     if (dry_run) {
         const uint64_t rounds = n_paths ? (plain ? n_paths : 1) : 0;
+        c.stats.n_sweep_launches += rounds * chains.size();
         for (size_t li = 0; li < launches.size(); ++li) {
             const Launch &ln = launches[li];
             if (ln.kind != Launch::GATHER && ln.kind != Launch::FOLD) {
-                if (!(li > 0 && launches[li - 1].pair_next)) c.stats.n_sweep_launches += rounds;   // a pair is one launch
+                if (in_chain[li]) c.stats.n_chained_passes += rounds;
+                else if (!(li > 0 && launches[li - 1].pair_next)) c.stats.n_sweep_launches += rounds;   // a pair is one launch
                 c.stats.sweep_bytes += rounds * ln.bytes;
                 (ln.half ? c.stats.n_passes_b : c.stats.n_passes_a)++;
             }
@@ -988,6 +1086,64 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
 
     char *buf = ws + off_buffers;
+    auto pass_args = [&](const Launch &ln) {
+        PassArgs a = ln.pa;
+        a.dst = buf + ln.dst_off;
+        a.src = buf + ln.src_off;
+        a.slot_path = (const uint64_t *)(ws + off_tpath) + ln.table_off;
+        a.slot_parent = (const uint32_t *)(ws + off_tparent) + ln.table_off;
+        a.slot_parent_base = 0;
+        a.prog = (const uint32_t *)(ws + off_blob + ln.plan_off);
+        a.prog_words = ln.prog_words;
+        a.groups_word = ln.groups_word;
+        a.terms_word = ln.terms_word;
+        return a;
+    };
+    // the chains' pass arguments and phases (the same for every round: the plain form rewrites
+    // the slot tables in place)
+    const PassArgs *d_chain_args = (const PassArgs *)(ws + off_chain);
+    const ChainPhase *d_chain_phases = (const ChainPhase *)(ws + off_chain + chain_budget / 2);
+    uint64_t *d_bar = (uint64_t *)(d_flag + 4);
+    std::vector<PassArgs> chain_args;
+    std::vector<ChainPhase> chain_phases;
+    for (const ChainRec &ch : chains) {
+        if (chain_phases.size() != ch.phases_first || chain_args.size() != ch.args_first) {
+            err = "internal: chained launch tables out of order";
+            return SF_ERR_UNSUPPORTED;
+        }
+        for (size_t j = ch.begin; j < ch.end;) {
+            const Launch &ln = launches[j];
+            ChainPhase ph{};
+            ph.first = (uint32_t)chain_args.size();     // index into the whole array
+            chain_args.push_back(pass_args(ln));
+            if (ln.pair_next) {
+                const Launch &l2 = launches[j + 1];
+                chain_args.push_back(pass_args(l2));
+                const uint64_t g0 = ln.grid, gs = (uint64_t)ln.grid + l2.grid;
+                const uint64_t split = (ch.grid * g0 + gs / 2) / gs;
+                ph.n = 2;
+                ph.split = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(split, 1), ch.grid - 1);
+                j += 2;
+            } else {
+                ph.n = 1;
+                j += 1;
+            }
+            chain_phases.push_back(ph);
+        }
+    }
+    if (chain_args.size() > chain_args_cap || chain_phases.size() > chain_phases_cap) {
+        err = "internal: chained launches exceed their reservation";
+        return SF_ERR_UNSUPPORTED;
+    }
+    if (!chain_args.empty()) {
+        if ((he = hipMemcpyAsync(ws + off_chain, chain_args.data(), chain_args.size() * sizeof(PassArgs),
+                                 hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return dev_err("copy chains", he);
+        if ((he = hipMemcpyAsync(ws + off_chain + chain_budget / 2, chain_phases.data(),
+                                 chain_phases.size() * sizeof(ChainPhase), hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return dev_err("copy chains", he);
+    }
+    uint64_t bar_base = 0;
     const uint64_t rounds = n_paths ? (plain ? n_paths : 1) : 0;
     for (uint64_t r = 0; r < rounds; ++r) {
         if (plain && r > 0) {
@@ -1016,21 +1172,23 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             cur_id = ev_begin(cat);
             cur_cat = cat;
         };
-        auto pass_args = [&](const Launch &ln) {
-            PassArgs a = ln.pa;
-            a.dst = buf + ln.dst_off;
-            a.src = buf + ln.src_off;
-            a.slot_path = (const uint64_t *)(ws + off_tpath) + ln.table_off;
-            a.slot_parent = (const uint32_t *)(ws + off_tparent) + ln.table_off;
-            a.slot_parent_base = 0;
-            a.prog = (const uint32_t *)(ws + off_blob + ln.plan_off);
-            a.prog_words = ln.prog_words;
-            a.groups_word = ln.groups_word;
-            a.terms_word = ln.terms_word;
-            return a;
-        };
+        size_t ci = 0;    // next chain
         for (size_t li = 0; li < launches.size(); ++li) {
             const Launch &ln = launches[li];
+            if (ci < chains.size() && li == chains[ci].begin) {
+                const ChainRec &ch = chains[ci++];
+                timed(0);
+                // phases index the call's whole argument array; each chain reads its own phases
+                if ((he = launch_pass_chain(fp64, ch.R, ch.flip, ch.zskip, d_chain_args, d_chain_phases + ch.phases_first, ch.n_phases, d_bar, bar_base, d_flag + 2,
+                                            ch.grid, stream)) != hipSuccess)
+                    return dev_err("chained passes", he);
+                bar_base += (uint64_t)(ch.n_phases - 1) * ch.grid;
+                c.stats.n_sweep_launches++;
+                c.stats.n_chained_passes += ch.end - ch.begin;
+                for (size_t t = ch.begin; t < ch.end; ++t) c.stats.sweep_bytes += launches[t].bytes;
+                li = ch.end - 1;
+                continue;
+            }
             if (ln.kind == Launch::PASS && ln.pair_next) {
                 const Launch &l2 = launches[li + 1];
                 timed(0);
@@ -1112,10 +1270,15 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
     if (!out_dev && n_bits)
         if ((he = hipMemcpyAsync(amps, d_acc, n_bits * 16, hipMemcpyDeviceToHost, stream)) != hipSuccess) return dev_err("copy amps", he);
-    int flag[2] = {0, 0};
+    int flag[3] = {0, 0, 0};
     if ((he = hipMemcpyAsync(flag, d_flag, sizeof(flag), hipMemcpyDeviceToHost, stream)) != hipSuccess) return dev_err("copy flag", he);
     if ((he = hipStreamSynchronize(stream)) != hipSuccess) return dev_err("synchronize", he);
     if (flag[0]) { err = "bitstring has bits outside the grid"; return SF_ERR_INVALID; }
+    if (flag[2]) {
+        err = "a chained launch's grid barrier did not complete (its workgroups were not all resident); "
+              "chain_passes = 0 runs one launch per pass";
+        return SF_ERR_DEVICE;
+    }
     account_gather(launches, rounds, (uint64_t)flag[1]);
 
     if (timing) {

@@ -372,8 +372,13 @@ __device__ __forceinline__ uint64_t reg_offset(const int32_t (&pos)[6], int j, i
 // them, whose register allocation they do not affect.  ZSKIP: registers (and lanes) that the
 // source's zero subspace (PassArgs::n_zero) says are zero are set to zero instead of loaded;
 // where a whole cache line is zero its bytes are never fetched.
-template <typename T, int R, bool FLIP, bool ZSKIP = false>
-__device__ __forceinline__ void pass_body(PassArgs a, uint32_t block, uint32_t nblocks)
+//
+// A (the way the arguments arrive): PassArgs by value for a kernel's own arguments, which then
+// stay in the kernel-argument segment and scalar registers; const PassArgs & for the chained
+// kernel's arguments in device memory, which a local copy would put in scratch memory (the
+// arrays in PassArgs are indexed with run-time indices).
+template <typename T, int R, bool FLIP, bool ZSKIP = false, typename A = PassArgs>
+__device__ __forceinline__ void pass_body(A a, uint32_t block, uint32_t nblocks)
 {
     using C = typename Cplx<T>::type;
     constexpr int N = 1 << R;
@@ -632,6 +637,108 @@ hipError_t launch_pass(bool fp64, int R, bool flips, bool zskip, const PassArgs 
     if (flips)
         return fp64 ? launch_pass_t<double, true>(R, a, grid, s) : launch_pass_t<float, true>(R, a, grid, s);
     return fp64 ? launch_pass_t<double, false>(R, a, grid, s) : launch_pass_t<float, false>(R, a, grid, s);
+}
+
+// ---------------------------------------------------------------- chained passes
+
+// Grid barrier of a cooperative launch.  *count only grows during a call: the barrier after
+// phase i of a chain waits until it reaches base + (i + 1) * gridDim.x, base being what the
+// call's earlier chains added.  Every thread first makes its stores visible device-wide (a
+// release fence at agent scope, which covers the other XCDs' L2s); one thread per workgroup
+// arrives and waits; after the wait every thread acquires at agent scope before it reads what
+// other workgroups wrote.  The wait is bounded (2^22 polls of at least one sleep each, between
+// about 0.2 s and a few seconds): past it *err gets bit 1 and the workgroup goes on, so a
+// barrier that cannot complete ends the call with an error instead of hanging it.
+__device__ __forceinline__ void chain_barrier(uint64_t *count, uint64_t target, int *err)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(count, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t polls = 0;
+        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls == (1u << 22)) {
+                __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// A chain of passes (ChainPhase): the workgroups run phase i's pass (or the two passes of a
+// pair, split between them) and meet at a grid barrier before phase i + 1.  pass_body stages each
+// program in LDS; the barrier's workgroup syncs keep a phase's staging behind the last reads of
+// the one before.
+template <typename T, int R, bool FLIP, bool ZSKIP>
+__global__ __launch_bounds__(256) void pass_chain_kernel(const PassArgs *__restrict__ args,
+                                                         const ChainPhase *__restrict__ phases, uint32_t n_phases,
+                                                         uint64_t *__restrict__ count, uint64_t base,
+                                                         int *__restrict__ err)
+{
+    for (uint32_t i = 0; i < n_phases; ++i) {
+        const ChainPhase ph = phases[i];
+        using Ref = const PassArgs &;
+        if (ph.n == 1) pass_body<T, R, FLIP, ZSKIP, Ref>(args[ph.first], blockIdx.x, gridDim.x);
+        else if (blockIdx.x < ph.split) pass_body<T, R, FLIP, ZSKIP, Ref>(args[ph.first], blockIdx.x, ph.split);
+        else pass_body<T, R, FLIP, ZSKIP, Ref>(args[ph.first + 1], blockIdx.x - ph.split, gridDim.x - ph.split);
+        if (i + 1 < n_phases) chain_barrier(count, base + (uint64_t)(i + 1) * gridDim.x, err);
+    }
+}
+
+// the chain kernel of a variant, or nullptr
+static const void *chain_kernel_ptr(bool fp64, int R, bool flips, bool zskip)
+{
+    if (zskip_variant(zskip, fp64, R, flips))
+        return R == 5 ? (const void *)pass_chain_kernel<float, 5, false, true>
+                      : (const void *)pass_chain_kernel<float, 4, false, true>;
+#define SF_CHAIN_CASES(T, F)                                                    \
+    switch (R) {                                                                \
+    case 0: return (const void *)pass_chain_kernel<T, 0, F, false>;             \
+    case 1: return (const void *)pass_chain_kernel<T, 1, F, false>;             \
+    case 2: return (const void *)pass_chain_kernel<T, 2, F, false>;             \
+    case 3: return (const void *)pass_chain_kernel<T, 3, F, false>;             \
+    case 4: return (const void *)pass_chain_kernel<T, 4, F, false>;             \
+    default: break;                                                             \
+    }
+    if (fp64) {
+        if (flips) { SF_CHAIN_CASES(double, true) } else { SF_CHAIN_CASES(double, false) }
+        return nullptr;
+    }
+    if (flips) { SF_CHAIN_CASES(float, true) } else { SF_CHAIN_CASES(float, false) }
+#undef SF_CHAIN_CASES
+    if (R == 5) return flips ? (const void *)pass_chain_kernel<float, 5, true, false>
+                             : (const void *)pass_chain_kernel<float, 5, false, false>;
+    return nullptr;
+}
+
+bool chain_zskip(bool fp64, int R, bool flips)
+{
+    return zskip_variant(true, fp64, R, flips);
+}
+
+hipError_t chain_max_grid(bool fp64, int R, bool flips, bool zskip, unsigned *grid)
+{
+    const void *k = chain_kernel_ptr(fp64, R, flips, zskip);
+    if (!k) return hipErrorInvalidValue;
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    *grid = (unsigned)(per_cu > 0 ? per_cu : 0) * (unsigned)cus;
+    return hipSuccess;
+}
+
+hipError_t launch_pass_chain(bool fp64, int R, bool flips, bool zskip, const PassArgs *args, const ChainPhase *phases,
+                             uint32_t n_phases, uint64_t *count, uint64_t base, int *err, unsigned grid, hipStream_t s)
+{
+    const void *k = chain_kernel_ptr(fp64, R, flips, zskip);
+    if (!k || grid == 0 || n_phases == 0) return hipErrorInvalidValue;
+    void *kargs[] = {(void *)&args, (void *)&phases, (void *)&n_phases, (void *)&count, (void *)&base, (void *)&err};
+    return hipLaunchCooperativeKernel(k, dim3(grid), dim3(256), kargs, 0, s);
 }
 
 // ---------------------------------------------------------------- dense block on matrix cores

@@ -22,6 +22,20 @@ hipError_t launch_pass(bool fp64, int R, bool flips, bool zskip, const PassArgs 
 hipError_t launch_pass_pair(bool fp64, int R, bool flips, bool zskip, const PassArgs &a0, unsigned grid0,
                             const PassArgs &a1, unsigned grid1, hipStream_t s);
 
+// A run of small dependent passes of one kernel variant in one cooperative (all workgroups
+// resident) launch: n_phases ChainPhase entries from device memory, a grid barrier between
+// phases on the 64-bit counter *count, which the call zeroes once and which only grows: base is
+// what the call's earlier chains added to it ((phases - 1) * grid each).  A barrier wait that
+// does not end sets bit 1 of *err and lets the kernel finish (the call then fails), so the launch
+// always ends.  grid must not exceed chain_max_grid.
+hipError_t launch_pass_chain(bool fp64, int R, bool flips, bool zskip, const PassArgs *args, const ChainPhase *phases,
+                             uint32_t n_phases, uint64_t *count, uint64_t base, int *err, unsigned grid, hipStream_t s);
+// Largest grid of launch_pass_chain for that variant whose workgroups are all resident at once.
+hipError_t chain_max_grid(bool fp64, int R, bool flips, bool zskip, unsigned *grid);
+// Whether launch_pass_chain runs that variant with zero-subspace skipping (otherwise it ignores
+// PassArgs::n_zero, which only ever costs reads).
+bool chain_zskip(bool fp64, int R, bool flips);
+
 // Dense 4-qubit block on matrix cores (complex64 states only).
 hipError_t launch_dense(const DenseArgs &a, unsigned grid, hipStream_t s);
 

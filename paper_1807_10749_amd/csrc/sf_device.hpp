@@ -118,6 +118,16 @@ struct PassArgs {
     uint8_t zero_bit[kMaxZeroEntries];
 };
 
+// A run of small dependent passes in one persistent launch (pass_chain_kernel): phase i runs
+// args[first] on every workgroup, or (n = 2, the two blocks' independent passes) args[first] on
+// workgroups [0, split) and args[first + 1] on the rest; a grid barrier separates the phases.
+struct ChainPhase {
+    uint32_t first;
+    uint32_t n;
+    uint32_t split;
+    uint32_t pad;
+};
+
 // Dense fused block: a 2^4 x 2^4 complex matrix U applied to four qubits (extended bit
 // positions bpos[0] < ... < bpos[3], all >= 5), on matrix cores.  `mat` is the real
 // embedding [[Ur, -Ui], [Ui, Ur]] (32 x 32, row-major, FP32).  The 5 lowest extended
