@@ -177,7 +177,8 @@ typedef struct {
     uint32_t reg_qubits;     /* qubits held in registers per pass, 1..5 (1..4 with SF_FP64_SWEEPS) */
     uint32_t leaf_batch;     /* max paths per leaf batch (power of two) */
     uint32_t max_slots;      /* max slots of any batch (power of two) */
-    uint32_t waves_per_cu;   /* persistent-grid size per compute unit */
+    uint32_t waves_per_cu;   /* grid cap of the sweep kernels in waves per compute unit
+                                (default 128; 4 waves per workgroup) */
     uint32_t dense_qubits;   /* 0: gates on registers and lanes only; 2..4: also fuse windows of up to
                                 this many qubits into dense 16 x 16 blocks applied on matrix cores
                                 (complex64 sweeps only) */

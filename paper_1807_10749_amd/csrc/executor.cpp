@@ -546,7 +546,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
     };
 
-    const unsigned max_grid = (unsigned)std::max(1, c.device_cus) * (c.tuning.waves_per_cu ? c.tuning.waves_per_cu / 4 : 8);
+    // grid cap of the sweep kernels: waves_per_cu / 4 workgroups per compute unit (default 128
+    // waves, more than can be resident: short workgroups keep every channel busy to the end)
+    const unsigned max_grid = (unsigned)std::max(1, c.device_cus) * (c.tuning.waves_per_cu ? std::max(1u, c.tuning.waves_per_cu / 4) : 32);
     uint64_t &n_leaf_batches = PL.n_leaf_batches;
 
     // appends the slot tables of one batch (padded to `slots` entries)

@@ -33,6 +33,13 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n)
 template <typename T>
 __device__ __forceinline__ T inv_sqrt2() { return T(0.70710678118654752440084436210485); }
 
+// x with its sign bit XORed with bit 31 of s (s is 0 or 1 << 31)
+__device__ __forceinline__ float flip_sign(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
+__device__ __forceinline__ double flip_sign(double x, uint32_t s)
+{
+    return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(x) ^ ((unsigned long long)s << 32)));
+}
+
 // ---------------------------------------------------------------- register tier
 
 template <int K, int R, typename C>
@@ -313,45 +320,76 @@ __device__ __forceinline__ void apply_diag(const DiagGroup *gp, const uint8_t *t
         pval |= s;
     }
     const bool has_proj = (g.flags & 2u) != 0;
+    // The phase of amplitude (lane, j) is omega^m, m = mB + t(j) + 4 parity(j & cmask) (mod 8):
+    // mB and cmask depend on the lane (its lane and tile bits, its slot's path bits), t(j) (the
+    // terms on register qubits only) is the same for every lane.  The parity sign is kept in the
+    // sign-bit word sg, updated with one XOR per register because the registers are visited in
+    // Gray-code order (consecutive j differ in one bit); the sign is applied by flipping sign bits.
+    // bit k of cmask moved to the sign bit
+    auto cbit = [&](int k) { return (cmask << (31 - k)) & 0x80000000u; };
     if (!(g.flags & 1u)) {
         // every weight is a multiple of 4: the phase is a sign
-        const int sB = (mB >> 2) & 1;
+        auto run = [&](auto with_proj) {
+            uint32_t sg = (uint32_t)((mB >> 2) & 1) << 31;
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const int s = sB ^ ((tab_entry(g.tab, j) >> 2) & 1) ^ (__popc((uint32_t)j & cmask) & 1);
-            T x = s ? -v[j].x : v[j].x;
-            T y = s ? -v[j].y : v[j].y;
-            if (has_proj) {
-                const bool k = keep && (((uint32_t)j & pset) == pval);
-                x = k ? x : T(0);
-                y = k ? y : T(0);
+            for (int i = 0; i < N; ++i) {
+                const int j = i ^ (i >> 1);
+                if (i) sg ^= cbit(__builtin_ctz(i));
+                const uint32_t su = sg ^ ((uint32_t)((tab_entry(g.tab, j) >> 2) & 1) << 31);
+                T x = flip_sign(v[j].x, su), y = flip_sign(v[j].y, su);
+                if (decltype(with_proj)::value) {
+                    const bool k = keep && (((uint32_t)j & pset) == pval);
+                    x = k ? x : T(0);
+                    y = k ? y : T(0);
+                }
+                v[j].x = x;
+                v[j].y = y;
             }
-            v[j].x = x;
-            v[j].y = y;
-        }
+        };
+        if (has_proj) run(std::true_type{});
+        else run(std::false_type{});
     } else {
+        // per lane: f0 = omega^mB and f1 = omega^(mB+1); per register the uniform t(j) picks f0
+        // or f1 (bit 0), then times i (bit 1) and -1 (bit 2, joined to the sign): one complex
+        // product per amplitude
         const T r = inv_sqrt2<T>();
+        auto omega = [&](int m, T &c, T &sn) {
+            const bool odd = (m & 1) != 0;
+            T c1 = odd ? r : T(1), s1 = odd ? r : T(0);
+            if (m & 2) { const T t = c1; c1 = -s1; s1 = t; }
+            if (m & 4) { c1 = -c1; s1 = -s1; }
+            c = c1;
+            sn = s1;
+        };
+        T c0, s0, c1, s1;
+        omega(mB & 7, c0, s0);
+        omega((mB + 1) & 7, c1, s1);
+        auto run = [&](auto with_proj) {
+            uint32_t sg = 0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const int m = (mB + tab_entry(g.tab, j) + 4 * __popc((uint32_t)j & cmask)) & 7;
-            T x = v[j].x, y = v[j].y;
-            if (m & 1) {                      // times omega = (1+i)/sqrt2
-                const T nx = (x - y) * r, ny = (x + y) * r;
-                x = nx; y = ny;
+            for (int i = 0; i < N; ++i) {
+                const int j = i ^ (i >> 1);
+                if (i) sg ^= cbit(__builtin_ctz(i));
+                const int t = tab_entry(g.tab, j);
+                const T x = v[j].x, y = v[j].y;
+                const T c = (t & 1) ? c1 : c0, sn = (t & 1) ? s1 : s0;
+                const T px = x * c - y * sn, py = x * sn + y * c;
+                // times i: (px, py) -> (-py, px)
+                T nx = (t & 2) ? -py : px, ny = (t & 2) ? px : py;
+                const uint32_t su = sg ^ ((uint32_t)((t >> 2) & 1) << 31);
+                nx = flip_sign(nx, su);
+                ny = flip_sign(ny, su);
+                if (decltype(with_proj)::value) {
+                    const bool k = keep && (((uint32_t)j & pset) == pval);
+                    nx = k ? nx : T(0);
+                    ny = k ? ny : T(0);
+                }
+                v[j].x = nx;
+                v[j].y = ny;
             }
-            if (m & 2) {                      // times i
-                const T nx = -y;
-                y = x; x = nx;
-            }
-            if (m & 4) { x = -x; y = -y; }    // times -1
-            if (has_proj) {
-                const bool k = keep && (((uint32_t)j & pset) == pval);
-                x = k ? x : T(0);
-                y = k ? y : T(0);
-            }
-            v[j].x = x;
-            v[j].y = y;
-        }
+        };
+        if (has_proj) run(std::true_type{});
+        else run(std::false_type{});
     }
 }
 
@@ -554,8 +592,13 @@ __device__ __forceinline__ void pass_body(A a, uint32_t block, uint32_t nblocks)
     }
 }
 
+// The pass kernels keep at least three waves per SIMD resident (at most 168 VGPRs): the
+// sweeps alternate whole-tile loads, register work and stores, and fewer waves leave the SIMDs
+// idle while a tile's loads are in flight.
+#define SF_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(3)))
+
 template <typename T, int R, bool FLIP, bool ZSKIP = false>
-__global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
+__global__ __launch_bounds__(256) SF_PASS_OCCUPANCY void pass_kernel(PassArgs a)
 {
     pass_body<T, R, FLIP, ZSKIP>(a, blockIdx.x, gridDim.x);
 }
@@ -564,7 +607,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 // first grid0 workgroups run a0, the rest a1.  The choice is per workgroup, so every wave
 // takes one branch.
 template <typename T, int R, bool FLIP, bool ZSKIP = false>
-__global__ __launch_bounds__(256) void pass_kernel_pair(PassArgs a0, PassArgs a1, uint32_t grid0)
+__global__ __launch_bounds__(256) SF_PASS_OCCUPANCY void pass_kernel_pair(PassArgs a0, PassArgs a1, uint32_t grid0)
 {
     if (blockIdx.x < grid0) pass_body<T, R, FLIP, ZSKIP>(a0, blockIdx.x, grid0);
     else pass_body<T, R, FLIP, ZSKIP>(a1, blockIdx.x - grid0, gridDim.x - grid0);
@@ -673,7 +716,7 @@ __device__ __forceinline__ void chain_barrier(uint64_t *count, uint64_t target, 
 // program in LDS; the barrier's workgroup syncs keep a phase's staging behind the last reads of
 // the one before.
 template <typename T, int R, bool FLIP, bool ZSKIP>
-__global__ __launch_bounds__(256) void pass_chain_kernel(const PassArgs *__restrict__ args,
+__global__ __launch_bounds__(256) SF_PASS_OCCUPANCY void pass_chain_kernel(const PassArgs *__restrict__ args,
                                                          const ChainPhase *__restrict__ phases, uint32_t n_phases,
                                                          uint64_t *__restrict__ count, uint64_t base,
                                                          int *__restrict__ err)

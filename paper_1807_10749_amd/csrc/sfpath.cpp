@@ -346,7 +346,7 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
         std::vector<sf_tuning_t> cands;
         const uint32_t regs[3] = {fp64 ? 4u : 5u, fp64 ? 3u : 4u, fp64 ? 2u : 3u};
         const uint32_t leafs[4] = {0u, 4096u, 1024u, 256u};
-        const uint32_t wpcs[3] = {32u, 16u, 64u};
+        const uint32_t wpcs[3] = {128u, 32u, 64u};
         sf_tuning_t probe = c->tuning;
         probe.no_leaf_fold = 0;
         probe.fold_levels = 0;
