@@ -33,6 +33,10 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n)
 template <typename T>
 __device__ __forceinline__ T inv_sqrt2() { return T(0.70710678118654752440084436210485); }
 
+// a * b + c, one rounding
+__device__ __forceinline__ float fma1(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma1(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // x with its sign bit XORed with bit 31 of s (s is 0 or 1 << 31)
 __device__ __forceinline__ float flip_sign(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
 __device__ __forceinline__ double flip_sign(double x, uint32_t s)
@@ -95,20 +99,14 @@ template <int R, typename C>
 __device__ __forceinline__ void lane_gate(int b, int kind, int lane, C (&v)[1 << R])
 {
     constexpr int N = 1 << R;
+    using T = decltype(v[0].x);
     const int m = 1 << b;
     const bool hi = (lane & m) != 0;
-    if (kind == GK_H) {
-        // lo' = lo + hi, hi' = lo - hi
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            C o = v[j];
-            C t;
-            t.x = __shfl_xor(o.x, m);
-            t.y = __shfl_xor(o.y, m);
-            v[j].x = hi ? t.x - o.x : o.x + t.x;
-            v[j].y = hi ? t.y - o.y : o.y + t.y;
-        }
-    } else if (kind == GK_X) {
+    // H:  lo' = lo + hi, hi' = lo - hi  ->  self' = sg * self + other, sg = -1 on the hi lanes
+    // Y:  lo' = lo - hi, hi' = lo + hi  ->  self' = self + sg * other, sg = -1 on the lo lanes
+    // (multiplying by +-1 is exact, so each is one rounded operation as an add would be)
+    const T sg = (kind == GK_H) == hi ? T(-1) : T(1);
+    if (kind == GK_X) {
         // both halves: self' = self - i * other
 #pragma unroll
         for (int j = 0; j < N; ++j) {
@@ -119,16 +117,25 @@ __device__ __forceinline__ void lane_gate(int b, int kind, int lane, C (&v)[1 <<
             v[j].x = o.x + t.y;
             v[j].y = o.y - t.x;
         }
-    } else {
-        // lo' = lo - hi, hi' = lo + hi
+    } else if (kind == GK_H) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             C o = v[j];
             C t;
             t.x = __shfl_xor(o.x, m);
             t.y = __shfl_xor(o.y, m);
-            v[j].x = hi ? t.x + o.x : o.x - t.x;
-            v[j].y = hi ? t.y + o.y : o.y - t.y;
+            v[j].x = fma1(o.x, sg, t.x);
+            v[j].y = fma1(o.y, sg, t.y);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            C o = v[j];
+            C t;
+            t.x = __shfl_xor(o.x, m);
+            t.y = __shfl_xor(o.y, m);
+            v[j].x = fma1(t.x, sg, o.x);
+            v[j].y = fma1(t.y, sg, o.y);
         }
     }
 }
@@ -364,7 +371,8 @@ __device__ __forceinline__ void apply_diag(const DiagGroup *gp, const uint8_t *t
         T c0, s0, c1, s1;
         omega(mB & 7, c0, s0);
         omega((mB + 1) & 7, c1, s1);
-        auto run = [&](auto with_proj) {
+        // FULL: registers pick f0 or f1 and may turn by i; otherwise every register takes f0
+        auto run = [&](auto with_proj, auto full) {
             uint32_t sg = 0;
 #pragma unroll
             for (int i = 0; i < N; ++i) {
@@ -372,10 +380,17 @@ __device__ __forceinline__ void apply_diag(const DiagGroup *gp, const uint8_t *t
                 if (i) sg ^= cbit(__builtin_ctz(i));
                 const int t = tab_entry(g.tab, j);
                 const T x = v[j].x, y = v[j].y;
-                const T c = (t & 1) ? c1 : c0, sn = (t & 1) ? s1 : s0;
-                const T px = x * c - y * sn, py = x * sn + y * c;
-                // times i: (px, py) -> (-py, px)
-                T nx = (t & 2) ? -py : px, ny = (t & 2) ? px : py;
+                T nx, ny;
+                if (decltype(full)::value) {
+                    const T c = (t & 1) ? c1 : c0, sn = (t & 1) ? s1 : s0;
+                    const T px = x * c - y * sn, py = x * sn + y * c;
+                    // times i: (px, py) -> (-py, px)
+                    nx = (t & 2) ? -py : px;
+                    ny = (t & 2) ? px : py;
+                } else {
+                    nx = x * c0 - y * s0;
+                    ny = x * s0 + y * c0;
+                }
                 const uint32_t su = sg ^ ((uint32_t)((t >> 2) & 1) << 31);
                 nx = flip_sign(nx, su);
                 ny = flip_sign(ny, su);
@@ -388,8 +403,14 @@ __device__ __forceinline__ void apply_diag(const DiagGroup *gp, const uint8_t *t
                 v[j].y = ny;
             }
         };
-        if (has_proj) run(std::true_type{});
-        else run(std::false_type{});
+        const bool full = (g.flags & 12u) != 0;
+        if (has_proj) {
+            if (full) run(std::true_type{}, std::true_type{});
+            else run(std::true_type{}, std::false_type{});
+        } else {
+            if (full) run(std::false_type{}, std::true_type{});
+            else run(std::false_type{}, std::false_type{});
+        }
     }
 }
 

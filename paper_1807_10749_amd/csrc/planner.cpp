@@ -589,7 +589,14 @@ void flush(PendingDiag &pd, PassPlan &pp, const int (&kidx)[64])
     g.n_zs_r = (uint16_t)zsr.size();
     g.n_proj_b = (uint16_t)pb.size();
     g.n_proj_r = (uint16_t)pr.size();
-    g.flags = (odd ? 1u : 0u) | ((pb.size() + pr.size()) ? 2u : 0u);
+    // bits 2 and 3: some register-only weight sum has bit 0 (an odd power of omega) or bit 1
+    // (a factor i); without them every register takes the lane's own factor
+    bool reg_odd = false, reg_i = false;
+    for (int j = 0; j < N; ++j) {
+        reg_odd = reg_odd || (tab[j] & 1);
+        reg_i = reg_i || (tab[j] & 2);
+    }
+    g.flags = (odd ? 1u : 0u) | ((pb.size() + pr.size()) ? 2u : 0u) | (reg_odd ? 4u : 0u) | (reg_i ? 8u : 0u);
     for (int j = 0; j < 64; ++j) {
         const uint64_t v = (uint64_t)(tab[j] & 7);
         g.tab[j >> 4] |= v << ((j & 15) * 4);

@@ -53,7 +53,8 @@ struct PassOp {
 // given by register index k) or base bits ("b", extended bit position).
 struct DiagGroup {
     uint16_t n_lin_b, n_quad_bb, n_quad_br, n_zs_b, n_zs_r, n_proj_b, n_proj_r;
-    uint16_t flags;            // bit 0: some weight not a multiple of 4; bit 1: has projectors
+    uint16_t flags;            // bit 0: some weight not a multiple of 4; bit 1: has projectors;
+                               // bit 2 (3): some register entry of tab has bit 0 (bit 1) set
     uint32_t term_off;         // offset (in byte pairs) into the term array
     uint32_t pad;
     uint64_t tab[4];           // m contribution of register-only terms, 4 bits per j < 64

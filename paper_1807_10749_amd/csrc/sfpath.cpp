@@ -525,7 +525,11 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
                     // zN: the pass reads a source whose zero subspace spans N projected qubits
                     uint64_t zq = 0;
                     for (const auto &e : sp.passes[i].zero_in) zq |= uint64_t(1) << e.first;
-                    s += (i ? "," : "") + std::to_string(sp.passes[i].n_nondiag) + "g/" +
+                    // gates on register qubits (r) and on lane qubits (l, lane shuffles)
+                    int n_lane = 0;
+                    for (const sf::PassOp &op : sp.passes[i].ops) n_lane += op.type == sf::PO_LANE ? 1 : 0;
+                    s += (i ? "," : "") + std::to_string(sp.passes[i].n_nondiag) + "g" +
+                         (n_lane ? "(" + std::to_string(n_lane) + "l)" : std::string()) + "/" +
                          (sp.passes[i].dense ? std::string("dense") : std::to_string(sp.passes[i].groups.size()) + "d") +
                          (zq ? "/z" + std::to_string(__builtin_popcountll(zq)) : std::string());
                 }
