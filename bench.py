@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--tuning", default="",
                     help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes]]]] "
                          "(skips autotune)")
+    ap.add_argument("--ceilings-only", action="store_true",
+                    help="only measure the bandwidth ceilings (and the read rate per buffer size) and print them")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (known HBM traffic for counter scaling)")
     return ap.parse_args()
@@ -225,6 +227,18 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": x.numel(), "calibrate_copy_bytes_written": y.numel()}))
         return
     from paper_1807_10749_amd import binding as sf
+    if args.ceilings_only:
+        out = measure_ceilings()
+        buf = torch.ones(1 << 32, dtype=torch.uint8, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+        sweep = {}
+        for shift in range(21, 33):
+            nbytes = 1 << shift
+            reps = max(4, (1 << 36) // nbytes // 4)
+            sweep[f"{nbytes >> 20} MiB"] = nbytes * reps / (sf.read_bandwidth(buf, nbytes, reps, 0, stream) * 1e-3) / 1e9
+        out["read_GB_per_s_by_buffer_size"] = sweep
+        print(json.dumps({"ceilings": out}), flush=True)
+        return
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(args.serve_jobs, policies=tuple(args.serve_policies.split(",")))}),
               flush=True)
@@ -400,6 +414,19 @@ def config_line(name, ceilings, max_paths=0, steps=3, warmup=1, with_sampling=Fa
         out["gather"] = {"contributions_per_s": req["npaths"] * req["bits"].size / (tot["ms_gather"] / steps * 1e-3),
                          "row_bytes_per_step": rows, "ms_per_step": tot["ms_gather"] / steps,
                          "row_GB_per_s": rows / (tot["ms_gather"] / steps * 1e-3) / 1e9}
+        if ceilings and tot["ms_gather"] >= tot["ms_sweep"]:
+            # The path sum dominates.  Its block-B rows are read at random over the block-B
+            # state of the level it reads (the working set); the smallest level of the memory
+            # hierarchy that holds it serves the reads, and its measured read ceiling is the
+            # roof: the XCDs' 4 MB L2s, the 256 MB Infinity Cache, else HBM.
+            ws = req["c"].stats()["gather_ws_bytes"]
+            level, key = (("l2", "l2_read_GB_per_s") if ws <= 4 << 20 else
+                          ("mall", "mall_read_GB_per_s") if ws <= 256 * 10 ** 6 else ("hbm", "hbm_read_GB_per_s"))
+            peak = ceilings[key]
+            out["roofline"] = {"kernel": dom, "bound": level, "achieved": ach, "peak": peak, "unit": "GB/s",
+                               "frac": ach / peak, "peak_kind": f"measured {key.replace('_GB_per_s', '')} ceiling (read_bandwidth)",
+                               "working_set_bytes": ws, "bytes_per_launch": bpl, "avg_launch_ms": avg_ms,
+                               "contributions_per_s": out["gather"]["contributions_per_s"]}
     if req["tuning"] is not None and tot["n_sweep_launches"] > steps:
         # the same request and tuning with the passes of small tree levels chained into
         # persistent cooperative launches (grid barriers instead of kernel boundaries)
@@ -426,34 +453,36 @@ def config_line(name, ceilings, max_paths=0, steps=3, warmup=1, with_sampling=Fa
 
 
 def measure_ceilings():
-    """Measured bandwidth ceilings on this GPU: a 2 GiB device-to-device copy (HBM read + write),
-    a 2 GiB read (HBM read), and reads of a 128 MiB buffer that stays in the 256 MB Infinity
-    Cache between repetitions (the ceiling of kernels whose working set is cache-resident)."""
+    """Measured bandwidth ceilings on this GPU: a 2 GiB device-to-device copy (HBM read + write,
+    torch), and the library's streaming read (read_bandwidth) of buffers sized for each level:
+    4 GiB (HBM), 128 MiB (fits the 256 MB Infinity Cache, not an XCD's 4 MB L2) and 2 MiB
+    (fits every XCD's L2)."""
     import torch
+    from paper_1807_10749_amd import binding as sf
     out = {}
-    def bw(fn, nbytes, reps):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        e1.synchronize()
-        return nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     x = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
     y = torch.empty_like(x)
-    out["hbm_copy_GB_per_s"] = bw(lambda: y.copy_(x), 2 * x.numel(), 10)
-    xf = x.view(torch.float32)
-    out["hbm_read_GB_per_s"] = bw(lambda: xf.sum(), x.numel(), 10)
-    del x, y, xf
-    a = torch.ones(1 << 26, dtype=torch.uint8, device="cuda")             # 2 x 64 MiB, Infinity-Cache resident
-    b = torch.empty_like(a)
-    out["mall_copy_GB_per_s"] = bw(lambda: b.copy_(a), 2 * a.numel(), 200)
-    del a, b
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    out["hbm_copy_GB_per_s"] = 2 * x.numel() * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    buf = torch.ones(1 << 32, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    for key, nbytes, reps in (("hbm_read_GB_per_s", 1 << 32, 4), ("mall_read_GB_per_s", 1 << 27, 200),
+                              ("l2_read_GB_per_s", 1 << 21, 20000)):
+        ms = sf.read_bandwidth(buf, nbytes, reps, 0, stream)
+        out[key] = nbytes * reps / (ms * 1e-3) / 1e9
+    del buf
     torch.cuda.empty_cache()
-    out["note"] = ("torch copy_ and sum kernels, timed with events; copies count read + write bytes, the read "
-                   "counts the bytes read once")
+    out["note"] = ("copy: torch copy_, read + write bytes; reads: the library's read_bandwidth streaming kernel "
+                   "(32 workgroups per compute unit less one, 8 loads of 16 B in flight per thread), bytes read "
+                   "per second")
     return out
 
 

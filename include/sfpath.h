@@ -267,6 +267,9 @@ typedef struct {
     uint64_t n_paths_live;   /* requested paths whose term is not known to be zero (see run_paths) */
     uint64_t n_chained_passes;  /* sweep passes run inside chained launches (see chain_passes); a chain
                                    counts once in n_sweep_launches */
+    uint64_t gather_ws_bytes;   /* largest block-B state one gather launch reads rows of (slots x 2^qB x
+                                   element size): every bitstring reads rows anywhere in it, so this working
+                                   set decides which level of the memory hierarchy serves the path sum */
 } sf_run_stats_t;
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);
@@ -367,6 +370,23 @@ int fidelity_estimate(const double *a, const double *b, uint64_t n, void *hip_st
  * cross-entropy check the paper mentions beside the overlap estimate).
  */
 int xeb_fidelity(const double *amps, uint64_t n, uint32_t n_qubits, void *hip_stream, double *f);
+
+/*
+ * read_bandwidth: measured read ceiling of one level of the memory hierarchy,
+ * for the rooflines of the path-sum kernels, whose working sets live in the
+ * caches rather than in HBM.  Reads the first `bytes` (a power of two, at
+ * least 4096) of the device buffer `buf` `reps` times in one launch of a
+ * streaming kernel with eight 16-byte loads in flight per thread: a buffer
+ * far larger than the Infinity Cache measures HBM, one that fits the
+ * Infinity Cache but not an XCD's L2 (4 MB) measures the Infinity Cache, one
+ * that fits an XCD's L2 measures L2.
+ * `grid` workgroups of 256 threads (0: 32 per compute unit less one; with an
+ * odd count every workgroup's reads walk the whole buffer instead of
+ * revisiting a few 4 KB chunks that its XCD's L2 would keep).  Enqueued on
+ * hip_stream, which the call synchronizes; ms_out = launch time from events
+ * on that stream.  The buffer is only read; its contents do not matter.
+ */
+int read_bandwidth(const void *buf, size_t bytes, uint32_t reps, uint32_t grid, void *hip_stream, double *ms_out);
 
 /*
  * verify_claim: the Verifier's side of the two-party validation protocol.

@@ -25,7 +25,7 @@ EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_pa
            "server_drain", "server_stats", "server_destroy", "server_last_error", "rejection_m",
            "sample_bitstrings", "rejection_workspace_size", "rejection_accept", "frugal_sample",
            "fidelity_estimate", "xeb_fidelity", "verify_claim", "save_tuning_cache", "load_tuning_cache",
-           "server_set_policy", "run_paths_noalloc"]
+           "server_set_policy", "run_paths_noalloc", "read_bandwidth"]
 SF_PENDING = 1
 SF_SERVE_OLDEST_FIRST, SF_SERVE_ROUND_ROBIN, SF_SERVE_LEAST_WORK = 0, 1, 2
 
@@ -51,7 +51,8 @@ class RunStats(ctypes.Structure):
                 ("n_batches", ctypes.c_uint64), ("n_passes_a", ctypes.c_uint64),
                 ("n_passes_b", ctypes.c_uint64), ("gather_row_bytes", ctypes.c_uint64),
                 ("a_groups", ctypes.c_uint64), ("ms_plan", ctypes.c_double),
-                ("n_paths_live", ctypes.c_uint64), ("n_chained_passes", ctypes.c_uint64)]
+                ("n_paths_live", ctypes.c_uint64), ("n_chained_passes", ctypes.c_uint64),
+                ("gather_ws_bytes", ctypes.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -116,6 +117,7 @@ def _load():
     pd = ctypes.POINTER(ctypes.c_double)
     lib.fidelity_estimate.argtypes = [vp, vp, u64, vp, pd, pd, pd]
     lib.xeb_fidelity.argtypes = [vp, u64, u32, vp, pd]
+    lib.read_bandwidth.argtypes = [vp, sz, u32, u32, vp, pd]
     lib.verify_claim.argtypes = [vp, vp, u64, u64, ctypes.c_double, u64, ctypes.c_double, u32, vp, vp, sz, pd,
                                  ctypes.POINTER(ctypes.c_int)]
     lib.server_last_error.restype = ctypes.c_char_p
@@ -255,6 +257,13 @@ def xeb_fidelity(amps, n: int, n_qubits: int, stream=None) -> float:
     f = ctypes.c_double()
     _check(lib.xeb_fidelity(_ptr(amps), n, n_qubits, _stream_handle(stream), ctypes.byref(f)))
     return f.value
+
+
+def read_bandwidth(buf, nbytes: int, reps: int, grid: int = 0, stream=None) -> float:
+    """Milliseconds of one launch reading the first nbytes of device buffer buf reps times."""
+    ms = ctypes.c_double()
+    _check(lib.read_bandwidth(_ptr(buf), nbytes, reps, grid, _stream_handle(stream), ctypes.byref(ms)))
+    return ms.value
 
 
 def verify_claim(c: int, claimed, index_seed: int, f1: float, path_seed: int, delta: float, flags: int = 0,

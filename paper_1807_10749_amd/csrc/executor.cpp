@@ -541,6 +541,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             const uint64_t per = slots * elem * (a_groups * ra + (uint64_t)n_bits * rb) + (uint64_t)n_bits * 44 +
                                  (ln.kind == Launch::FOLD ? slots * 4 : 0);
             c.stats.n_gather_launches += rounds;
+            c.stats.gather_ws_bytes = std::max<uint64_t>(c.stats.gather_ws_bytes, slots * (uint64_t(1) << qh[1]) * elem);
             c.stats.gather_bytes += rounds * per;
             c.stats.gather_row_bytes += rounds * ln.bytes;
         }

@@ -1583,6 +1583,36 @@ hipError_t launch_overlap(const double *a, const double *b, uint64_t n, double *
     return hipGetLastError();
 }
 
+// Streaming read of reps x n16 16-byte words of a buffer of n16 (a power of two) words: thread
+// index i (grid-stride) reads word i mod n16, eight independent loads in flight per thread
+// whatever the buffer size, so a buffer that fits a cache level (the XCDs' L2s, the Infinity
+// Cache) is read from it at that level's rate.  The sum is stored only in an impossible case,
+// which keeps the loads.
+__global__ __launch_bounds__(256) void read_probe_kernel(const float4 *__restrict__ buf, uint64_t n16, uint32_t reps,
+                                                         float *sink)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    const uint64_t total = (uint64_t)reps * n16, mask = n16 - 1;
+    float acc = 0.f;
+    uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    for (; i + 7 * stride < total; i += 8 * stride) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = buf[(i + u * stride) & mask];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
+    }
+    for (; i < total; i += stride) acc += buf[i & mask].x;
+    if (acc == -1.2345e30f) sink[0] = acc;
+}
+
+hipError_t launch_read_probe(const void *buf, uint64_t bytes, uint32_t reps, unsigned grid, float *sink, hipStream_t s)
+{
+    if (!buf || !sink || bytes < 16 || (bytes & (bytes - 1)) || grid == 0) return hipErrorInvalidValue;
+    read_probe_kernel<<<grid, 256, 0, s>>>((const float4 *)buf, bytes / 16, reps, sink);
+    return hipGetLastError();
+}
+
 __global__ void fill_zero_kernel(double *p, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

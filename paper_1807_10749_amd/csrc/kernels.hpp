@@ -86,6 +86,8 @@ hipError_t launch_order_by_key(const uint32_t *keys, uint32_t *keys_sorted, uint
 
 // Fill n doubles with zero (a kernel, so it can also sit inside a captured graph).
 hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t s);
+// Streaming read of the first bytes (a power of two, at least 16) of buf, reps times (read_bandwidth).
+hipError_t launch_read_probe(const void *buf, uint64_t bytes, uint32_t reps, unsigned grid, float *sink, hipStream_t s);
 hipError_t launch_fill_zero_i32(int *p, uint64_t n, hipStream_t s);
 
 }  // namespace sf

@@ -770,6 +770,47 @@ int xeb_fidelity(const double *amps, uint64_t n, uint32_t n_qubits, void *hip_st
     });
 }
 
+int read_bandwidth(const void *buf, size_t bytes, uint32_t reps, uint32_t grid, void *hip_stream, double *ms_out)
+{
+    return guarded([&]() -> int {
+        if (!buf || !ms_out) return fail(SF_ERR_INVALID, "NULL argument");
+        if (bytes < 4096 || (bytes & (bytes - 1))) return fail(SF_ERR_INVALID, "bytes must be a power of two, at least 4096");
+        if (reps == 0 || reps > 100000) return fail(SF_ERR_INVALID, "reps must be 1..100000");
+        hipStream_t s = (hipStream_t)hip_stream;
+        hipError_t he;
+        unsigned g = grid;
+        if (!g) {
+            int dev = 0, cus = 0;
+            if ((he = hipGetDevice(&dev)) != hipSuccess ||
+                (he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+                return fail(SF_ERR_DEVICE, std::string("device query: ") + hipGetErrorString(he));
+            g = (unsigned)std::max(cus, 1) * 32u - 1u;   // odd: see the header
+        }
+        float *sink = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        auto done = [&](int rc, const std::string &msg) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (sink) (void)hipFree(sink);
+            return rc ? fail(rc, msg) : ok();
+        };
+        if ((he = hipMalloc(&sink, 16)) != hipSuccess) return done(SF_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(he));
+        if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess)
+            return done(SF_ERR_DEVICE, std::string("event: ") + hipGetErrorString(he));
+        // one untimed repetition first (fills the caches a resident buffer is read from)
+        if ((he = sf::launch_read_probe(buf, bytes, 1, g, sink, s)) != hipSuccess ||
+            (he = hipEventRecord(e0, s)) != hipSuccess ||
+            (he = sf::launch_read_probe(buf, bytes, reps, g, sink, s)) != hipSuccess ||
+            (he = hipEventRecord(e1, s)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess)
+            return done(SF_ERR_DEVICE, std::string("read probe: ") + hipGetErrorString(he));
+        float ms = 0.f;
+        if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+            return done(SF_ERR_DEVICE, std::string("event time: ") + hipGetErrorString(he));
+        *ms_out = ms;
+        return done(SF_OK, "");
+    });
+}
+
 int verify_claim(sf_circuit_t *c, const double *claimed, uint64_t k, uint64_t index_seed, double f1,
                  uint64_t path_seed, double delta, uint32_t flags, void *hip_stream, void *workspace,
                  size_t workspace_bytes, double *f_e, int *passed)

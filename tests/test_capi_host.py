@@ -384,3 +384,13 @@ def test_zero_subspace_marked_in_plan(sf):
     assert all("/z" not in b for _, _, b in parts), parts
     assert any("/z" in a for _, a, _ in parts), parts
     sf.destroy_circuit(c)
+
+
+def test_read_bandwidth_rejects_bad_arguments(sf):
+    """Argument checks come before any device work (no GPU needed)."""
+    fake = 1 << 40        # never dereferenced: every call below fails its checks first
+    for args in ((None, 1 << 20, 1, 0), (fake, 1024, 1, 0), (fake, (1 << 20) + 16, 1, 0), (fake, 1 << 20, 0, 0),
+                 (fake, 1 << 20, 100001, 0)):
+        with pytest.raises(sf.SFError) as e:
+            sf.read_bandwidth(*args)
+        assert e.value.code == sf.SF_ERR_INVALID
