@@ -168,6 +168,7 @@ def time_steps(req, steps, warmup, chunk_paths=0, label=""):
     elapsed = time.perf_counter() - t0
     tot["elapsed_s"] = elapsed
     tot["a_groups"] = st["a_groups"] if st else 0
+    tot["gather_ws_bytes"] = st["gather_ws_bytes"] if st else 0
     return tot
 
 
@@ -284,10 +285,11 @@ def main():
     torch.cuda.empty_cache()
 
     extra = None
+    ceilings = None
     if not args.no_extra:
         extra = {}
         progress("bandwidth ceilings")
-        extra["ceilings"] = measure_ceilings()
+        ceilings = extra["ceilings"] = measure_ceilings()
         for name in ("grid4x4_d16", "grid5x6_d24", "grid6x7_d32"):
             if name == args.workload:
                 continue
@@ -305,6 +307,17 @@ def main():
     if args.serve_jobs > 0:
         progress(f"serving mix, {args.serve_jobs} jobs")
         serving = serving_bench(args.serve_jobs, policies=tuple(args.serve_policies.split(",")))
+
+    # the dominant kernel's roof: HBM for the gate sweeps; for a dominant path sum, the measured
+    # read ceiling of the memory level that holds its working set
+    if dom.startswith("pass_kernel"):
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    else:
+        if ceilings is None:
+            progress("bandwidth ceilings")
+            ceilings = measure_ceilings()
+        roof = gather_roofline(dom, achieved, run_stats["gather_ws_bytes"], ceilings)
 
     cpu = None
     if not args.no_cpu:
@@ -340,10 +353,8 @@ def main():
                                "other": run_stats["ms_other"] / args.steps},
         "run_paths_wall_ms_per_step": run_stats["ms_total"] / args.steps,
         "host_plan_ms_per_step": run_stats["ms_plan"] / args.steps,
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_ms": avg_launch_ms, "launches_per_step": launches_per_step,
-                     "bytes_per_launch": bytes_per_launch},
+        "roofline": dict(roof, traffic=traffic, avg_launch_ms=avg_launch_ms, launches_per_step=launches_per_step,
+                         bytes_per_launch=bytes_per_launch),
         "sweep_roofline": {"kernels": "pass_kernel + dense_kernel (gate sweeps, all levels written)", "bound": "hbm",
                            "achieved": (run_stats["sweep_bytes"] / max(run_stats["ms_sweep"], 1e-9)) / 1e6,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -415,18 +426,9 @@ def config_line(name, ceilings, max_paths=0, steps=3, warmup=1, with_sampling=Fa
                          "row_bytes_per_step": rows, "ms_per_step": tot["ms_gather"] / steps,
                          "row_GB_per_s": rows / (tot["ms_gather"] / steps * 1e-3) / 1e9}
         if ceilings and tot["ms_gather"] >= tot["ms_sweep"]:
-            # The path sum dominates.  Its block-B rows are read at random over the block-B
-            # state of the level it reads (the working set); the smallest level of the memory
-            # hierarchy that holds it serves the reads, and its measured read ceiling is the
-            # roof: the XCDs' 4 MB L2s, the 256 MB Infinity Cache, else HBM.
-            ws = req["c"].stats()["gather_ws_bytes"]
-            level, key = (("l2", "l2_read_GB_per_s") if ws <= 4 << 20 else
-                          ("mall", "mall_read_GB_per_s") if ws <= 256 * 10 ** 6 else ("hbm", "hbm_read_GB_per_s"))
-            peak = ceilings[key]
-            out["roofline"] = {"kernel": dom, "bound": level, "achieved": ach, "peak": peak, "unit": "GB/s",
-                               "frac": ach / peak, "peak_kind": f"measured {key.replace('_GB_per_s', '')} ceiling (read_bandwidth)",
-                               "working_set_bytes": ws, "bytes_per_launch": bpl, "avg_launch_ms": avg_ms,
-                               "contributions_per_s": out["gather"]["contributions_per_s"]}
+            out["roofline"] = dict(gather_roofline(dom, ach, tot["gather_ws_bytes"], ceilings),
+                                   bytes_per_launch=bpl, avg_launch_ms=avg_ms,
+                                   contributions_per_s=out["gather"]["contributions_per_s"])
     if req["tuning"] is not None and tot["n_sweep_launches"] > steps:
         # the same request and tuning with the passes of small tree levels chained into
         # persistent cooperative launches (grid barriers instead of kernel boundaries)
@@ -450,6 +452,18 @@ def config_line(name, ceilings, max_paths=0, steps=3, warmup=1, with_sampling=Fa
     del req
     torch.cuda.empty_cache()
     return out
+
+
+def gather_roofline(dom, achieved, ws, ceilings):
+    """Roofline of a dominant path-sum kernel.  Its block-B rows are read at random over the
+    block-B state of the level it reads (the working set ws); the smallest level of the memory
+    hierarchy that holds it serves the reads, and that level's measured read ceiling is the roof:
+    an XCD's 4 MB L2, the 256 MB Infinity Cache, else HBM."""
+    level, key = (("l2", "l2_read_GB_per_s") if ws <= 4 << 20 else
+                  ("mall", "mall_read_GB_per_s") if ws <= 256 * 10 ** 6 else ("hbm", "hbm_read_GB_per_s"))
+    peak = ceilings[key]
+    return {"kernel": dom, "bound": level, "achieved": achieved, "peak": peak, "unit": "GB/s", "frac": achieved / peak,
+            "peak_kind": f"measured {key.replace('_GB_per_s', '')} ceiling (read_bandwidth)", "working_set_bytes": ws}
 
 
 def measure_ceilings():
