@@ -194,6 +194,10 @@ typedef struct {
                                 persistent cooperative launch with a grid barrier between them.
                                 The barrier costs more than a kernel boundary between back-to-back
                                 launches on one stream, so 0 is the default */
+    uint32_t no_row_skip;    /* 0: the last pass of each block at the level the path sum reads
+                                computes only the tiles holding rows the requested bitstrings
+                                read (when they are expected to be under 80% of its tiles);
+                                1: whole states */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);
@@ -270,6 +274,9 @@ typedef struct {
     uint64_t gather_ws_bytes;   /* largest block-B state one gather launch reads rows of (slots x 2^qB x
                                    element size): every bitstring reads rows anywhere in it, so this working
                                    set decides which level of the memory hierarchy serves the path sum */
+    double row_mask_frac[2];    /* per block: fraction of the tiles of its last pass before the path sum
+                                   that were computed (the rest hold no row a requested bitstring reads;
+                                   tuning no_row_skip); 0 when that pass computed every tile */
 } sf_run_stats_t;
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);

@@ -40,7 +40,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("reg_qubits", ctypes.c_uint32), ("leaf_batch", ctypes.c_uint32),
                 ("max_slots", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
                 ("dense_qubits", ctypes.c_uint32), ("no_leaf_fold", ctypes.c_uint32),
-                ("fold_levels", ctypes.c_uint32), ("chain_passes", ctypes.c_uint32)]
+                ("fold_levels", ctypes.c_uint32), ("chain_passes", ctypes.c_uint32),
+                ("no_row_skip", ctypes.c_uint32)]
 
 
 class RunStats(ctypes.Structure):
@@ -52,10 +53,11 @@ class RunStats(ctypes.Structure):
                 ("n_passes_b", ctypes.c_uint64), ("gather_row_bytes", ctypes.c_uint64),
                 ("a_groups", ctypes.c_uint64), ("ms_plan", ctypes.c_double),
                 ("n_paths_live", ctypes.c_uint64), ("n_chained_passes", ctypes.c_uint64),
-                ("gather_ws_bytes", ctypes.c_uint64)]
+                ("gather_ws_bytes", ctypes.c_uint64), ("row_mask_frac", ctypes.c_double * 2)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        return {name: (list(getattr(self, name)) if name == "row_mask_frac" else getattr(self, name))
+                for name, _ in self._fields_}
 
 
 class Job(ctypes.Structure):
@@ -305,8 +307,9 @@ def workspace_size(c: int, n_paths: int, n_bits: int, flags: int = 0) -> int:
 
 
 def set_tuning(c: int, reg_qubits=0, leaf_batch=0, max_slots=0, waves_per_cu=0, dense_qubits=0, no_leaf_fold=0,
-               fold_levels=0, chain_passes=0):
-    t = Tuning(reg_qubits, leaf_batch, max_slots, waves_per_cu, dense_qubits, no_leaf_fold, fold_levels, chain_passes)
+               fold_levels=0, chain_passes=0, no_row_skip=0):
+    t = Tuning(reg_qubits, leaf_batch, max_slots, waves_per_cu, dense_qubits, no_leaf_fold, fold_levels, chain_passes,
+               no_row_skip)
     _check(lib.set_tuning(c, ctypes.byref(t)))
 
 

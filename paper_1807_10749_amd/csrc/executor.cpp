@@ -97,6 +97,7 @@ struct Launch {
     bool flip = false;            // PASS: the program holds per-path flips
     bool pair_next = false;       // PASS: launched together with the next launch (the other block's pass)
     bool zskip = false;           // PASS: leaves the source's zero subspace unread (pa.n_zero entries)
+    bool row_last = false;        // PASS: last pass of its block at the level the path sum reads
     PassArgs pa{};
     GatherArgs ga{};
     size_t plan_off = 0;      // device offset of the pass program inside the plan blob
@@ -147,6 +148,8 @@ struct BlobEntry { size_t off; uint32_t words, groups_word, terms_word; };
 struct Planned {
     std::vector<LevelBuf> lb;
     size_t table_bound = 0;
+    size_t rowmask_off = 0;               // row masks of both blocks, inside the table reservation
+    uint64_t rowmask_words[2] = {0, 0};   // 32-bit words per block (0: no mask possible)
     std::vector<Launch> launches;
     std::vector<BatchRec> batches;
     std::vector<uint64_t> tpath;          // per slot of every batch: the node's path id
@@ -359,8 +362,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         if (!bits_dev && n_bits)
             if ((he = hipMemcpyAsync((void *)d_bits, bits, n_bits * 8, hipMemcpyHostToDevice, stream)) != hipSuccess) return dev_err("copy bitstrings", he);
         // flags: [0] bad bitstring, [1] visiting groups, [2] barrier fault of a chained launch,
-        // [4..5] the chained launches' 64-bit barrier counter
-        if ((he = launch_fill_zero_i32(d_flag, 6, stream)) != hipSuccess) return dev_err("fill", he);
+        // [4..5] the chained launches' 64-bit barrier counter, [6..7] and [8..9] the set bits of
+        // block A's and block B's row mask (64-bit)
+        if ((he = launch_fill_zero_i32(d_flag, 10, stream)) != hipSuccess) return dev_err("fill", he);
         if ((he = launch_pext(d_bits, n_bits, c.mask_a, c.mask_b, all, d_xa, d_xb, d_flag, stream)) != hipSuccess) return dev_err("pext", he);
         const uint32_t *keys = d_xa;
         int key_bits = qh[0];
@@ -432,6 +436,12 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
         table_bound = align_up(table_bound * 8) + align_up(table_bound * 4);
         if (fold) table_bound += align_up(tree.node[fold_at].size() * 8 + 8);   // descendant masks
+        // row masks of the last passes before the path sum: one bit per row of a block state
+        PL.rowmask_off = table_bound;
+        for (int h = 0; h < 2; ++h) {
+            PL.rowmask_words[h] = (!c.tuning.no_row_skip && n_bits && qh[h] <= 30) ? ((uint64_t(1) << qh[h]) + 31) / 32 : 0;
+            table_bound += align_up(PL.rowmask_words[h] * 4);
+        }
         size_t budget;
         if (workspace) {
             if (workspace_bytes < fixed + table_bound) { err = "workspace too small"; return SF_ERR_OOM; }
@@ -688,6 +698,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 hl[h].push_back(ln);
             }
         }
+        // the last pass of each block at the level the path sum reads may skip the tiles no
+        // requested bitstring reads (row masks, decided once the plan is complete)
+        if (level == fold_at)
+            for (int h = 0; h < 2; ++h)
+                if (!hl[h].empty() && hl[h].back().kind == Launch::PASS) hl[h].back().row_last = true;
         // The two blocks' passes are independent: interleave them, and launch the i-th pass of
         // block A together with the i-th pass of block B (one kernel, the blocks of the grid split
         // between them) when both run the same kernel variant.  Small levels are bound by launch
@@ -1004,6 +1019,58 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             li = j;
         }
     }
+    // Row masks.  The path sum reads, per bitstring x and slot, the rows (x_h & ~vary) | m of
+    // block h for every m inside vary (the qubits its fold varies: S, S' or the iSWAP qubits; none
+    // for a plain gather).  The last pass of block h at that level computes a tile only if it
+    // holds such a row; the tile of a row is the row with the qubits inside a tile (registers,
+    // lane qubits) cleared.  Used when the tiles to compute are expected to be under 80% of the
+    // state (1 - exp(-bitstrings x rows / tile positions)) and all those passes tile alike.
+    bool mask_on[2] = {false, false};
+    uint32_t mask_keep[2] = {0, 0}, mask_spread[2] = {0, 0};
+    double mask_est[2] = {1.0, 1.0}, mask_positions[2] = {0.0, 0.0};
+    if (n_paths && n_bits) {
+        for (int h = 0; h < 2; ++h) {
+            if (!PL.rowmask_words[h]) continue;
+            uint32_t inside = 0;
+            bool ok = true, any = false;
+            for (const Launch &ln : launches) {
+                if (!ln.row_last || ln.half != h) continue;
+                const PassArgs &a = ln.pa;
+                const int p = a.p_dst;
+                uint32_t in = 0;
+                for (int kk = 0; kk < ln.R; ++kk) {
+                    if (a.reg_pos[kk] < p) ok = false;
+                    else in |= 1u << (a.reg_pos[kk] - p);
+                }
+                const int lane_bits = a.lane_qpos4 > 0 ? 4 : a.lane_qpos > 0 ? 5 : 6;
+                if (lane_bits > p) in |= (1u << (lane_bits - p)) - 1u;
+                if (a.lane_qpos > 0) in |= 1u << (a.lane_qpos - p);
+                if (a.lane_qpos4 > 0) in |= 1u << (a.lane_qpos4 - p);
+                for (int kk = 0; kk < a.n_low; ++kk) if (a.low_pos[kk] >= p) ok = false;
+                if (any && in != inside) ok = false;
+                inside = in;
+                any = true;
+            }
+            if (!any || !ok) continue;
+            const uint32_t qmask = qh[h] >= 32 ? ~0u : (1u << qh[h]) - 1u;
+            const uint32_t vary = !fold ? 0u : gfold ? fh[h]->g_smask : fh[h]->iswap ? fh[h]->qmask : fh[h]->smask;
+            const uint32_t spread = vary & ~inside & qmask;
+            if (__builtin_popcount(spread) > 6) continue;
+            const double positions = std::ldexp(1.0, qh[h] - __builtin_popcount(inside & qmask));
+            const double est = 1.0 - std::exp(-(double)n_bits * std::ldexp(1.0, __builtin_popcount(spread)) / positions);
+            if (est > 0.8) continue;
+            mask_on[h] = true;
+            mask_keep[h] = qmask & ~(vary | inside);
+            mask_spread[h] = spread;
+            mask_est[h] = est;
+            mask_positions[h] = positions;
+        }
+    }
+    // algorithmic bytes of the masked passes at full size (scaled by the computed fraction later)
+    uint64_t masked_bytes[2] = {0, 0};
+    for (const Launch &ln : launches)
+        if (ln.kind == Launch::PASS && ln.row_last && mask_on[ln.half]) masked_bytes[ln.half] += ln.bytes;
+
     if (dry_run) {
         const uint64_t rounds = n_paths ? (plain ? n_paths : 1) : 0;
         c.stats.n_sweep_launches += rounds * chains.size();
@@ -1021,9 +1088,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                             : qh[0];
         account_gather(launches, rounds, std::min<uint64_t>(n_bits, kb >= 32 ? n_bits : (uint64_t(1) << kb)));
         c.stats.n_batches = n_leaf_batches * rounds;
+        for (int h = 0; h < 2; ++h)
+            c.stats.sweep_bytes -= (uint64_t)((double)(rounds * masked_bytes[h]) * (1.0 - mask_est[h]));
         return SF_OK;
     }
-    if (n_paths && tables_bytes > table_bound) { err = "internal: slot tables exceed their reservation"; return SF_ERR_UNSUPPORTED; }
+    if (n_paths && tables_bytes > PL.rowmask_off) { err = "internal: slot tables exceed their reservation"; return SF_ERR_UNSUPPORTED; }
     if (cacheable && !hit) {
         cache.valid = false;
         cache.plan = fresh;
@@ -1087,6 +1156,23 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     } else if ((he = launch_fill_zero(d_acc, 2 * (uint64_t)n_bits, stream)) != hipSuccess) {
         return dev_err("fill", he);
     }
+    // row masks: cleared, marked from the bitstrings' block bits, their set bits counted
+    uint32_t *d_rowmask[2] = {nullptr, nullptr};
+    {
+        size_t o = fixed + PL.rowmask_off;
+        for (int h = 0; h < 2; ++h) {
+            if (mask_on[h]) {
+                d_rowmask[h] = (uint32_t *)(ws + o);
+                if ((he = launch_fill_zero_i32((int *)d_rowmask[h], PL.rowmask_words[h], stream)) != hipSuccess ||
+                    (he = launch_mark_rows(h ? d_xb : d_xa, n_bits, mask_keep[h], mask_spread[h], d_rowmask[h],
+                                           stream)) != hipSuccess ||
+                    (he = launch_count_bits(d_rowmask[h], PL.rowmask_words[h],
+                                            (unsigned long long *)(d_flag + 6 + 2 * h), stream)) != hipSuccess)
+                    return dev_err("row mask", he);
+            }
+            o += align_up(PL.rowmask_words[h] * 4);
+        }
+    }
 
     char *buf = ws + off_buffers;
     auto pass_args = [&](const Launch &ln) {
@@ -1097,6 +1183,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         a.slot_parent = (const uint32_t *)(ws + off_tparent) + ln.table_off;
         a.slot_parent_base = 0;
         a.prog = (const uint32_t *)(ws + off_blob + ln.plan_off);
+        a.row_mask = ln.row_last ? d_rowmask[ln.half] : nullptr;
         a.prog_words = ln.prog_words;
         a.groups_word = ln.groups_word;
         a.terms_word = ln.terms_word;
@@ -1273,7 +1360,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
     if (!out_dev && n_bits)
         if ((he = hipMemcpyAsync(amps, d_acc, n_bits * 16, hipMemcpyDeviceToHost, stream)) != hipSuccess) return dev_err("copy amps", he);
-    int flag[3] = {0, 0, 0};
+    int flag[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if ((he = hipMemcpyAsync(flag, d_flag, sizeof(flag), hipMemcpyDeviceToHost, stream)) != hipSuccess) return dev_err("copy flag", he);
     if ((he = hipStreamSynchronize(stream)) != hipSuccess) return dev_err("synchronize", he);
     if (flag[0]) { err = "bitstring has bits outside the grid"; return SF_ERR_INVALID; }
@@ -1283,6 +1370,15 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         return SF_ERR_DEVICE;
     }
     account_gather(launches, rounds, (uint64_t)flag[1]);
+    // the masked passes moved the bytes of the tiles they computed
+    for (int h = 0; h < 2; ++h) {
+        if (!mask_on[h]) continue;
+        uint64_t set = 0;
+        std::memcpy(&set, flag + 6 + 2 * h, 8);
+        const double frac = std::min(1.0, (double)set / mask_positions[h]);
+        c.stats.sweep_bytes -= (uint64_t)((double)(rounds * masked_bytes[h]) * (1.0 - frac));
+        c.stats.row_mask_frac[h] = frac;
+    }
 
     if (timing) {
         for (size_t i = 0; i < ev_cat.size(); ++i) {

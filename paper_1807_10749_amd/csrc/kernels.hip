@@ -490,9 +490,14 @@ __device__ __forceinline__ void pass_body(A a, uint32_t block, uint32_t nblocks)
     }
     for (; tile < a.n_tiles; tile += nwaves) {
         const uint64_t et = tile_base(tile);
-        if (a.slots_real && (et & pmask_dst) >= a.slots_real) {
-            // every slot of the tile is padding (the lane bits hold the 4 to 6 lowest slot bits):
-            // only fetch the next tile's tables
+        bool skip = a.slots_real && (et & pmask_dst) >= a.slots_real;
+        if (!skip && a.row_mask) {
+            const uint64_t qb = et >> a.p_dst;
+            skip = ((a.row_mask[qb >> 5] >> (qb & 31u)) & 1u) == 0;
+        }
+        if (skip) {
+            // every slot of the tile is padding (the lane bits hold the 4 to 6 lowest slot bits),
+            // or no amplitude of it is read by the path sum: only fetch the next tile's tables
             const uint64_t nt = tile + nwaves;
             if (nt < a.n_tiles) {
                 const uint64_t slot = (tile_base(nt) | lx) & pmask_dst;
@@ -1580,6 +1585,64 @@ hipError_t launch_overlap(const double *a, const double *b, uint64_t n, double *
 {
     if (n == 0 || blocks == 0) return hipSuccess;
     overlap_kernel<<<blocks, 256, 0, s>>>(a, b, n, partial);
+    return hipGetLastError();
+}
+
+// Row masks of the passes that write the level the path sum reads (PassArgs::row_mask): bitstring
+// i reads the rows (x_i & ~vary) | m of a block for every m inside the vary mask (the qubits its
+// fold varies; none for a plain gather); the tile holding a row has the row's qubit bits with the
+// qubits inside a tile cleared.  keep = ~(vary | inside) over the block's qubits; each thread
+// marks the 2^|vary & ~inside| tiles one bitstring reads.
+__global__ void mark_rows_kernel(const uint32_t *__restrict__ xh, uint64_t n, uint32_t keep, uint32_t spread,
+                                 uint32_t *bitmap)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t base = xh[i] & keep;
+    const int nv = __popc(spread);
+    for (uint32_t s = 0; s < (1u << nv); ++s) {
+        // deposit the bits of s at the positions of spread
+        uint32_t m = 0, rest = spread;
+        for (int b = 0; b < nv; ++b) {
+            const uint32_t low = rest & (0u - rest);
+            if ((s >> b) & 1u) m |= low;
+            rest ^= low;
+        }
+        const uint32_t r = base | m;
+        atomicOr(&bitmap[r >> 5], 1u << (r & 31u));
+    }
+}
+
+// Number of set bits in n words (one atomic add per workgroup).
+__global__ void count_bits_kernel(const uint32_t *__restrict__ words, uint64_t n, unsigned long long *count)
+{
+    __shared__ unsigned long long part[256];
+    unsigned long long c = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        c += (unsigned long long)__popc(words[i]);
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (unsigned w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(count, part[0]);
+}
+
+hipError_t launch_mark_rows(const uint32_t *xh, uint64_t n, uint32_t keep, uint32_t spread, uint32_t *bitmap,
+                            hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    if (__builtin_popcount(spread) > 8) return hipErrorInvalidValue;
+    mark_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xh, n, keep, spread, bitmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_bits(const uint32_t *words, uint64_t n, unsigned long long *count, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<uint64_t>((n + 255) / 256, 4096);
+    count_bits_kernel<<<grid, 256, 0, s>>>(words, n, count);
     return hipGetLastError();
 }
 

@@ -86,6 +86,12 @@ hipError_t launch_order_by_key(const uint32_t *keys, uint32_t *keys_sorted, uint
 
 // Fill n doubles with zero (a kernel, so it can also sit inside a captured graph).
 hipError_t launch_fill_zero(double *p, uint64_t n, hipStream_t s);
+// Row masks of the last passes before the path sum (PassArgs::row_mask): set bit
+// (x_i & keep) | m for every bitstring i and every m inside spread (at most 8 bits).
+hipError_t launch_mark_rows(const uint32_t *xh, uint64_t n, uint32_t keep, uint32_t spread, uint32_t *bitmap,
+                            hipStream_t s);
+// *count += set bits of words[0 .. n).
+hipError_t launch_count_bits(const uint32_t *words, uint64_t n, unsigned long long *count, hipStream_t s);
 // Streaming read of the first bytes (a power of two, at least 16) of buf, reps times (read_bandwidth).
 hipError_t launch_read_probe(const void *buf, uint64_t bytes, uint32_t reps, unsigned grid, float *sink, hipStream_t s);
 hipError_t launch_fill_zero_i32(int *p, uint64_t n, hipStream_t s);

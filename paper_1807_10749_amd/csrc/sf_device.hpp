@@ -79,6 +79,11 @@ struct PassArgs {
     const uint64_t *slot_path;    // per destination slot: path id of the node (low bits 0 below its level)
     const uint32_t *slot_parent;  // per destination slot: slot of its parent in src (SRC_FANOUT)
     const uint32_t *prog;         // pass program in global memory
+    // Rows the path sum reads (nullptr: all).  Bit b of row_mask says whether the tiles whose
+    // block-qubit bits (extended index >> p_dst, zero at the qubits inside a tile) equal b hold
+    // an amplitude the gather or fold reads; the others are neither read nor written.  Only the
+    // last pass of a block at the level the gather reads carries it.
+    const uint32_t *row_mask;
     uint32_t prog_words;          // its size
     uint32_t groups_word;         // word offset of the DiagGroup array (8-byte aligned)
     uint32_t terms_word;          // word offset of the term bytes

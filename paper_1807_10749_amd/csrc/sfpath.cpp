@@ -285,6 +285,7 @@ int set_tuning(sf_circuit_t *c, const sf_tuning_t *t)
     if (t->no_leaf_fold > 1) return fail(SF_ERR_INVALID, "no_leaf_fold must be 0 or 1");
     if (t->fold_levels > 62) return fail(SF_ERR_INVALID, "fold_levels must be at most 62");
     if (t->chain_passes > 1) return fail(SF_ERR_INVALID, "chain_passes must be 0 or 1");
+    if (t->no_row_skip > 1) return fail(SF_ERR_INVALID, "no_row_skip must be 0 or 1");
     auto pow2ok = [](uint32_t v) { return v == 0 || (v & (v - 1)) == 0; };
     if (!pow2ok(t->leaf_batch) || !pow2ok(t->max_slots)) return fail(SF_ERR_INVALID, "batch sizes must be powers of two");
     c->tuning = *t;
@@ -360,9 +361,9 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
                     for (int F = 1; F <= max_fold; ++F) {     // F trailing levels folded into the gather
                         const int Fp = max_fold > 1 ? max_fold - 1 : 1;
                         if (F != max_fold && F != Fp) continue;
-                        cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0, (uint32_t)F, start.chain_passes});
+                        cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0, (uint32_t)F, start.chain_passes, start.no_row_skip});
                     }
-                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1, 0, start.chain_passes});
+                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1, 0, start.chain_passes, start.no_row_skip});
                 }
         // rank by the planned cost
         std::vector<std::pair<double, size_t>> ranked;
@@ -424,11 +425,12 @@ int save_tuning_cache(const char *path)
         FILE *f = std::fopen(path, "w");
         if (!f) return fail(SF_ERR_INVALID, std::string("cannot write ") + path);
         std::fprintf(f, "# sfpath tuning cache: key reg_qubits leaf_batch max_slots waves_per_cu dense_qubits "
-                        "no_leaf_fold fold_levels chain_passes\n");
+                        "no_leaf_fold fold_levels chain_passes no_row_skip\n");
         for (const auto &kv : g_tune_cache) {
             const sf_tuning_t &t = kv.second;
-            std::fprintf(f, "%s %u %u %u %u %u %u %u %u\n", kv.first.c_str(), t.reg_qubits, t.leaf_batch, t.max_slots,
-                         t.waves_per_cu, t.dense_qubits, t.no_leaf_fold, t.fold_levels, t.chain_passes);
+            std::fprintf(f, "%s %u %u %u %u %u %u %u %u %u\n", kv.first.c_str(), t.reg_qubits, t.leaf_batch,
+                         t.max_slots, t.waves_per_cu, t.dense_qubits, t.no_leaf_fold, t.fold_levels, t.chain_passes,
+                         t.no_row_skip);
         }
         const bool bad = std::ferror(f) != 0;
         if (std::fclose(f) != 0 || bad) return fail(SF_ERR_INVALID, std::string("cannot write ") + path);
@@ -451,12 +453,12 @@ int load_tuning_cache(const char *path, uint32_t *n_loaded)
             char key[512];
             sf_tuning_t t{};
             char extra;
-            // entries written before chain_passes existed have one field less (chain_passes 0)
-            const int got_n = std::sscanf(line, "%511s %u %u %u %u %u %u %u %u %c", key, &t.reg_qubits, &t.leaf_batch,
-                                          &t.max_slots, &t.waves_per_cu, &t.dense_qubits, &t.no_leaf_fold,
-                                          &t.fold_levels, &t.chain_passes, &extra);
-            if ((got_n != 8 && got_n != 9) || t.reg_qubits > 5 || t.dense_qubits == 1 || t.dense_qubits > 4 ||
-                t.no_leaf_fold > 1 || t.fold_levels > 62 || t.chain_passes > 1) {
+            // entries written before chain_passes / no_row_skip existed have fields less (read as 0)
+            const int got_n = std::sscanf(line, "%511s %u %u %u %u %u %u %u %u %u %c", key, &t.reg_qubits,
+                                          &t.leaf_batch, &t.max_slots, &t.waves_per_cu, &t.dense_qubits,
+                                          &t.no_leaf_fold, &t.fold_levels, &t.chain_passes, &t.no_row_skip, &extra);
+            if (got_n < 8 || got_n > 10 || t.reg_qubits > 5 || t.dense_qubits == 1 || t.dense_qubits > 4 ||
+                t.no_leaf_fold > 1 || t.fold_levels > 62 || t.chain_passes > 1 || t.no_row_skip > 1) {
                 std::fclose(f);
                 return fail(SF_ERR_INVALID, std::string(path) + ":" + std::to_string(lineno) + ": malformed entry");
             }
@@ -536,6 +538,34 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
                 s += "]";
             }
             s += "\n";
+            // the level the path sum reads: qubits inside a tile of each block's last pass, and
+            // the qubits whose rows the path sum varies (row masks skip the other tiles)
+            const int FDr = sf::fold_depth(*c);
+            if (l == L - FDr) {
+                s += "  path-sum reads this level:";
+                for (int h = 0; h < 2; ++h) {
+                    const sf::SegmentPlan &sp = sf::get_segment_plan(*c, h, l, p, R, (int)c->tuning.dense_qubits);
+                    uint32_t inside = 0;
+                    if (!sp.passes.empty() && !sp.passes.back().dense) {
+                        const sf::PassPlan &pp = sp.passes.back();
+                        for (int k = 0; k < pp.R; ++k) inside |= 1u << (pp.reg_pos[k] - p);
+                        const int lane_bits = pp.lane_q4 >= 0 ? 4 : pp.lane_q >= 0 ? 5 : 6;
+                        if (lane_bits > p) inside |= (1u << (lane_bits - p)) - 1u;
+                        if (pp.lane_q >= 0) inside |= 1u << pp.lane_q;
+                        if (pp.lane_q4 >= 0) inside |= 1u << pp.lane_q4;
+                    }
+                    uint32_t vary = 0;
+                    if (FDr) {
+                        const sf::LeafFold &f = c->half[h].folds[FDr - 1];
+                        vary = sf::fold_general(*c, FDr) ? f.g_smask : f.iswap ? f.qmask : f.smask;
+                    }
+                    char buf[96];
+                    std::snprintf(buf, sizeof buf, " %s tile qubits 0x%x, rows vary 0x%x (%d outside);", h ? "B" : "A",
+                                  inside, vary, __builtin_popcount(vary & ~inside));
+                    s += buf;
+                }
+                s += "\n";
+            }
         }
         std::strncpy(out, s.c_str(), cap - 1);
         out[cap - 1] = 0;
