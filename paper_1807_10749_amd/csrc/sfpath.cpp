@@ -536,6 +536,18 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
                          (zq ? "/z" + std::to_string(__builtin_popcountll(zq)) : std::string());
                 }
                 s += "]";
+                // qubits of the level's non-diagonal gates and of its branch operators
+                uint64_t ndq = 0, brq = 0;
+                for (const sf::HalfOp &op : c->half[h].segments[l]) {
+                    if (sf::is_branch(op.kind)) brq |= uint64_t(1) << op.q0;
+                    else if (!sf::is_diag(op.kind)) {
+                        ndq |= uint64_t(1) << op.q0;
+                        if (sf::is_two_qubit(op.kind)) ndq |= uint64_t(1) << op.q1;
+                    }
+                }
+                char qb[64];
+                std::snprintf(qb, sizeof qb, "{nd 0x%llx br 0x%llx}", (unsigned long long)ndq, (unsigned long long)brq);
+                s += qb;
             }
             s += "\n";
             // the level the path sum reads: qubits inside a tile of each block's last pass, and
