@@ -198,6 +198,11 @@ typedef struct {
                                 computes only the tiles holding rows the requested bitstrings
                                 read (when they are expected to be under 80% of its tiles);
                                 1: whole states */
+    uint32_t no_defer;       /* 0: when block A's part of the level the general fold reads is only
+                                its crossing gates' projectors and one-qubit gates on the projected
+                                qubits, that level's block-A states are not written: the fold
+                                reads the level above with the projected bits set and applies
+                                the gates itself; 1: always write them */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);

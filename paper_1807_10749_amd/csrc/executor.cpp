@@ -92,6 +92,8 @@ struct Launch {
     FoldIswapArgs fia{};          // FOLD of crossing iSWAPs
     GFoldArgs gfa{};              // FOLD in the general form
     size_t mask_off = 0;          // FOLD: element offset of the batch's child masks
+    bool defer = false;           // FOLD (general form): block A read from the parent batch (GFoldHalf)
+    size_t dpar_off = 0, dsub_off = 0, dfac_off = 0;   // its per-slot tables (element offsets in tmaskv)
     int half = 0;
     int R = 0;
     bool flip = false;            // PASS: the program holds per-path flips
@@ -277,6 +279,17 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     gfold = gfold && fold;
     const int fold_at = L - FD;            // the level the gather reads
     const LeafFold *fh[2] = {fold ? &c.half[0].folds[FD - 1] : nullptr, fold ? &c.half[1].folds[FD - 1] : nullptr};
+    // Deferred block-A level: when block A's operations at the level the general fold reads are
+    // its crossing CZs' projectors and one-qubit gates on the projected qubits (deferred_level),
+    // that level's block-A states are not written.  The fold reads the parent batch at the rows
+    // whose projected bits equal the slot's path bits and multiplies by the gates' entry, which
+    // saves the level's block-A writes (a fan-out of every parent into its children).
+    DeferredLevel dA;
+    bool defer = false;
+    if (gfold && FD == 1 && fold_at >= 1 && !plain && !c.tuning.no_defer && n_paths) {
+        dA = deferred_level(c, 0, fold_at);
+        defer = dA.ok && !(dA.mask & fh[0]->g_smask);
+    }
     const uint64_t all = c.n == 64 ? ~uint64_t(0) : ((uint64_t(1) << c.n) - 1);
     if (!bits_dev && !dry_run)
         for (size_t j = 0; j < n_bits; ++j)
@@ -457,7 +470,10 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         for (;;) {
             for (int l = 1; l <= L; ++l) if (lb[l].alias >= 0) lb[l].cap = lb[lb[l].alias].cap;
             size_t need = 0;
-            for (int l = 0; l <= L; ++l) if (lb[l].alias < 0 && !lb[l].none) need += align_up(lb[l].cap * (size_t(1) << qh[0]) * elem) + align_up(lb[l].cap * (size_t(1) << qh[1]) * elem);
+            for (int l = 0; l <= L; ++l)
+                if (lb[l].alias < 0 && !lb[l].none)
+                    need += (defer && l == fold_at ? 0 : align_up(lb[l].cap * (size_t(1) << qh[0]) * elem)) +
+                            align_up(lb[l].cap * (size_t(1) << qh[1]) * elem);
             if (need <= budget) break;
             int big = -1;
             for (int l = 0; l <= L; ++l)
@@ -468,7 +484,10 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         size_t o = 0;
         for (int l = 0; l <= L; ++l) {
             if (lb[l].alias >= 0 || lb[l].none) continue;
-            for (int h = 0; h < 2; ++h) { lb[l].off[h] = o; o += align_up(lb[l].cap * (size_t(1) << qh[h]) * elem); }
+            for (int h = 0; h < 2; ++h) {
+                lb[l].off[h] = o;
+                if (!(defer && l == fold_at && h == 0)) o += align_up(lb[l].cap * (size_t(1) << qh[h]) * elem);
+            }
         }
         for (int l = 0; l <= L; ++l)
             if (lb[l].alias >= 0) { lb[l].off[0] = lb[lb[l].alias].off[0]; lb[l].off[1] = lb[lb[l].alias].off[1]; }
@@ -561,6 +580,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     // waves, more than can be resident: short workgroups keep every channel busy to the end)
     const unsigned max_grid = (unsigned)std::max(1, c.device_cus) * (c.tuning.waves_per_cu ? std::max(1u, c.tuning.waves_per_cu / 4) : 32);
     uint64_t &n_leaf_batches = PL.n_leaf_batches;
+    // the batch that a deferred level's fold reads block A from: its offset, slot bits, and the
+    // parent slot of each slot of the batch being visited
+    size_t defer_par_off = 0;
+    int defer_par_p = 0;
+    std::vector<uint32_t> defer_par;
 
     // appends the slot tables of one batch (padded to `slots` entries)
     auto put_tables = [&](const std::vector<uint64_t> &paths, const std::vector<uint32_t> &parents, uint64_t slots) {
@@ -585,6 +609,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         const int ps = log2u(src_slots);
         std::vector<Launch> hl[2];      // each block's launches of this segment, in order
         for (int h = 0; h < 2; ++h) {
+            if (defer && h == 0 && level == fold_at) continue;   // block A's states of this level are not written
             const SegmentPlan &sp = get_segment_plan(c, h, level, p, R, fp64 ? 0 : (int)c.tuning.dense_qubits);
             if (!sp.ok) { plan_error = true; return; }
             const std::vector<BlobEntry> &be = blob_entries(sp);
@@ -784,6 +809,48 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 f.all_children = all && !plain ? 1 : 0;
                 ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem *
                            ((uint64_t(1) << fh[0]->g_ns) + (uint64_t(1) << fh[1]->g_ns));
+                if (defer) {
+                    // block A from the parent batch: per slot its parent slot, the projected bits
+                    // (the slot's path bits at the projected qubits) and the deferred gates'
+                    // entries V[x at the projected qubits][path bits] (with the segment's power of
+                    // two that its passes would have divided out)
+                    ln.defer = true;
+                    f.h[0].p_par = defer_par_p;
+                    f.h[0].dmask = dA.mask;
+                    f.h[0].nd = dA.n;
+                    ln.dst_off = defer_par_off;
+                    ln.dpar_off = tmaskv.size();
+                    for (size_t i = 0; i < nodes.size(); ++i) tmaskv.push_back(defer_par[i]);
+                    ln.dsub_off = tmaskv.size();
+                    const std::vector<uint64_t> &pid = tree.node[fold_at];
+                    for (size_t i = 0; i < nodes.size(); ++i) {
+                        uint32_t sub = 0;
+                        for (int k = 0; k < dA.n; ++k) sub |= (uint32_t)((pid[nodes[i]] >> dA.u[k]) & 1u) << dA.q[k];
+                        tmaskv.push_back(sub);
+                    }
+                    while (tmaskv.size() & 3) tmaskv.push_back(0);   // 16-byte aligned complex entries
+                    ln.dfac_off = tmaskv.size();
+                    const double e2 = std::ldexp(1.0, -c.half[0].seg_rescale_exp[fold_at]);
+                    int rank[kMaxDeferredBits];
+                    for (int k = 0; k < dA.n; ++k) rank[k] = __builtin_popcount(dA.mask & ((1u << dA.q[k]) - 1u));
+                    for (size_t i = 0; i < nodes.size(); ++i)
+                        for (uint32_t xd = 0; xd < (1u << dA.n); ++xd) {
+                            std::complex<double> v = e2;
+                            for (int k = 0; k < dA.n; ++k)
+                                v *= dA.v[k][(xd >> rank[k]) & 1u][(pid[nodes[i]] >> dA.u[k]) & 1u];
+                            if (fp64) {
+                                uint32_t w[4];
+                                const double d2[2] = {v.real(), v.imag()};
+                                std::memcpy(w, d2, 16);
+                                tmaskv.insert(tmaskv.end(), w, w + 4);
+                            } else {
+                                uint32_t w[2];
+                                const float f2[2] = {(float)v.real(), (float)v.imag()};
+                                std::memcpy(w, f2, 8);
+                                tmaskv.insert(tmaskv.end(), w, w + 2);
+                            }
+                        }
+                }
             } else {
                 FoldArgs &f = ln.fa;
                 std::memset(&f, 0, sizeof(f));
@@ -816,7 +883,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 ln.bytes = (uint64_t)n_bits * (uint64_t)nodes.size() * elem *
                            ((uint64_t(1) << fh[0]->n_s) + (uint64_t(1) << fh[1]->n_s));
             }
-            ln.dst_off = lb[own].off[0];
+            if (!ln.defer) ln.dst_off = lb[own].off[0];
             ln.src_off = lb[own].off[1];
             launches.push_back(ln);
             ++n_leaf_batches;
@@ -852,6 +919,13 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             batches.push_back(BatchRec{l + 1, toff, nslots});
             const size_t base[2] = {lb[own].off[0], lb[own].off[1]};
             add_segment(l + 1, nslots, nodes.size(), base, SRC_SAME, base, nslots, toff);
+            if (defer && l + 1 == fold_at) {
+                // in place: block A's slots still hold the parents' states
+                defer_par_off = base[0];
+                defer_par_p = log2u(nslots);
+                defer_par.resize(nodes.size());
+                for (size_t i = 0; i < nodes.size(); ++i) defer_par[i] = (uint32_t)i;
+            }
             visit(l + 1, ch, nslots);
             return;
         }
@@ -902,6 +976,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             batches.push_back(BatchRec{l + 1, toff, ns});
             const size_t dst[2] = {cb.off[0], cb.off[1]};
             add_segment(l + 1, ns, a1 - a0, dst, SRC_FANOUT, src, nslots, toff, n_low, log2u(nslots), n_read);
+            if (defer && l + 1 == fold_at) {
+                defer_par_off = src[0];
+                defer_par_p = log2u(nslots);
+                defer_par = par;
+            }
             visit(l + 1, ch, ns);
             if (plan_error) return;
         }
@@ -1321,6 +1400,12 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 GFoldArgs f = ln.gfa;
                 f.h[0].par = buf + ln.dst_off;
                 f.h[1].par = buf + ln.src_off;
+                if (ln.defer) {
+                    const uint32_t *tm = (const uint32_t *)(ws + off_tmask);
+                    f.h[0].par_slot = tm + ln.dpar_off;
+                    f.h[0].dsub = tm + ln.dsub_off;
+                    f.h[0].dfac = tm + ln.dfac_off;
+                }
                 for (int h = 0; h < 2; ++h) {
                     f.h[h].tab = ws + off_blob + fold_tab_off[h];
                     f.h[h].off = (const uint32_t *)(ws + off_blob + PL.fold_off_off[h]);

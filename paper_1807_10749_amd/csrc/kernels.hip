@@ -1191,7 +1191,7 @@ hipError_t launch_fold(bool fp64, int nb, const FoldArgs &g, hipStream_t s)
 // ordered branch bits first, so every accumulator index is a compile-time constant.  Products
 // with V and the sums over column patterns run in the state precision (the work of the gates the
 // fold replaces), the products c_A c_B and all sums over slots in FP64.
-template <typename T, int NB, bool WIDE, bool MASKED>
+template <typename T, int NB, bool WIDE, bool MASKED, bool DEFER>
 __global__ __launch_bounds__(256) void gfold_kernel(GFoldArgs g)
 {
     using C = typename Cplx<T>::type;
@@ -1221,15 +1221,19 @@ __global__ __launch_bounds__(256) void gfold_kernel(GFoldArgs g)
             trow[h] = (const C *)f.tab + ((uint64_t)pext32(x, f.tmask) << f.n_s);
             base[h] = (const C *)f.par + ((uint64_t)(x & ~f.smask) << g.p);
         }
-        // w[b] = sum_r V[x_T', b | r << NB] * row(b | r << NB)[slot] for one block
-        auto accumulate = [&](const GFoldHalf &f, const C *bs, const C *tr, uint32_t s, C (&w)[V]) {
+        // deferred block-A level: x_A without S' and the projected qubits, and x at those qubits
+        const uint32_t xa_rest = DEFER ? g.xa[j] & ~g.h[0].smask & ~g.h[0].dmask : 0u;
+        const uint32_t xa_d = DEFER ? pext32(g.xa[j], g.h[0].dmask) : 0u;
+        // w[b] = sum_r V[x_T', b | r << NB] * row(b | r << NB)[slot] for one block; bs points at
+        // the slot's row (x & ~smask), consecutive rows are 2^sh elements apart
+        auto accumulate = [&](const GFoldHalf &f, const C *bs, int sh, const C *tr, C (&w)[V]) {
 #pragma unroll
             for (int b = 0; b < V; ++b) { w[b].x = T(0); w[b].y = T(0); }
             const uint32_t nr = 1u << f.n_rest;
             for (uint32_t r = 0; r < nr; ++r) {
                 C t[V];
 #pragma unroll
-                for (int b = 0; b < V; ++b) t[b] = bs[((uint64_t)f.off[b | (r << NB)] << g.p) + s];
+                for (int b = 0; b < V; ++b) t[b] = bs[(uint64_t)f.off[b | (r << NB)] << sh];
 #pragma unroll
                 for (int b = 0; b < V; ++b) {
                     const C v = tr[b | (r << NB)];
@@ -1240,8 +1244,21 @@ __global__ __launch_bounds__(256) void gfold_kernel(GFoldArgs g)
         };
         for (uint32_t s = sl; s < g.n_slots; s += L) {
             C wb[V], wa[V];
-            accumulate(g.h[1], base[1], trow[1], s, wb);
-            accumulate(g.h[0], base[0], trow[0], s, wa);
+            accumulate(g.h[1], base[1] + s, g.p, trow[1], wb);
+            if (DEFER) {
+                const GFoldHalf &f = g.h[0];
+                const C *bs = (const C *)f.par + ((uint64_t)(xa_rest | f.dsub[s]) << f.p_par) + f.par_slot[s];
+                accumulate(f, bs, f.p_par, trow[0], wa);
+                const C fac = ((const C *)f.dfac)[((uint64_t)s << f.nd) + xa_d];
+#pragma unroll
+                for (int b = 0; b < V; ++b) {
+                    const T x = wa[b].x, y = wa[b].y;
+                    wa[b].x = x * fac.x - y * fac.y;
+                    wa[b].y = x * fac.y + y * fac.x;
+                }
+            } else {
+                accumulate(g.h[0], base[0] + s, g.p, trow[0], wa);
+            }
             // block B: the descendant's Z^b signs summed over the column patterns' branch bits
 #pragma unroll
             for (int stp = 1; stp < V; stp <<= 1)
@@ -1281,16 +1298,23 @@ __global__ __launch_bounds__(256) void gfold_kernel(GFoldArgs g)
     }
 }
 
+template <typename T, int NB, bool DEFER>
+static void gfold_launch_d(const GFoldArgs &g, unsigned blocks, bool wide, hipStream_t s)
+{
+    if (g.all_children) {
+        if (wide) gfold_kernel<T, NB, true, false, DEFER><<<blocks, 256, 0, s>>>(g);
+        else gfold_kernel<T, NB, false, false, DEFER><<<blocks, 256, 0, s>>>(g);
+    } else {
+        if (wide) gfold_kernel<T, NB, true, true, DEFER><<<blocks, 256, 0, s>>>(g);
+        else gfold_kernel<T, NB, false, true, DEFER><<<blocks, 256, 0, s>>>(g);
+    }
+}
+
 template <typename T, int NB>
 static void gfold_launch(const GFoldArgs &g, unsigned blocks, bool wide, hipStream_t s)
 {
-    if (g.all_children) {
-        if (wide) gfold_kernel<T, NB, true, false><<<blocks, 256, 0, s>>>(g);
-        else gfold_kernel<T, NB, false, false><<<blocks, 256, 0, s>>>(g);
-    } else {
-        if (wide) gfold_kernel<T, NB, true, true><<<blocks, 256, 0, s>>>(g);
-        else gfold_kernel<T, NB, false, true><<<blocks, 256, 0, s>>>(g);
-    }
+    if (g.h[0].par_slot) gfold_launch_d<T, NB, true>(g, blocks, wide, s);
+    else gfold_launch_d<T, NB, false>(g, blocks, wide, s);
 }
 
 hipError_t launch_gfold(bool fp64, int nb, const GFoldArgs &g, hipStream_t s)
@@ -1300,6 +1324,10 @@ hipError_t launch_gfold(bool fp64, int nb, const GFoldArgs &g, hipStream_t s)
     for (int h = 0; h < 2; ++h)
         if (!g.h[h].par || !g.h[h].tab || !g.h[h].off || g.h[h].n_rest < 0 || g.h[h].n_s != nb + g.h[h].n_rest)
             return hipErrorInvalidValue;
+    if (g.h[1].par_slot) return hipErrorInvalidValue;   // only block A's level is deferred
+    if (g.h[0].par_slot && (!g.h[0].dsub || !g.h[0].dfac || g.h[0].p_par < 0 || g.h[0].p_par > 31 ||
+                            g.h[0].nd < 1 || g.h[0].nd > 4 || (g.h[0].dmask & g.h[0].smask)))
+        return hipErrorInvalidValue;
     const uint64_t P = (uint64_t)1 << g.p;
     const bool wide = P >= 64;
     const uint64_t per_wave = wide ? 1 : 64 / P;

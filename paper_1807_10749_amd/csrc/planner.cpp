@@ -286,6 +286,46 @@ int fold_depth(const Circuit &c)
     return best ? best : best_gen;
 }
 
+DeferredLevel deferred_level(const Circuit &c, int h, int level)
+{
+    DeferredLevel d;
+    if (level < 1 || level >= (int)c.half[h].segments.size()) return d;
+    const std::complex<double> I(0.0, 1.0), w(std::sqrt(0.5), std::sqrt(0.5));
+    int slot_of[64];
+    for (int q = 0; q < 64; ++q) slot_of[q] = -1;
+    for (const HalfOp &op : c.half[h].segments[level]) {
+        if (op.kind == HK_PROJ) {
+            // the projector must come first on its qubit, once
+            if (slot_of[op.q0] >= 0 || d.n == kMaxDeferredBits) return DeferredLevel();
+            const int i = d.n++;
+            slot_of[op.q0] = i;
+            d.q[i] = op.q0;
+            d.u[i] = op.bit;
+            d.mask |= 1u << op.q0;
+            d.v[i][0][0] = d.v[i][1][1] = 1.0;
+            d.v[i][0][1] = d.v[i][1][0] = 0.0;
+            continue;
+        }
+        std::complex<double> g[2][2];
+        switch (op.kind) {
+        case HK_H: g[0][0] = 1.0; g[0][1] = 1.0; g[1][0] = 1.0; g[1][1] = -1.0; break;
+        case HK_X: g[0][0] = 1.0; g[0][1] = -I; g[1][0] = -I; g[1][1] = 1.0; break;
+        case HK_Y: g[0][0] = 1.0; g[0][1] = -1.0; g[1][0] = 1.0; g[1][1] = 1.0; break;
+        case HK_T: g[0][0] = 1.0; g[0][1] = 0.0; g[1][0] = 0.0; g[1][1] = w; break;
+        default: return DeferredLevel();          // two-qubit, other branch operators
+        }
+        const int i = op.q0 < 64 ? slot_of[op.q0] : -1;
+        if (i < 0) return DeferredLevel();        // a gate on a qubit without a projector
+        std::complex<double> m[2][2];
+        for (int r = 0; r < 2; ++r)
+            for (int s = 0; s < 2; ++s) m[r][s] = g[r][0] * d.v[i][0][s] + g[r][1] * d.v[i][1][s];
+        for (int r = 0; r < 2; ++r)
+            for (int s = 0; s < 2; ++s) d.v[i][r][s] = m[r][s];
+    }
+    d.ok = d.n > 0;
+    return d;
+}
+
 bool fold_general(const Circuit &c, int FD)
 {
     if (FD < 1) return false;

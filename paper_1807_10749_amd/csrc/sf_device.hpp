@@ -213,6 +213,17 @@ struct GFoldHalf {
     uint32_t smask, tmask;        // local qubits of S', of T'
     int32_t n_s;                  // |S'|
     int32_t n_rest;               // |S'| - nb
+    // Deferred level (block A, par_slot != nullptr): par is the batch of the level above (2^p_par
+    // slots); gather slot s reads parent slot par_slot[s] at the rows with the projected qubits
+    // (dmask) set to dsub[s], and its sums are multiplied by dfac[s * 2^nd + pext(x, dmask)]
+    // (complex, state precision): the entry of the deferred one-qubit gates.
+    const uint32_t *par_slot;
+    const uint32_t *dsub;
+    const void *dfac;
+    uint32_t dmask;
+    int32_t p_par;
+    int32_t nd;
+    int32_t pad;
 };
 
 struct GFoldArgs {

@@ -168,6 +168,21 @@ bool path_is_live(const Circuit &c, uint64_t id);
 // Whether those FD levels use the general form (LeafFold::gen_ok) rather than the one whose
 // non-diagonal gates act on branch qubits only.
 bool fold_general(const Circuit &c, int FD);
+// A level whose block-h operations are the projectors P_s of its crossing CZs (block A side),
+// each the first operation on its qubit, followed only by one-qubit gates on the projected qubits:
+// its node states are V P_s (parent state), V a tensor product of 2x2 matrices on those qubits,
+// so the gather can read the parent's rows with the projected bits set to s and multiply by V's
+// entry instead of reading states written for the level (the executor's deferred level).
+constexpr int kMaxDeferredBits = 4;
+struct DeferredLevel {
+    bool ok = false;
+    int n = 0;                                   // projected qubits (one path bit each)
+    int q[kMaxDeferredBits] = {0};               // local qubit
+    int u[kMaxDeferredBits] = {0};               // its path bit
+    std::complex<double> v[kMaxDeferredBits][2][2];   // V_i[out][in], the unnormalised gates' product
+    uint32_t mask = 0;                           // local qubits q[]
+};
+DeferredLevel deferred_level(const Circuit &c, int h, int level);
 // dense_m: 0 = register/lane passes only; 2..4 = also fuse windows of up to dense_m qubits
 // into dense 4-qubit blocks applied on matrix cores.
 const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m = 0);

@@ -286,6 +286,7 @@ int set_tuning(sf_circuit_t *c, const sf_tuning_t *t)
     if (t->fold_levels > 62) return fail(SF_ERR_INVALID, "fold_levels must be at most 62");
     if (t->chain_passes > 1) return fail(SF_ERR_INVALID, "chain_passes must be 0 or 1");
     if (t->no_row_skip > 1) return fail(SF_ERR_INVALID, "no_row_skip must be 0 or 1");
+    if (t->no_defer > 1) return fail(SF_ERR_INVALID, "no_defer must be 0 or 1");
     auto pow2ok = [](uint32_t v) { return v == 0 || (v & (v - 1)) == 0; };
     if (!pow2ok(t->leaf_batch) || !pow2ok(t->max_slots)) return fail(SF_ERR_INVALID, "batch sizes must be powers of two");
     c->tuning = *t;
@@ -361,9 +362,9 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
                     for (int F = 1; F <= max_fold; ++F) {     // F trailing levels folded into the gather
                         const int Fp = max_fold > 1 ? max_fold - 1 : 1;
                         if (F != max_fold && F != Fp) continue;
-                        cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0, (uint32_t)F, start.chain_passes, start.no_row_skip});
+                        cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0, (uint32_t)F, start.chain_passes, start.no_row_skip, start.no_defer});
                     }
-                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1, 0, start.chain_passes, start.no_row_skip});
+                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1, 0, start.chain_passes, start.no_row_skip, start.no_defer});
                 }
         // rank by the planned cost
         std::vector<std::pair<double, size_t>> ranked;
@@ -425,12 +426,12 @@ int save_tuning_cache(const char *path)
         FILE *f = std::fopen(path, "w");
         if (!f) return fail(SF_ERR_INVALID, std::string("cannot write ") + path);
         std::fprintf(f, "# sfpath tuning cache: key reg_qubits leaf_batch max_slots waves_per_cu dense_qubits "
-                        "no_leaf_fold fold_levels chain_passes no_row_skip\n");
+                        "no_leaf_fold fold_levels chain_passes no_row_skip no_defer\n");
         for (const auto &kv : g_tune_cache) {
             const sf_tuning_t &t = kv.second;
-            std::fprintf(f, "%s %u %u %u %u %u %u %u %u %u\n", kv.first.c_str(), t.reg_qubits, t.leaf_batch,
+            std::fprintf(f, "%s %u %u %u %u %u %u %u %u %u %u\n", kv.first.c_str(), t.reg_qubits, t.leaf_batch,
                          t.max_slots, t.waves_per_cu, t.dense_qubits, t.no_leaf_fold, t.fold_levels, t.chain_passes,
-                         t.no_row_skip);
+                         t.no_row_skip, t.no_defer);
         }
         const bool bad = std::ferror(f) != 0;
         if (std::fclose(f) != 0 || bad) return fail(SF_ERR_INVALID, std::string("cannot write ") + path);
@@ -453,12 +454,15 @@ int load_tuning_cache(const char *path, uint32_t *n_loaded)
             char key[512];
             sf_tuning_t t{};
             char extra;
-            // entries written before chain_passes / no_row_skip existed have fields less (read as 0)
-            const int got_n = std::sscanf(line, "%511s %u %u %u %u %u %u %u %u %u %c", key, &t.reg_qubits,
+            // entries written before chain_passes / no_row_skip / no_defer existed have fields less
+            // (read as 0)
+            const int got_n = std::sscanf(line, "%511s %u %u %u %u %u %u %u %u %u %u %c", key, &t.reg_qubits,
                                           &t.leaf_batch, &t.max_slots, &t.waves_per_cu, &t.dense_qubits,
-                                          &t.no_leaf_fold, &t.fold_levels, &t.chain_passes, &t.no_row_skip, &extra);
-            if (got_n < 8 || got_n > 10 || t.reg_qubits > 5 || t.dense_qubits == 1 || t.dense_qubits > 4 ||
-                t.no_leaf_fold > 1 || t.fold_levels > 62 || t.chain_passes > 1 || t.no_row_skip > 1) {
+                                          &t.no_leaf_fold, &t.fold_levels, &t.chain_passes, &t.no_row_skip,
+                                          &t.no_defer, &extra);
+            if (got_n < 8 || got_n > 11 || t.reg_qubits > 5 || t.dense_qubits == 1 || t.dense_qubits > 4 ||
+                t.no_leaf_fold > 1 || t.fold_levels > 62 || t.chain_passes > 1 || t.no_row_skip > 1 ||
+                t.no_defer > 1) {
                 std::fclose(f);
                 return fail(SF_ERR_INVALID, std::string(path) + ":" + std::to_string(lineno) + ": malformed entry");
             }
@@ -575,6 +579,13 @@ int describe_plan(sf_circuit_t *c, char *out, size_t cap)
                     std::snprintf(buf, sizeof buf, " %s tile qubits 0x%x, rows vary 0x%x (%d outside);", h ? "B" : "A",
                                   inside, vary, __builtin_popcount(vary & ~inside));
                     s += buf;
+                    if (h == 0 && FDr == 1 && sf::fold_general(*c, FDr) && !c->tuning.no_defer) {
+                        const sf::DeferredLevel d = sf::deferred_level(*c, 0, l);
+                        if (d.ok && !(d.mask & vary)) {
+                            std::snprintf(buf, sizeof buf, " A deferred (projected qubits 0x%x);", d.mask);
+                            s += buf;
+                        }
+                    }
                 }
                 s += "\n";
             }
