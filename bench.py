@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--max-paths", type=int, default=0,
                     help="time only the first N paths of the request (a bounded sample, for profiling)")
     ap.add_argument("--tuning", default="",
-                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes[,no_row_skip[,no_defer]]]]]]] "
+                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes[,no_row_skip[,no_defer[,no_chain_merge]]]]]]]] "
                          "(skips autotune)")
     ap.add_argument("--ceilings-only", action="store_true",
                     help="only measure the bandwidth ceilings (and the read rate per buffer size) and print them")
@@ -116,7 +116,8 @@ def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure
         chain = vals[6] if len(vals) > 6 else 0
         sf.set_tuning(c.handle, reg_qubits=r, leaf_batch=lb, waves_per_cu=wpc, dense_qubits=dense,
                       no_leaf_fold=nofold, fold_levels=flev, chain_passes=chain,
-                      no_row_skip=vals[7] if len(vals) > 7 else 0, no_defer=vals[8] if len(vals) > 8 else 0)
+                      no_row_skip=vals[7] if len(vals) > 7 else 0, no_defer=vals[8] if len(vals) > 8 else 0,
+                      no_chain_merge=vals[9] if len(vals) > 9 else 0)
         tuned = sf.get_tuning(c.handle)
     elif autotune:
         tuned = sf.autotune(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,

@@ -203,6 +203,10 @@ typedef struct {
                                 qubits, that level's block-A states are not written: the fold
                                 reads the level above with the projected bits set and applies
                                 the gates itself; 1: always write them */
+    uint32_t no_chain_merge; /* 0: a run of consecutive chain levels (every node one child) is
+                                planned as one segment, its operations sharing passes, when that
+                                takes no more passes than planning the levels one by one (the
+                                root joins the run below it); 1: one segment per level */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);

@@ -600,9 +600,11 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     // n_real: slots in use (the rest of the nslots pad the batch to a power of two); src_read:
     // parent slots a fan-out actually reads (distinct parents of its children), for the byte
     // count, 0 = all src_slots
+    // level0 < level: the segments of levels level0..level as one (chain levels, chain_run)
     auto add_segment = [&](int level, uint64_t nslots, uint64_t n_real, const size_t dst[2], int mode,
                            const size_t src[2], uint64_t src_slots, size_t table_off, int n_low = 0,
-                           int low_first = 0, uint64_t src_read = 0) {
+                           int low_first = 0, uint64_t src_read = 0, int level0 = -1) {
+        const int lev0 = level0 < 0 ? level : level0;
         const int p = log2u(nslots);
         const uint64_t slots_real = n_real && n_real < nslots ? n_real : 0;
         const uint64_t used = slots_real ? slots_real : nslots;
@@ -610,7 +612,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         std::vector<Launch> hl[2];      // each block's launches of this segment, in order
         for (int h = 0; h < 2; ++h) {
             if (defer && h == 0 && level == fold_at) continue;   // block A's states of this level are not written
-            const SegmentPlan &sp = get_segment_plan(c, h, level, p, R, fp64 ? 0 : (int)c.tuning.dense_qubits);
+            const SegmentPlan &sp = get_segment_plan_range(c, h, lev0, level, p, R, fp64 ? 0 : (int)c.tuning.dense_qubits);
             if (!sp.ok) { plan_error = true; return; }
             const std::vector<BlobEntry> &be = blob_entries(sp);
             const int n_ext = p + qh[h];
@@ -742,6 +744,33 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             }
             if (i < hl[1].size()) launches.push_back(hl[1][i]);
         }
+    };
+
+    // Chain levels: below level l every node has one child, evolved in place in the same slots.
+    // Returns the deepest level last such that levels l+1..last are all chain levels (stopping
+    // before a deferred level), with nodes[] advanced to it; the segments of levels first..last
+    // then run as one plan when that takes no more passes than planning them one by one.
+    auto chain_run = [&](int l, std::vector<uint32_t> &nodes) {
+        int last = l;
+        while (last + 1 <= L && lb[last + 1].alias >= 0 && !(defer && last + 1 == fold_at)) {
+            const std::vector<uint64_t> &fc = tree.first_child[last];
+            for (uint32_t &x : nodes) x = (uint32_t)fc[x];
+            ++last;
+        }
+        return last;
+    };
+    auto merge_ok = [&](int first, int last, uint64_t nslots) {
+        if (first == last) return true;
+        if (c.tuning.no_chain_merge) return false;
+        const int p = log2u(nslots), dm = fp64 ? 0 : (int)c.tuning.dense_qubits;
+        size_t merged = 0, apart = 0;
+        for (int h = 0; h < 2; ++h) {
+            const SegmentPlan &m = get_segment_plan_range(c, h, first, last, p, R, dm);
+            if (!m.ok) return false;
+            merged += m.passes.size();
+            for (int lv = first; lv <= last; ++lv) apart += get_segment_plan(c, h, lv, p, R, dm).passes.size();
+        }
+        return merged <= apart;
     };
 
     // nodes: node indices of this batch in slot order
@@ -910,23 +939,29 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         const std::vector<uint64_t> &fc = tree.first_child[l];
         const std::vector<uint64_t> &cnode = tree.node[l + 1];
         if (lb[l + 1].alias >= 0) {
-            // chain level: one child per node, evolved in place in the same slots
+            // chain level(s): one child per node, evolved in place in the same slots; a run of
+            // them is planned as one segment when that saves passes
             std::vector<uint32_t> ch(nodes.size());
+            for (size_t i = 0; i < nodes.size(); ++i) ch[i] = (uint32_t)fc[nodes[i]];
+            std::vector<uint32_t> deep(ch);
+            int last = chain_run(l + 1, deep);
+            if (!merge_ok(l + 1, last, nslots)) last = l + 1;
+            else ch.swap(deep);
             std::vector<uint64_t> pv(nodes.size());
             std::vector<uint32_t> pz(nodes.size(), 0);
-            for (size_t i = 0; i < nodes.size(); ++i) { ch[i] = (uint32_t)fc[nodes[i]]; pv[i] = cnode[ch[i]]; }
+            for (size_t i = 0; i < nodes.size(); ++i) pv[i] = tree.node[last][ch[i]];
             const size_t toff = put_tables(pv, pz, nslots);
-            batches.push_back(BatchRec{l + 1, toff, nslots});
+            batches.push_back(BatchRec{last, toff, nslots});
             const size_t base[2] = {lb[own].off[0], lb[own].off[1]};
-            add_segment(l + 1, nslots, nodes.size(), base, SRC_SAME, base, nslots, toff);
-            if (defer && l + 1 == fold_at) {
+            add_segment(last, nslots, nodes.size(), base, SRC_SAME, base, nslots, toff, 0, 0, 0, l + 1);
+            if (defer && last == fold_at) {
                 // in place: block A's slots still hold the parents' states
                 defer_par_off = base[0];
                 defer_par_p = log2u(nslots);
                 defer_par.resize(nodes.size());
                 for (size_t i = 0; i < nodes.size(); ++i) defer_par[i] = (uint32_t)i;
             }
-            visit(l + 1, ch, nslots);
+            visit(last, ch, nslots);
             return;
         }
         // Slot order of the children.  Full fan-outs (every parent has all 2^n_cut children) go
@@ -1030,11 +1065,18 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     }
     if (n_paths && !hit) {
         const uint64_t ns0 = std::max<uint64_t>(1, min_slots);
-        const size_t toff = put_tables(std::vector<uint64_t>{0}, std::vector<uint32_t>{0}, ns0);
-        batches.push_back(BatchRec{0, toff, ns0});
+        // the root and the chain levels below it (one node each) as one segment when that saves passes
+        std::vector<uint32_t> deep{0};
+        int last = chain_run(0, deep);
+        if (!merge_ok(0, last, ns0)) {
+            last = 0;
+            deep.assign(1, 0);
+        }
+        const size_t toff = put_tables(std::vector<uint64_t>{tree.node[last][deep[0]]}, std::vector<uint32_t>{0}, ns0);
+        batches.push_back(BatchRec{last, toff, ns0});
         const size_t base0[2] = {lb[0].off[0], lb[0].off[1]};
-        add_segment(0, ns0, 1, base0, SRC_INIT, base0, ns0, toff);
-        visit(0, std::vector<uint32_t>{0}, ns0);
+        add_segment(last, ns0, 1, base0, SRC_INIT, base0, ns0, toff, 0, 0, 0, 0);
+        visit(last, deep, ns0);
     }
     if (plan_error) { err = "internal: a segment could not be scheduled into passes"; return SF_ERR_UNSUPPORTED; }
     if (blob.size() > blob_budget) { err = "internal: pass programs exceed their reservation"; return SF_ERR_UNSUPPORTED; }

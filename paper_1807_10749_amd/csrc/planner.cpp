@@ -718,9 +718,11 @@ std::vector<float> dense_matrix(const std::vector<HalfOp> &ops, const int qs[4])
 
 }  // namespace
 
-// The passes of one block over one tree level.  max_lq: a pass may keep up to this many qubits
-// (0..2) in lane bits 5 and 4 when the slots fill all six lane bits (PassArgs::lane_qpos).
-static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, int R, int dense_m, int max_lq)
+// The passes of one block over tree levels level0..level (usually one level).  max_lq: a pass may
+// keep up to this many qubits (0..2) in lane bits 5 and 4 when the slots fill all six lane bits
+// (PassArgs::lane_qpos).
+static SegmentPlan plan_segment(const Circuit &c, int half, int level0, int level, int p, int R, int dense_m,
+                                int max_lq)
 {
     const HalfProgram &hp = c.half[half];
     const int q = hp.q;
@@ -734,16 +736,20 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
     const int R_eff = std::max(0, std::min({R, n_ext - 6, n_free}));
 
     SegmentPlan sp;
-    std::vector<HalfOp> rem = hp.segments[level];
+    std::vector<HalfOp> rem;
+    int seg_exp = 0;
+    for (int l = level0; l <= level; ++l) {
+        rem.insert(rem.end(), hp.segments[l].begin(), hp.segments[l].end());
+        seg_exp += hp.seg_rescale_exp[l];
+    }
     // rescaling inside the segment: keep the running norm gain below 2^16
     int carry = 0;
-    for (int l = 0; l < level; ++l) {
+    for (int l = 0; l < level0; ++l) {
         int nn = 0;
         for (const HalfOp &op : hp.segments[l]) if (has_gain(op.kind)) ++nn;
         carry = (carry + nn) % 2;
     }
     int taken = 0;
-    int seg_exp = hp.seg_rescale_exp[level];
     // An iSWAP whose two qubits cannot both sit in one pass (fewer free registers and lane-qubit
     // slots than it needs) is applied as H_b H_a CZ H_a H_b CZ H_b H_a followed by S = T^2 on both
     // qubits, which is the iSWAP exactly; its six unnormalised H gates gain a factor 8, divided
@@ -787,7 +793,7 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
                      zs.end());
         }
     };
-    for (int l = 0; l < level; ++l)
+    for (int l = 0; l < level0; ++l)
         for (const HalfOp &op : hp.segments[l]) zupdate(op);
 
     bool first = true;
@@ -1001,22 +1007,27 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level, int p, in
     return sp;
 }
 
-const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m)
+const SegmentPlan &get_segment_plan_range(Circuit &c, int half, int first, int last, int p, int R, int dense_m)
 {
-    const auto key = std::make_tuple(half, level, p, R, dense_m);
+    const auto key = std::make_tuple(half, first, last, p, R, dense_m);
     auto it = c.plan_cache.find(key);
     if (it != c.plan_cache.end()) return it->second;
     // a qubit in a lane bit splits the contiguous runs of a load (two of 32 amplitudes, or four
     // of 16 = one cache line each with two): use one or two only where that saves a pass
-    SegmentPlan sp = plan_segment(c, half, level, p, R, dense_m, 0);
+    SegmentPlan sp = plan_segment(c, half, first, last, p, R, dense_m, 0);
     const int q = c.half[half].q;
     if (p >= 6 || q > 6 - p)
         for (int m = 1; m <= 2 && (p >= 6 || 6 - p - m >= 0); ++m) {
-            SegmentPlan lq = plan_segment(c, half, level, p, R, dense_m, m);
+            SegmentPlan lq = plan_segment(c, half, first, last, p, R, dense_m, m);
             if (lq.ok && (!sp.ok || lq.passes.size() < sp.passes.size())) sp = std::move(lq);
         }
     auto res = c.plan_cache.emplace(key, std::move(sp));
     return res.first->second;
+}
+
+const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m)
+{
+    return get_segment_plan_range(c, half, level, level, p, R, dense_m);
 }
 
 }  // namespace sf

@@ -144,7 +144,8 @@ struct Circuit {
 
     // tuning
     sf_tuning_t tuning{};
-    std::map<std::tuple<int, int, int, int, int>, SegmentPlan> plan_cache;  // (half, level, p, R, dense)
+    // (half, first level, last level, p, R, dense)
+    std::map<std::tuple<int, int, int, int, int, int>, SegmentPlan> plan_cache;
 
     // device resources owned by the circuit
     void *dev_ws = nullptr;
@@ -186,6 +187,10 @@ DeferredLevel deferred_level(const Circuit &c, int h, int level);
 // dense_m: 0 = register/lane passes only; 2..4 = also fuse windows of up to dense_m qubits
 // into dense 4-qubit blocks applied on matrix cores.
 const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int R, int dense_m = 0);
+// The passes of the segments of levels first..last planned as one operation sequence (a chain
+// of tree levels whose nodes have one child each run in the same slots, so their operations can
+// share passes across the level boundaries).
+const SegmentPlan &get_segment_plan_range(Circuit &c, int half, int first, int last, int p, int R, int dense_m = 0);
 
 // sfpath.cpp: run_paths' argument checks and execution on a given workspace of any size (the
 // entry point without allocations), and the thread's last_error() message.
