@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--max-paths", type=int, default=0,
                     help="time only the first N paths of the request (a bounded sample, for profiling)")
     ap.add_argument("--tuning", default="",
-                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes[,no_row_skip[,no_defer[,no_chain_merge]]]]]]]] "
+                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes[,no_row_skip[,no_defer[,no_chain_merge[,jit]]]]]]]]] "
                          "(skips autotune)")
     ap.add_argument("--ceilings-only", action="store_true",
                     help="only measure the bandwidth ceilings (and the read rate per buffer size) and print them")
@@ -68,10 +68,12 @@ def progress(msg):
     print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
-def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure=4, ws_frac=0.85):
+def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure=4, ws_frac=0.85, jit=1):
     """Set up one request the way the benchmark times it: circuit and cut, path ids (all,
     an aligned block or a seeded f-sample), bitstrings, output and workspace resident on the
-    device, and the tuning (fixed, autotuned on this request, or the library default)."""
+    device, and the tuning (fixed, autotuned on this request, or the library default).  jit: the
+    passes run kernels compiled for their programs (tuning jit; compiled by the first step, which
+    the warm-up covers)."""
     import torch
     from paper_1807_10749_amd import binding as sf
     from workload import CONFIGS, make_workload, workload_block
@@ -117,9 +119,10 @@ def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure
         sf.set_tuning(c.handle, reg_qubits=r, leaf_batch=lb, waves_per_cu=wpc, dense_qubits=dense,
                       no_leaf_fold=nofold, fold_levels=flev, chain_passes=chain,
                       no_row_skip=vals[7] if len(vals) > 7 else 0, no_defer=vals[8] if len(vals) > 8 else 0,
-                      no_chain_merge=vals[9] if len(vals) > 9 else 0)
+                      no_chain_merge=vals[9] if len(vals) > 9 else 0, jit=vals[10] if len(vals) > 10 else jit)
         tuned = sf.get_tuning(c.handle)
     elif autotune:
+        sf.set_tuning(c.handle, jit=jit)
         tuned = sf.autotune(c.handle, ids, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,
                             n_measure=n_measure)
     return {"cfg": cfg, "c": c, "gates": gates, "bits": bits, "ids": ids, "begin": begin, "npaths": npaths,

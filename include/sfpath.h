@@ -207,6 +207,14 @@ typedef struct {
                                 planned as one segment, its operations sharing passes, when that
                                 takes no more passes than planning the levels one by one (the
                                 root joins the run below it); 1: one segment per level */
+    uint32_t jit;            /* 0: the pass kernels interpret each pass program (read per tile from
+                                LDS); 1: every pass whose program holds only one-qubit gates and
+                                diagonal groups (no per-path flips, no in-block iSWAP, no dense
+                                block) runs a kernel compiled at run time for that program (hiprtc,
+                                a few seconds per distinct set of programs, cached for the
+                                process): the gates' kinds and positions become constants, which
+                                removes the interpreter's per-operation register copies and
+                                selects.  Results agree with the interpreted passes to rounding */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);
@@ -286,6 +294,9 @@ typedef struct {
     double row_mask_frac[2];    /* per block: fraction of the tiles of its last pass before the path sum
                                    that were computed (the rest hold no row a requested bitstring reads;
                                    tuning no_row_skip); 0 when that pass computed every tile */
+    uint64_t n_jit_passes;      /* sweep passes run by kernels compiled for their program (tuning jit) */
+    double jit_compile_ms;      /* host time this call spent compiling such kernels (0 when all were
+                                   compiled by earlier calls of the process) */
 } sf_run_stats_t;
 
 int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);

@@ -21,6 +21,7 @@
 #include <mutex>
 #include <tuple>
 
+#include "jit.hpp"
 #include "kernels.hpp"
 #include "sf_host.hpp"
 
@@ -109,6 +110,8 @@ struct Launch {
     size_t table_off = 0;     // element offset of the batch's slot tables
     unsigned grid = 1;
     uint64_t bytes = 0;
+    std::string jit_prog;         // PASS with tuning jit: its program as code (jit_program; "" = not covered)
+    hipFunction_t jit_fn = nullptr;   // PASS: the compiled kernel of this pass (of the pair it heads)
 };
 
 struct BatchRec { int level; size_t table_off; uint64_t slots; };
@@ -670,6 +673,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                     a.n_skip = (int)skip.size();
                     for (size_t t = 0; t < skip.size(); ++t) a.skip_pos[t] = skip[t];
                 }
+                if (c.tuning.jit) ln.jit_prog = jit_program(pp);
                 ln.dst_off = dst[h];
                 ln.src_off = dst[h];
                 if (i == 0 && mode == SRC_INIT) {
@@ -1214,6 +1218,31 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         return SF_OK;
     }
     if (n_paths && tables_bytes > PL.rowmask_off) { err = "internal: slot tables exceed their reservation"; return SF_ERR_UNSUPPORTED; }
+
+    // Compiled passes (tuning jit): every pass launch outside a chain whose program (both
+    // programs of a pair) the compiled form covers gets the kernel compiled for it; a repeated
+    // request keeps them with its plan, other requests with the same programs find them in the
+    // process-wide cache.
+    if (c.tuning.jit && n_paths) {
+        std::vector<std::string> srcs;
+        std::vector<size_t> at;
+        for (size_t li = 0; li < launches.size(); ++li) {
+            Launch &ln = launches[li];
+            if (ln.kind != Launch::PASS || in_chain[li] || (li > 0 && launches[li - 1].pair_next)) continue;
+            if (ln.jit_fn || ln.jit_prog.empty()) continue;
+            const Launch *l2 = ln.pair_next ? &launches[li + 1] : nullptr;
+            if (l2 && l2->jit_prog.empty()) continue;
+            auto zs = [&](const Launch &x) { return x.zskip && !fp64 && (x.R == 4 || x.R == 5); };
+            srcs.push_back(jit_kernel(fp64, ln.R, ln.jit_prog, zs(ln), l2 ? l2->R : 0, l2 ? l2->jit_prog : std::string(),
+                                      l2 ? zs(*l2) : false));
+            at.push_back(li);
+        }
+        std::vector<hipFunction_t> fns;
+        double ms = 0;
+        if (int rc = jit_kernels(srcs, fns, &ms, err)) return rc;
+        for (size_t i = 0; i < at.size(); ++i) launches[at[i]].jit_fn = fns[i];
+        c.stats.jit_compile_ms += ms;
+    }
     if (cacheable && !hit) {
         cache.valid = false;
         cache.plan = fresh;
@@ -1403,9 +1432,18 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             if (ln.kind == Launch::PASS && ln.pair_next) {
                 const Launch &l2 = launches[li + 1];
                 timed(0);
-                if ((he = launch_pass_pair(fp64, ln.R, ln.flip, ln.zskip || l2.zskip, pass_args(ln), ln.grid,
-                                           pass_args(l2), l2.grid, stream)) != hipSuccess)
+                if (ln.jit_fn) {
+                    PassArgs a0 = pass_args(ln), a1 = pass_args(l2);
+                    uint32_t g0 = ln.grid;
+                    void *kp[] = {&a0, &a1, &g0};
+                    if ((he = hipModuleLaunchKernel(ln.jit_fn, ln.grid + l2.grid, 1, 1, 256, 1, 1, 0, stream, kp,
+                                                    nullptr)) != hipSuccess)
+                        return dev_err("compiled pass", he);
+                    c.stats.n_jit_passes += 2;
+                } else if ((he = launch_pass_pair(fp64, ln.R, ln.flip, ln.zskip || l2.zskip, pass_args(ln), ln.grid,
+                                                  pass_args(l2), l2.grid, stream)) != hipSuccess) {
                     return dev_err("pass", he);
+                }
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes + l2.bytes;
                 ++li;
@@ -1422,8 +1460,15 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 c.stats.sweep_bytes += ln.bytes;
             } else if (ln.kind == Launch::PASS) {
                 timed(0);
-                if ((he = launch_pass(fp64, ln.R, ln.flip, ln.zskip, pass_args(ln), ln.grid, stream)) != hipSuccess)
+                if (ln.jit_fn) {
+                    PassArgs a0 = pass_args(ln);
+                    void *kp[] = {&a0};
+                    if ((he = hipModuleLaunchKernel(ln.jit_fn, ln.grid, 1, 1, 256, 1, 1, 0, stream, kp, nullptr)) != hipSuccess)
+                        return dev_err("compiled pass", he);
+                    c.stats.n_jit_passes++;
+                } else if ((he = launch_pass(fp64, ln.R, ln.flip, ln.zskip, pass_args(ln), ln.grid, stream)) != hipSuccess) {
                     return dev_err("pass", he);
+                }
                 c.stats.n_sweep_launches++;
                 c.stats.sweep_bytes += ln.bytes;
             } else if (ln.kind == Launch::FOLD && fh[0]->iswap) {
