@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--tuning", default="",
                     help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes[,no_row_skip[,no_defer[,no_chain_merge[,jit]]]]]]]]] "
                          "(skips autotune)")
+    ap.add_argument("--no-interpreted", action="store_true",
+                    help="with compiled passes (tuning jit), skip timing the same request with interpreted passes "
+                         "(profiles then hold the compiled kernels only)")
     ap.add_argument("--ceilings-only", action="store_true",
                     help="only measure the bandwidth ceilings (and the read rate per buffer size) and print them")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -155,12 +158,13 @@ def time_steps(req, steps, warmup, chunk_paths=0, label=""):
     times come from the library's HIP events on the launch stream (SF_TIMING)."""
     import torch
     from paper_1807_10749_amd import binding as sf
+    jit_ms = 0.0
     for i in range(warmup):
         progress(f"{label}warm-up step {i + 1}/{warmup}")
-        run_step(req, chunk_paths=chunk_paths)
+        jit_ms += run_step(req, chunk_paths=chunk_paths)["jit_compile_ms"]
     torch.cuda.synchronize()
     keys = ("ms_sweep", "ms_gather", "ms_other", "ms_total", "ms_plan", "n_sweep_launches", "n_gather_launches",
-            "sweep_bytes", "gather_bytes", "gather_row_bytes", "n_chained_passes")
+            "sweep_bytes", "gather_bytes", "gather_row_bytes", "n_chained_passes", "n_jit_passes", "jit_compile_ms")
     tot = {k: 0 for k in keys}
     st = None
     t0 = time.perf_counter()
@@ -172,9 +176,27 @@ def time_steps(req, steps, warmup, chunk_paths=0, label=""):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tot["elapsed_s"] = elapsed
+    tot["jit_compile_ms_warmup"] = jit_ms
     tot["a_groups"] = st["a_groups"] if st else 0
     tot["gather_ws_bytes"] = st["gather_ws_bytes"] if st else 0
     return tot
+
+
+def compiled_passes(req, tot, steps, warmup, chunk_paths=0, compare=True):
+    """With tuning jit: passes run by kernels compiled for their programs per step, the warm-up's
+    compile time, and (compare) the same request timed with interpreted passes (tuning jit = 0)."""
+    from paper_1807_10749_amd import binding as sf
+    t = req["tuning"]
+    if not t or not t.get("jit"):
+        return None
+    out = {"per_step": tot["n_jit_passes"] / steps, "compile_s_in_warmup": tot["jit_compile_ms_warmup"] / 1e3}
+    if not compare:
+        return out
+    sf.set_tuning(req["c"].handle, **dict(t, jit=0))
+    it = time_steps(req, steps, max(warmup, 1), chunk_paths, label="interpreted passes: ")
+    sf.set_tuning(req["c"].handle, **t)
+    return dict(out, interpreted_ms_per_step=1e3 * it["elapsed_s"] / steps,
+                interpreted_ms_sweep_per_step=it["ms_sweep"] / steps)
 
 
 def dominant(req, tot, steps):
@@ -268,6 +290,7 @@ def main():
     plain = plain_form(req, args.plain_paths)
     if plain:
         plain["speedup_of_batched"] = paths_per_s / plain["paths_per_s"]
+    compiled = compiled_passes(req, tot, args.steps, args.warmup, args.chunk_paths, not args.no_interpreted)
     progress("timed steps done")
     # rejection sampling and the validation protocol need the full output distribution: they run
     # on an all-paths request (this one, or the 5x6 line's)
@@ -358,6 +381,7 @@ def main():
                                "other": run_stats["ms_other"] / args.steps},
         "run_paths_wall_ms_per_step": run_stats["ms_total"] / args.steps,
         "host_plan_ms_per_step": run_stats["ms_plan"] / args.steps,
+        "compiled_passes": compiled,
         "roofline": dict(roof, traffic=traffic, avg_launch_ms=avg_launch_ms, launches_per_step=launches_per_step,
                          bytes_per_launch=bytes_per_launch),
         "sweep_roofline": {"kernels": "pass_kernel + dense_kernel (gate sweeps, all levels written)", "bound": "hbm",
@@ -417,6 +441,8 @@ def config_line(name, ceilings, max_paths=0, steps=3, warmup=1, with_sampling=Fa
                         "bytes_per_launch": bpl, "GB_per_s": ach},
            "sweep_launches_per_step": tot["n_sweep_launches"] / steps,
            "chained_passes_per_step": tot["n_chained_passes"] / steps,
+           "compiled_passes_per_step": tot["n_jit_passes"] / steps,
+           "compile_s_in_warmup": tot["jit_compile_ms_warmup"] / 1e3,
            "sweep_GB_per_s": tot["sweep_bytes"] / max(tot["ms_sweep"], 1e-9) / 1e6,
            "sweep_frac_of_hbm_peak": tot["sweep_bytes"] / max(tot["ms_sweep"], 1e-9) / 1e6 / HBM_PEAK_GBS,
            "tuning": req["tuning"], "dtype": "c128" if req["cfg"].fp64_sweeps else "c64 sweeps, f64 path sum"}

@@ -655,10 +655,13 @@ __device__ __forceinline__ void pass_body(A a, uint32_t block, uint32_t nblocks)
 #pragma unroll
             for (int j = 0; j < N; ++j) { v[j].x *= sc; v[j].y *= sc; }
         }
+        // streaming stores: nothing reads the destination before the next pass or the path sum
+        using V2 = T __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             C *row = (C *)a.dst + (et + reg_offset<R>(pos, j, 0, 0));   // uniform
-            row[lx] = v[j];
+            const V2 val = {v[j].x, v[j].y};
+            __builtin_nontemporal_store(val, (V2 *)(row + lx));
         }
     }
 }
