@@ -208,9 +208,8 @@ typedef struct {
                                 takes no more passes than planning the levels one by one (the
                                 root joins the run below it); 1: one segment per level */
     uint32_t jit;            /* 0: the pass kernels interpret each pass program (read per tile from
-                                LDS); 1: every pass whose program holds only one-qubit gates and
-                                diagonal groups (no per-path flips, no in-block iSWAP, no dense
-                                block) runs a kernel compiled at run time for that program (hiprtc,
+                                LDS); 1: every pass outside a chained launch that is not a dense
+                                block runs a kernel compiled at run time for its program (hiprtc,
                                 a few seconds per distinct set of programs, cached for the
                                 process): the gates' kinds and positions become constants, which
                                 removes the interpreter's per-operation register copies and

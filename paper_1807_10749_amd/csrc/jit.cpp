@@ -129,7 +129,7 @@ void compile_unit(Unit &u, const std::string &arch)
 
 std::string jit_program(const PassPlan &pp)
 {
-    if (pp.dense || pp.has_flip) return "";
+    if (pp.dense) return "";
     std::string body;
     for (const PassOp &op : pp.ops) {
         if (op.type == PO_REG) {
@@ -139,6 +139,24 @@ std::string jit_program(const PassPlan &pp)
         } else if (op.type == PO_DIAG) {
             if (op.group >= pp.groups.size()) return "";
             body += diag_code(pp.groups[op.group], pp.terms);
+        } else if (op.type == PO_ISWAP) {
+            // the same dispatch as the interpreted pass (pass_dev.hpp), with constant positions
+            const std::string t0 = num(op.target), t1 = num(op.group & 0xffu);
+            if (op.kind == 0) body += "        sf::reg_iswap_dispatch<R>(" + t0 + ", " + t1 + ", v);\n";
+            else if (op.kind == 3) body += "        sf::lane_iswap<R>(" + t0 + ", " + t1 + ", lane, v);\n";
+            else if (op.kind == 1) body += "        sf::reg_lane_iswap_dispatch<R>(" + t1 + ", " + t0 + ", lane, v);\n";
+            else body += "        sf::reg_lane_iswap_dispatch<R>(" + t0 + ", " + t1 + ", lane, v);\n";
+        } else if (op.type == PO_PFLIP_REG || op.type == PO_PFLIP_LANE) {
+            // flip where path bits u and u + 1 differ, times i there for kind 1
+            const std::string u = num(op.group), u1 = num(op.group + 1);
+            body += "    {\n        const bool f = (((sp >> " + u + ") ^ (sp >> " + u1 + ")) & 1u) != 0;\n";
+            if (op.type == PO_PFLIP_REG) body += "        sf::reg_flip_dispatch<R>(" + num(op.target) + ", f, v);\n";
+            else body += "        sf::lane_flip<R>(" + num(op.target) + ", f, v);\n";
+            if (op.kind)
+                body += "#pragma unroll\n        for (int j = 0; j < (1 << R); ++j) {\n"
+                        "            const T x = v[j].x, y = v[j].y;\n            v[j].x = f ? -y : x;\n"
+                        "            v[j].y = f ? x : y;\n        }\n";
+            body += "    }\n";
         } else {
             return "";
         }

@@ -19,8 +19,7 @@
 namespace sf {
 
 // The body of the program (the statements of pass_body's P::apply, see pass_dev.hpp) for one
-// pass plan, or "" when the plan holds operations the compiled form does not cover (per-path
-// flips, in-block iSWAPs, dense blocks).
+// pass plan, or "" for a dense block (matrix cores, its own kernel).
 std::string jit_program(const PassPlan &pp);
 
 // Kernel source of one pass (prog1 empty) or of the two blocks' passes of one level in one launch

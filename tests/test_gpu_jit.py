@@ -1,5 +1,5 @@
-"""Compiled passes (tuning jit = 1): every pass whose program holds one-qubit gates and diagonal
-groups only runs a kernel compiled at run time for that program.
+"""Compiled passes (tuning jit = 1): every pass outside a chained launch that is not a dense block
+runs a kernel compiled at run time for its program.
 
 The compiled kernel runs the same device code as the interpreted one with the program's
 operations as constants, so its amplitudes agree with the interpreted passes' to rounding (the
@@ -124,18 +124,36 @@ def test_jit_plain_form(sf):
     c.close()
 
 
-def test_jit_iswap_circuit(sf):
-    """Crossing iSWAPs: passes with per-path flips or in-block iSWAPs stay interpreted, the rest
-    are compiled."""
+@pytest.mark.parametrize("tune", [{"reg_qubits": 4}, {"reg_qubits": 2}, {"reg_qubits": 4, "no_leaf_fold": 1}])
+def test_jit_iswap_circuit(sf, tune):
+    """Crossing iSWAPs: per-path flips (with the factor i) and in-block iSWAPs on registers and
+    lanes, compiled with constant positions."""
     g = grid_circuit(4, 4, 12, 5, two_qubit=ISWAP)
     c = sf.Circuit(4, 4, g)
     bits = random_bitstrings(16, 1024, 3)
-    say("compiled passes iswap 4x4 d12 all paths")
-    out = _both(c, bits, {"reg_qubits": 4})
-    a_jit, a_int = _check_runs(out, expect_jit=False)
+    say(f"compiled passes iswap 4x4 d12 all paths {tune}")
+    out = _both(c, bits, tune)
+    a_jit, a_int = _check_runs(out)
     o = oracle.path_sum(16, g, c.mask_a, np.arange(1 << c.k, dtype=np.uint64), bits)
     for a in (a_jit, a_int):
         assert c11_error(a, o, 1 << c.k, c.k, 16) <= TOL_C64
+    c.close()
+
+
+def test_jit_iswap_grid5x6_subset(sf):
+    """The iSWAP variant of the 5x6 benchmark circuit on a path subset (fan-outs with flips)."""
+    from workload import CONFIGS
+    cfg = CONFIGS["grid5x6_d24"]
+    g = grid_circuit(cfg.rows, cfg.cols, cfg.depth, cfg.circuit_seed, two_qubit=ISWAP)
+    c = sf.Circuit(cfg.rows, cfg.cols, g, cfg.cut_mask())
+    bits = random_bitstrings(30, 800, 12)
+    rng = np.random.default_rng(4)
+    ids = np.sort(rng.choice(1 << c.k, size=600, replace=False)).astype(np.uint64)
+    say("compiled passes iswap 5x6 d24, 600 paths")
+    a_jit, a_int = _check_runs(_both(c, bits, {"reg_qubits": 5}, path_ids=ids))
+    o = oracle.path_sum(30, g, cfg.cut_mask(), ids, bits)
+    for a in (a_jit, a_int):
+        assert c11_error(a, o, ids.size, c.k, 30) <= TOL_C64
     c.close()
 
 
