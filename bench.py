@@ -612,10 +612,10 @@ def validation_bench(c, bits, d_amps, index_seed, ws, ws_bytes, stream, f1=0.25,
             "ms": best[0] * 1e3}
 
 
-def iswap_bench(stream, steps=3, warmup=1):
+def iswap_bench(stream, steps=3, warmup=1, jit=1):
     """The harder variant (every CZ of the default circuit an iSWAP, Eq. (4way): four terms and
     two path bits per crossing gate, k = 30): one seeded aligned block of 2^18 paths, 1e5
-    bitstrings, autotuned, timed like the headline step."""
+    bitstrings, autotuned, compiled passes (jit), timed like the headline step."""
     import torch
     from paper_1807_10749_amd import binding as sf
     from workload import make_workload, workload_block
@@ -630,10 +630,13 @@ def iswap_bench(stream, steps=3, warmup=1):
     ws_bytes = min(sf.workspace_size(c.handle, npaths, bits.size, 0), 64 << 30, int(free_b * 0.5))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     flags = sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
+    sf.set_tuning(c.handle, jit=jit)
     tuning = sf.autotune(c.handle, None, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes,
                          n_measure=4)
+    compile_ms = 0.0
     for _ in range(warmup):
         sf.run_paths(c.handle, None, begin, npaths, d_bits, bits.size, d_amps, flags, stream, ws, ws_bytes)
+        compile_ms += c.stats()["jit_compile_ms"]
     torch.cuda.synchronize()
     tot = {"ms_sweep": 0.0, "ms_gather": 0.0, "ms_other": 0.0, "sweep_bytes": 0, "n_sweep_launches": 0}
     t0 = time.perf_counter()
@@ -652,7 +655,7 @@ def iswap_bench(stream, steps=3, warmup=1):
                                   "other": tot["ms_other"] / steps},
            "sweep_launches_per_step": tot["n_sweep_launches"] / steps,
            "sweep_GB_per_s": sweep_gbs, "sweep_frac_of_hbm_peak": sweep_gbs / HBM_PEAK_GBS,
-           "tuning": tuning}
+           "compile_s_in_warmup": compile_ms / 1e3, "tuning": tuning}
     c.close()
     return out
 
