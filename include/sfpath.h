@@ -312,6 +312,21 @@ int get_run_stats(const sf_circuit_t *c, sf_run_stats_t *s);
  */
 int describe_plan(sf_circuit_t *c, char *out, size_t cap);
 
+/*
+ * compile_segment_kernels: the kernels that tuning jit = 1 compiles for the passes of one block
+ * (half 0 = A, 1 = B) over tree levels first_level..last_level planned as one segment for 2^slot_bits
+ * slots and reg_qubits register qubits (complex128 states when fp64 is nonzero, reg_qubits <= 4),
+ * one kernel per pass that is not a dense block, compiled for gfx950 with hiprtc on the host and
+ * discarded (no device is needed or used).  *n_kernels (host) receives their number and
+ * *code_bytes (host) the total code-object size.  For checking the generated kernels on a
+ * machine without a GPU.  SF_ERR_INVALID on NULL pointers or out-of-range arguments,
+ * SF_ERR_NO_CUT before set_cut, SF_ERR_UNSUPPORTED if the segment cannot be planned or a kernel
+ * does not compile (the compiler's log in last_error).
+ */
+int compile_segment_kernels(sf_circuit_t *c, int half, uint32_t first_level, uint32_t last_level,
+                            uint32_t slot_bits, uint32_t reg_qubits, uint32_t fp64, uint32_t *n_kernels,
+                            uint64_t *code_bytes);
+
 /* Message for the last error on the calling thread ("" if none). */
 const char *last_error(void);
 

@@ -25,7 +25,7 @@ EXPORTS = ["create_circuit", "destroy_circuit", "set_cut", "choose_cut", "num_pa
            "server_drain", "server_stats", "server_destroy", "server_last_error", "rejection_m",
            "sample_bitstrings", "rejection_workspace_size", "rejection_accept", "frugal_sample",
            "fidelity_estimate", "xeb_fidelity", "verify_claim", "save_tuning_cache", "load_tuning_cache",
-           "server_set_policy", "run_paths_noalloc", "read_bandwidth"]
+           "server_set_policy", "run_paths_noalloc", "read_bandwidth", "compile_segment_kernels"]
 SF_PENDING = 1
 SF_SERVE_OLDEST_FIRST, SF_SERVE_ROUND_ROBIN, SF_SERVE_LEAST_WORK = 0, 1, 2
 
@@ -122,6 +122,8 @@ def _load():
     lib.fidelity_estimate.argtypes = [vp, vp, u64, vp, pd, pd, pd]
     lib.xeb_fidelity.argtypes = [vp, u64, u32, vp, pd]
     lib.read_bandwidth.argtypes = [vp, sz, u32, u32, vp, pd]
+    lib.compile_segment_kernels.argtypes = [vp, ctypes.c_int, u32, u32, u32, u32, u32, ctypes.POINTER(u32),
+                                            ctypes.POINTER(u64)]
     lib.verify_claim.argtypes = [vp, vp, u64, u64, ctypes.c_double, u64, ctypes.c_double, u32, vp, vp, sz, pd,
                                  ctypes.POINTER(ctypes.c_int)]
     lib.server_last_error.restype = ctypes.c_char_p
@@ -347,6 +349,16 @@ def get_run_stats(c: int) -> dict:
     s = RunStats()
     _check(lib.get_run_stats(c, ctypes.byref(s)))
     return s.as_dict()
+
+
+def compile_segment_kernels(c: int, half: int, first_level: int, last_level: int, slot_bits: int, reg_qubits: int,
+                            fp64: bool = False) -> tuple:
+    """(kernels, code-object bytes) of the compiled passes of one segment plan (host only)."""
+    n = ctypes.c_uint32()
+    nb = ctypes.c_uint64()
+    _check(lib.compile_segment_kernels(c, half, first_level, last_level, slot_bits, reg_qubits, int(bool(fp64)),
+                                       ctypes.byref(n), ctypes.byref(nb)))
+    return n.value, nb.value
 
 
 def describe_plan(c: int) -> str:

@@ -186,6 +186,59 @@ std::string jit_kernel(bool fp64, int R0, const std::string &prog0, bool zskip0,
     return s;
 }
 
+namespace {
+
+// the sources as units of a few kernels each, their placeholders filled (kernel_name)
+std::vector<Unit> make_units(const std::vector<std::string> &uniq, size_t n_threads,
+                             std::vector<std::vector<size_t>> &members)
+{
+    const size_t per = (uniq.size() + n_threads - 1) / n_threads;
+    std::vector<Unit> units;
+    for (size_t b = 0; b < uniq.size(); b += per) {
+        Unit u;
+        u.src = "#include \"pass_dev.hpp\"\n";
+        std::vector<size_t> m;
+        for (size_t i = b; i < std::min(uniq.size(), b + per); ++i) {
+            const std::string name = kernel_name(uniq[i]);
+            u.src += replace_all(replace_all(uniq[i], "SFJ_NS", name + "_ns"), "SFJ_KERNEL", name);
+            m.push_back(i);
+        }
+        units.push_back(std::move(u));
+        members.push_back(std::move(m));
+    }
+    return units;
+}
+
+size_t compile_threads(size_t n)
+{
+    return std::max<size_t>(1, std::min<size_t>({16, n, (size_t)std::max(1u, std::thread::hardware_concurrency())}));
+}
+
+void compile_all(std::vector<Unit> &units, const std::string &arch)
+{
+    std::vector<std::thread> th;
+    for (size_t i = 1; i < units.size(); ++i) th.emplace_back(compile_unit, std::ref(units[i]), std::cref(arch));
+    if (!units.empty()) compile_unit(units[0], arch);
+    for (std::thread &t : th) t.join();
+}
+
+}  // namespace
+
+int jit_compile_only(const std::vector<std::string> &sources, const std::string &arch, uint64_t *code_bytes,
+                     std::string &err)
+{
+    std::vector<std::vector<size_t>> members;
+    std::vector<Unit> units = make_units(sources, compile_threads(sources.size()), members);
+    compile_all(units, arch);
+    uint64_t n = 0;
+    for (const Unit &u : units) {
+        if (!u.err.empty()) { err = "compiling a pass kernel: " + u.err; return SF_ERR_UNSUPPORTED; }
+        n += u.code.size();
+    }
+    if (code_bytes) *code_bytes = n;
+    return SF_OK;
+}
+
 int jit_kernels(const std::vector<std::string> &sources, std::vector<hipFunction_t> &fns, double *compile_ms,
                 std::string &err)
 {
@@ -213,27 +266,9 @@ int jit_kernels(const std::vector<std::string> &sources, std::vector<hipFunction
         arch = arch.substr(0, arch.find(':'));
         const auto t0 = std::chrono::steady_clock::now();
         // a few kernels per hiprtc program, the programs compiled on up to 16 threads
-        const size_t n_threads = std::max<size_t>(1, std::min<size_t>({16, uniq.size(),
-                                                   (size_t)std::max(1u, std::thread::hardware_concurrency())}));
-        const size_t per = (uniq.size() + n_threads - 1) / n_threads;
-        std::vector<Unit> units;
         std::vector<std::vector<size_t>> members;
-        for (size_t b = 0; b < uniq.size(); b += per) {
-            Unit u;
-            u.src = "#include \"pass_dev.hpp\"\n";
-            std::vector<size_t> m;
-            for (size_t i = b; i < std::min(uniq.size(), b + per); ++i) {
-                const std::string name = kernel_name(uniq[i]);
-                u.src += replace_all(replace_all(uniq[i], "SFJ_NS", name + "_ns"), "SFJ_KERNEL", name);
-                m.push_back(i);
-            }
-            units.push_back(std::move(u));
-            members.push_back(std::move(m));
-        }
-        std::vector<std::thread> th;
-        for (size_t i = 1; i < units.size(); ++i) th.emplace_back(compile_unit, std::ref(units[i]), std::cref(arch));
-        compile_unit(units[0], arch);
-        for (std::thread &t : th) t.join();
+        std::vector<Unit> units = make_units(uniq, compile_threads(uniq.size()), members);
+        compile_all(units, arch);
         for (const Unit &u : units)
             if (!u.err.empty()) { err = "compiling a pass kernel: " + u.err; return SF_ERR_DEVICE; }
         for (size_t ui = 0; ui < units.size(); ++ui) {

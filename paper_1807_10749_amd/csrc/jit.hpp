@@ -36,4 +36,9 @@ std::string jit_kernel(bool fp64, int R0, const std::string &prog0, bool zskip0,
 int jit_kernels(const std::vector<std::string> &sources, std::vector<hipFunction_t> &fns, double *compile_ms,
                 std::string &err);
 
+// Compiles the sources for `arch` (e.g. "gfx950") without a device and loads nothing: the total
+// code-object size, or an SF_ERR_* code with the compiler's log in err.
+int jit_compile_only(const std::vector<std::string> &sources, const std::string &arch, uint64_t *code_bytes,
+                     std::string &err);
+
 }  // namespace sf

@@ -16,6 +16,7 @@
 #include <string>
 #include <unordered_set>
 
+#include "jit.hpp"
 #include "kernels.hpp"
 #include "sf_host.hpp"
 
@@ -825,6 +826,35 @@ int xeb_fidelity(const double *amps, uint64_t n, uint32_t n_qubits, void *hip_st
         const int rc = overlap_sums(amps, nullptr, n, (hipStream_t)hip_stream, sm);
         if (rc) return rc;
         *f = n ? std::ldexp(sm[2], (int)n_qubits) / (double)n - 1.0 : 0.0;   // N <p(x)> - 1
+        return ok();
+    });
+}
+
+int compile_segment_kernels(sf_circuit_t *c, int half, uint32_t first_level, uint32_t last_level,
+                            uint32_t slot_bits, uint32_t reg_qubits, uint32_t fp64, uint32_t *n_kernels,
+                            uint64_t *code_bytes)
+{
+    return guarded([&]() -> int {
+        if (!c || !n_kernels || !code_bytes) return fail(SF_ERR_INVALID, "NULL argument");
+        if (!c->has_cut) return fail(SF_ERR_NO_CUT, "set_cut has not been called");
+        if (half < 0 || half > 1) return fail(SF_ERR_INVALID, "half must be 0 or 1");
+        const uint32_t L = (uint32_t)c->levels.size() - 1;
+        if (first_level > last_level || last_level > L) return fail(SF_ERR_INVALID, "levels out of range");
+        if (reg_qubits < 1 || reg_qubits > (fp64 ? 4u : 5u)) return fail(SF_ERR_INVALID, "reg_qubits out of range");
+        if (slot_bits > 24) return fail(SF_ERR_INVALID, "slot_bits must be at most 24");
+        const sf::SegmentPlan &sp = sf::get_segment_plan_range(*c, half, (int)first_level, (int)last_level,
+                                                               (int)slot_bits, (int)reg_qubits, 0);
+        if (!sp.ok) return fail(SF_ERR_UNSUPPORTED, "the segment could not be planned");
+        std::vector<std::string> srcs;
+        for (const sf::PassPlan &pp : sp.passes) {
+            const std::string prog = sf::jit_program(pp);
+            if (prog.empty()) continue;
+            const bool z = !pp.zero_in.empty() && !fp64 && (pp.R == 4 || pp.R == 5);
+            srcs.push_back(sf::jit_kernel(fp64 != 0, pp.R, prog, z, 0, std::string(), false));
+        }
+        std::string err;
+        if (int rc = sf::jit_compile_only(srcs, "gfx950", code_bytes, err)) return fail(rc, err);
+        *n_kernels = (uint32_t)srcs.size();
         return ok();
     });
 }

@@ -409,3 +409,33 @@ def test_read_bandwidth_rejects_bad_arguments(sf):
         with pytest.raises(sf.SFError) as e:
             sf.read_bandwidth(*args)
         assert e.value.code == sf.SF_ERR_INVALID
+
+
+@pytest.mark.parametrize("circuit,tune", [("cz", {}), ("iswap", {}), ("cz_fp64", {"fp64": True})])
+def test_compiled_pass_kernels_build_on_host(sf, circuit, tune):
+    """The kernels tuning jit compiles per pass program (one-qubit gates, diagonal groups with
+    their constant register weights, per-path flips and in-block iSWAPs for crossing iSWAPs)
+    compile for gfx950 on the host: every non-dense pass of every level of both blocks."""
+    from workload import ISWAP, grid_circuit
+    g = grid_circuit(4, 5, 12, 7, two_qubit=ISWAP) if circuit == "iswap" else grid_circuit(4, 5, 12, 7)
+    c = sf.create_circuit(4, 5, g)
+    sf.set_cut(c, sf.choose_cut(c))
+    levels = [int(l.split()[1]) for l in sf.describe_plan(c).splitlines() if l.startswith("level ")]
+    R = 4 if tune.get("fp64") else 5
+    total = 0
+    for half in (0, 1):
+        # the root with the levels below it as one segment, then the last levels one by one
+        n, nb = sf.compile_segment_kernels(c, half, 0, 1, 0, R, **tune)
+        total += n
+        assert n >= 1 and nb > 0
+        for lv in levels[2:]:
+            n, nb = sf.compile_segment_kernels(c, half, lv, lv, min(lv * 2, 8), R, **tune)
+            total += n
+    assert total >= 4
+    with pytest.raises(sf.SFError):
+        sf.compile_segment_kernels(c, 2, 0, 0, 0, R)
+    with pytest.raises(sf.SFError):
+        sf.compile_segment_kernels(c, 0, 1, 0, 0, R)
+    with pytest.raises(sf.SFError):
+        sf.compile_segment_kernels(c, 0, 0, 0, 0, 6)
+    sf.destroy_circuit(c)
