@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--max-paths", type=int, default=0,
                     help="time only the first N paths of the request (a bounded sample, for profiling)")
     ap.add_argument("--tuning", default="",
-                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes[,no_row_skip[,no_defer[,no_chain_merge[,jit]]]]]]]]] "
+                    help="fixed tuning R,leaf_batch,waves_per_cu[,dense_qubits[,no_leaf_fold[,fold_levels[,chain_passes[,no_row_skip[,no_defer[,no_chain_merge[,jit[,no_tail_move]]]]]]]]]] "
                          "(skips autotune)")
     ap.add_argument("--no-interpreted", action="store_true",
                     help="with compiled passes (tuning jit), skip timing the same request with interpreted passes "
@@ -122,7 +122,8 @@ def prepare(workload, n_bits=0, max_paths=0, tuning="", autotune=True, n_measure
         sf.set_tuning(c.handle, reg_qubits=r, leaf_batch=lb, waves_per_cu=wpc, dense_qubits=dense,
                       no_leaf_fold=nofold, fold_levels=flev, chain_passes=chain,
                       no_row_skip=vals[7] if len(vals) > 7 else 0, no_defer=vals[8] if len(vals) > 8 else 0,
-                      no_chain_merge=vals[9] if len(vals) > 9 else 0, jit=vals[10] if len(vals) > 10 else jit)
+                      no_chain_merge=vals[9] if len(vals) > 9 else 0, jit=vals[10] if len(vals) > 10 else jit,
+                      no_tail_move=vals[11] if len(vals) > 11 else 0)
         tuned = sf.get_tuning(c.handle)
     elif autotune:
         sf.set_tuning(c.handle, jit=jit)

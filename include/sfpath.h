@@ -214,6 +214,11 @@ typedef struct {
                                 process): the gates' kinds and positions become constants, which
                                 removes the interpreter's per-operation register copies and
                                 selects.  Results agree with the interpreted passes to rounding */
+    uint32_t no_tail_move;   /* 0: a block whose segment ends in an in-place pass and whose
+                                children are written by a fan-out (at most 16 children per parent)
+                                leaves that last pass to the children's first pass when their plan
+                                takes no more passes with it: one read and write of the parent
+                                batch saved, that pass's gates run once per child; 1: never */
 } sf_tuning_t;
 
 int set_tuning(sf_circuit_t *c, const sf_tuning_t *t);

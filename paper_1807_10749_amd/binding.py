@@ -42,7 +42,7 @@ class Tuning(ctypes.Structure):
                 ("dense_qubits", ctypes.c_uint32), ("no_leaf_fold", ctypes.c_uint32),
                 ("fold_levels", ctypes.c_uint32), ("chain_passes", ctypes.c_uint32),
                 ("no_row_skip", ctypes.c_uint32), ("no_defer", ctypes.c_uint32),
-                ("no_chain_merge", ctypes.c_uint32), ("jit", ctypes.c_uint32)]
+                ("no_chain_merge", ctypes.c_uint32), ("jit", ctypes.c_uint32), ("no_tail_move", ctypes.c_uint32)]
 
 
 class RunStats(ctypes.Structure):
@@ -311,9 +311,9 @@ def workspace_size(c: int, n_paths: int, n_bits: int, flags: int = 0) -> int:
 
 
 def set_tuning(c: int, reg_qubits=0, leaf_batch=0, max_slots=0, waves_per_cu=0, dense_qubits=0, no_leaf_fold=0,
-               fold_levels=0, chain_passes=0, no_row_skip=0, no_defer=0, no_chain_merge=0, jit=0):
+               fold_levels=0, chain_passes=0, no_row_skip=0, no_defer=0, no_chain_merge=0, jit=0, no_tail_move=0):
     t = Tuning(reg_qubits, leaf_batch, max_slots, waves_per_cu, dense_qubits, no_leaf_fold, fold_levels, chain_passes,
-               no_row_skip, no_defer, no_chain_merge, jit)
+               no_row_skip, no_defer, no_chain_merge, jit, no_tail_move)
     _check(lib.set_tuning(c, ctypes.byref(t)))
 
 

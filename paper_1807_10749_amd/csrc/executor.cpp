@@ -116,6 +116,13 @@ struct Launch {
 
 struct BatchRec { int level; size_t table_off; uint64_t slots; };
 
+// A segment's last pass left to the fan-out of its children: mask bit h = block h; the segment
+// (levels first..last planned for 2^p slots) whose last pass the children's first pass applies.
+struct Tail {
+    int mask = 0;
+    int first = 0, last = 0, p = 0;
+};
+
 // A run of PASS launches [begin, end) that executes as one chained launch (pass_chain_kernel).
 struct ChainRec {
     size_t begin = 0, end = 0;
@@ -603,10 +610,13 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     // n_real: slots in use (the rest of the nslots pad the batch to a power of two); src_read:
     // parent slots a fan-out actually reads (distinct parents of its children), for the byte
     // count, 0 = all src_slots
-    // level0 < level: the segments of levels level0..level as one (chain levels, chain_run)
+    // level0 < level: the segments of levels level0..level as one (chain levels, chain_run).
+    // drop: bit h = block h leaves its segment's last pass to the fan-out of the children
+    // (tail_moves); pre: the parent segment whose dropped last pass this fan-out applies first.
     auto add_segment = [&](int level, uint64_t nslots, uint64_t n_real, const size_t dst[2], int mode,
                            const size_t src[2], uint64_t src_slots, size_t table_off, int n_low = 0,
-                           int low_first = 0, uint64_t src_read = 0, int level0 = -1) {
+                           int low_first = 0, uint64_t src_read = 0, int level0 = -1, int drop = 0,
+                           const Tail *pre = nullptr) {
         const int lev0 = level0 < 0 ? level : level0;
         const int p = log2u(nslots);
         const uint64_t slots_real = n_real && n_real < nslots ? n_real : 0;
@@ -615,11 +625,15 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         std::vector<Launch> hl[2];      // each block's launches of this segment, in order
         for (int h = 0; h < 2; ++h) {
             if (defer && h == 0 && level == fold_at) continue;   // block A's states of this level are not written
-            const SegmentPlan &sp = get_segment_plan_range(c, h, lev0, level, p, R, fp64 ? 0 : (int)c.tuning.dense_qubits);
+            const int dm = fp64 ? 0 : (int)c.tuning.dense_qubits;
+            const SegmentPlan &sp = pre && ((pre->mask >> h) & 1)
+                                        ? get_segment_plan_tail(c, h, lev0, level, p, R, dm, pre->first, pre->last, pre->p)
+                                        : get_segment_plan_range(c, h, lev0, level, p, R, dm);
             if (!sp.ok) { plan_error = true; return; }
             const std::vector<BlobEntry> &be = blob_entries(sp);
             const int n_ext = p + qh[h];
-            for (size_t i = 0; i < sp.passes.size(); ++i) {
+            const size_t n_pass = sp.passes.size() - (((drop >> h) & 1) ? 1 : 0);
+            for (size_t i = 0; i < n_pass; ++i) {
                 const PassPlan &pp = sp.passes[i];
                 if (pp.dense) {
                     Launch ln;
@@ -777,9 +791,47 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         return merged <= apart;
     };
 
-    // nodes: node indices of this batch in slot order
-    std::function<void(int, const std::vector<uint32_t> &, uint64_t)> visit;
-    visit = [&](int l, const std::vector<uint32_t> &nodes, uint64_t nslots) {
+    // Whether each block's segment first..last (the batch `nodes` of 2^p slots at level last)
+    // leaves its last pass to the fan-out of its children, which then apply that pass's
+    // operations first: it saves reading and writing the parent batch once, for running those
+    // operations once per child.  Taken when the children are written by a fan-out (level
+    // last + 1 is not a chain level, not folded into the path sum, not block A's deferred level),
+    // the segment's last pass is an in-place pass that is not a dense block, the parents have at
+    // most 16 children each, and the children's plan with those operations takes no more passes
+    // than without (tuning no_tail_move = 1: never).  keep: blocks whose segment here itself
+    // starts with its parent's last pass (their plan is not the one the children would take the
+    // last pass of), which keep theirs.
+    auto tail_moves = [&](int first, int last, const std::vector<uint32_t> &nodes, uint64_t nslots, int keep = 0) {
+        Tail t;
+        t.first = first;
+        t.last = last;
+        t.p = log2u(nslots);
+        if (c.tuning.no_tail_move || nodes.empty() || last + 1 > L || lb[last + 1].alias >= 0 || lb[last + 1].none ||
+            (fold && last == fold_at))
+            return t;
+        const std::vector<uint64_t> &fc = tree.first_child[last];
+        uint64_t nch = 0;
+        for (uint32_t x : nodes) nch += fc[x + 1] - fc[x];
+        if (nch > 16 * (uint64_t)nodes.size()) return t;
+        const uint64_t cs = std::max<uint64_t>(std::min<uint64_t>(next_pow2(nch), lb[last + 1].cap), min_slots);
+        const int pc = log2u(cs);
+        const int dm = fp64 ? 0 : (int)c.tuning.dense_qubits;
+        for (int h = 0; h < 2; ++h) {
+            if ((keep >> h) & 1) continue;
+            if (defer && h == 0 && last + 1 == fold_at) continue;   // the fold reads this batch as it is
+            const SegmentPlan &par = get_segment_plan_range(c, h, first, last, t.p, R, dm);
+            if (!par.ok || par.passes.size() < 2 || par.passes.back().dense) continue;
+            const SegmentPlan &with = get_segment_plan_tail(c, h, last + 1, last + 1, pc, R, dm, first, last, t.p);
+            const SegmentPlan &without = get_segment_plan_range(c, h, last + 1, last + 1, pc, R, dm);
+            if (with.ok && without.ok && with.passes.size() <= without.passes.size()) t.mask |= 1 << h;
+        }
+        return t;
+    };
+
+    // nodes: node indices of this batch in slot order; pre: this batch's segment's last pass, left
+    // to the children (tail_moves)
+    std::function<void(int, const std::vector<uint32_t> &, uint64_t, const Tail &)> visit;
+    visit = [&](int l, const std::vector<uint32_t> &nodes, uint64_t nslots, const Tail &pre) {
         if (plan_error) return;
         const int own = lb[l].alias >= 0 ? lb[l].alias : l;
         if (fold && l == fold_at) {
@@ -957,7 +1009,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             const size_t toff = put_tables(pv, pz, nslots);
             batches.push_back(BatchRec{last, toff, nslots});
             const size_t base[2] = {lb[own].off[0], lb[own].off[1]};
-            add_segment(last, nslots, nodes.size(), base, SRC_SAME, base, nslots, toff, 0, 0, 0, l + 1);
+            // (a level above a chain level keeps its last pass: tail_moves wants a fan-out)
+            const Tail tl = tail_moves(l + 1, last, ch, nslots);
+            add_segment(last, nslots, nodes.size(), base, SRC_SAME, base, nslots, toff, 0, 0, 0, l + 1, tl.mask);
             if (defer && last == fold_at) {
                 // in place: block A's slots still hold the parents' states
                 defer_par_off = base[0];
@@ -965,7 +1019,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
                 defer_par.resize(nodes.size());
                 for (size_t i = 0; i < nodes.size(); ++i) defer_par[i] = (uint32_t)i;
             }
-            visit(last, ch, nslots);
+            visit(last, ch, nslots, tl);
             return;
         }
         // Slot order of the children.  Full fan-outs (every parent has all 2^n_cut children) go
@@ -1014,13 +1068,15 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
             const size_t toff = put_tables(pv, par, ns);
             batches.push_back(BatchRec{l + 1, toff, ns});
             const size_t dst[2] = {cb.off[0], cb.off[1]};
-            add_segment(l + 1, ns, a1 - a0, dst, SRC_FANOUT, src, nslots, toff, n_low, log2u(nslots), n_read);
+            const Tail tl = tail_moves(l + 1, l + 1, ch, ns, pre.mask);
+            add_segment(l + 1, ns, a1 - a0, dst, SRC_FANOUT, src, nslots, toff, n_low, log2u(nslots), n_read, -1,
+                        tl.mask, &pre);
             if (defer && l + 1 == fold_at) {
                 defer_par_off = src[0];
                 defer_par_p = log2u(nslots);
                 defer_par = par;
             }
-            visit(l + 1, ch, ns);
+            visit(l + 1, ch, ns, tl);
             if (plan_error) return;
         }
     };
@@ -1079,8 +1135,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         const size_t toff = put_tables(std::vector<uint64_t>{tree.node[last][deep[0]]}, std::vector<uint32_t>{0}, ns0);
         batches.push_back(BatchRec{last, toff, ns0});
         const size_t base0[2] = {lb[0].off[0], lb[0].off[1]};
-        add_segment(last, ns0, 1, base0, SRC_INIT, base0, ns0, toff, 0, 0, 0, 0);
-        visit(last, deep, ns0);
+        const Tail tl = tail_moves(0, last, deep, ns0);
+        add_segment(last, ns0, 1, base0, SRC_INIT, base0, ns0, toff, 0, 0, 0, 0, tl.mask);
+        visit(last, deep, ns0, tl);
     }
     if (plan_error) { err = "internal: a segment could not be scheduled into passes"; return SF_ERR_UNSUPPORTED; }
     if (blob.size() > blob_budget) { err = "internal: pass programs exceed their reservation"; return SF_ERR_UNSUPPORTED; }

@@ -722,7 +722,7 @@ std::vector<float> dense_matrix(const std::vector<HalfOp> &ops, const int qs[4])
 // keep up to this many qubits (0..2) in lane bits 5 and 4 when the slots fill all six lane bits
 // (PassArgs::lane_qpos).
 static SegmentPlan plan_segment(const Circuit &c, int half, int level0, int level, int p, int R, int dense_m,
-                                int max_lq)
+                                int max_lq, const std::vector<HalfOp> *prefix = nullptr, int prefix_exp = 0)
 {
     const HalfProgram &hp = c.half[half];
     const int q = hp.q;
@@ -737,7 +737,8 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level0, int leve
 
     SegmentPlan sp;
     std::vector<HalfOp> rem;
-    int seg_exp = 0;
+    int seg_exp = prefix_exp;
+    if (prefix) rem = *prefix;
     for (int l = level0; l <= level; ++l) {
         rem.insert(rem.end(), hp.segments[l].begin(), hp.segments[l].end());
         seg_exp += hp.seg_rescale_exp[l];
@@ -793,8 +794,10 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level0, int leve
                      zs.end());
         }
     };
-    for (int l = 0; l < level0; ++l)
-        for (const HalfOp &op : hp.segments[l]) zupdate(op);
+    // (with a prefix the parent state lacks the prefix's operations: start with no known zeros)
+    if (!prefix)
+        for (int l = 0; l < level0; ++l)
+            for (const HalfOp &op : hp.segments[l]) zupdate(op);
 
     bool first = true;
     const bool dense_ok = dense_m >= 2 && n_ext >= 9 && q >= 4;
@@ -847,6 +850,7 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level0, int leve
                 }
                 pp.zero_in = zs;
                 for (const HalfOp &op : blk) zupdate(op);
+                pp.src = blk;
                 sp.passes.push_back(std::move(pp));
                 rem.swap(dfr);
                 continue;
@@ -1000,6 +1004,7 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level0, int leve
         }
         pp.zero_in = zs;
         for (const HalfOp &op : sched) zupdate(op);
+        pp.src = sched;
         sp.passes.push_back(std::move(pp));
         rem.swap(defer);
     }
@@ -1007,20 +1012,47 @@ static SegmentPlan plan_segment(const Circuit &c, int half, int level0, int leve
     return sp;
 }
 
-const SegmentPlan &get_segment_plan_range(Circuit &c, int half, int first, int last, int p, int R, int dense_m)
+namespace {
+// the plan with the fewest passes over lane-qubit choices: a qubit in a lane bit splits the
+// contiguous runs of a load (two of 32 amplitudes, or four of 16 = one cache line each with
+// two), so one or two are used only where that saves a pass
+SegmentPlan best_plan(const Circuit &c, int half, int first, int last, int p, int R, int dense_m,
+                      const std::vector<HalfOp> *prefix, int prefix_exp)
 {
-    const auto key = std::make_tuple(half, first, last, p, R, dense_m);
-    auto it = c.plan_cache.find(key);
-    if (it != c.plan_cache.end()) return it->second;
-    // a qubit in a lane bit splits the contiguous runs of a load (two of 32 amplitudes, or four
-    // of 16 = one cache line each with two): use one or two only where that saves a pass
-    SegmentPlan sp = plan_segment(c, half, first, last, p, R, dense_m, 0);
+    SegmentPlan sp = plan_segment(c, half, first, last, p, R, dense_m, 0, prefix, prefix_exp);
     const int q = c.half[half].q;
     if (p >= 6 || q > 6 - p)
         for (int m = 1; m <= 2 && (p >= 6 || 6 - p - m >= 0); ++m) {
-            SegmentPlan lq = plan_segment(c, half, first, last, p, R, dense_m, m);
+            SegmentPlan lq = plan_segment(c, half, first, last, p, R, dense_m, m, prefix, prefix_exp);
             if (lq.ok && (!sp.ok || lq.passes.size() < sp.passes.size())) sp = std::move(lq);
         }
+    return sp;
+}
+}  // namespace
+
+const SegmentPlan &get_segment_plan_range(Circuit &c, int half, int first, int last, int p, int R, int dense_m)
+{
+    const auto key = std::make_tuple(half, first, last, p, R, dense_m, -1, 0, 0);
+    auto it = c.plan_cache.find(key);
+    if (it != c.plan_cache.end()) return it->second;
+    auto res = c.plan_cache.emplace(key, best_plan(c, half, first, last, p, R, dense_m, nullptr, 0));
+    return res.first->second;
+}
+
+const SegmentPlan &get_segment_plan_tail(Circuit &c, int half, int first, int last, int p, int R, int dense_m,
+                                         int pre_first, int pre_last, int pre_p)
+{
+    const auto key = std::make_tuple(half, first, last, p, R, dense_m, pre_first, pre_last, pre_p);
+    auto it = c.plan_cache.find(key);
+    if (it != c.plan_cache.end()) return it->second;
+    const SegmentPlan &par = get_segment_plan_range(c, half, pre_first, pre_last, pre_p, R, dense_m);
+    SegmentPlan sp;
+    if (!par.ok || par.passes.size() < 2 || par.passes.back().dense) {
+        sp.ok = false;
+    } else {
+        const std::vector<HalfOp> prefix = par.passes.back().src;
+        sp = best_plan(c, half, first, last, p, R, dense_m, &prefix, par.passes.back().rescale_exp);
+    }
     auto res = c.plan_cache.emplace(key, std::move(sp));
     return res.first->second;
 }

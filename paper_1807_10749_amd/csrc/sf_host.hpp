@@ -51,6 +51,7 @@ struct PassPlan {
     // amplitude whose bit t differs from path bit u is zero (a projector on t applied, and no
     // non-diagonal gate on t since)
     std::vector<std::pair<uint8_t, uint8_t>> zero_in;
+    std::vector<HalfOp> src;        // the block operations this pass applies, in program order
     int lane_q = -1;                // local qubit held by lane bit 5 (when the slots fill all lane bits)
     int lane_q4 = -1;               // local qubit held by lane bit 4 (only with lane_q)
     // dense pass (matrix cores): a 16 x 16 block on four qubits instead of the op list
@@ -145,7 +146,9 @@ struct Circuit {
     // tuning
     sf_tuning_t tuning{};
     // (half, first level, last level, p, R, dense)
-    std::map<std::tuple<int, int, int, int, int, int>, SegmentPlan> plan_cache;
+    // (half, first, last, p, R, dense_m, prefix first, prefix last, prefix p) -> plan; prefix first
+    // -1: no prefix (get_segment_plan_tail)
+    std::map<std::tuple<int, int, int, int, int, int, int, int, int>, SegmentPlan> plan_cache;
 
     // device resources owned by the circuit
     void *dev_ws = nullptr;
@@ -191,6 +194,12 @@ const SegmentPlan &get_segment_plan(Circuit &c, int half, int level, int p, int 
 // of tree levels whose nodes have one child each run in the same slots, so their operations can
 // share passes across the level boundaries).
 const SegmentPlan &get_segment_plan_range(Circuit &c, int half, int first, int last, int p, int R, int dense_m = 0);
+// The segment first..last with, in front of its operations, those of the last pass of the
+// segment pre_first..pre_last planned for 2^pre_p slots (and that pass's rescaling): the plan of a
+// fan-out whose parent level leaves its last pass to the children.  Passes of such a plan
+// carry no known zero subspace.
+const SegmentPlan &get_segment_plan_tail(Circuit &c, int half, int first, int last, int p, int R, int dense_m,
+                                         int pre_first, int pre_last, int pre_p);
 
 // sfpath.cpp: run_paths' argument checks and execution on a given workspace of any size (the
 // entry point without allocations), and the thread's last_error() message.

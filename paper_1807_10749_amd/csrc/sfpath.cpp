@@ -290,6 +290,7 @@ int set_tuning(sf_circuit_t *c, const sf_tuning_t *t)
     if (t->no_defer > 1) return fail(SF_ERR_INVALID, "no_defer must be 0 or 1");
     if (t->no_chain_merge > 1) return fail(SF_ERR_INVALID, "no_chain_merge must be 0 or 1");
     if (t->jit > 1) return fail(SF_ERR_INVALID, "jit must be 0 or 1");
+    if (t->no_tail_move > 1) return fail(SF_ERR_INVALID, "no_tail_move must be 0 or 1");
     auto pow2ok = [](uint32_t v) { return v == 0 || (v & (v - 1)) == 0; };
     if (!pow2ok(t->leaf_batch) || !pow2ok(t->max_slots)) return fail(SF_ERR_INVALID, "batch sizes must be powers of two");
     c->tuning = *t;
@@ -365,9 +366,9 @@ int autotune(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin, uin
                     for (int F = 1; F <= max_fold; ++F) {     // F trailing levels folded into the gather
                         const int Fp = max_fold > 1 ? max_fold - 1 : 1;
                         if (F != max_fold && F != Fp) continue;
-                        cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0, (uint32_t)F, start.chain_passes, start.no_row_skip, start.no_defer, start.no_chain_merge, 0});
+                        cands.push_back(sf_tuning_t{r, 0, 0, w, dq, 0, (uint32_t)F, start.chain_passes, start.no_row_skip, start.no_defer, start.no_chain_merge, 0, start.no_tail_move});
                     }
-                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1, 0, start.chain_passes, start.no_row_skip, start.no_defer, start.no_chain_merge, 0});
+                    for (uint32_t lf : leafs) cands.push_back(sf_tuning_t{r, lf, 0, w, dq, 1, 0, start.chain_passes, start.no_row_skip, start.no_defer, start.no_chain_merge, 0, start.no_tail_move});
                 }
         // rank by the planned cost
         std::vector<std::pair<double, size_t>> ranked;
@@ -433,12 +434,12 @@ int save_tuning_cache(const char *path)
         FILE *f = std::fopen(path, "w");
         if (!f) return fail(SF_ERR_INVALID, std::string("cannot write ") + path);
         std::fprintf(f, "# sfpath tuning cache: key reg_qubits leaf_batch max_slots waves_per_cu dense_qubits "
-                        "no_leaf_fold fold_levels chain_passes no_row_skip no_defer no_chain_merge jit\n");
+                        "no_leaf_fold fold_levels chain_passes no_row_skip no_defer no_chain_merge jit no_tail_move\n");
         for (const auto &kv : g_tune_cache) {
             const sf_tuning_t &t = kv.second;
-            std::fprintf(f, "%s %u %u %u %u %u %u %u %u %u %u %u %u\n", kv.first.c_str(), t.reg_qubits, t.leaf_batch,
+            std::fprintf(f, "%s %u %u %u %u %u %u %u %u %u %u %u %u %u\n", kv.first.c_str(), t.reg_qubits, t.leaf_batch,
                          t.max_slots, t.waves_per_cu, t.dense_qubits, t.no_leaf_fold, t.fold_levels, t.chain_passes,
-                         t.no_row_skip, t.no_defer, t.no_chain_merge, t.jit);
+                         t.no_row_skip, t.no_defer, t.no_chain_merge, t.jit, t.no_tail_move);
         }
         const bool bad = std::ferror(f) != 0;
         if (std::fclose(f) != 0 || bad) return fail(SF_ERR_INVALID, std::string("cannot write ") + path);
@@ -461,15 +462,15 @@ int load_tuning_cache(const char *path, uint32_t *n_loaded)
             char key[512];
             sf_tuning_t t{};
             char extra;
-            // entries written before chain_passes / no_row_skip / no_defer / no_chain_merge / jit
-            // existed have fields less (read as 0)
-            const int got_n = std::sscanf(line, "%511s %u %u %u %u %u %u %u %u %u %u %u %u %c", key, &t.reg_qubits,
+            // entries written before chain_passes / no_row_skip / no_defer / no_chain_merge / jit /
+            // no_tail_move existed have fields less (read as 0)
+            const int got_n = std::sscanf(line, "%511s %u %u %u %u %u %u %u %u %u %u %u %u %u %c", key, &t.reg_qubits,
                                           &t.leaf_batch, &t.max_slots, &t.waves_per_cu, &t.dense_qubits,
                                           &t.no_leaf_fold, &t.fold_levels, &t.chain_passes, &t.no_row_skip,
-                                          &t.no_defer, &t.no_chain_merge, &t.jit, &extra);
-            if (got_n < 8 || got_n > 13 || t.reg_qubits > 5 || t.dense_qubits == 1 || t.dense_qubits > 4 ||
+                                          &t.no_defer, &t.no_chain_merge, &t.jit, &t.no_tail_move, &extra);
+            if (got_n < 8 || got_n > 14 || t.reg_qubits > 5 || t.dense_qubits == 1 || t.dense_qubits > 4 ||
                 t.no_leaf_fold > 1 || t.fold_levels > 62 || t.chain_passes > 1 || t.no_row_skip > 1 ||
-                t.no_defer > 1 || t.no_chain_merge > 1 || t.jit > 1) {
+                t.no_defer > 1 || t.no_chain_merge > 1 || t.jit > 1 || t.no_tail_move > 1) {
                 std::fclose(f);
                 return fail(SF_ERR_INVALID, std::string(path) + ":" + std::to_string(lineno) + ": malformed entry");
             }

@@ -279,10 +279,10 @@ def test_tuning_roundtrip(sf):
     w = make_workload("grid4x4_d16", n_bits=4)
     c = sf.create_circuit(4, 4, w["gates"])
     sf.set_tuning(c, reg_qubits=3, leaf_batch=64, max_slots=1024, waves_per_cu=16, dense_qubits=4, no_leaf_fold=1,
-                  fold_levels=2, chain_passes=1, no_row_skip=1, no_defer=1, no_chain_merge=1, jit=1)
+                  fold_levels=2, chain_passes=1, no_row_skip=1, no_defer=1, no_chain_merge=1, jit=1, no_tail_move=1)
     assert sf.get_tuning(c) == {"reg_qubits": 3, "leaf_batch": 64, "max_slots": 1024, "waves_per_cu": 16,
                                 "dense_qubits": 4, "no_leaf_fold": 1, "fold_levels": 2, "chain_passes": 1,
-                                "no_row_skip": 1, "no_defer": 1, "no_chain_merge": 1, "jit": 1}
+                                "no_row_skip": 1, "no_defer": 1, "no_chain_merge": 1, "jit": 1, "no_tail_move": 1}
     with pytest.raises(sf.SFError):
         sf.set_tuning(c, no_leaf_fold=2)
     with pytest.raises(sf.SFError):
@@ -295,6 +295,8 @@ def test_tuning_roundtrip(sf):
         sf.set_tuning(c, no_chain_merge=2)
     with pytest.raises(sf.SFError):
         sf.set_tuning(c, jit=2)
+    with pytest.raises(sf.SFError):
+        sf.set_tuning(c, no_tail_move=2)
     with pytest.raises(sf.SFError):
         sf.set_tuning(c, dense_qubits=1)
     with pytest.raises(sf.SFError):
@@ -322,8 +324,8 @@ def test_rejection_host_entries_match_oracle(sf):
 
 def test_tuning_cache_file_roundtrip(sf, tmp_path):
     """Autotuner results kept across processes: a text file of keyed tunings, validated on load
-    (entries without the last fields, chain_passes, no_row_skip, no_defer, no_chain_merge and jit,
-    read as 0)."""
+    (entries without the last fields, chain_passes, no_row_skip, no_defer, no_chain_merge, jit and
+    no_tail_move, read as 0)."""
     src = tmp_path / "in.txt"
     src.write_text("# comment\n"
                    "gfx950:256/15/15/15/7/32768/100000/0 5 0 0 32 4 0 2\n"
@@ -334,13 +336,14 @@ def test_tuning_cache_file_roundtrip(sf, tmp_path):
     out = tmp_path / "out.txt"
     sf.save_tuning_cache(str(out))
     lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
-    assert "gfx950:256/15/15/15/7/32768/100000/0 5 0 0 32 4 0 2 0 0 0 0 0" in lines
-    assert "gfx950:256/15/15/30/7/262144/100000/0 4 4096 0 16 0 1 0 1 1 0 0 0" in lines
-    assert "gfx950:256/15/15/28/7/1024/1000000/0 5 0 0 128 0 0 0 0 0 0 1 0" in lines
-    assert "gfx950:256/15/15/28/7/2048/1000000/0 5 0 0 128 0 0 0 0 0 0 0 1" in lines
+    assert "gfx950:256/15/15/15/7/32768/100000/0 5 0 0 32 4 0 2 0 0 0 0 0 0" in lines
+    assert "gfx950:256/15/15/30/7/262144/100000/0 4 4096 0 16 0 1 0 1 1 0 0 0 0" in lines
+    assert "gfx950:256/15/15/28/7/1024/1000000/0 5 0 0 128 0 0 0 0 0 0 1 0 0" in lines
+    assert "gfx950:256/15/15/28/7/2048/1000000/0 5 0 0 128 0 0 0 0 0 0 0 1 0" in lines
     for bad in ["k 1 2 3\n", "k 9 0 0 32 0 0 0\n", "k 5 0 0 32 1 0 0\n", "k 5 0 0 32 0 0 0 7\n",
-                "k 5 0 0 32 0 0 0 0 0 0 0 0 0\n", "k 5 0 0 32 0 0 0 0 2\n", "k 5 0 0 32 0 0 0 0 0 3\n",
-                "k 5 0 0 32 0 0 0 0 0 0 2\n", "k 5 0 0 32 0 0 0 0 0 0 0 2\n"]:
+                "k 5 0 0 32 0 0 0 0 0 0 0 0 0 0\n", "k 5 0 0 32 0 0 0 0 2\n", "k 5 0 0 32 0 0 0 0 0 3\n",
+                "k 5 0 0 32 0 0 0 0 0 0 2\n", "k 5 0 0 32 0 0 0 0 0 0 0 2\n",
+                "k 5 0 0 32 0 0 0 0 0 0 0 0 2\n"]:
         f = tmp_path / "bad.txt"
         f.write_text(bad)
         with pytest.raises(sf.SFError) as e:

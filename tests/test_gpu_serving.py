@@ -176,12 +176,12 @@ def test_autotune_cache_file(sf, tmp_path):
     sf.save_tuning_cache(str(path))
     want = " ".join(str(t[k]) for k in ("reg_qubits", "leaf_batch", "max_slots", "waves_per_cu", "dense_qubits",
                                          "no_leaf_fold", "fold_levels", "chain_passes", "no_row_skip", "no_defer",
-                                         "no_chain_merge", "jit"))
+                                         "no_chain_merge", "jit", "no_tail_move"))
     lines = [l for l in path.read_text().splitlines() if l.endswith("/200/333/0 " + want)]
     assert len(lines) == 1 and lines[0].startswith("gfx950:"), path.read_text()
     # a stored tuning for this key replaces the cached one and is returned as is
     key = lines[0].split()[0]
-    forced = "4 0 0 16 0 1 0 1 1 0 1 0"
+    forced = "4 0 0 16 0 1 0 1 1 0 1 0 1"
     (tmp_path / "forced.txt").write_text(f"{key} {forced}\n")
     assert sf.load_tuning_cache(str(tmp_path / "forced.txt")) == 1
     c.tune()
@@ -190,7 +190,7 @@ def test_autotune_cache_file(sf, tmp_path):
     assert time.perf_counter() - t0 < 0.5
     assert " ".join(str(t2[k]) for k in ("reg_qubits", "leaf_batch", "max_slots", "waves_per_cu", "dense_qubits",
                                          "no_leaf_fold", "fold_levels", "chain_passes", "no_row_skip", "no_defer",
-                                         "no_chain_merge", "jit")) == forced
+                                         "no_chain_merge", "jit", "no_tail_move")) == forced
     assert sf.get_tuning(c.handle) == t2
     a = c.amplitudes(bits, n_paths=200)
     o = oracle.path_sum(16, g, cfg.cut_mask(), np.arange(200, dtype=np.uint64), bits)
