@@ -156,7 +156,9 @@ int run_paths(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin,
  * not fit in 64 MiB (bitstring indices and visiting order, slot tables, pass programs, one
  * block-state slot per tree level) returns SF_ERR_OOM with that reason.  Every call on a GPU
  * uses that GPU's one array: calls that overlap on one GPU (other threads or streams) race and
- * must be serialised by the caller; each call initialises what it reads.
+ * must be serialised by the caller; each call initialises what it reads.  With tuning jit it
+ * compiles nothing (loading a compiled kernel allocates device memory for its code): passes
+ * whose kernel an earlier call of the process compiled run it, the others run interpreted.
  */
 int run_paths_noalloc(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin,
                       uint64_t n_paths, const uint64_t *bitstrings, size_t n_bits,

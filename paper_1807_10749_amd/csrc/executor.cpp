@@ -216,7 +216,7 @@ int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32
 
 int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
             const uint64_t *bits, size_t n_bits, double *amps, uint32_t flags, void *stream_v,
-            void *workspace, size_t workspace_bytes, std::string &err, bool dry_run)
+            void *workspace, size_t workspace_bytes, std::string &err, bool dry_run, bool no_compile)
 {
     const auto t_start = std::chrono::steady_clock::now();
     hipStream_t stream = (hipStream_t)stream_v;
@@ -1279,7 +1279,9 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
     // Compiled passes (tuning jit): every pass launch outside a chain whose program (both
     // programs of a pair) the compiled form covers gets the kernel compiled for it; a repeated
     // request keeps them with its plan, other requests with the same programs find them in the
-    // process-wide cache.
+    // process-wide cache.  no_compile (the entry point without allocations: loading a kernel
+    // allocates device memory for its code): only kernels already in the cache, the other passes
+    // interpreted.
     if (c.tuning.jit && n_paths) {
         std::vector<std::string> srcs;
         std::vector<size_t> at;
@@ -1296,7 +1298,7 @@ int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t 
         }
         std::vector<hipFunction_t> fns;
         double ms = 0;
-        if (int rc = jit_kernels(srcs, fns, &ms, err)) return rc;
+        if (int rc = jit_kernels(srcs, fns, &ms, err, !no_compile)) return rc;
         for (size_t i = 0; i < at.size(); ++i) launches[at[i]].jit_fn = fns[i];
         c.stats.jit_compile_ms += ms;
     }

@@ -240,7 +240,7 @@ int jit_compile_only(const std::vector<std::string> &sources, const std::string 
 }
 
 int jit_kernels(const std::vector<std::string> &sources, std::vector<hipFunction_t> &fns, double *compile_ms,
-                std::string &err)
+                std::string &err, bool compile)
 {
     fns.assign(sources.size(), nullptr);
     if (compile_ms) *compile_ms = 0;
@@ -256,7 +256,7 @@ int jit_kernels(const std::vector<std::string> &sources, std::vector<hipFunction
         if (it != g_cache.end()) fns[i] = it->second;
         else if (std::find(uniq.begin(), uniq.end(), sources[i]) == uniq.end()) uniq.push_back(sources[i]);
     }
-    if (!uniq.empty()) {
+    if (!uniq.empty() && compile) {
         hipDeviceProp_t prop;
         if ((he = hipGetDeviceProperties(&prop, dev)) != hipSuccess) {
             err = std::string("hipGetDeviceProperties: ") + hipGetErrorString(he);

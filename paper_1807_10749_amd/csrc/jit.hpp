@@ -30,11 +30,11 @@ std::string jit_kernel(bool fp64, int R0, const std::string &prog0, bool zskip0,
                        bool zskip1);
 
 // The kernels of the given sources on the current device: from the process-wide cache, or
-// compiled (the missing ones in parallel, a few per hiprtc program) and loaded.  fns[i] receives
-// the kernel of sources[i]; *compile_ms the time spent compiling in this call.  0 or an SF_ERR_*
-// code with err set.
+// (compile) compiled, the missing ones in parallel, a few per hiprtc program, and loaded.
+// fns[i] receives the kernel of sources[i] (nullptr if not cached and compile is false);
+// *compile_ms the time spent compiling in this call.  0 or an SF_ERR_* code with err set.
 int jit_kernels(const std::vector<std::string> &sources, std::vector<hipFunction_t> &fns, double *compile_ms,
-                std::string &err);
+                std::string &err, bool compile = true);
 
 // Compiles the sources for `arch` (e.g. "gfx950") without a device and loads nothing: the total
 // code-object size, or an SF_ERR_* code with the compiler's log in err.

@@ -213,7 +213,8 @@ int set_error(int code, const std::string &msg);
 // c.stats without touching device memory.
 int execute(Circuit &c, const uint64_t *path_ids, uint64_t path_begin, uint64_t n_paths,
             const uint64_t *bits, size_t n_bits, double *amps, uint32_t flags, void *stream,
-            void *workspace, size_t workspace_bytes, std::string &err, bool dry_run = false);
+            void *workspace, size_t workspace_bytes, std::string &err, bool dry_run = false,
+            bool no_compile = false);
 int estimate_workspace(const Circuit &c, uint64_t n_paths, size_t n_bits, uint32_t flags, size_t *bytes);
 
 }  // namespace sf

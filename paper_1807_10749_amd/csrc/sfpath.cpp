@@ -255,7 +255,7 @@ int run_paths_in(sf_circuit_t *c, const uint64_t *path_ids, uint64_t path_begin,
         if (const int rc = check_run_args(c, bitstrings, n_bits, amps, flags, nullptr, 0)) return rc;
         std::string err;
         const int rc = sf::execute(*c, path_ids, path_begin, n_paths, bitstrings, n_bits, amps, flags, hip_stream,
-                                   workspace, workspace_bytes, err);
+                                   workspace, workspace_bytes, err, false, true);
         return rc ? fail(rc, err) : ok();
     });
 }

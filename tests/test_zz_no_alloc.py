@@ -66,3 +66,48 @@ def test_noalloc_matches_run_paths():
     sf.run_paths(c.handle, None, 0, 64, bits[:1000], 1000, ref)
     assert c11_error(d_a.cpu().numpy()[:2000].view(np.complex128), ref.view(np.complex128), 64, c.k, 30) <= TOL_C64
     c.close()
+
+
+def test_noalloc_with_compiled_passes_compiles_nothing():
+    """With tuning jit the entry point compiles and loads no kernel (that allocates device memory):
+    before any compile of the circuit's programs it runs interpreted, after run_paths compiled
+    them it runs the cached kernels; both equal run_paths."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1807_10749_amd import binding as sf
+    stream = torch.cuda.current_stream()
+    flags_dev = sf.SF_OUT_ON_DEVICE | sf.SF_BITS_ON_DEVICE
+    rows, cols, depth, seed, nb = 4, 5, 14, 4242, 5_000
+    n = rows * cols
+    g = grid_circuit(rows, cols, depth, seed)
+    c = sf.Circuit(rows, cols, g, column_cut_mask(rows, cols, 2))
+    bits = random_bitstrings(n, nb, seed + 1)
+    ids = np.arange(1 << c.k, dtype=np.uint64)
+    d_bits = torch.from_numpy(bits.view(np.int64)).cuda()
+    d_a = torch.zeros(2 * nb, dtype=torch.float64, device="cuda")
+    d_b = torch.zeros(2 * nb, dtype=torch.float64, device="cuda")
+    say("noalloc with tuning jit before any compile of the circuit's programs")
+    c.tune(jit=1)
+    sf.run_paths_noalloc(c.handle, ids, 0, ids.size, d_bits, nb, d_b, flags_dev, stream)
+    torch.cuda.synchronize()
+    s = c.stats()
+    assert s["n_jit_passes"] == 0 and s["jit_compile_ms"] == 0.0, s
+    c.tune(jit=0)
+    sf.run_paths(c.handle, ids, 0, ids.size, d_bits, nb, d_a, flags_dev, stream)
+    torch.cuda.synchronize()
+    a, b = d_a.cpu().numpy().view(np.complex128), d_b.cpu().numpy().view(np.complex128)
+    assert c11_error(b, a, ids.size, c.k, n) <= TOL_C64
+    say("noalloc with tuning jit after run_paths compiled the programs")
+    c.tune(jit=1)
+    sf.run_paths(c.handle, ids, 0, ids.size, d_bits, nb, d_a, flags_dev, stream)
+    torch.cuda.synchronize()
+    assert c.stats()["n_jit_passes"] > 0
+    sf.run_paths_noalloc(c.handle, ids, 0, ids.size, d_bits, nb, d_b, flags_dev, stream)
+    torch.cuda.synchronize()
+    s = c.stats()
+    assert s["n_jit_passes"] > 0 and s["jit_compile_ms"] == 0.0, s
+    a, b = d_a.cpu().numpy().view(np.complex128), d_b.cpu().numpy().view(np.complex128)
+    assert c11_error(b, a, ids.size, c.k, n) <= TOL_C64
+    o = oracle.path_sum(n, g, column_cut_mask(rows, cols, 2), ids, bits)
+    assert c11_error(b, o, ids.size, c.k, n) <= TOL_C64
+    c.close()
